@@ -1,0 +1,428 @@
+"""CPU FP64 oracle for the row-splitting ILU least-squares method.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use this module; the GPU library never imports it, and it
+imports nothing from the library.
+
+It follows the paper step by step:
+  * prescale            Section 5.1 (unit 2-norm columns)
+  * ilup                Algorithms 4-6 (rectangular ILUP(p, tau), threshold
+                        partial pivoting, minimum row count, Li-Shao pivot
+                        modification), sequential C in oracle_core.c
+  * extract             the splitting (3.8): P A ~ [L1; L2] U
+  * levels              dependency depths of the triangular factors
+  * dense_S             S~ = I + Y~ Y~^T with Y~ = L2 L1^{-1}, (3.9), factored
+                        once by Cholesky (Section 3.2)
+  * apply_alg3          Algorithm 3 on the residual components (r1, r2)
+  * pcgls               Algorithm 1 (left-preconditioned, factorization-free
+                        CGLS) with Algorithm 3 in place of h = M^{-1} A^T r
+The method does not converge to anything faster than it converges; its limit
+is the least-squares solution, which the tests pin with dense QR.
+"""
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import build as _build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
+            _build.build(quiet=True)
+        lib = ctypes.CDLL(_build.LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        lib.orc_prescale.argtypes = [I64, P, P, P, P, P]
+        lib.orc_prescale.restype = ctypes.c_int
+        lib.orc_ilup.argtypes = [I64, I64, P, P, P, I64, D, D, D, P, P, P, P, I64, P, P, P, I64, P]
+        lib.orc_ilup.restype = ctypes.c_int
+        lib.orc_csr_matvec.argtypes = [I64, P, P, P, P, P]
+        lib.orc_csr_matvec.restype = None
+        lib.orc_lower_solve.argtypes = [I64, P, P, P, P, P, P]
+        lib.orc_lower_solve.restype = I64
+        lib.orc_upper_solve.argtypes = [I64, P, P, P, P, P, P]
+        lib.orc_upper_solve.restype = I64
+        lib.orc_levels.argtypes = [I64, P, P, ctypes.c_int, P]
+        lib.orc_levels.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ----------------------------------------------------------------------------
+# sparse containers (plain CSR triples)
+
+
+@dataclass
+class CSR:
+    nrows: int
+    ncols: int
+    rowptr: np.ndarray  # int64
+    col: np.ndarray  # int32
+    val: np.ndarray  # float64
+
+    @property
+    def nnz(self):
+        return int(self.rowptr[-1])
+
+    def scipy(self):
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.nrows, self.ncols))
+
+    def dense(self):
+        return self.scipy().toarray()
+
+    def matvec(self, x):
+        """y = A x, sequential sums in stored order."""
+        x = _c(x, np.float64)
+        assert x.shape == (self.ncols,)
+        y = np.empty(self.nrows)
+        _load().orc_csr_matvec(self.nrows, _p(self.rowptr), _p(self.col), _p(self.val), _p(x), _p(y))
+        return y
+
+    def transpose(self):
+        t = self.scipy().T.tocsr()
+        t.sort_indices()
+        return CSR(self.ncols, self.nrows, t.indptr.astype(np.int64), t.indices.astype(np.int32),
+                   t.data.astype(np.float64))
+
+
+def csr_from_scipy(a):
+    a = a.tocsr()
+    a.sort_indices()
+    return CSR(a.shape[0], a.shape[1], a.indptr.astype(np.int64), a.indices.astype(np.int32),
+               a.data.astype(np.float64))
+
+
+def lower_solve(L, b, diag=None):
+    """Forward substitution with lower-triangular CSR L (unit diagonal if diag is None)."""
+    b = _c(b, np.float64)
+    x = np.empty(L.nrows)
+    d = None if diag is None else _c(diag, np.float64)
+    bad = _load().orc_lower_solve(L.nrows, _p(L.rowptr), _p(L.col), _p(L.val), _p(d), _p(b), _p(x))
+    if bad:
+        raise ValueError("matrix is not strictly lower triangular at row %d" % (bad - 1))
+    return x
+
+
+def upper_solve(U, b, diag=None):
+    """Back substitution with upper-triangular CSR U (unit diagonal if diag is None)."""
+    b = _c(b, np.float64)
+    x = np.empty(U.nrows)
+    d = None if diag is None else _c(diag, np.float64)
+    bad = _load().orc_upper_solve(U.nrows, _p(U.rowptr), _p(U.col), _p(U.val), _p(d), _p(b), _p(x))
+    if bad:
+        raise ValueError("matrix is not strictly upper triangular at row %d" % (bad - 1))
+    return x
+
+
+# ----------------------------------------------------------------------------
+# Section 5.1 and the problem statement (1.1)
+
+
+def validate(m, n, rowptr, col, val):
+    """Check CSR input of A (m x n, m >= n) and strip explicit zeros."""
+    rowptr = _c(rowptr, np.int64)
+    col = _c(col, np.int64)
+    val = _c(val, np.float64)
+    if n < 1 or m < n:
+        raise ValueError("need m >= n >= 1")
+    if rowptr.shape != (m + 1,) or rowptr[0] != 0 or np.any(np.diff(rowptr) < 0):
+        raise ValueError("bad row pointer")
+    nnz = int(rowptr[-1])
+    if col.shape != (nnz,) or val.shape != (nnz,):
+        raise ValueError("bad array lengths")
+    if nnz and (col.min() < 0 or col.max() >= n):
+        raise ValueError("column index out of range")
+    if not np.all(np.isfinite(val)):
+        raise ValueError("non-finite value")
+    rows = np.repeat(np.arange(m), np.diff(rowptr))
+    if nnz > 1:
+        same_row = rows[1:] == rows[:-1]
+        if np.any(same_row & (col[1:] <= col[:-1])):
+            raise ValueError("column indices must be sorted and unique within a row")
+    keep = val != 0.0
+    rows, col, val = rows[keep], col[keep], val[keep]
+    newptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=newptr[1:])
+    return newptr, col.astype(np.int32), val
+
+
+def to_csc(m, n, rowptr, col, val):
+    """Column-compressed copy with ascending row indices in each column."""
+    a = sp.csr_matrix((val, col, rowptr), shape=(m, n)).tocsc()
+    a.sort_indices()
+    return a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data.astype(np.float64)
+
+
+def prescale(n, colptr, rowind, val):
+    """Section 5.1: every column of A scaled to unit 2-norm. Returns (scaled values, norms)."""
+    sval = np.empty_like(val)
+    nrm = np.empty(n)
+    _load().orc_prescale(n, _p(colptr), _p(rowind), _p(val), _p(sval), _p(nrm))
+    return sval, nrm
+
+
+# ----------------------------------------------------------------------------
+# Algorithms 4-6
+
+
+def ilup(m, n, colptr, rowind, val, p=10, tau=1e-2, mu=0.1, small=1e-10):
+    """Rectangular ILUP(p, tau) of the (prescaled) CSC matrix. See oracle_core.c."""
+    colptr = _c(colptr, np.int64)
+    rowind = _c(rowind, np.int32)
+    val = _c(val, np.float64)
+    pe = int(min(p, m))
+    lcap = max(1, n * min(pe, m))
+    ucap = n * (min(pe, n) + 1)
+    perm = np.empty(m, dtype=np.int32)
+    lptr = np.empty(n + 1, dtype=np.int64)
+    lrow = np.empty(lcap, dtype=np.int32)
+    lval = np.empty(lcap)
+    uptr = np.empty(n + 1, dtype=np.int64)
+    ustep = np.empty(ucap, dtype=np.int32)
+    uval = np.empty(ucap)
+    nmod = ctypes.c_int64(0)
+    rc = _load().orc_ilup(m, n, _p(colptr), _p(rowind), _p(val), pe, float(tau), float(mu), float(small),
+                          _p(perm), _p(lptr), _p(lrow), _p(lval), lcap, _p(uptr), _p(ustep), _p(uval), ucap,
+                          ctypes.byref(nmod))
+    if rc != 0:
+        raise RuntimeError("orc_ilup failed with code %d" % rc)
+    lnz, unz = int(lptr[-1]), int(uptr[-1])
+    return dict(perm=perm, lptr=lptr, lrow=lrow[:lnz].copy(), lval=lval[:lnz].copy(), uptr=uptr,
+                ustep=ustep[:unz].copy(), uval=uval[:unz].copy(), nmod=int(nmod.value))
+
+
+def level_sets(level):
+    """(level_ptr, level_rows): rows grouped by level, ascending inside a level."""
+    level = np.asarray(level, dtype=np.int64)
+    nlev = int(level.max()) + 1 if level.size else 0
+    rows = np.argsort(level, kind="stable").astype(np.int32)
+    ptr = np.zeros(nlev + 1, dtype=np.int32)
+    np.cumsum(np.bincount(level, minlength=nlev), out=ptr[1:])
+    return ptr, rows
+
+
+def levels(T, forward):
+    """Depth of each row of triangular CSR T in its dependency DAG."""
+    lv = np.empty(T.nrows, dtype=np.int32)
+    _load().orc_levels(T.nrows, _p(T.rowptr), _p(T.col), 1 if forward else 0, _p(lv))
+    return lv
+
+
+@dataclass
+class Factors:
+    m: int
+    n: int
+    perm: np.ndarray  # int32[m], perm[k] = original row at position k
+    colnorm: np.ndarray  # float64[n], A_hat = P A diag(1/colnorm)
+    A: CSR  # user's A (validated)
+    Ahat: CSR  # rows in pivot order, prescaled columns
+    AhatT: CSR
+    L1: CSR  # n x n strictly lower (unit diagonal implicit), by position
+    L1T: CSR
+    L2: CSR  # (m-n) x n
+    L2T: CSR
+    U: CSR  # n x n strictly upper part of U~
+    Udiag: np.ndarray
+    UT: CSR
+    nmod: int
+    smode: str
+    S_chol: np.ndarray = field(default=None)  # lower Cholesky factor of S~ (dense mode)
+    lev: dict = field(default_factory=dict)
+
+    @property
+    def psize(self):
+        """Stored entries used by Algorithm 3: nnz(L1) + nnz(L2) + nnz(U) (diagonal of U
+        counted, unit diagonal of L1 not), plus the packed S~ factor in dense mode."""
+        s = self.L1.nnz + self.L2.nnz + self.U.nnz + self.n
+        if self.smode == "dense":
+            k = self.m - self.n
+            s += k * (k + 1) // 2
+        return s
+
+
+def extract(m, n, res):
+    """Split L~ into L1 (rows at positions < n) and L2 (positions >= n) and build U by rows."""
+    perm = res["perm"].astype(np.int64)
+    pos = np.empty(m, dtype=np.int64)
+    pos[perm] = np.arange(m)
+    lcol = np.repeat(np.arange(n), np.diff(res["lptr"]))
+    lposn = pos[res["lrow"]]
+    in1 = lposn < n
+    L1 = csr_from_scipy(sp.coo_matrix((res["lval"][in1], (lposn[in1], lcol[in1])), shape=(n, n)))
+    L2 = csr_from_scipy(sp.coo_matrix((res["lval"][~in1], (lposn[~in1] - n, lcol[~in1])), shape=(m - n, n)))
+    ucol = np.repeat(np.arange(n), np.diff(res["uptr"]))
+    ustep = res["ustep"].astype(np.int64)
+    isdiag = ustep == ucol
+    Udiag = np.zeros(n)
+    Udiag[ucol[isdiag]] = res["uval"][isdiag]
+    U = csr_from_scipy(sp.coo_matrix((res["uval"][~isdiag], (ustep[~isdiag], ucol[~isdiag])), shape=(n, n)))
+    return L1, L2, U, Udiag
+
+
+def dense_S(L1, L2):
+    """S~ = I + Y~ Y~^T with Y~^T = L1^{-T} L2^T (dense), and its Cholesky factor (Section 3.2)."""
+    n = L1.nrows
+    L1d = L1.dense() + np.eye(n)
+    YT = sla.solve_triangular(L1d.T, L2.dense().T, lower=False, unit_diagonal=True)
+    S = np.eye(L2.nrows) + YT.T @ YT
+    return S, np.linalg.cholesky(S)
+
+
+def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=True, smode="identity"):
+    """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~."""
+    rowptr, col, val = validate(m, n, rowptr, col, val)
+    A = CSR(m, n, rowptr, col, val)
+    colptr, rowind, cval = to_csc(m, n, rowptr, col, val)
+    if colscale:
+        sval, nrm = prescale(n, colptr, rowind, cval)
+    else:
+        sval, nrm = cval, np.ones(n)
+    res = ilup(m, n, colptr, rowind, sval, p=p, tau=tau, mu=mu, small=small)
+    perm = res["perm"]
+    L1, L2, U, Udiag = extract(m, n, res)
+    scaled = sp.csc_matrix((sval, rowind, colptr), shape=(m, n)).tocsr()
+    Ahat = csr_from_scipy(scaled[perm.astype(np.int64), :])
+    F = Factors(m=m, n=n, perm=perm, colnorm=nrm, A=A, Ahat=Ahat, AhatT=Ahat.transpose(), L1=L1,
+                L1T=L1.transpose(), L2=L2, L2T=L2.transpose(), U=U, Udiag=Udiag, UT=U.transpose(),
+                nmod=res["nmod"], smode=smode)
+    F.lev = {
+        "L1": level_sets(levels(F.L1, True)),
+        "L1T": level_sets(levels(F.L1T, False)),
+        "U": level_sets(levels(F.U, False)),
+        "UT": level_sets(levels(F.UT, True)),
+    }
+    if smode == "dense":
+        _, F.S_chol = dense_S(L1, L2)
+    elif smode != "identity":
+        raise ValueError(smode)
+    return F
+
+
+def factor_problem(prob, **kw):
+    return factor(prob.m, prob.n, prob.rowptr, prob.col, prob.val, **kw)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 3 and Algorithm 1
+
+
+def apply_alg3(F, r):
+    """Algorithm 3 on the residual r (pivot order): h from (r1, r2).
+
+    u = r2 - Y~ r1 with Y~ r1 = L2 (L1^{-1} r1); solve S^ w = u (S^ = I or the
+    dense S~); y = r1 + Y~^T w with Y~^T w = L1^{-T} (L2^T w); L1 v = y; U h = v.
+    """
+    n = F.n
+    r1, r2 = r[:n], r[n:]
+    t = lower_solve(F.L1, r1)
+    u = r2 - F.L2.matvec(t)
+    if F.smode == "dense":
+        w = sla.cho_solve((F.S_chol, True), u)
+    else:
+        w = u
+    g = F.L2T.matvec(w)
+    y = r1 + upper_solve(F.L1T, g)
+    v = lower_solve(F.L1, y)
+    return upper_solve(F.U, v, F.Udiag)
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    status: str  # "ok", "not_converged", "breakdown"
+    atr_norm: float  # true ||A^T (b - A x)||
+    atr_rel: float  # atr_norm / ||A^T b||
+    hist: list = field(default_factory=list)  # recurrence ||A^T r|| per iteration
+    rnorm: list = field(default_factory=list)  # ||r|| per iteration (with trace=True)
+    orth: list = field(default_factory=list)  # (p_prev, z_new)/(p_prev, z_old) (with trace=True)
+
+
+def true_residual(A, b, x):
+    """||A^T (b - A x)|| and its ratio to ||A^T b|| on the user's A."""
+    r = b - A.matvec(x)
+    AT = A.transpose()
+    atr = float(np.linalg.norm(AT.matvec(r)))
+    atb = float(np.linalg.norm(AT.matvec(np.asarray(b, dtype=np.float64))))
+    return atr, (atr / atb if atb > 0 else 0.0)
+
+
+def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False):
+    """Algorithm 1 on A_hat x_hat ~ P b with h = B(r) from Algorithm 3.
+
+    Initialisation: x0 = 0, r0 = P b, z0 = A_hat^T r0, h0 = B(r0),
+    rho0 = (z0, h0), p0 = h0. Iteration i: q = A_hat p, alpha = rho/(q,q),
+    x += alpha p, r -= alpha q, z = A_hat^T r; stop when ||D^{-1} z|| <=
+    tol ||D^{-1} z0|| (this is ||A^T r|| <= tol ||A^T b|| on the user's A);
+    else h = B(r), rho' = (z,h), beta = rho'/rho, p = h + beta p.
+    Breakdown: (q,q) = 0, rho' = 0 or a non-finite scalar.
+    """
+    apply = apply or apply_alg3
+    b = _c(b, np.float64)
+    n = F.n
+    r = b[F.perm.astype(np.int64)].copy()
+    xh = np.zeros(n)
+    z = F.AhatT.matvec(r)
+    nb = math.sqrt(float(np.dot(F.colnorm * z, F.colnorm * z)))
+    hist = [nb]
+    rn, orth = [float(np.linalg.norm(r))], []
+    status = "not_converged"
+    iters = 0
+    if nb == 0.0:
+        status = "ok"
+    else:
+        h = apply(F, r)
+        rho = float(np.dot(z, h))
+        p = h.copy()
+        if rho == 0.0 or not math.isfinite(rho):
+            status = "breakdown"
+        else:
+            for it in range(1, maxit + 1):
+                q = F.Ahat.matvec(p)
+                delta = float(np.dot(q, q))
+                if delta == 0.0 or not math.isfinite(delta):
+                    status = "breakdown"
+                    break
+                alpha = rho / delta
+                xh += alpha * p
+                r -= alpha * q
+                z = F.AhatT.matvec(r)
+                zn = math.sqrt(float(np.dot(F.colnorm * z, F.colnorm * z)))
+                hist.append(zn)
+                if trace:
+                    rn.append(float(np.linalg.norm(r)))
+                    orth.append(float(np.dot(p, z)) / rho)
+                iters = it
+                if zn <= tol * nb:
+                    status = "ok"
+                    break
+                h = apply(F, r)
+                rho_new = float(np.dot(z, h))
+                if rho_new == 0.0 or not math.isfinite(rho_new):
+                    status = "breakdown"
+                    break
+                beta = rho_new / rho
+                rho = rho_new
+                p = h + beta * p
+    x = xh / F.colnorm
+    atr, rel = true_residual(F.A, b, x)
+    return SolveResult(x=x, iters=iters, status=status, atr_norm=atr, atr_rel=rel, hist=hist, rnorm=rn, orth=orth)
