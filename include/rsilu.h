@@ -1,0 +1,198 @@
+/*
+ * rsilu: row-splitting ILU preconditioned least squares on one AMD MI355X.
+ *
+ * Solves min ||b - A x||_2 for a sparse A (m x n, m >= n), the problem (1.1)
+ * of Scott and Tuma, "Row-Splitting ILU Preconditioners for Sparse
+ * Least-Squares Problems". Setup (rsilu_factor) runs on the host: it prescales
+ * the columns of A to unit 2-norm (Section 5.1) and computes the rectangular
+ * ILUP(p, tau) factorization with threshold partial pivoting by rows
+ * (Algorithms 4, 5 and 6), which selects the square block A1 and returns
+ *   P A D ~ [L1; L2] U                                            (3.8)
+ * with D the column scaling, L1 unit lower triangular (n x n), L2 (m-n) x n
+ * and U upper triangular. The solve (rsilu_solve) runs entirely on the GPU:
+ * the left-preconditioned CGLS of Algorithm 1 with the preconditioner applied
+ * by Algorithm 3 (u = r2 - Y r1, S^ w = u, y = r1 + Y^T w, L1 v = y, U h = v,
+ * Y = L2 L1^{-1} applied implicitly, S^ = I or the dense S~ = I + Y Y^T).
+ *
+ * Conventions for every call
+ *   - Indices are 0-based. Host arrays are owned by the caller and only read
+ *     during the call; the library keeps its own copies.
+ *   - Device pointers are HIP device memory owned by the caller. Work is
+ *     enqueued on the caller's stream (0 = the null stream).
+ *   - Internal coordinates: "pivot order" means row k of the permuted,
+ *     prescaled matrix A_hat = P A D is original row perm[k]; positions
+ *     0..n-1 form A1, positions n..m-1 form A2.
+ *   - No call throws; errors are returned as rsilu_status_t. A handle may be
+ *     used by one thread / one stream at a time; separate handles are
+ *     independent.
+ */
+#ifndef RSILU_H
+#define RSILU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSILU_OK = 0,            /* success / converged */
+    RSILU_NOT_CONVERGED = 1, /* maxit reached; x holds the last iterate */
+    RSILU_BREAKDOWN = 2,     /* (q,q) = 0, rho = 0 or a non-finite scalar in
+                                Algorithm 1, or a dense S~ that is not
+                                numerically positive definite at setup */
+    RSILU_EINVAL = -1,       /* invalid argument (shape, index, NaN/Inf, ...) */
+    RSILU_ENOMEM = -2,       /* host allocation failed or device buffer too small */
+    RSILU_EHIP = -3,         /* a HIP runtime call failed */
+    RSILU_ESTATE = -4,       /* call out of order (e.g. solve before upload) */
+    RSILU_EINTERNAL = -5     /* a kernel hit its internal wait bound */
+} rsilu_status_t;
+
+/* S^ used in step 2 of Algorithm 3 (Section 3.2). */
+enum {
+    RSILU_S_AUTO = -1,    /* dense when m - n <= 4096, identity otherwise */
+    RSILU_S_IDENTITY = 0, /* S^ = I: w = u */
+    RSILU_S_DENSE = 1     /* S~ = I + Y Y^T assembled and Cholesky-factored once */
+};
+
+/* Schedule of the sparse triangular solves with L1, L1^T and U. */
+enum {
+    RSILU_TRSV_SYNCFREE = 0, /* one launch per solve; rows wait on their inputs */
+    RSILU_TRSV_LEVELS = 1    /* one launch per level of the dependency DAG */
+};
+
+typedef struct {
+    int32_t p;        /* ILUP: at most p entries kept per column of L~ and of U~
+                         above the diagonal (Algorithm 4); default 10 */
+    double tau;       /* ILUP drop tolerance: entries with |v| < tau dropped; 1e-2 */
+    double mu;        /* threshold pivoting parameter, 0 < mu <= 1 (Algorithm 5); 0.1 */
+    double small;     /* pivots with |v| < small are modified (Algorithm 6); 1e-10 */
+    int32_t colscale; /* 1: prescale columns to unit 2-norm (Section 5.1); 1 */
+    int32_t smode;    /* RSILU_S_*; default RSILU_S_AUTO */
+    int32_t maxit;    /* Algorithm 1 iteration limit; 2000 (Section 5.1) */
+    int32_t trsv;     /* RSILU_TRSV_*; default RSILU_TRSV_SYNCFREE */
+    int32_t poll;     /* iterations enqueued between host polls of the stop flag; 8 */
+} rsilu_params_t;
+
+typedef struct {
+    int64_t m, n, nnz_a;   /* after stripping explicit zeros */
+    int64_t nnz_l1;        /* strictly lower entries of L1 (unit diagonal implicit) */
+    int64_t nnz_l2;        /* entries of L2 */
+    int64_t nnz_u;         /* strictly upper entries of U (diagonal not counted) */
+    int64_t psize;         /* nnz_l1 + nnz_l2 + nnz_u + n, plus (m-n)(m-n+1)/2
+                              for the packed dense S~ (Tables 2 and 3) */
+    int64_t nmod;          /* pivots modified by Algorithm 6 */
+    int32_t levels_l1;     /* levels of the DAG of the L1 forward solve */
+    int32_t levels_l1t;    /* ... of the L1^T backward solve */
+    int32_t levels_u;      /* ... of the U backward solve */
+    int32_t levels_ut;     /* ... of the U^T forward solve */
+    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY or RSILU_S_DENSE) */
+    int32_t reserved;
+    size_t device_bytes;   /* what rsilu_upload needs */
+} rsilu_stats_t;
+
+typedef struct rsilu_ctx *rsilu_handle_t;
+
+/* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
+ * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
+ * maxit = 2000 (Section 5.1), trsv = SYNCFREE, poll = 8. */
+void rsilu_params_default(rsilu_params_t *params);
+
+/* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting
+ * (3.8); Section 3.2 dense S~ when requested).
+ * A is given in CSR: rowptr[m+1] (int64), colind[nnz] (int32, sorted and
+ * unique within each row), val[nnz] (finite FP64). Explicit zeros are
+ * stripped. params may be NULL (defaults). On success *out owns a new handle
+ * (free it with rsilu_destroy).
+ * Errors: EINVAL for m < n, n < 1, bad pointers or indices, unsorted or
+ * duplicated columns, non-finite values, invalid parameters, more than
+ * 2^31 - 1 entries in a factor; ENOMEM when host memory runs out;
+ * BREAKDOWN when the dense S~ is not numerically positive definite.
+ * Rank deficiency is not an error: Algorithm 6 modifies the pivots and
+ * stats.nmod counts them. */
+rsilu_status_t rsilu_factor(int64_t m, int64_t n, const int64_t *rowptr, const int32_t *colind,
+                            const double *val, const rsilu_params_t *params, rsilu_handle_t *out);
+
+/* Exact size in bytes of the device buffer rsilu_upload needs: operators,
+ * level schedules, Krylov state and workspace. 0 for a NULL handle. */
+size_t rsilu_device_bytes(rsilu_handle_t h);
+
+/* Copy the operators into dev_buf (caller-owned device memory of at least
+ * rsilu_device_bytes(h) bytes, 256-byte aligned; it must outlive every later
+ * call on h) on the given stream, and wait for the copy to finish.
+ * Errors: EINVAL (NULL handle or buffer, misaligned buffer), ENOMEM (bytes too
+ * small), EHIP (runtime error). May be called again with another buffer. */
+rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipStream_t stream);
+
+/* Setup statistics (Tables 2 and 3 report psize and nmod). */
+rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *stats);
+
+/* perm[m]: original row index at each position of the ILUP row permutation
+ * (Algorithm 4 interchanges). Host array owned by the caller. */
+rsilu_status_t rsilu_get_perm(rsilu_handle_t h, int32_t *perm);
+
+/* colnorm[n]: the 2-norms of the columns of A (1 for an empty column, or all
+ * ones without prescaling); A_hat = P A diag(1/colnorm). */
+rsilu_status_t rsilu_get_colnorm(rsilu_handle_t h, double *colnorm);
+
+/* Factor and operator export, for inspection and tests (host arrays).
+ * which: 0 = L1 (n x n, strictly lower), 1 = L2 ((m-n) x n),
+ *        2 = U (n x n, strictly upper), 3 = A_hat (m x n, pivot order),
+ *        4 = diagonal of U (val[n] only; rowptr and col may be NULL).
+ * rsilu_factor_nnz returns the entry count of `which` (or -1 if invalid).
+ * rowptr has nrows+1 entries; columns are sorted within each row. */
+int64_t rsilu_factor_nnz(rsilu_handle_t h, int32_t which);
+rsilu_status_t rsilu_get_factor(rsilu_handle_t h, int32_t which, int64_t *rowptr, int32_t *col,
+                                double *val);
+
+/* Level schedule of a triangular solve: which = 0 L1 (forward), 1 L1^T
+ * (backward), 2 U (backward), 3 U^T (forward). level_ptr[nlev+1] and
+ * level_rows[n]; rows are ascending inside a level; nlev is in the stats. */
+rsilu_status_t rsilu_get_levels(rsilu_handle_t h, int32_t which, int32_t *level_ptr,
+                                int32_t *level_rows);
+
+/* Algorithm 1 with Algorithm 3 (after rsilu_upload).
+ * b_dev[m]: the right-hand side in the original row order (device, read only).
+ * x_dev[n]: the solution in the user's coordinates (device, written); must not
+ * alias b_dev. Starts from x = 0 and stops when ||A^T r|| <= tol ||A^T b||
+ * (on the user's A) or after maxit iterations.
+ * Host outputs (each may be NULL): *iters, *atr_norm = ||A^T (b - A x)|| and
+ * *atr_rel = atr_norm / ||A^T b||, both recomputed from x at exit.
+ * Returns OK, NOT_CONVERGED, BREAKDOWN (x holds the last finite iterate's
+ * update), EINVAL, ESTATE, EHIP or EINTERNAL. Blocks until the results are on
+ * the host; all device work is on `stream`. If ||A^T b|| = 0 then x = 0,
+ * iters = 0 and OK. */
+rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b_dev, double tol, double *x_dev,
+                           int32_t *iters, double *atr_norm, double *atr_rel, hipStream_t stream);
+
+/* The steps of one iteration, on caller-owned device vectors in internal
+ * coordinates, enqueued asynchronously on `stream` (after rsilu_upload).
+ *
+ * rsilu_spmv, op: 0  y[m] = A_hat x[n]        (Algorithm 1, q = A p)
+ *                 1  y[n] = A_hat^T x[m]      (Algorithm 1, z = A^T r)
+ *                 2  y[m-n] = L2 x[n]         (Algorithm 3, Y r1 = L2 L1^{-1} r1)
+ *                 3  y[n] = L2^T x[m-n]       (Algorithm 3, Y^T w = L1^{-T} L2^T w)
+ * rsilu_trsv, which: 0  L1 x = rhs   1  L1^T x = rhs   2  U x = rhs   (n-vectors)
+ * rsilu_apply: h[n] from the residual r[m] by Algorithm 3.
+ * x and y (rhs and x) must not alias. EINVAL for a bad op/which or NULL. */
+rsilu_status_t rsilu_spmv(rsilu_handle_t h, int32_t op, const double *x_dev, double *y_dev,
+                          hipStream_t stream);
+rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs_dev, double *x_dev,
+                          hipStream_t stream);
+rsilu_status_t rsilu_apply(rsilu_handle_t h, const double *r_dev, double *h_dev, hipStream_t stream);
+
+/* Release the handle's host memory and any HIP objects it created (not the
+ * caller's device buffer). NULL is ignored. */
+void rsilu_destroy(rsilu_handle_t h);
+
+/* Static description of a status code. */
+const char *rsilu_status_string(rsilu_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSILU_H */

@@ -415,6 +415,8 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False):
                 if zn <= tol * nb:
                     status = "ok"
                     break
+                if it == maxit:
+                    break
                 h = apply(F, r)
                 rho_new = float(np.dot(z, h))
                 if rho_new == 0.0 or not math.isfinite(rho_new):

@@ -1,0 +1,114 @@
+// Internal types shared by the host setup and the device driver.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "rsilu.h"
+
+namespace rsilu {
+
+// Host CSR with 32-bit row pointers (every operator has fewer than 2^31 entries).
+struct Csr {
+    int32_t nrows = 0, ncols = 0;
+    std::vector<int32_t> ptr;  // nrows + 1
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+// Level schedule of one triangular solve.
+struct Levels {
+    std::vector<int32_t> ptr;   // nlev + 1
+    std::vector<int32_t> rows;  // n, rows ascending inside a level
+    int32_t nlev() const { return ptr.empty() ? 0 : (int32_t)ptr.size() - 1; }
+};
+
+// Sync-free schedule: groups of consecutive rows of one level, each group at
+// most `cap` rows, processed by one wavefront.
+struct Chunks {
+    std::vector<int32_t> ptr;  // nchunks + 1, positions in Levels::rows
+    int32_t cap = 0;
+};
+
+// Work plan for a CSR product: rows with more than `long_thresh` entries are
+// split into segments of at most `seg` entries, reduced in a fixed order.
+struct SpmvPlan {
+    int32_t lanes = 8;           // lanes per row for ordinary rows
+    int32_t long_thresh = 0;     // rows longer than this are "long"
+    std::vector<int32_t> long_rows;
+    std::vector<int32_t> seg_ptr;   // long row i owns segments seg_ptr[i]..seg_ptr[i+1]
+    std::vector<int32_t> seg_beg;   // entry range of each segment
+    std::vector<int32_t> seg_end;
+};
+
+// Offsets (bytes) of every array inside the caller's device buffer.
+struct DevCsrOff {
+    size_t ptr = 0, col = 0, val = 0;
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+};
+struct DevPlanOff {
+    size_t long_rows = 0, seg_ptr = 0, seg_beg = 0, seg_end = 0;
+    int32_t nlong = 0, nseg = 0, lanes = 8, long_thresh = 0;
+};
+struct DevTriOff {
+    DevCsrOff a;
+    size_t diag = 0;     // 0 = unit diagonal
+    size_t rows = 0;     // level-ordered rows
+    size_t chunk = 0;    // chunk pointer
+    int32_t nchunks = 0;
+    int32_t cap = 0;
+    int32_t lanes = 8;
+    int32_t nlev = 0;
+};
+
+struct Layout {
+    size_t total = 0;
+    DevCsrOff A, AT, L2, L2T;
+    DevPlanOff pA, pAT, pL2, pL2T;
+    DevTriOff L1f, L1b, Ub;  // L1 forward, L1^T backward, U backward
+    size_t perm = 0, colnorm = 0, sfac = 0;
+    // Krylov vectors
+    size_t xh = 0, p = 0, z = 0, h = 0, t = 0, y = 0, v = 0, g = 0, gp = 0;  // n
+    size_t r = 0, q = 0;                                                       // m
+    size_t u = 0;                                                              // m - n
+    size_t partials = 0;  // reduction partials
+    int32_t npartials = 0;
+    size_t segpart = 0;   // long-row segment partials
+    int32_t nsegpart = 0;
+    size_t state = 0;     // device scalars and flags
+};
+
+struct Ctx {
+    int64_t m = 0, n = 0, nnz_a = 0;
+    rsilu_params_t prm{};
+    int32_t smode = RSILU_S_IDENTITY;
+    int64_t nmod = 0;
+
+    std::vector<int32_t> perm;     // position -> original row
+    std::vector<double> colnorm;   // n
+    Csr A;                         // user's A (validated), original order, unscaled
+    Csr Ahat, AhatT;               // pivot order, prescaled
+    Csr L1, L1T, L2, L2T, U, UT;   // strictly triangular parts
+    std::vector<double> Udiag;
+    Levels lvL1, lvL1T, lvU, lvUT;
+    Chunks chL1, chL1T, chU;
+    SpmvPlan plA, plAT, plL2, plL2T;
+    std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
+
+    Layout lay;
+    // device side
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    int device = -1;
+    void *pinned = nullptr;  // small host-pinned mailbox for polling
+};
+
+// host setup (setup.cpp)
+rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *rowptr,
+                                   const int32_t *colind, const double *val);
+void plan_layout(Ctx &c);
+
+}  // namespace rsilu

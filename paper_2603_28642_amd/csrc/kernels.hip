@@ -1,0 +1,645 @@
+// HIP kernels for CDNA4 (gfx950) of the preconditioned CGLS solve.
+//
+// Everything on this path is sparse FP64 streaming (about 0.15 flop per byte),
+// so the kernels are written for HBM bandwidth and latency, not for MFMA:
+//  - CSR products give each row a group of G lanes of a 64-wide wavefront
+//    (G chosen from the mean row length) so consecutive rows' entries are read
+//    contiguously; rows far longer than the mean are cut into fixed segments
+//    reduced in a fixed order, so results never depend on scheduling.
+//  - Norms and dot products are reduced per block in a fixed tree and then by
+//    one block in index order (bit-reproducible), and the same single block
+//    advances the scalar recurrence of Algorithm 1 on the device.
+//  - Triangular solves run "sync-free": one launch; wavefronts take chunks of
+//    rows (one level each) from an atomic ticket in level order and wait on
+//    their inputs, which are published with a single 64-bit store over a
+//    signalling-NaN sentinel (no flag array, no fences). Taking chunks in level
+//    order guarantees that every awaited row belongs to a wave already running.
+#include <cmath>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace rsilu {
+
+namespace {
+
+// Signalling NaN: arithmetic only ever produces quiet NaNs, so no computed
+// value can equal it.
+constexpr unsigned long long kSentinel = 0x7FF4DEADBEEF0001ull;
+constexpr unsigned long long kQuietNaN = 0x7FF8000000000000ull;
+constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ bool stop_now(const int32_t *done) { return done != nullptr && *done != 0; }
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Fixed-order sum of one value per thread of a 256-thread block; thread 0 gets it.
+__device__ __forceinline__ double block_sum256(double v, double *lds4)
+{
+    v = group_sum<64>(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds4[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+    return s;
+}
+
+__device__ void apply_fin(Fin fin, double total, DevState *st)
+{
+    switch (fin) {
+    case FIN_INIT: {
+        const double nb = sqrt(total);
+        st->nb = nb;
+        st->zn = nb;
+        if (nb == 0.0) {
+            st->done = 1;
+            st->status = 0;
+        } else if (!isfinite(nb)) {
+            st->done = 1;
+            st->status = 2;
+        }
+        break;
+    }
+    case FIN_ALPHA:
+        st->delta = total;
+        if (!(total > 0.0) || !isfinite(total)) {
+            st->done = 1;
+            st->status = 2;
+        } else {
+            st->alpha = st->rho / total;
+        }
+        break;
+    case FIN_STOP: {
+        const double zn = sqrt(total);
+        st->zn = zn;
+        st->iter += 1;
+        if (zn <= st->tol * st->nb) {
+            st->done = 1;
+            st->status = 0;
+        } else if (!isfinite(zn)) {
+            st->done = 1;
+            st->status = 2;
+        } else if (st->iter >= st->maxit) {
+            st->done = 1;
+            st->status = 1;
+        }
+        break;
+    }
+    case FIN_RHO0:
+        st->rho = total;
+        if (total == 0.0 || !isfinite(total)) {
+            st->done = 1;
+            st->status = 2;
+        }
+        break;
+    case FIN_BETA:
+        if (total == 0.0 || !isfinite(total)) {
+            st->done = 1;
+            st->status = 2;
+        } else {
+            st->beta = total / st->rho;
+            st->rho = total;
+        }
+        break;
+    case FIN_ATR:
+        st->atr = sqrt(total);
+        break;
+    default:
+        break;
+    }
+}
+
+// ------------------------------------------------------------------ products
+
+template <int G, int EPI>
+__global__ __launch_bounds__(kBlock) void k_spmv(DCsr a, int32_t long_thresh, const double *__restrict__ x,
+                                                  double *__restrict__ y, const double *__restrict__ aux,
+                                                  double *__restrict__ partials, const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    constexpr int RPB = kBlock / G;
+    const int row = blockIdx.x * RPB + threadIdx.x / G;
+    const int gl = threadIdx.x % G;
+    double sum = 0.0;
+    bool own = false;
+    if (row < a.nrows) {
+        const int b = a.ptr[row], e = a.ptr[row + 1];
+        if (e - b <= long_thresh) {
+            own = true;
+            for (int k = b + gl; k < e; k += G) sum += a.val[k] * x[a.col[k]];
+        }
+    }
+    sum = group_sum<G>(sum);
+    double contrib = 0.0;
+    if (own && gl == 0) {
+        double out = sum;
+        if (EPI == EPI_SUB) out = aux[row] - sum;
+        y[row] = out;
+        if (EPI == EPI_SQ) contrib = out * out;
+        if (EPI == EPI_WSQ) {
+            const double t = aux[row] * out;
+            contrib = t * t;
+        }
+    }
+    if (EPI == EPI_SQ || EPI == EPI_WSQ) {
+        const double s = block_sum256(contrib, lds4);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// One block per segment of a long row.
+__global__ __launch_bounds__(kBlock) void k_spmv_seg(DCsr a, DPlan pl, const double *__restrict__ x,
+                                                      double *__restrict__ segpart, const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    const int s = blockIdx.x;
+    const int b = pl.seg_beg[s], e = pl.seg_end[s];
+    double sum = 0.0;
+    for (int k = b + threadIdx.x; k < e; k += kBlock) sum += a.val[k] * x[a.col[k]];
+    const double t = block_sum256(sum, lds4);
+    if (threadIdx.x == 0) segpart[s] = t;
+}
+
+// Single block: finish the long rows, reduce the partials in index order and
+// take the scalar step of Algorithm 1 selected by `fin`.
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, double *__restrict__ y,
+                                                    const double *__restrict__ aux,
+                                                    const double *__restrict__ segpart,
+                                                    double *__restrict__ partials, Fin fin, DevState *st,
+                                                    const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    for (int i = threadIdx.x; i < pl.nlong; i += kBlock) {
+        const int row = pl.long_rows[i];
+        double s = 0.0;
+        for (int q = pl.seg_ptr[i]; q < pl.seg_ptr[i + 1]; ++q) s += segpart[q];
+        double out = (EPI == EPI_SUB) ? aux[row] - s : s;
+        y[row] = out;
+        double c = 0.0;
+        if (EPI == EPI_SQ) c = out * out;
+        if (EPI == EPI_WSQ) {
+            const double t = aux[row] * out;
+            c = t * t;
+        }
+        partials[nparts + i] = c;
+    }
+    if (fin == FIN_NONE) return;
+    __syncthreads();
+    const int total_n = nparts + pl.nlong;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < total_n; k += kBlock) s += partials[k];
+    const double total = block_sum256(s, lds4);
+    if (threadIdx.x == 0) apply_fin(fin, total, st);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double *__restrict__ a,
+                                                 const double *__restrict__ b, double *__restrict__ partials,
+                                                 const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    double s = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) s += a[i] * b[i];
+    const double t = block_sum256(s, lds4);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_fin(int32_t nparts, const double *__restrict__ partials,
+                                                        Fin fin, DevState *st, const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kBlock) s += partials[k];
+    const double total = block_sum256(s, lds4);
+    if (threadIdx.x == 0) apply_fin(fin, total, st);
+}
+
+// ------------------------------------------------------------------ vectors
+
+__global__ __launch_bounds__(kBlock) void k_gather(int32_t m, int32_t n, const int32_t *__restrict__ perm,
+                                                    const double *__restrict__ b, double *__restrict__ r,
+                                                    double *__restrict__ xh, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+        r[i] = b[perm[i]];
+        if (i < n) xh[i] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(int32_t n, int32_t m, const double *__restrict__ p,
+                                                    double *__restrict__ xh, const double *__restrict__ q,
+                                                    double *__restrict__ r, double *f0, double *f1, double *f2,
+                                                    double *f3, DevState *st, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double alpha = st->alpha;
+    const double sent = __longlong_as_double((long long)kSentinel);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+        r[i] = r[i] - alpha * q[i];
+        if (i < n) {
+            xh[i] = xh[i] + alpha * p[i];
+            if (f0) {
+                f0[i] = sent;
+                f1[i] = sent;
+                f2[i] = sent;
+                f3[i] = sent;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) st->ticket[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int32_t n, double *f0, double *f1, double *f2, double *f3,
+                                                  DevState *st)
+{
+    const double sent = __longlong_as_double((long long)kSentinel);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        if (f0) f0[i] = sent;
+        if (f1) f1[i] = sent;
+        if (f2) f2[i] = sent;
+        if (f3) f3[i] = sent;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) st->ticket[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->err = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pupdate(int32_t n, const double *__restrict__ h, double *__restrict__ p,
+                                                     const DevState *st, int32_t first, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double beta = first ? 0.0 : st->beta;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        p[i] = first ? h[i] : h[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_out(int32_t n, const double *__restrict__ xh,
+                                                       const double *__restrict__ colnorm, double *__restrict__ x)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) x[i] = xh[i] / colnorm[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual(int32_t m, const int32_t *__restrict__ perm,
+                                                      const double *__restrict__ b, const double *__restrict__ ax,
+                                                      double *__restrict__ r)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) r[i] = b[perm[i]] - ax[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const double *__restrict__ src, double *__restrict__ dst,
+                                                  const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ triangular solves
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_trsv_syncfree(DTri t, const double *__restrict__ rhs, double *x,
+                                                           const double *__restrict__ add, double *__restrict__ y2,
+                                                           DevState *st, int32_t tk, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / G, gl = lane % G;
+    unsigned long long *xb = reinterpret_cast<unsigned long long *>(x);
+    for (;;) {
+        unsigned int c = 0;
+        if (lane == 0) c = atomicAdd(&st->ticket[tk], 1u);
+        c = __shfl(c, 0);
+        if (c >= (unsigned int)t.nchunks) break;
+        const int beg = t.chunk[c], end = t.chunk[c + 1];
+        const int idx = beg + grp;
+        const bool act = idx < end;
+        const int row = act ? t.rows[idx] : 0;
+        double sum = 0.0;
+        if (act) {
+            const int b = t.a.ptr[row], e = t.a.ptr[row + 1];
+            for (int k = b + gl; k < e; k += G) {
+                const int cc = t.a.col[k];
+                const double v = t.a.val[k];
+                unsigned long long bits;
+                int spins = 0;
+                for (;;) {
+                    bits = __hip_atomic_load(xb + cc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (bits != kSentinel) break;
+                    ++spins;
+                    // bounded wait: past the limit, or once any wave has given up,
+                    // publish NaN and stop the solve (every later kernel sees done)
+                    if (spins > kSpinLimit ||
+                        ((spins & 255) == 0 &&
+                         __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                        __hip_atomic_store(&st->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        bits = kQuietNaN;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                sum += v * __longlong_as_double((long long)bits);
+            }
+        }
+        sum = group_sum<G>(sum);
+        if (act && gl == 0) {
+            double r = rhs[row] - sum;
+            if (t.diag) r = r / t.diag[row];
+            __hip_atomic_store(xb + row, (unsigned long long)__double_as_longlong(r), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (y2) y2[row] = add[row] + r;
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_trsv_level(DTri t, int32_t beg, int32_t end,
+                                                        const double *__restrict__ rhs, double *x,
+                                                        const double *__restrict__ add, double *__restrict__ y2,
+                                                        const int32_t *done)
+{
+    if (stop_now(done)) return;
+    constexpr int RPB = kBlock / G;
+    const int idx = beg + blockIdx.x * RPB + threadIdx.x / G;
+    const int gl = threadIdx.x % G;
+    const bool act = idx < end;
+    const int row = act ? t.rows[idx] : 0;
+    double sum = 0.0;
+    if (act) {
+        const int b = t.a.ptr[row], e = t.a.ptr[row + 1];
+        for (int k = b + gl; k < e; k += G) sum += t.a.val[k] * x[t.a.col[k]];
+    }
+    sum = group_sum<G>(sum);
+    if (act && gl == 0) {
+        double r = rhs[row] - sum;
+        if (t.diag) r = r / t.diag[row];
+        x[row] = r;
+        if (y2) y2[row] = add[row] + r;
+    }
+}
+
+// ------------------------------------------------------------------ dense S~ (Section 3.2)
+
+__device__ __forceinline__ long long pk(long long i, long long j) { return i * (i + 1) / 2 + j; }
+
+// Solve L L^T w = u in place (w holds u on entry), L packed lower by rows.
+// 64-row panels: the diagonal block is solved by one wavefront from LDS, the
+// rest of the vector is updated by the whole block.
+__global__ __launch_bounds__(1024) void k_dense_chol(int32_t k, const double *__restrict__ L, double *w,
+                                                      const int32_t *done)
+{
+    __shared__ double D[64][65];
+    __shared__ double yp[64];
+    if (stop_now(done)) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int p0 = 0; p0 < k; p0 += 64) {
+        const int pb = min(64, k - p0);
+        for (int e = tid; e < 64 * 64; e += 1024) {
+            const int i = e >> 6, j = e & 63;
+            if (i < pb && j <= i) D[i][j] = L[pk(p0 + i, p0 + j)];
+        }
+        if (tid < pb) yp[tid] = w[p0 + tid];
+        __syncthreads();
+        if (wv == 0) {
+            double yi = lane < pb ? yp[lane] : 0.0;
+            for (int j = 0; j < pb; ++j) {
+                const double yj = __shfl(yi, j) / D[j][j];
+                if (lane == j)
+                    yi = yj;
+                else if (lane > j && lane < pb)
+                    yi -= D[lane][j] * yj;
+            }
+            if (lane < pb) {
+                yp[lane] = yi;
+                w[p0 + lane] = yi;
+            }
+        }
+        __syncthreads();
+        for (int i = p0 + pb + tid; i < k; i += 1024) {
+            const double *Li = L + pk(i, p0);
+            double s = 0.0;
+            for (int jj = 0; jj < pb; ++jj) s += Li[jj] * yp[jj];
+            w[i] -= s;
+        }
+        __syncthreads();
+    }
+    for (int p0 = ((k - 1) / 64) * 64; p0 >= 0; p0 -= 64) {
+        const int pb = min(64, k - p0);
+        for (int e = tid; e < 64 * 64; e += 1024) {
+            const int i = e >> 6, j = e & 63;
+            if (i < pb && j <= i) D[i][j] = L[pk(p0 + i, p0 + j)];
+        }
+        if (tid < pb) yp[tid] = w[p0 + tid];
+        __syncthreads();
+        if (wv == 0) {
+            double yi = lane < pb ? yp[lane] : 0.0;
+            for (int s = pb - 1; s >= 0; --s) {
+                const double ws = __shfl(yi, s) / D[s][s];
+                if (lane == s)
+                    yi = ws;
+                else if (lane < s)
+                    yi -= D[s][lane] * ws;
+            }
+            if (lane < pb) {
+                yp[lane] = yi;
+                w[p0 + lane] = yi;
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < p0; c += 1024) {
+            double s = 0.0;
+            for (int r = 0; r < pb; ++r) s += L[pk(p0 + r, c)] * yp[r];
+            w[c] -= s;
+        }
+        __syncthreads();
+    }
+}
+
+int grid_for(long long n, int cap = 8192)
+{
+    long long g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+template <int EPI>
+void spmv_dispatch(hipStream_t s, int lanes, int blocks, const DCsr &a, int32_t lt, const double *x, double *y,
+                   const double *aux, double *partials, const int32_t *done)
+{
+#define RSILU_SPMV_CASE(G)                                                                                     \
+    case G:                                                                                                    \
+        hipLaunchKernelGGL((k_spmv<G, EPI>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done); \
+        break;
+    switch (lanes) {
+        RSILU_SPMV_CASE(2)
+        RSILU_SPMV_CASE(4)
+        RSILU_SPMV_CASE(8)
+        RSILU_SPMV_CASE(16)
+        RSILU_SPMV_CASE(32)
+        RSILU_SPMV_CASE(64)
+    default:
+        hipLaunchKernelGGL((k_spmv<64, EPI>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done);
+    }
+#undef RSILU_SPMV_CASE
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_gather(hipStream_t s, int32_t m, int32_t n, const int32_t *perm, const double *b, double *r,
+                   double *xh, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(m)), dim3(kBlock), 0, s, m, n, perm, b, r, xh, done);
+}
+
+void launch_spmv(hipStream_t s, const DCsr &a, const DPlan &pl, const double *x, double *y, const double *aux,
+                 Epi epi, Fin fin, double *partials, double *segpart, DevState *st, const int32_t *done)
+{
+    if (a.nrows <= 0) return;
+    const int lanes = pl.lanes;
+    const int blocks = (int)((a.nrows + (kBlock / lanes) - 1) / (kBlock / lanes));
+    switch (epi) {
+    case EPI_PLAIN: spmv_dispatch<EPI_PLAIN>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_SQ: spmv_dispatch<EPI_SQ>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_SUB: spmv_dispatch<EPI_SUB>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_WSQ: spmv_dispatch<EPI_WSQ>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    }
+    if (pl.nseg > 0)
+        hipLaunchKernelGGL(k_spmv_seg, dim3(pl.nseg), dim3(kBlock), 0, s, a, pl, x, segpart, done);
+    const bool norm = (epi == EPI_SQ || epi == EPI_WSQ);
+    if (pl.nlong > 0 || (norm && fin != FIN_NONE)) {
+        const int nparts = norm ? blocks : 0;
+        switch (epi) {
+        case EPI_PLAIN:
+            hipLaunchKernelGGL(k_finish<EPI_PLAIN>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
+                               fin, st, done);
+            break;
+        case EPI_SQ:
+            hipLaunchKernelGGL(k_finish<EPI_SQ>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
+                               fin, st, done);
+            break;
+        case EPI_SUB:
+            hipLaunchKernelGGL(k_finish<EPI_SUB>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
+                               fin, st, done);
+            break;
+        case EPI_WSQ:
+            hipLaunchKernelGGL(k_finish<EPI_WSQ>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
+                               fin, st, done);
+            break;
+        }
+    }
+}
+
+void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin fin, double *partials,
+                DevState *st, const int32_t *done)
+{
+    const int g = grid_for(n, 2048);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, n, a, b, partials, done);
+    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+}
+
+void launch_update(hipStream_t s, int32_t n, int32_t m, const double *p, double *xh, const double *q, double *r,
+                   double *f0, double *f1, double *f2, double *f3, DevState *st, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_update, dim3(grid_for(m)), dim3(kBlock), 0, s, n, m, p, xh, q, r, f0, f1, f2, f3, st,
+                       done);
+}
+
+void launch_fill(hipStream_t s, int32_t n, double *f0, double *f1, double *f2, double *f3, DevState *st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, s, n, f0, f1, f2, f3, st);
+}
+
+void launch_pupdate(hipStream_t s, int32_t n, const double *h, double *p, const DevState *st, bool first,
+                    const int32_t *done)
+{
+    hipLaunchKernelGGL(k_pupdate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, h, p, st, first ? 1 : 0, done);
+}
+
+void launch_scale_out(hipStream_t s, int32_t n, const double *xh, const double *colnorm, double *x)
+{
+    hipLaunchKernelGGL(k_scale_out, dim3(grid_for(n)), dim3(kBlock), 0, s, n, xh, colnorm, x);
+}
+
+void launch_residual(hipStream_t s, int32_t m, const int32_t *perm, const double *b, const double *ax, double *r)
+{
+    hipLaunchKernelGGL(k_residual, dim3(grid_for(m)), dim3(kBlock), 0, s, m, perm, b, ax, r);
+}
+
+void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, n, src, dst, done);
+}
+
+void launch_trsv_syncfree(hipStream_t s, const DTri &t, const double *rhs, double *x, const double *add,
+                          double *y2, DevState *st, int ticket, const int32_t *done)
+{
+    if (t.nchunks <= 0) return;
+    // enough waves to cover the widest levels; each wave keeps taking chunks
+    int blocks = (t.nchunks + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+#define RSILU_TRSV_CASE(G)                                                                                      \
+    case G:                                                                                                     \
+        hipLaunchKernelGGL(k_trsv_syncfree<G>, dim3(blocks), dim3(kBlock), 0, s, t, rhs, x, add, y2, st, ticket, \
+                           done);                                                                               \
+        break;
+    switch (t.lanes) {
+        RSILU_TRSV_CASE(1)
+        RSILU_TRSV_CASE(2)
+        RSILU_TRSV_CASE(4)
+        RSILU_TRSV_CASE(8)
+        RSILU_TRSV_CASE(16)
+        RSILU_TRSV_CASE(32)
+        RSILU_TRSV_CASE(64)
+    default:
+        break;
+    }
+#undef RSILU_TRSV_CASE
+}
+
+void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, const double *rhs, double *x,
+                       const double *add, double *y2, const int32_t *done)
+{
+    const int rpb = kBlock / t.lanes;
+    const int blocks = (end - beg + rpb - 1) / rpb;
+    if (blocks <= 0) return;
+#define RSILU_TRSVL_CASE(G)                                                                                      \
+    case G:                                                                                                      \
+        hipLaunchKernelGGL(k_trsv_level<G>, dim3(blocks), dim3(kBlock), 0, s, t, beg, end, rhs, x, add, y2, done); \
+        break;
+    switch (t.lanes) {
+        RSILU_TRSVL_CASE(1)
+        RSILU_TRSVL_CASE(2)
+        RSILU_TRSVL_CASE(4)
+        RSILU_TRSVL_CASE(8)
+        RSILU_TRSVL_CASE(16)
+        RSILU_TRSVL_CASE(32)
+        RSILU_TRSVL_CASE(64)
+    default:
+        break;
+    }
+#undef RSILU_TRSVL_CASE
+}
+
+void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done)
+{
+    if (k <= 0) return;
+    hipLaunchKernelGGL(k_dense_chol, dim3(1), dim3(1024), 0, s, k, lfac, w, done);
+}
+
+}  // namespace rsilu

@@ -1,0 +1,100 @@
+// Device-side types and kernel launchers (kernels.hip).
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace rsilu {
+
+// Device scalars of Algorithm 1 and the stop/breakdown flags.
+struct alignas(256) DevState {
+    double rho, alpha, beta, delta;
+    double nb;    // ||D^{-1} z0|| = ||A^T b||
+    double zn;    // latest ||D^{-1} z|| = ||A^T r||
+    double tol;
+    double atr;   // exit: true ||A^T (b - A x)||
+    int32_t iter;    // completed iterations
+    int32_t maxit;
+    int32_t done;    // nonzero: every later kernel of the solve returns at once
+    int32_t status;  // 0 converged / running, 1 not converged, 2 breakdown
+    int32_t err;     // a sync-free wait exceeded its bound
+    int32_t pad0;
+    uint32_t ticket[4];  // chunk dispensers of the sync-free solves
+};
+
+// CSR operator in device memory.
+struct DCsr {
+    const int32_t *ptr;
+    const int32_t *col;
+    const double *val;
+    int32_t nrows;
+};
+
+// Split of long rows into fixed segments (reduced in a fixed order).
+struct DPlan {
+    const int32_t *long_rows;
+    const int32_t *seg_ptr;
+    const int32_t *seg_beg;
+    const int32_t *seg_end;
+    int32_t nlong, nseg, lanes, long_thresh;
+};
+
+// Triangular operator: strictly triangular CSR, optional diagonal, level-ordered rows,
+// chunks of one level each.
+struct DTri {
+    DCsr a;
+    const double *diag;   // nullptr: unit diagonal
+    const int32_t *rows;  // rows in level order
+    const int32_t *chunk; // nchunks + 1 positions into rows
+    int32_t nchunks;
+    int32_t lanes;        // lanes per row (64 / chunk capacity)
+};
+
+enum Epi : int32_t {
+    EPI_PLAIN = 0,  // y = A x
+    EPI_SQ = 1,     // y = A x, partial sums of y^2
+    EPI_SUB = 2,    // y = aux - A x
+    EPI_WSQ = 3     // y = A x, partial sums of (aux * y)^2
+};
+
+enum Fin : int32_t {
+    FIN_NONE = 0,   // long rows only
+    FIN_INIT = 1,   // nb = sqrt(sum); nb == 0 -> done, converged, 0 iterations
+    FIN_ALPHA = 2,  // delta = sum; alpha = rho / delta
+    FIN_STOP = 3,   // zn = sqrt(sum); ++iter; stop test
+    FIN_RHO0 = 4,   // rho = sum
+    FIN_BETA = 5,   // beta = sum / rho; rho = sum
+    FIN_ATR = 6     // atr = sqrt(sum)
+};
+
+constexpr int kBlock = 256;
+
+// ---- launchers (all asynchronous on `s`); `done` may be nullptr
+void launch_gather(hipStream_t s, int32_t m, int32_t n, const int32_t *perm, const double *b, double *r,
+                   double *xh, const int32_t *done);
+// y = op(A) x with epilogue; long rows through segments; partial sums of the
+// epilogue norm, then the single-block finish (reduction + scalar step).
+void launch_spmv(hipStream_t s, const DCsr &a, const DPlan &pl, const double *x, double *y, const double *aux,
+                 Epi epi, Fin fin, double *partials, double *segpart, DevState *st, const int32_t *done);
+void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin fin, double *partials,
+                DevState *st, const int32_t *done);
+// x_hat += alpha p; r -= alpha q; sentinel-fill the sync-free outputs; reset tickets
+void launch_update(hipStream_t s, int32_t n, int32_t m, const double *p, double *xh, const double *q, double *r,
+                   double *f0, double *f1, double *f2, double *f3, DevState *st, const int32_t *done);
+void launch_fill(hipStream_t s, int32_t n, double *f0, double *f1, double *f2, double *f3, DevState *st);
+void launch_pupdate(hipStream_t s, int32_t n, const double *h, double *p, const DevState *st, bool first,
+                    const int32_t *done);
+void launch_scale_out(hipStream_t s, int32_t n, const double *xh, const double *colnorm, double *x);
+void launch_residual(hipStream_t s, int32_t m, const int32_t *perm, const double *b, const double *ax, double *r);
+// Triangular solve T x = rhs (unit diagonal if T.diag is null). Optionally y2 = add + x.
+// Sync-free: x must be sentinel-filled and the ticket zero (launch_fill / launch_update).
+void launch_trsv_syncfree(hipStream_t s, const DTri &t, const double *rhs, double *x, const double *add,
+                          double *y2, DevState *st, int ticket, const int32_t *done);
+void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, const double *rhs, double *x,
+                       const double *add, double *y2, const int32_t *done);
+// w = (L L^T)^{-1} u with L packed lower (k x k), in place on w (w = u on entry)
+void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done);
+void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);
+
+}  // namespace rsilu

@@ -1,0 +1,556 @@
+// Host setup of the row-splitting ILU preconditioner.
+//
+//   validate     CSR input of A, explicit zeros stripped            (1.1)
+//   prescale     unit 2-norm columns                                Section 5.1
+//   ilup         rectangular ILUP(p, tau), threshold partial
+//                pivoting by rows, minimum row count, modification  Algorithms 4-6
+//   split        P A D ~ [L1; L2] U, transposes                     (3.8)
+//   levels       dependency levels of the triangular solves
+//   dense S~     S~ = I + Y Y^T, Y = L2 L1^{-1}, Cholesky           Section 3.2
+//
+// Floating-point decisions of the factorization (pivot choice, dropping) are
+// taken on values computed in a fixed order with separately rounded products
+// and sums (this file is compiled with -ffp-contract=off), so the row
+// permutation and the factors are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <queue>
+#include <utility>
+
+#include "internal.hpp"
+
+namespace rsilu {
+
+namespace {
+
+constexpr int64_t kMaxIdx = 2147483647LL;
+
+// ---------------------------------------------------------------- CSR helpers
+
+// Transpose of a CSR (counting sort by column; rows ascend within each output row).
+Csr transpose(const Csr &a)
+{
+    Csr t;
+    t.nrows = a.ncols;
+    t.ncols = a.nrows;
+    t.ptr.assign((size_t)t.nrows + 1, 0);
+    for (int32_t c : a.col) t.ptr[(size_t)c + 1]++;
+    for (int32_t i = 0; i < t.nrows; ++i) t.ptr[(size_t)i + 1] += t.ptr[i];
+    t.col.resize(a.col.size());
+    t.val.resize(a.val.size());
+    std::vector<int32_t> fill(t.ptr.begin(), t.ptr.end() - 1);
+    for (int32_t i = 0; i < a.nrows; ++i) {
+        for (int32_t e = a.ptr[i]; e < a.ptr[(size_t)i + 1]; ++e) {
+            int32_t d = fill[a.col[e]]++;
+            t.col[d] = i;
+            t.val[d] = a.val[e];
+        }
+    }
+    return t;
+}
+
+// CSR from per-row (col, val) lists; each row is sorted by column.
+Csr from_rows(int32_t nrows, int32_t ncols, std::vector<std::vector<std::pair<int32_t, double>>> &rows)
+{
+    Csr a;
+    a.nrows = nrows;
+    a.ncols = ncols;
+    a.ptr.assign((size_t)nrows + 1, 0);
+    for (int32_t i = 0; i < nrows; ++i) a.ptr[(size_t)i + 1] = a.ptr[i] + (int32_t)rows[i].size();
+    a.col.reserve((size_t)a.ptr.back());
+    a.val.reserve((size_t)a.ptr.back());
+    for (auto &r : rows) {
+        std::sort(r.begin(), r.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (auto &e : r) {
+            a.col.push_back(e.first);
+            a.val.push_back(e.second);
+        }
+        std::vector<std::pair<int32_t, double>>().swap(r);
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------- levels
+
+// Kahn layering: a row becomes ready once all rows it depends on are placed;
+// rows made ready by the same layer form the next level (sorted ascending).
+// deps: row -> rows it reads; users: row -> rows that read it.
+Levels kahn_levels(const Csr &deps, const Csr &users)
+{
+    const int32_t n = deps.nrows;
+    Levels out;
+    std::vector<int32_t> waiting((size_t)n);
+    std::vector<int32_t> cur, next;
+    for (int32_t i = 0; i < n; ++i) {
+        waiting[i] = deps.ptr[(size_t)i + 1] - deps.ptr[i];
+        if (waiting[i] == 0) cur.push_back(i);
+    }
+    out.rows.reserve((size_t)n);
+    out.ptr.push_back(0);
+    while (!cur.empty()) {
+        std::sort(cur.begin(), cur.end());
+        out.rows.insert(out.rows.end(), cur.begin(), cur.end());
+        out.ptr.push_back((int32_t)out.rows.size());
+        next.clear();
+        for (int32_t r : cur)
+            for (int32_t e = users.ptr[r]; e < users.ptr[(size_t)r + 1]; ++e)
+                if (--waiting[users.col[e]] == 0) next.push_back(users.col[e]);
+        cur.swap(next);
+    }
+    return out;
+}
+
+Chunks make_chunks(const Levels &lv, int32_t cap)
+{
+    Chunks ch;
+    ch.cap = cap;
+    ch.ptr.push_back(0);
+    for (int32_t l = 0; l < lv.nlev(); ++l)
+        for (int32_t s = lv.ptr[l]; s < lv.ptr[(size_t)l + 1]; s += cap)
+            ch.ptr.push_back(std::min(s + cap, lv.ptr[(size_t)l + 1]));
+    return ch;
+}
+
+int32_t lanes_for(double avg)
+{
+    int32_t g = 2;
+    while (g < 64 && g < avg) g *= 2;
+    return g;
+}
+
+SpmvPlan plan_spmv(const Csr &a)
+{
+    SpmvPlan pl;
+    double avg = a.nrows ? (double)a.nnz() / (double)a.nrows : 1.0;
+    pl.lanes = lanes_for(avg);
+    pl.long_thresh = std::max<int32_t>(32 * pl.lanes, 2048);
+    const int32_t seg = 4096;
+    pl.seg_ptr.push_back(0);
+    for (int32_t i = 0; i < a.nrows; ++i) {
+        int32_t b = a.ptr[i], e = a.ptr[(size_t)i + 1];
+        if (e - b <= pl.long_thresh) continue;
+        pl.long_rows.push_back(i);
+        for (int32_t s = b; s < e; s += seg) {
+            pl.seg_beg.push_back(s);
+            pl.seg_end.push_back(std::min(s + seg, e));
+        }
+        pl.seg_ptr.push_back((int32_t)pl.seg_beg.size());
+    }
+    return pl;
+}
+
+// ---------------------------------------------------------------- ILUP
+
+struct Cand {
+    double mag;
+    double v;
+    int32_t key;
+};
+
+// Entries kept by the dropping rule of Algorithm 4: v != 0 and |v| >= tau,
+// then the p largest |v| (ties to the smaller key). Order of the result is
+// unspecified.
+void keep_largest(std::vector<Cand> &c, int64_t p, double tau)
+{
+    auto last = std::remove_if(c.begin(), c.end(), [tau](const Cand &e) { return !(e.v != 0.0 && e.mag >= tau); });
+    c.erase(last, c.end());
+    if ((int64_t)c.size() > p) {
+        auto before = [](const Cand &x, const Cand &y) {
+            return x.mag > y.mag || (x.mag == y.mag && x.key < y.key);
+        };
+        std::nth_element(c.begin(), c.begin() + p, c.end(), before);
+        c.resize((size_t)p);
+    }
+}
+
+double modified_pivot(int64_t j1, int64_t n, double colmax, double small)
+{
+    // Algorithm 6: beta = 10^(-2(1 - j/n)), value max(beta ||A(:,j)||_inf, small)
+    double beta = std::pow(10.0, -2.0 * (1.0 - (double)j1 / (double)n));
+    double v = beta * colmax;
+    return v > small ? v : small;
+}
+
+}  // namespace
+
+rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *rowptr,
+                                   const int32_t *colind, const double *val)
+{
+    const rsilu_params_t &P = c.prm;
+    if (n < 1 || m < n || m > kMaxIdx || !rowptr || (rowptr[m] > 0 && (!colind || !val)))
+        return RSILU_EINVAL;
+    if (P.p < 0 || !(P.tau >= 0.0) || !(P.mu > 0.0 && P.mu <= 1.0) || !(P.small > 0.0) ||
+        !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
+        (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE) ||
+        (P.trsv != RSILU_TRSV_SYNCFREE && P.trsv != RSILU_TRSV_LEVELS))
+        return RSILU_EINVAL;
+    if (rowptr[0] != 0 || rowptr[m] > kMaxIdx) return RSILU_EINVAL;
+
+    // ---- validate, strip explicit zeros (problem (1.1): A real, sparse, m >= n)
+    Csr &A = c.A;
+    A.nrows = (int32_t)m;
+    A.ncols = (int32_t)n;
+    A.ptr.assign((size_t)m + 1, 0);
+    for (int64_t i = 0; i < m; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) return RSILU_EINVAL;
+        int32_t prev = -1;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            int32_t cc = colind[e];
+            if (cc < 0 || cc >= n || cc <= prev || !std::isfinite(val[e])) return RSILU_EINVAL;
+            prev = cc;
+            if (val[e] != 0.0) {
+                A.col.push_back(cc);
+                A.val.push_back(val[e]);
+            }
+        }
+        A.ptr[(size_t)i + 1] = (int32_t)A.col.size();
+    }
+    c.m = m;
+    c.n = n;
+    c.nnz_a = A.nnz();
+
+    // ---- columns of A (rows ascending), Section 5.1 prescaling
+    Csr AT = transpose(A);  // row j of AT = column j of A
+    c.colnorm.assign((size_t)n, 1.0);
+    std::vector<double> sval(AT.val.size());
+    for (int32_t j = 0; j < (int32_t)n; ++j) {
+        const int32_t b = AT.ptr[j], e = AT.ptr[(size_t)j + 1];
+        double nrm = 1.0;
+        if (P.colscale && e > b) {
+            double s = 0.0;
+            for (int32_t k = b; k < e; ++k) {
+                double sq = AT.val[k] * AT.val[k];
+                s = s + sq;
+            }
+            nrm = std::sqrt(s);
+            if (nrm == 0.0) nrm = 1.0;
+        }
+        c.colnorm[j] = nrm;
+        for (int32_t k = b; k < e; ++k) sval[k] = P.colscale ? AT.val[k] / nrm : AT.val[k];
+    }
+
+    // ---- Algorithm 4: left-looking ILUP over the columns
+    const int64_t pcap = std::min<int64_t>(P.p, m);
+    std::vector<int32_t> &perm = c.perm;
+    perm.resize((size_t)m);
+    std::vector<int32_t> pos((size_t)m);
+    for (int32_t i = 0; i < (int32_t)m; ++i) perm[i] = pos[i] = i;
+    std::vector<int32_t> rc((size_t)m, 0);
+    for (int32_t i = 0; i < (int32_t)m; ++i) rc[i] = A.ptr[(size_t)i + 1] - A.ptr[i];
+
+    std::vector<int32_t> lptr(1, 0), lrow;  // columns of L~ (original row ids)
+    std::vector<double> lval;
+    std::vector<std::vector<std::pair<int32_t, double>>> urows((size_t)n);  // U by rows (step)
+    c.Udiag.assign((size_t)n, 0.0);
+
+    std::vector<double> w((size_t)m, 0.0);
+    std::vector<int32_t> stamp((size_t)m, -1);     // row touched in column j
+    std::vector<int32_t> queued((size_t)n, -1);    // step queued in column j
+    std::vector<int32_t> touched;
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> ready;
+    std::vector<Cand> lc, uc;
+    c.nmod = 0;
+
+    for (int32_t j = 0; j < (int32_t)n; ++j) {
+        touched.clear();
+        double colmax = 0.0;
+        for (int32_t k = AT.ptr[j]; k < AT.ptr[(size_t)j + 1]; ++k) {
+            const int32_t i = AT.col[k];
+            w[i] = sval[k];
+            stamp[i] = j;
+            touched.push_back(i);
+            const double a = std::fabs(sval[k]);
+            if (a > colmax) colmax = a;
+            if (pos[i] < j && queued[pos[i]] != j) {
+                queued[pos[i]] = j;
+                ready.push(pos[i]);
+            }
+        }
+        // Sparse triangular solve for U(1:j-1, j) and update of L(j:m, j):
+        // steps are taken in increasing order; a step is final when popped
+        // because only smaller steps update its row.
+        uc.clear();
+        while (!ready.empty()) {
+            const int32_t k = ready.top();
+            ready.pop();
+            const double uk = w[perm[k]];
+            if (uk == 0.0) continue;
+            uc.push_back({std::fabs(uk), uk, k});
+            for (int32_t e = lptr[k]; e < lptr[(size_t)k + 1]; ++e) {
+                const int32_t r = lrow[e];
+                const double prod = lval[e] * uk;
+                w[r] = w[r] - prod;
+                if (stamp[r] != j) {
+                    stamp[r] = j;
+                    touched.push_back(r);
+                }
+                const int32_t pr = pos[r];
+                if (pr < j && queued[pr] != j) {
+                    queued[pr] = j;
+                    ready.push(pr);
+                }
+            }
+        }
+        // Candidates of the L column: unpivoted rows with a nonzero value.
+        lc.clear();
+        double amax = 0.0;
+        for (int32_t r : touched) {
+            if (pos[r] >= j && w[r] != 0.0) {
+                const double a = std::fabs(w[r]);
+                lc.push_back({a, w[r], r});
+                if (a > amax) amax = a;
+            }
+        }
+        // Algorithm 5 (pivot choice) and Algorithm 6 (modification).
+        int32_t piv;
+        double pv;
+        if (lc.empty()) {
+            piv = perm[j];
+            pv = modified_pivot(j + 1, n, colmax, P.small);
+            c.nmod++;
+        } else {
+            const double thr = P.mu * amax;
+            const Cand *best = nullptr;
+            for (const Cand &e : lc) {
+                if (!(e.mag >= thr)) continue;
+                if (!best) {
+                    best = &e;
+                    continue;
+                }
+                const int32_t re = rc[e.key], rb = rc[best->key];
+                if (re != rb ? re < rb : (e.mag != best->mag ? e.mag > best->mag : e.key < best->key)) best = &e;
+            }
+            piv = best->key;
+            pv = best->v;
+            if (std::fabs(pv) < P.small) {
+                pv = modified_pivot(j + 1, n, colmax, P.small);
+                c.nmod++;
+            }
+        }
+        // Interchange positions j and pos[piv].
+        {
+            const int32_t pp = pos[piv], rj = perm[j];
+            perm[pp] = rj;
+            pos[rj] = pp;
+            perm[j] = piv;
+            pos[piv] = j;
+        }
+        // Scale by the pivot, then drop (L after scaling, U on the exact values).
+        size_t kept = 0;
+        for (const Cand &e : lc) {
+            if (e.key == piv) continue;
+            const double l = e.v / pv;
+            lc[kept++] = {std::fabs(l), l, e.key};
+        }
+        lc.resize(kept);
+        keep_largest(lc, pcap, P.tau);
+        keep_largest(uc, pcap, P.tau);
+        if ((int64_t)lrow.size() + (int64_t)lc.size() > kMaxIdx) return RSILU_EINVAL;
+        for (const Cand &e : lc) {
+            lrow.push_back(e.key);
+            lval.push_back(e.v);
+        }
+        lptr.push_back((int32_t)lrow.size());
+        for (const Cand &e : uc) urows[e.key].push_back({j, e.v});
+        c.Udiag[j] = pv;
+        // rc(i) counts the entries of row i in the columns still to come.
+        for (int32_t k = AT.ptr[j]; k < AT.ptr[(size_t)j + 1]; ++k) rc[AT.col[k]]--;
+        for (int32_t r : touched) w[r] = 0.0;
+    }
+
+    // ---- the splitting (3.8): L1 (positions < n), L2 (positions >= n), U
+    {
+        std::vector<std::vector<std::pair<int32_t, double>>> r1((size_t)n), r2((size_t)(m - n));
+        for (int32_t k = 0; k < (int32_t)n; ++k) {
+            for (int32_t e = lptr[k]; e < lptr[(size_t)k + 1]; ++e) {
+                const int32_t q = pos[lrow[e]];
+                if (q < n)
+                    r1[q].push_back({k, lval[e]});
+                else
+                    r2[(size_t)(q - n)].push_back({k, lval[e]});
+            }
+        }
+        c.L1 = from_rows((int32_t)n, (int32_t)n, r1);
+        c.L2 = from_rows((int32_t)(m - n), (int32_t)n, r2);
+        c.U = from_rows((int32_t)n, (int32_t)n, urows);
+    }
+    c.L1T = transpose(c.L1);
+    c.L2T = transpose(c.L2);
+    c.UT = transpose(c.U);
+
+    // ---- A_hat = P A D in pivot order, and its transpose
+    {
+        Csr &H = c.Ahat;
+        H.nrows = (int32_t)m;
+        H.ncols = (int32_t)n;
+        H.ptr.assign((size_t)m + 1, 0);
+        H.col.reserve(A.col.size());
+        H.val.reserve(A.val.size());
+        for (int32_t k = 0; k < (int32_t)m; ++k) {
+            const int32_t i = perm[k];
+            for (int32_t e = A.ptr[i]; e < A.ptr[(size_t)i + 1]; ++e) {
+                H.col.push_back(A.col[e]);
+                H.val.push_back(P.colscale ? A.val[e] / c.colnorm[A.col[e]] : A.val[e]);
+            }
+            H.ptr[(size_t)k + 1] = (int32_t)H.col.size();
+        }
+        c.AhatT = transpose(H);
+    }
+
+    // ---- level schedules
+    c.lvL1 = kahn_levels(c.L1, c.L1T);
+    c.lvL1T = kahn_levels(c.L1T, c.L1);
+    c.lvU = kahn_levels(c.U, c.UT);
+    c.lvUT = kahn_levels(c.UT, c.U);
+    if ((int64_t)c.lvL1.rows.size() != n || (int64_t)c.lvU.rows.size() != n) return RSILU_EINVAL;
+
+    // ---- schedules of the products and sync-free solves
+    c.plA = plan_spmv(c.Ahat);
+    c.plAT = plan_spmv(c.AhatT);
+    c.plL2 = plan_spmv(c.L2);
+    c.plL2T = plan_spmv(c.L2T);
+    auto tri_lanes = [](const Csr &t) { return lanes_for(t.nrows ? (double)t.nnz() / t.nrows : 1.0); };
+    c.chL1 = make_chunks(c.lvL1, 64 / tri_lanes(c.L1));
+    c.chL1T = make_chunks(c.lvL1T, 64 / tri_lanes(c.L1T));
+    c.chU = make_chunks(c.lvU, 64 / tri_lanes(c.U));
+
+    // ---- S^ (Section 3.2)
+    c.smode = P.smode;
+    if (c.smode == RSILU_S_AUTO) c.smode = (m - n > 0 && m - n <= 4096) ? RSILU_S_DENSE : RSILU_S_IDENTITY;
+    if (c.smode == RSILU_S_DENSE && m > n) {
+        const int64_t k = m - n;
+        if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
+        // Y^T = L1^{-T} L2^T, one column (row of Y) per row of L2
+        std::vector<double> Y((size_t)(k * n), 0.0);  // row-major k x n
+        for (int64_t i = 0; i < k; ++i) {
+            double *y = &Y[(size_t)(i * n)];
+            for (int32_t e = c.L2.ptr[i]; e < c.L2.ptr[(size_t)i + 1]; ++e) y[c.L2.col[e]] = c.L2.val[e];
+            for (int64_t r = n - 1; r >= 0; --r) {  // L1^T y = l2_i, backward
+                double s = y[r];
+                for (int32_t e = c.L1T.ptr[r]; e < c.L1T.ptr[(size_t)r + 1]; ++e) s -= c.L1T.val[e] * y[c.L1T.col[e]];
+                y[r] = s;
+            }
+        }
+        // S~ = I + Y Y^T, lower Cholesky factor, packed by rows
+        c.sfac.assign((size_t)(k * (k + 1) / 2), 0.0);
+        auto at = [](int64_t i, int64_t jj) { return (size_t)(i * (i + 1) / 2 + jj); };
+        for (int64_t i = 0; i < k; ++i) {
+            const double *yi = &Y[(size_t)(i * n)];
+            for (int64_t jj = 0; jj <= i; ++jj) {
+                const double *yj = &Y[(size_t)(jj * n)];
+                double s = (i == jj) ? 1.0 : 0.0;
+                for (int64_t t = 0; t < n; ++t) s += yi[t] * yj[t];
+                c.sfac[at(i, jj)] = s;
+            }
+        }
+        for (int64_t jj = 0; jj < k; ++jj) {
+            double d = c.sfac[at(jj, jj)];
+            for (int64_t t = 0; t < jj; ++t) d -= c.sfac[at(jj, t)] * c.sfac[at(jj, t)];
+            if (!(d > 0.0) || !std::isfinite(d)) return RSILU_BREAKDOWN;
+            d = std::sqrt(d);
+            c.sfac[at(jj, jj)] = d;
+            for (int64_t i = jj + 1; i < k; ++i) {
+                double s = c.sfac[at(i, jj)];
+                for (int64_t t = 0; t < jj; ++t) s -= c.sfac[at(i, t)] * c.sfac[at(jj, t)];
+                c.sfac[at(i, jj)] = s / d;
+            }
+        }
+    } else {
+        c.smode = RSILU_S_IDENTITY;
+    }
+    return RSILU_OK;
+}
+
+// ---------------------------------------------------------------- device layout
+
+namespace {
+struct Bump {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        size_t o = off;
+        off += std::max<size_t>(bytes, 8);
+        return o;
+    }
+};
+
+DevCsrOff place_csr(Bump &b, const Csr &a)
+{
+    DevCsrOff o;
+    o.nrows = a.nrows;
+    o.ncols = a.ncols;
+    o.nnz = a.nnz();
+    o.ptr = b.take(sizeof(int32_t) * a.ptr.size());
+    o.col = b.take(sizeof(int32_t) * a.col.size());
+    o.val = b.take(sizeof(double) * a.val.size());
+    return o;
+}
+
+DevPlanOff place_plan(Bump &b, const SpmvPlan &pl)
+{
+    DevPlanOff o;
+    o.nlong = (int32_t)pl.long_rows.size();
+    o.nseg = (int32_t)pl.seg_beg.size();
+    o.lanes = pl.lanes;
+    o.long_thresh = pl.long_thresh;
+    o.long_rows = b.take(sizeof(int32_t) * pl.long_rows.size());
+    o.seg_ptr = b.take(sizeof(int32_t) * pl.seg_ptr.size());
+    o.seg_beg = b.take(sizeof(int32_t) * pl.seg_beg.size());
+    o.seg_end = b.take(sizeof(int32_t) * pl.seg_end.size());
+    return o;
+}
+
+DevTriOff place_tri(Bump &b, const Csr &a, bool diag, const Levels &lv, const Chunks &ch, size_t n)
+{
+    DevTriOff o;
+    o.a = place_csr(b, a);
+    o.diag = diag ? b.take(sizeof(double) * n) : 0;
+    o.rows = b.take(sizeof(int32_t) * lv.rows.size());
+    o.chunk = b.take(sizeof(int32_t) * ch.ptr.size());
+    o.nchunks = (int32_t)ch.ptr.size() - 1;
+    o.cap = ch.cap;
+    o.lanes = 64 / ch.cap;
+    o.nlev = lv.nlev();
+    return o;
+}
+}  // namespace
+
+void plan_layout(Ctx &c)
+{
+    Bump b;
+    Layout &L = c.lay;
+    const size_t m = (size_t)c.m, n = (size_t)c.n, k = (size_t)(c.m - c.n);
+    L.state = b.take(4096);
+    L.A = place_csr(b, c.Ahat);
+    L.AT = place_csr(b, c.AhatT);
+    L.L2 = place_csr(b, c.L2);
+    L.L2T = place_csr(b, c.L2T);
+    L.pA = place_plan(b, c.plA);
+    L.pAT = place_plan(b, c.plAT);
+    L.pL2 = place_plan(b, c.plL2);
+    L.pL2T = place_plan(b, c.plL2T);
+    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, n);
+    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, n);
+    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, n);
+    L.perm = b.take(sizeof(int32_t) * m);
+    L.colnorm = b.take(sizeof(double) * n);
+    L.sfac = b.take(sizeof(double) * c.sfac.size());
+    for (size_t *o : {&L.xh, &L.p, &L.z, &L.h, &L.t, &L.y, &L.v, &L.g, &L.gp}) *o = b.take(sizeof(double) * n);
+    L.r = b.take(sizeof(double) * m);
+    L.q = b.take(sizeof(double) * m);
+    L.u = b.take(sizeof(double) * std::max<size_t>(k, 1));
+    // one partial per block of the largest reduction, plus one per long row
+    L.npartials = 65536;
+    L.partials = b.take(sizeof(double) * (size_t)L.npartials);
+    int32_t nseg = std::max({(int32_t)c.plA.seg_beg.size(), (int32_t)c.plAT.seg_beg.size(),
+                             (int32_t)c.plL2.seg_beg.size(), (int32_t)c.plL2T.seg_beg.size(), 1});
+    L.nsegpart = nseg;
+    L.segpart = b.take(sizeof(double) * (size_t)nseg);
+    L.total = (b.off + 255) & ~(size_t)255;
+}
+
+}  // namespace rsilu

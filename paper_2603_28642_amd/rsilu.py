@@ -1,0 +1,296 @@
+"""ctypes binding of the rsilu C ABI (include/rsilu.h).
+
+Argument marshalling only: numpy arrays for host data, torch tensors for
+device memory and streams. Every step of the solve runs in the HIP library;
+this module raises if the library has not been built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "librsilu.so")
+
+# status codes
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+EINVAL, ENOMEM, EHIP, ESTATE, EINTERNAL = -1, -2, -3, -4, -5
+S_AUTO, S_IDENTITY, S_DENSE = -1, 0, 1
+TRSV_SYNCFREE, TRSV_LEVELS = 0, 1
+# factor / level selectors
+L1, L2, U, AHAT, UDIAG = 0, 1, 2, 3, 4
+LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
+
+EXPORTS = [
+    "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_get_stats",
+    "rsilu_get_perm", "rsilu_get_colnorm", "rsilu_factor_nnz", "rsilu_get_factor", "rsilu_get_levels",
+    "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_destroy", "rsilu_status_string",
+]
+
+
+class rsilu_params_t(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("tau", ctypes.c_double), ("mu", ctypes.c_double),
+                ("small", ctypes.c_double), ("colscale", ctypes.c_int32), ("smode", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32)]
+
+
+class rsilu_stats_t(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz_a", ctypes.c_int64),
+                ("nnz_l1", ctypes.c_int64), ("nnz_l2", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
+                ("psize", ctypes.c_int64), ("nmod", ctypes.c_int64), ("levels_l1", ctypes.c_int32),
+                ("levels_l1t", ctypes.c_int32), ("levels_u", ctypes.c_int32), ("levels_ut", ctypes.c_int32),
+                ("smode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class RsiluError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s: %s (status %d)" % (what, status_string(code), code))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librsilu.so is not built (run __graft_entry__.build() or "
+                               "python paper_2603_28642_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.rsilu_params_default.argtypes = [ctypes.POINTER(rsilu_params_t)]
+        L.rsilu_params_default.restype = None
+        L.rsilu_factor.argtypes = [I64, I64, P, P, P, ctypes.POINTER(rsilu_params_t), ctypes.POINTER(P)]
+        L.rsilu_factor.restype = ctypes.c_int
+        L.rsilu_device_bytes.argtypes = [P]
+        L.rsilu_device_bytes.restype = ctypes.c_size_t
+        L.rsilu_upload.argtypes = [P, P, ctypes.c_size_t, P]
+        L.rsilu_upload.restype = ctypes.c_int
+        L.rsilu_get_stats.argtypes = [P, ctypes.POINTER(rsilu_stats_t)]
+        L.rsilu_get_stats.restype = ctypes.c_int
+        L.rsilu_get_perm.argtypes = [P, P]
+        L.rsilu_get_perm.restype = ctypes.c_int
+        L.rsilu_get_colnorm.argtypes = [P, P]
+        L.rsilu_get_colnorm.restype = ctypes.c_int
+        L.rsilu_factor_nnz.argtypes = [P, I32]
+        L.rsilu_factor_nnz.restype = I64
+        L.rsilu_get_factor.argtypes = [P, I32, P, P, P]
+        L.rsilu_get_factor.restype = ctypes.c_int
+        L.rsilu_get_levels.argtypes = [P, I32, P, P]
+        L.rsilu_get_levels.restype = ctypes.c_int
+        L.rsilu_solve.argtypes = [P, P, D, P, ctypes.POINTER(I32), ctypes.POINTER(D), ctypes.POINTER(D), P]
+        L.rsilu_solve.restype = ctypes.c_int
+        L.rsilu_spmv.argtypes = [P, I32, P, P, P]
+        L.rsilu_spmv.restype = ctypes.c_int
+        L.rsilu_trsv.argtypes = [P, I32, P, P, P]
+        L.rsilu_trsv.restype = ctypes.c_int
+        L.rsilu_apply.argtypes = [P, P, P, P]
+        L.rsilu_apply.restype = ctypes.c_int
+        L.rsilu_destroy.argtypes = [P]
+        L.rsilu_destroy.restype = None
+        L.rsilu_status_string.argtypes = [ctypes.c_int]
+        L.rsilu_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(code):
+    return lib().rsilu_status_string(int(code)).decode()
+
+
+def _check(code, what):
+    if code < 0:
+        raise RsiluError(code, what)
+    return code
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- the C calls
+
+
+def rsilu_params_default(**overrides):
+    p = rsilu_params_t()
+    lib().rsilu_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def rsilu_factor(m, n, rowptr, colind, val, params=None):
+    rp, prp = _host(rowptr, np.int64)
+    ci, pci = _host(colind, np.int32)
+    vv, pvv = _host(val, np.float64)
+    if rp.shape != (m + 1,):
+        raise ValueError("rowptr must have m + 1 entries")
+    nnz = int(rp[-1]) if rp.size else 0
+    if ci.size < nnz or vv.size < nnz:
+        raise ValueError("colind/val shorter than rowptr[m]")
+    h = ctypes.c_void_p()
+    code = lib().rsilu_factor(int(m), int(n), prp, pci, pvv,
+                              ctypes.byref(params) if params is not None else None, ctypes.byref(h))
+    return code, (h if code == OK else None)
+
+
+def rsilu_device_bytes(h):
+    return int(lib().rsilu_device_bytes(h))
+
+
+def rsilu_upload(h, dev_buf, stream=None):
+    nbytes = dev_buf.numel() * dev_buf.element_size()
+    return lib().rsilu_upload(h, _dev(dev_buf), nbytes, _stream(stream))
+
+
+def rsilu_get_stats(h):
+    s = rsilu_stats_t()
+    _check(lib().rsilu_get_stats(h, ctypes.byref(s)), "rsilu_get_stats")
+    return s
+
+
+def rsilu_get_perm(h, m):
+    out = np.empty(m, dtype=np.int32)
+    _check(lib().rsilu_get_perm(h, out.ctypes.data_as(ctypes.c_void_p)), "rsilu_get_perm")
+    return out
+
+
+def rsilu_get_colnorm(h, n):
+    out = np.empty(n, dtype=np.float64)
+    _check(lib().rsilu_get_colnorm(h, out.ctypes.data_as(ctypes.c_void_p)), "rsilu_get_colnorm")
+    return out
+
+
+def rsilu_factor_nnz(h, which):
+    return int(lib().rsilu_factor_nnz(h, int(which)))
+
+
+def rsilu_get_factor(h, which, nrows):
+    """(rowptr int64, col int32, val float64) of factor `which`, or val only for UDIAG."""
+    nnz = rsilu_factor_nnz(h, which)
+    if nnz < 0:
+        raise ValueError("bad factor selector")
+    val = np.empty(nnz, dtype=np.float64)
+    if which == UDIAG:
+        _check(lib().rsilu_get_factor(h, which, None, None, val.ctypes.data_as(ctypes.c_void_p)), "get_factor")
+        return val
+    rowptr = np.empty(nrows + 1, dtype=np.int64)
+    col = np.empty(nnz, dtype=np.int32)
+    _check(lib().rsilu_get_factor(h, which, rowptr.ctypes.data_as(ctypes.c_void_p),
+                                  col.ctypes.data_as(ctypes.c_void_p), val.ctypes.data_as(ctypes.c_void_p)),
+           "get_factor")
+    return rowptr, col, val
+
+
+def rsilu_get_levels(h, which, n, nlev):
+    ptr = np.empty(nlev + 1, dtype=np.int32)
+    rows = np.empty(n, dtype=np.int32)
+    _check(lib().rsilu_get_levels(h, int(which), ptr.ctypes.data_as(ctypes.c_void_p),
+                                  rows.ctypes.data_as(ctypes.c_void_p)), "get_levels")
+    return ptr, rows
+
+
+def rsilu_solve(h, b_dev, tol, x_dev, stream=None):
+    it = ctypes.c_int32(0)
+    atr = ctypes.c_double(0.0)
+    rel = ctypes.c_double(0.0)
+    code = lib().rsilu_solve(h, _dev(b_dev), float(tol), _dev(x_dev), ctypes.byref(it), ctypes.byref(atr),
+                             ctypes.byref(rel), _stream(stream))
+    return code, int(it.value), float(atr.value), float(rel.value)
+
+
+def rsilu_spmv(h, op, x_dev, y_dev, stream=None):
+    return lib().rsilu_spmv(h, int(op), _dev(x_dev), _dev(y_dev), _stream(stream))
+
+
+def rsilu_trsv(h, which, rhs_dev, x_dev, stream=None):
+    return lib().rsilu_trsv(h, int(which), _dev(rhs_dev), _dev(x_dev), _stream(stream))
+
+
+def rsilu_apply(h, r_dev, h_dev, stream=None):
+    return lib().rsilu_apply(h, _dev(r_dev), _dev(h_dev), _stream(stream))
+
+
+def rsilu_destroy(h):
+    if h is not None:
+        lib().rsilu_destroy(h)
+
+
+# ---------------------------------------------------------------- convenience
+
+
+class Solver:
+    """Owns a handle and the device buffer it was uploaded to."""
+
+    def __init__(self, m, n, rowptr, colind, val, device="cuda", **params):
+        self.m, self.n = int(m), int(n)
+        self.params = rsilu_params_default(**params)
+        code, h = rsilu_factor(m, n, rowptr, colind, val, self.params)
+        _check(code, "rsilu_factor")
+        if code != OK:
+            raise RsiluError(code, "rsilu_factor")
+        self.h = h
+        self.stats = rsilu_get_stats(h)
+        self.buf = None
+        self.device = device
+
+    @classmethod
+    def from_problem(cls, prob, **params):
+        return cls(prob.m, prob.n, prob.rowptr, prob.col, prob.val, **params)
+
+    def upload(self, stream=None):
+        import torch
+
+        nbytes = rsilu_device_bytes(self.h)
+        # over-allocate so the buffer can start on a 256-byte boundary
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self.buf = raw[off:off + nbytes]
+        self._raw = raw
+        _check(rsilu_upload(self.h, self.buf, stream), "rsilu_upload")
+        return self
+
+    def solve(self, b_dev, tol=1e-8, x_dev=None, stream=None):
+        import torch
+
+        if x_dev is None:
+            x_dev = torch.empty(self.n, dtype=torch.float64, device=b_dev.device)
+        code, it, atr, rel = rsilu_solve(self.h, b_dev, tol, x_dev, stream)
+        _check(code, "rsilu_solve")
+        return x_dev, code, it, atr, rel
+
+    def perm(self):
+        return rsilu_get_perm(self.h, self.m)
+
+    def close(self):
+        if self.h is not None:
+            rsilu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,193 @@
+"""The library's host setup (rsilu_factor) against the oracle, through the C ABI.
+
+The row permutation, every factor entry, the column norms and the level
+schedules must be bit-identical: both sides take the same floating-point
+decisions in the same order (Algorithms 4-6). No GPU is needed: rsilu_factor
+and the getters are host code.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_2603_28642_amd import rsilu as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def dense_problem(A):
+    A = np.asarray(A, dtype=float)
+    m, n = A.shape
+    rows, cols = np.nonzero(A)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rowptr[1:])
+    return m, n, rowptr, cols.astype(np.int32), A[rows, cols]
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.int64)
+
+
+def compare(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=1):
+    prm = R.rsilu_params_default(p=p, tau=tau, mu=mu, small=small, colscale=colscale, smode=R.S_IDENTITY)
+    code, h = R.rsilu_factor(m, n, rowptr, col, val, prm)
+    assert code == R.OK, R.status_string(code)
+    try:
+        F = oracle.factor(m, n, rowptr, col, val, p=p, tau=tau, mu=mu, small=small, colscale=bool(colscale))
+        st = R.rsilu_get_stats(h)
+        assert np.array_equal(R.rsilu_get_perm(h, m), F.perm)
+        assert st.nmod == F.nmod
+        for which, C in [(R.L1, F.L1), (R.L2, F.L2), (R.U, F.U), (R.AHAT, F.Ahat)]:
+            rp, cc, vv = R.rsilu_get_factor(h, which, C.nrows)
+            assert np.array_equal(rp, C.rowptr), which
+            assert np.array_equal(cc, C.col), which
+            assert np.array_equal(bits(vv), bits(C.val)), which
+        assert np.array_equal(bits(R.rsilu_get_factor(h, R.UDIAG, n)), bits(F.Udiag))
+        assert np.array_equal(bits(R.rsilu_get_colnorm(h, n)), bits(F.colnorm))
+        for which, key, nl in [(R.LEV_L1, "L1", st.levels_l1), (R.LEV_L1T, "L1T", st.levels_l1t),
+                               (R.LEV_U, "U", st.levels_u), (R.LEV_UT, "UT", st.levels_ut)]:
+            ptr, rows = R.rsilu_get_levels(h, which, n, nl)
+            assert np.array_equal(ptr, F.lev[key][0]), key
+            assert np.array_equal(rows, F.lev[key][1]), key
+        assert st.psize == F.psize
+        return st
+    finally:
+        R.rsilu_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small", "c3-mini"])
+@pytest.mark.parametrize("mu", [0.1, 1.0])
+def test_named_workloads(name, mu):
+    p = gen.by_name(name)
+    compare(p.m, p.n, p.rowptr, p.col, p.val, mu=mu)
+
+
+@pytest.mark.parametrize("key", list(gen.PAPER_SHAPES))
+@pytest.mark.parametrize("tau", [0.0, 0.1])
+def test_paper_shapes(key, tau):
+    p = gen.paper_shape(key, scale=0.15, seed=3)
+    compare(p.m, p.n, p.rowptr, p.col, p.val, tau=tau)
+
+
+@pytest.mark.parametrize("p_,tau,mu", [(1, 0.0, 0.1), (3, 0.05, 0.5), (10**9, 0.0, 1.0), (0, 0.0, 0.1)])
+def test_parameter_corners(p_, tau, mu):
+    p = gen.random_sparse(120, 90, k=5, seed=4)
+    compare(p.m, p.n, p.rowptr, p.col, p.val, p=p_, tau=tau, mu=mu)
+
+
+def test_edge_matrices():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((12, 8)) * (rng.random((12, 8)) < 0.4)
+    A[:, 3] = 0.0  # empty column
+    A[:, 5] = A[:, 4]  # duplicated column
+    compare(*dense_problem(A))
+    compare(*dense_problem(np.zeros((4, 3))))  # all pivots modified
+    compare(*dense_problem(np.eye(5)))  # m = n
+    B = np.ones((6, 4))  # exact ties everywhere
+    compare(*dense_problem(B))
+    compare(*dense_problem(B), colscale=0)
+    C = rng.standard_normal((30, 10))
+    C[29, :] = 1.0  # a dense row
+    compare(*dense_problem(C), p=2)
+
+
+def test_explicit_zeros_are_stripped():
+    m, n, rp, c, v = dense_problem(np.array([[1.0, 2.0], [3.0, 0.0], [0.0, 4.0]]))
+    v2 = v.copy()
+    v2[1] = 0.0  # (0,1) becomes an explicit zero
+    code, h = R.rsilu_factor(m, n, rp, c, v2)
+    assert code == R.OK
+    st = R.rsilu_get_stats(h)
+    assert st.nnz_a == 3
+    R.rsilu_destroy(h)
+
+
+@pytest.mark.parametrize("case", ["m<n", "bad col", "unsorted", "duplicate", "nan", "inf", "bad ptr", "bad mu",
+                                  "bad tau", "bad small"])
+def test_invalid_input(case):
+    m, n, rp, c, v = dense_problem(np.array([[1.0, 2.0], [3.0, 0.0], [0.0, 4.0]]))
+    prm = R.rsilu_params_default()
+    if case == "m<n":
+        m2, n2, rp2, c2, v2 = dense_problem(np.array([[1.0, 2.0, 3.0]]))
+        code, h = R.rsilu_factor(m2, n2, rp2, c2, v2)
+    else:
+        c = c.copy()
+        v = v.copy()
+        rp = rp.copy()
+        if case == "bad col":
+            c[0] = 7
+        elif case == "unsorted":
+            c[0], c[1] = c[1], c[0]
+        elif case == "duplicate":
+            c[1] = c[0]
+        elif case == "nan":
+            v[2] = np.nan
+        elif case == "inf":
+            v[2] = np.inf
+        elif case == "bad ptr":
+            rp[1] = 3
+            rp[2] = 1
+        elif case == "bad mu":
+            prm.mu = 1.5
+        elif case == "bad tau":
+            prm.tau = -1.0
+        elif case == "bad small":
+            prm.small = 0.0
+        code, h = R.rsilu_factor(m, n, rp, c, v, prm)
+    assert code == R.EINVAL and h is None
+
+
+def test_dense_S_setup():
+    p = gen.random_sparse(90, 60, k=4, seed=8)
+    prm = R.rsilu_params_default(smode=R.S_DENSE, mu=1.0)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    st = R.rsilu_get_stats(h)
+    F = oracle.factor_problem(p, mu=1.0, smode="dense")
+    assert st.smode == R.S_DENSE and st.psize == F.psize
+    R.rsilu_destroy(h)
+    # AUTO picks dense for small m - n and identity otherwise
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, R.rsilu_params_default())
+    assert R.rsilu_get_stats(h).smode == R.S_DENSE
+    R.rsilu_destroy(h)
+
+
+def test_device_calls_need_upload():
+    p = gen.random_sparse(30, 20, k=3, seed=1)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val)
+    assert R.rsilu_device_bytes(h) > 0
+    dummy = ctypes.c_void_p(0x1000)
+    assert R.lib().rsilu_solve(h, dummy, 1e-8, ctypes.c_void_p(0x2000), None, None, None, None) == R.ESTATE
+    assert R.lib().rsilu_spmv(h, 0, dummy, ctypes.c_void_p(0x2000), None) == R.ESTATE
+    assert R.lib().rsilu_upload(h, ctypes.c_void_p(0x1001), 1 << 30, None) == R.EINVAL  # misaligned
+    assert R.lib().rsilu_upload(h, ctypes.c_void_p(0x1000), 16, None) == R.ENOMEM  # too small
+    R.rsilu_destroy(h)
+    R.rsilu_destroy(None)
+
+
+def test_exports_match_header():
+    """Every function declared in include/rsilu.h is exported by the library."""
+    with open(os.path.join(ROOT, "include", "rsilu.h")) as f:
+        text = f.read()
+    declared = sorted(set(re.findall(r"\b(rsilu_[a-z_]+)\s*\(", text)))
+    assert declared == sorted(R.EXPORTS)
+    for name in declared:
+        assert hasattr(R.lib(), name)
+    for code in [0, 1, 2, -1, -2, -3, -4, -5]:
+        assert R.status_string(code)
+
+
+def test_no_oracle_in_product():
+    """The library and its binding never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_2603_28642_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                with open(os.path.join(dirpath, fn)) as f:
+                    src = f.read()
+                assert "oracle" not in src.lower(), fn
