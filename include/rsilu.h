@@ -184,6 +184,29 @@ rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs_dev
                           hipStream_t stream);
 rsilu_status_t rsilu_apply(rsilu_handle_t h, const double *r_dev, double *h_dev, hipStream_t stream);
 
+/* Kernel timing with HIP events recorded on the solve's stream around every
+ * launch of the classes below, accumulated over all rsilu_solve calls made
+ * while enabled (rsilu_set_profiling resets the counters). */
+enum {
+    RSILU_PROF_SPMV_A = 0,   /* q = A_hat p (with its norm partials) */
+    RSILU_PROF_SPMV_AT = 1,  /* z = A_hat^T r (with its norm partials) */
+    RSILU_PROF_TRSV_L1 = 2,  /* L1 forward solves (two per iteration) */
+    RSILU_PROF_TRSV_L1T = 3, /* L1^T backward solve fused with y = r1 + g' */
+    RSILU_PROF_TRSV_U = 4,   /* U backward solve */
+    RSILU_PROF_SPMV_L2 = 5,  /* u = r2 - L2 t */
+    RSILU_PROF_SPMV_L2T = 6, /* g = L2^T w */
+    RSILU_PROF_DENSE_S = 7,  /* dense S~ solves */
+    RSILU_PROF_COUNT = 8
+};
+
+typedef struct {
+    int64_t launches[RSILU_PROF_COUNT];
+    double ms[RSILU_PROF_COUNT];
+} rsilu_profile_t;
+
+rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable);
+rsilu_status_t rsilu_get_profile(rsilu_handle_t h, rsilu_profile_t *out);
+
 /* Release the handle's host memory and any HIP objects it created (not the
  * caller's device buffer). NULL is ignored. */
 void rsilu_destroy(rsilu_handle_t h);

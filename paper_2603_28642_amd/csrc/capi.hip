@@ -50,6 +50,55 @@ DTri dtri(const Ctx &c, const DevTriOff &o)
                 at<int32_t>(c, o.chunk), o.nchunks, o.lanes};
 }
 
+// HIP events around one launch group of a profiled class (rsilu_set_profiling).
+class ProfScope {
+public:
+    ProfScope(Ctx &c, hipStream_t s, int cls) : c_(c), s_(s), cls_(cls)
+    {
+        if (!c_.prof) return;
+        while (c_.ev_next + 2 > c_.ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            c_.ev_pool.push_back(static_cast<void *>(e));
+        }
+        idx_ = (int)c_.ev_next;
+        if (hipEventRecord(static_cast<hipEvent_t>(c_.ev_pool[(size_t)idx_]), s_) != hipSuccess) {
+            idx_ = -1;
+            return;
+        }
+        c_.ev_next += 2;
+    }
+    ~ProfScope()
+    {
+        if (idx_ < 0) return;
+        if (hipEventRecord(static_cast<hipEvent_t>(c_.ev_pool[(size_t)idx_ + 1]), s_) == hipSuccess)
+            c_.ev_open.push_back({cls_, idx_, c_.ev_iter});
+    }
+
+private:
+    Ctx &c_;
+    hipStream_t s_;
+    int cls_;
+    int idx_ = -1;
+};
+
+// After a stream synchronisation: add up the recorded launches of the
+// iterations that really ran (later ones returned at once on the stop flag).
+void prof_collect(Ctx &c, int completed_iters)
+{
+    for (const Ctx::EvRec &r : c.ev_open) {
+        if (r.iter > completed_iters) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, static_cast<hipEvent_t>(c.ev_pool[(size_t)r.idx]),
+                                static_cast<hipEvent_t>(c.ev_pool[(size_t)r.idx + 1])) == hipSuccess) {
+            c.prof_ms[r.cls] += ms;
+            c.prof_launches[r.cls] += 1;
+        }
+    }
+    c.ev_open.clear();
+    c.ev_next = 0;
+}
+
 // Device pointers of one solve.
 struct Ptrs {
     DevState *st;
@@ -102,9 +151,10 @@ Ptrs ptrs(const Ctx &c)
 
 // One triangular solve with the configured schedule. Sync-free solves need x
 // sentinel-filled and their ticket cleared beforehand.
-void trsv(const Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv, const double *rhs,
-          double *x, const double *add, double *y2, int ticket, const int32_t *done)
+void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv, const double *rhs, double *x,
+          const double *add, double *y2, int ticket, const int32_t *done, int cls)
 {
+    ProfScope ps(c, s, cls);
     if (c.prm.trsv == RSILU_TRSV_LEVELS) {
         for (int32_t l = 0; l < lv.nlev(); ++l)
             launch_trsv_level(s, t, lv.ptr[l], lv.ptr[(size_t)l + 1], rhs, x, add, y2, done);
@@ -113,41 +163,56 @@ void trsv(const Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Level
     }
 }
 
+bool syncfree(const Ctx &c) { return c.prm.trsv == RSILU_TRSV_SYNCFREE; }
+
 // Algorithm 3 on the residual r (pivot order) -> hout. For sync-free solves the
 // outputs t, gp, v and hout must have been sentinel-filled, tickets cleared.
-void apply_alg3(const Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *hout, const int32_t *done)
+void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *hout, const int32_t *done)
 {
     const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
     // step 1: u = r2 - Y r1 with Y r1 = L2 (L1^{-1} r1)
-    trsv(c, s, P, P.L1f, c.lvL1, r, P.t, nullptr, nullptr, 0, done);
+    trsv(c, s, P, P.L1f, c.lvL1, r, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
     if (k == 0) {
         // no A2: h = U^{-1} L1^{-1} r1
-        trsv(c, s, P, P.Ub, c.lvU, P.t, hout, nullptr, nullptr, 3, done);
+        trsv(c, s, P, P.Ub, c.lvU, P.t, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
         return;
     }
-    launch_spmv(s, P.L2, P.pL2, P.t, P.u, r + n, EPI_SUB, FIN_NONE, P.partials, P.segpart, P.st, done);
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_L2);
+        launch_spmv(s, P.L2, P.pL2, P.t, P.u, r + n, EPI_SUB, FIN_NONE, P.partials, P.segpart, P.st, done);
+    }
     // step 2: S^ w = u (in place in u)
-    if (c.smode == RSILU_S_DENSE) launch_dense_chol_solve(s, k, P.sfac, P.u, done);
+    if (c.smode == RSILU_S_DENSE) {
+        ProfScope ps(c, s, RSILU_PROF_DENSE_S);
+        launch_dense_chol_solve(s, k, P.sfac, P.u, done);
+    }
     // step 3: y = r1 + Y^T w with Y^T w = L1^{-T} (L2^T w)
-    launch_spmv(s, P.L2T, P.pL2T, P.u, P.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, done);
-    trsv(c, s, P, P.L1b, c.lvL1T, P.g, P.gp, r, P.y, 1, done);
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
+        launch_spmv(s, P.L2T, P.pL2T, P.u, P.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, done);
+    }
+    trsv(c, s, P, P.L1b, c.lvL1T, P.g, P.gp, r, P.y, 1, done, RSILU_PROF_TRSV_L1T);
     // step 4: L1 v = y, U h = v
-    trsv(c, s, P, P.L1f, c.lvL1, P.y, P.v, nullptr, nullptr, 2, done);
-    trsv(c, s, P, P.Ub, c.lvU, P.v, hout, nullptr, nullptr, 3, done);
+    trsv(c, s, P, P.L1f, c.lvL1, P.y, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+    trsv(c, s, P, P.Ub, c.lvU, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
 }
 
-bool syncfree(const Ctx &c) { return c.prm.trsv == RSILU_TRSV_SYNCFREE; }
-
-void enqueue_iteration(const Ctx &c, hipStream_t s, const Ptrs &P)
+void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
 {
     const int32_t n = (int32_t)c.n, m = (int32_t)c.m;
     // q = A p, alpha = rho / (q, q)
-    launch_spmv(s, P.A, P.pA, P.p, P.q, nullptr, EPI_SQ, FIN_ALPHA, P.partials, P.segpart, P.st, P.done);
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_A);
+        launch_spmv(s, P.A, P.pA, P.p, P.q, nullptr, EPI_SQ, FIN_ALPHA, P.partials, P.segpart, P.st, P.done);
+    }
     // x += alpha p, r -= alpha q (and prepare the sync-free outputs)
     const bool sf = syncfree(c);
     launch_update(s, n, m, P.p, P.xh, P.q, P.r, sf ? P.t : nullptr, P.gp, P.v, P.h, P.st, P.done);
     // z = A^T r, stop test on ||D^{-1} z|| = ||A^T r||
-    launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_STOP, P.partials, P.segpart, P.st, P.done);
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_AT);
+        launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_STOP, P.partials, P.segpart, P.st, P.done);
+    }
     // h = M^{-1} z by Algorithm 3 on (r1, r2)
     apply_alg3(c, s, P, P.r, P.h, P.done);
     // rho' = (z, h), beta = rho'/rho, p = h + beta p
@@ -391,6 +456,9 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
     const bool sf = syncfree(c);
 
     // ---- initialisation: x0 = 0, r0 = P b, z0 = A^T r0, h0 = B(r0), rho0, p0 = h0
+    c.ev_iter = 0;
+    c.ev_open.clear();
+    c.ev_next = 0;
     launch_gather(s, m, n, P.perm, b, P.r, P.xh, nullptr);
     launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_INIT, P.partials, P.segpart, P.st, nullptr);
     if (sf) launch_fill(s, n, P.t, P.gp, P.v, P.h, P.st);
@@ -404,11 +472,15 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
     bool stop = c.prm.maxit == 0;
     while (!stop) {
         const int batch = (int)std::min<int64_t>(c.prm.poll, (int64_t)c.prm.maxit - enqueued);
-        for (int i = 0; i < batch; ++i) enqueue_iteration(c, s, P);
+        for (int i = 0; i < batch; ++i) {
+            c.ev_iter = (int)(enqueued + i + 1);
+            enqueue_iteration(c, s, P);
+        }
         enqueued += batch;
         RSILU_HIP(hipGetLastError());
         RSILU_HIP(hipMemcpyAsync(&mail->poll, P.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         RSILU_HIP(hipStreamSynchronize(s));
+        if (c.prof) prof_collect(c, mail->poll.done ? mail->poll.iter - 1 : mail->poll.iter);
         if (mail->poll.done || mail->poll.err || enqueued >= c.prm.maxit) stop = true;
     }
 
@@ -458,9 +530,9 @@ rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs, do
     const int32_t n = (int32_t)c.n;
     if (syncfree(c)) launch_fill(s, n, x, nullptr, nullptr, nullptr, P.st);
     switch (which) {
-    case 0: trsv(c, s, P, P.L1f, c.lvL1, rhs, x, nullptr, nullptr, 0, nullptr); break;
-    case 1: trsv(c, s, P, P.L1b, c.lvL1T, rhs, x, nullptr, nullptr, 0, nullptr); break;
-    case 2: trsv(c, s, P, P.Ub, c.lvU, rhs, x, nullptr, nullptr, 0, nullptr); break;
+    case 0: trsv(c, s, P, P.L1f, c.lvL1, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1); break;
+    case 1: trsv(c, s, P, P.L1b, c.lvL1T, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1T); break;
+    case 2: trsv(c, s, P, P.Ub, c.lvU, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_U); break;
     default: return RSILU_EINVAL;
     }
     RSILU_HIP(hipGetLastError());
@@ -480,10 +552,34 @@ rsilu_status_t rsilu_apply(rsilu_handle_t h, const double *r, double *hout, hipS
     return RSILU_OK;
 }
 
+rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable)
+{
+    if (!h) return RSILU_EINVAL;
+    h->prof = enable != 0;
+    h->ev_open.clear();
+    h->ev_next = 0;
+    for (int i = 0; i < RSILU_PROF_COUNT; ++i) {
+        h->prof_launches[i] = 0;
+        h->prof_ms[i] = 0.0;
+    }
+    return RSILU_OK;
+}
+
+rsilu_status_t rsilu_get_profile(rsilu_handle_t h, rsilu_profile_t *out)
+{
+    if (!h || !out) return RSILU_EINVAL;
+    for (int i = 0; i < RSILU_PROF_COUNT; ++i) {
+        out->launches[i] = h->prof_launches[i];
+        out->ms[i] = h->prof_ms[i];
+    }
+    return RSILU_OK;
+}
+
 void rsilu_destroy(rsilu_handle_t h)
 {
     if (!h) return;
     if (h->pinned) (void)hipHostFree(h->pinned);
+    for (void *e : h->ev_pool) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     delete h;
 }
 

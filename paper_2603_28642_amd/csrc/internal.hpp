@@ -104,6 +104,18 @@ struct Ctx {
     size_t dev_bytes = 0;
     int device = -1;
     void *pinned = nullptr;  // small host-pinned mailbox for polling
+
+    // kernel timing (rsilu_set_profiling)
+    bool prof = false;
+    std::vector<void *> ev_pool;                // hipEvent_t
+    struct EvRec {
+        int cls, idx, iter;  // class, first of two events, iteration it belongs to (0 = init)
+    };
+    std::vector<EvRec> ev_open;                 // recorded, not yet read back
+    int ev_iter = 0;                            // iteration being enqueued
+    size_t ev_next = 0;
+    int64_t prof_launches[RSILU_PROF_COUNT] = {};
+    double prof_ms[RSILU_PROF_COUNT] = {};
 };
 
 // host setup (setup.cpp)

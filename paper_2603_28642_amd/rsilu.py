@@ -25,8 +25,10 @@ LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
 EXPORTS = [
     "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_get_stats",
     "rsilu_get_perm", "rsilu_get_colnorm", "rsilu_factor_nnz", "rsilu_get_factor", "rsilu_get_levels",
-    "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_destroy", "rsilu_status_string",
+    "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_set_profiling", "rsilu_get_profile",
+    "rsilu_destroy", "rsilu_status_string",
 ]
+PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S"]
 
 
 class rsilu_params_t(ctypes.Structure):
@@ -44,6 +46,10 @@ class rsilu_stats_t(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class rsilu_profile_t(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
 
 
 class RsiluError(RuntimeError):
@@ -92,6 +98,10 @@ def lib():
         L.rsilu_trsv.restype = ctypes.c_int
         L.rsilu_apply.argtypes = [P, P, P, P]
         L.rsilu_apply.restype = ctypes.c_int
+        L.rsilu_set_profiling.argtypes = [P, I32]
+        L.rsilu_set_profiling.restype = ctypes.c_int
+        L.rsilu_get_profile.argtypes = [P, ctypes.POINTER(rsilu_profile_t)]
+        L.rsilu_get_profile.restype = ctypes.c_int
         L.rsilu_destroy.argtypes = [P]
         L.rsilu_destroy.restype = None
         L.rsilu_status_string.argtypes = [ctypes.c_int]
@@ -231,6 +241,17 @@ def rsilu_trsv(h, which, rhs_dev, x_dev, stream=None):
 
 def rsilu_apply(h, r_dev, h_dev, stream=None):
     return lib().rsilu_apply(h, _dev(r_dev), _dev(h_dev), _stream(stream))
+
+
+def rsilu_set_profiling(h, enable):
+    return lib().rsilu_set_profiling(h, 1 if enable else 0)
+
+
+def rsilu_get_profile(h):
+    """{kernel class: (launches, total ms)} from the HIP events recorded during solves."""
+    p = rsilu_profile_t()
+    _check(lib().rsilu_get_profile(h, ctypes.byref(p)), "rsilu_get_profile")
+    return {name: (int(p.launches[i]), float(p.ms[i])) for i, name in enumerate(PROF_NAMES)}
 
 
 def rsilu_destroy(h):
