@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--smode", default="identity", choices=["identity", "dense", "auto"])
-    ap.add_argument("--trsv", default="syncfree", choices=["syncfree", "levels"])
+    ap.add_argument("--trsv", default="hybrid", choices=["hybrid", "syncfree", "levels"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     return ap.parse_args()
@@ -135,7 +135,7 @@ def main():
     torch.cuda.set_device(0)
     prob = gen.by_name(args.workload)
     smode = {"identity": R.S_IDENTITY, "dense": R.S_DENSE, "auto": R.S_AUTO}[args.smode]
-    trsv = R.TRSV_SYNCFREE if args.trsv == "syncfree" else R.TRSV_LEVELS
+    trsv = {"hybrid": R.TRSV_HYBRID, "syncfree": R.TRSV_SYNCFREE, "levels": R.TRSV_LEVELS}[args.trsv]
     t0 = time.perf_counter()
     S = R.Solver.from_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit, trsv=trsv)
     t_setup = time.perf_counter() - t0

@@ -61,7 +61,9 @@ enum {
 /* Schedule of the sparse triangular solves with L1, L1^T and U. */
 enum {
     RSILU_TRSV_SYNCFREE = 0, /* one launch per solve; rows wait on their inputs */
-    RSILU_TRSV_LEVELS = 1    /* one launch per level of the dependency DAG */
+    RSILU_TRSV_LEVELS = 1,   /* one launch per level of the dependency DAG */
+    RSILU_TRSV_HYBRID = 2    /* wide levels one launch each; runs of narrow levels
+                                swept by a single workgroup through LDS (default) */
 };
 
 typedef struct {
@@ -73,7 +75,7 @@ typedef struct {
     int32_t colscale; /* 1: prescale columns to unit 2-norm (Section 5.1); 1 */
     int32_t smode;    /* RSILU_S_*; default RSILU_S_AUTO */
     int32_t maxit;    /* Algorithm 1 iteration limit; 2000 (Section 5.1) */
-    int32_t trsv;     /* RSILU_TRSV_*; default RSILU_TRSV_SYNCFREE */
+    int32_t trsv;     /* RSILU_TRSV_*; default RSILU_TRSV_HYBRID */
     int32_t poll;     /* iterations enqueued between host polls of the stop flag; 8 */
 } rsilu_params_t;
 
@@ -98,7 +100,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
- * maxit = 2000 (Section 5.1), trsv = SYNCFREE, poll = 8. */
+ * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

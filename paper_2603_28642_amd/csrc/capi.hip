@@ -110,6 +110,7 @@ struct Ptrs {
     const int32_t *perm;
     const double *colnorm, *sfac;
     double *xh, *p, *z, *h, *t, *y, *v, *g, *gp, *r, *q, *u;
+    double *lo_rhs, *lo_add;
 };
 
 Ptrs ptrs(const Ctx &c)
@@ -146,16 +147,34 @@ Ptrs ptrs(const Ctx &c)
     P.r = at<double>(c, L.r);
     P.q = at<double>(c, L.q);
     P.u = at<double>(c, L.u);
+    P.lo_rhs = at<double>(c, L.lo_rhs);
+    P.lo_add = at<double>(c, L.lo_add);
     return P;
 }
 
 // One triangular solve with the configured schedule. Sync-free solves need x
 // sentinel-filled and their ticket cleared beforehand.
-void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv, const double *rhs, double *x,
-          const double *add, double *y2, int ticket, const int32_t *done, int cls)
+void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv, const Sweep &sw,
+          const DevTriOff &o, const double *rhs, double *x, const double *add, double *y2, int ticket,
+          const int32_t *done, int cls)
 {
     ProfScope ps(c, s, cls);
-    if (c.prm.trsv == RSILU_TRSV_LEVELS) {
+    if (c.prm.trsv == RSILU_TRSV_HYBRID) {
+        const unsigned char *blob = at<unsigned char>(c, o.blob);
+        const bool runs = std::any_of(sw.segs.begin(), sw.segs.end(), [](const Sweep::Seg &g) { return g.wide_level < 0; });
+        if (runs) launch_gather_lo(s, (int32_t)c.n, t.rows, rhs, P.lo_rhs, add, y2 ? P.lo_add : nullptr, done);
+        for (const Sweep::Seg &g : sw.segs) {
+            if (g.wide_level >= 0) {
+                launch_trsv_level(s, t, lv.ptr[g.wide_level], lv.ptr[(size_t)g.wide_level + 1], rhs, x, add, y2,
+                                  done);
+            } else {
+                const int64_t off = sw.batch_off[(size_t)g.b0];
+                const int32_t size = (int32_t)(sw.batch_off[(size_t)g.b0 + 1] - off);
+                const int32_t *h0 = reinterpret_cast<const int32_t *>(sw.blob.data() + off);
+                launch_trsv_sweep(s, blob, off, size, h0[1], h0[6], g.b1 - g.b0, P.lo_rhs, x, P.lo_add, y2, done);
+            }
+        }
+    } else if (c.prm.trsv == RSILU_TRSV_LEVELS) {
         for (int32_t l = 0; l < lv.nlev(); ++l)
             launch_trsv_level(s, t, lv.ptr[l], lv.ptr[(size_t)l + 1], rhs, x, add, y2, done);
     } else {
@@ -171,10 +190,10 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *h
 {
     const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
     // step 1: u = r2 - Y r1 with Y r1 = L2 (L1^{-1} r1)
-    trsv(c, s, P, P.L1f, c.lvL1, r, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
+    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, r, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
     if (k == 0) {
         // no A2: h = U^{-1} L1^{-1} r1
-        trsv(c, s, P, P.Ub, c.lvU, P.t, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+        trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.t, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
         return;
     }
     {
@@ -191,10 +210,10 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *h
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
         launch_spmv(s, P.L2T, P.pL2T, P.u, P.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, done);
     }
-    trsv(c, s, P, P.L1b, c.lvL1T, P.g, P.gp, r, P.y, 1, done, RSILU_PROF_TRSV_L1T);
+    trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, P.g, P.gp, r, P.y, 1, done, RSILU_PROF_TRSV_L1T);
     // step 4: L1 v = y, U h = v
-    trsv(c, s, P, P.L1f, c.lvL1, P.y, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
-    trsv(c, s, P, P.Ub, c.lvU, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.y, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+    trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
 }
 
 void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
@@ -237,7 +256,7 @@ void rsilu_params_default(rsilu_params_t *p)
     p->colscale = 1;
     p->smode = RSILU_S_AUTO;
     p->maxit = 2000;
-    p->trsv = RSILU_TRSV_SYNCFREE;
+    p->trsv = RSILU_TRSV_HYBRID;
     p->poll = 8;
 }
 
@@ -409,6 +428,9 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
         if (e == hipSuccess) e = put(o.chunk, ch.ptr.data(), ch.ptr.size() * sizeof(int32_t));
         return e;
     };
+    auto put_sweep = [&](const DevTriOff &o, const Sweep &sw) -> hipError_t {
+        return put(o.blob, sw.blob.data(), sw.blob.size());
+    };
     RSILU_HIP(put_csr(L.A, c.Ahat));
     RSILU_HIP(put_csr(L.AT, c.AhatT));
     RSILU_HIP(put_csr(L.L2, c.L2));
@@ -420,6 +442,9 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put_tri(L.L1f, c.L1, nullptr, c.lvL1, c.chL1));
     RSILU_HIP(put_tri(L.L1b, c.L1T, nullptr, c.lvL1T, c.chL1T));
     RSILU_HIP(put_tri(L.Ub, c.U, &c.Udiag, c.lvU, c.chU));
+    RSILU_HIP(put_sweep(L.L1f, c.swL1));
+    RSILU_HIP(put_sweep(L.L1b, c.swL1T));
+    RSILU_HIP(put_sweep(L.Ub, c.swU));
     RSILU_HIP(put(L.perm, c.perm.data(), c.perm.size() * sizeof(int32_t)));
     RSILU_HIP(put(L.colnorm, c.colnorm.data(), c.colnorm.size() * sizeof(double)));
     RSILU_HIP(put(L.sfac, c.sfac.data(), c.sfac.size() * sizeof(double)));
@@ -530,9 +555,9 @@ rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs, do
     const int32_t n = (int32_t)c.n;
     if (syncfree(c)) launch_fill(s, n, x, nullptr, nullptr, nullptr, P.st);
     switch (which) {
-    case 0: trsv(c, s, P, P.L1f, c.lvL1, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1); break;
-    case 1: trsv(c, s, P, P.L1b, c.lvL1T, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1T); break;
-    case 2: trsv(c, s, P, P.Ub, c.lvU, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_U); break;
+    case 0: trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1); break;
+    case 1: trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1T); break;
+    case 2: trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_U); break;
     default: return RSILU_EINVAL;
     }
     RSILU_HIP(hipGetLastError());

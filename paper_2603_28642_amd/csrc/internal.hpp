@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "rsilu.h"
+#include "sweep_limits.hpp"
 
 namespace rsilu {
 
@@ -30,6 +31,21 @@ struct Levels {
 struct Chunks {
     std::vector<int32_t> ptr;  // nchunks + 1, positions in Levels::rows
     int32_t cap = 0;
+};
+
+// Hybrid schedule of a triangular solve. Levels wider than kSweepRows rows
+// (or too large for the LDS) are separate multi-CU launches; runs of the other
+// levels are swept by one workgroup, batch by batch: a batch is a contiguous
+// byte blob (levels, rows, entries, diagonal) copied into LDS, and a row's
+// input produced in the same batch is read from LDS.
+struct Sweep {
+    struct Seg {
+        int32_t wide_level;  // >= 0: one multi-CU launch for this level
+        int32_t b0, b1;      // otherwise: batches [b0, b1) in one single-workgroup launch
+    };
+    std::vector<Seg> segs;
+    std::vector<int64_t> batch_off;  // nbatches + 1 byte offsets into blob
+    std::vector<unsigned char> blob;
 };
 
 // Work plan for a CSR product: rows with more than `long_thresh` entries are
@@ -62,6 +78,7 @@ struct DevTriOff {
     int32_t cap = 0;
     int32_t lanes = 8;
     int32_t nlev = 0;
+    size_t blob = 0;  // hybrid sweep: batch blobs
 };
 
 struct Layout {
@@ -74,6 +91,7 @@ struct Layout {
     size_t xh = 0, p = 0, z = 0, h = 0, t = 0, y = 0, v = 0, g = 0, gp = 0;  // n
     size_t r = 0, q = 0;                                                       // m
     size_t u = 0;                                                              // m - n
+    size_t lo_rhs = 0, lo_add = 0;  // level-ordered right-hand side and addend of a sweep (n)
     size_t partials = 0;  // reduction partials
     int32_t npartials = 0;
     size_t segpart = 0;   // long-row segment partials
@@ -95,6 +113,7 @@ struct Ctx {
     std::vector<double> Udiag;
     Levels lvL1, lvL1T, lvU, lvUT;
     Chunks chL1, chL1T, chU;
+    Sweep swL1, swL1T, swU;
     SpmvPlan plA, plAT, plL2, plL2T;
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
 

@@ -391,6 +391,172 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(DTri t, int32_t beg, int3
     }
 }
 
+// Single-workgroup sweep over nb consecutive batches of narrow levels (the
+// hybrid schedule's runs). Every row reads its inputs from LDS: results of its
+// own batch, of the previous batch, or the batch's older inputs gathered from
+// x. While a batch's levels are solved (LDS reads, global stores only), the
+// next batch's blob, its slice of the level-ordered right-hand side (and
+// addend) and its older inputs are already in flight into registers; they are
+// written to LDS after the batch's last level. The older inputs of batch b+1
+// lie in batches <= b-1 or earlier launches, so they are final when batch b
+// starts; the list of them travels in batch b's blob.
+// Blob layout: int32 hdr[kSweepHdr] = {nlev, npos, nent, next, has_diag,
+// cur_base, p0, size, next_size, next_npos, next_next, -}, lev_off[nlev+1],
+// rowid[npos], eptr[npos+1], ext_idx[next], next_ext[kSweepExt],
+// uint16 eslot[nent], then (8-aligned) double eval[nent], diag[npos].
+// eslot indexes the LDS window xw = [even batches' results | odd batches'
+// results | older inputs].
+__global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned char *__restrict__ blob, int64_t off,
+                                                               int32_t size, int32_t npos_first, int32_t p0,
+                                                               int32_t nb, const double *__restrict__ rhs_lo,
+                                                               double *x, const double *__restrict__ add_lo,
+                                                               double *y2, const int32_t *done)
+{
+    constexpr int VB = (kSweepBlob / 16 + kSweepThreads - 1) / kSweepThreads;
+    constexpr int VP = (kSweepPos + kSweepThreads - 1) / kSweepThreads;
+    constexpr int VE = (kSweepExt + kSweepThreads - 1) / kSweepThreads;
+    __shared__ __attribute__((aligned(16))) unsigned char sb[kSweepBlob];
+    __shared__ double xw[2 * kSweepPos + kSweepExt];
+    __shared__ double rl[kSweepPos];
+    __shared__ double al[kSweepPos];
+    __shared__ double prod[kSweepLevEnt];
+    if (stop_now(done)) return;
+    const int tid = threadIdx.x;
+    static_assert(VB <= 5 && VP == 2 && VE == 2, "staging registers are written out for these limits");
+    // Staging registers for the next batch. Loads are unconditional with
+    // clamped indices (always in bounds: a batch has at least one row and one
+    // blob vector) so the values stay in registers; only LDS writes are
+    // predicated.
+    uint4 rb0, rb1, rb2, rb3, rb4;
+    double rr0, rr1, ra0, ra1, re0, re1;
+    uint4 *sb4 = reinterpret_cast<uint4 *>(sb);
+    const int t0 = tid, t1 = tid + kSweepThreads, t2 = tid + 2 * kSweepThreads, t3 = tid + 3 * kSweepThreads,
+              t4 = tid + 4 * kSweepThreads;
+#define RSILU_LOAD_BATCH(BOFF, NVEC, BP0, BNPOS)                                        \
+    {                                                                                   \
+        const uint4 *src_ = reinterpret_cast<const uint4 *>(blob + (BOFF));             \
+        const int lastv_ = (NVEC) - 1, lastp_ = (BNPOS) - 1;                            \
+        rb0 = src_[min(t0, lastv_)];                                                    \
+        rb1 = src_[min(t1, lastv_)];                                                    \
+        rb2 = src_[min(t2, lastv_)];                                                    \
+        rb3 = src_[min(t3, lastv_)];                                                    \
+        if (VB > 4) rb4 = src_[min(t4, lastv_)];                                        \
+        rr0 = rhs_lo[(BP0) + min(t0, lastp_)];                                          \
+        rr1 = rhs_lo[(BP0) + min(t1, lastp_)];                                          \
+        ra0 = y2 ? add_lo[(BP0) + min(t0, lastp_)] : 0.0;                               \
+        ra1 = y2 ? add_lo[(BP0) + min(t1, lastp_)] : 0.0;                               \
+    }
+#define RSILU_LOAD_EXT(LIST, CNT)                                                       \
+    {                                                                                   \
+        const int lastj_ = (CNT) - 1;                                                   \
+        re0 = (CNT) > 0 ? x[(LIST)[min(t0, lastj_)]] : 0.0;                             \
+        re1 = (CNT) > 0 ? x[(LIST)[min(t1, lastj_)]] : 0.0;                             \
+    }
+#define RSILU_STORE_BATCH(NVEC, BNPOS)                                                  \
+    {                                                                                   \
+        if (t0 < (NVEC)) sb4[t0] = rb0;                                                 \
+        if (t1 < (NVEC)) sb4[t1] = rb1;                                                 \
+        if (t2 < (NVEC)) sb4[t2] = rb2;                                                 \
+        if (t3 < (NVEC)) sb4[t3] = rb3;                                                 \
+        if (VB > 4 && t4 < (NVEC)) sb4[t4] = rb4;                                       \
+        if (t0 < (BNPOS)) {                                                             \
+            rl[t0] = rr0;                                                               \
+            al[t0] = ra0;                                                               \
+        }                                                                               \
+        if (t1 < (BNPOS)) {                                                             \
+            rl[t1] = rr1;                                                               \
+            al[t1] = ra1;                                                               \
+        }                                                                               \
+    }
+#define RSILU_STORE_EXT(CNT)                                                            \
+    {                                                                                   \
+        if (t0 < (CNT)) xw[2 * kSweepPos + t0] = re0;                                   \
+        if (t1 < (CNT)) xw[2 * kSweepPos + t1] = re1;                                   \
+    }
+
+    // prologue: the first batch, then its own older inputs
+    RSILU_LOAD_BATCH(off, size >> 4, p0, npos_first)
+    RSILU_STORE_BATCH(size >> 4, npos_first)
+    __syncthreads();
+    {
+        const int32_t *hdr = reinterpret_cast<const int32_t *>(sb);
+        const int32_t *own_ext = hdr + kSweepHdr + (hdr[0] + 1) + hdr[1] + (hdr[1] + 1);
+        RSILU_LOAD_EXT(own_ext, hdr[3])
+        RSILU_STORE_EXT(hdr[3])
+    }
+    __syncthreads();
+
+    for (int b = 0; b < nb; ++b) {
+        const int32_t *hdr = reinterpret_cast<const int32_t *>(sb);
+        const int nlev = hdr[0], npos = hdr[1], nent = hdr[2], next = hdr[3], hd = hdr[4], cur = hdr[5];
+        const int size_next = hdr[8], npos_next = hdr[9], nnext = hdr[10];
+        const int32_t *lev_off = hdr + kSweepHdr;
+        const int32_t *rowid = lev_off + nlev + 1;
+        const int32_t *eptr = rowid + npos;
+        const int32_t *ext_idx = eptr + npos + 1;
+        const int32_t *next_ext = ext_idx + next;
+        const uint16_t *eslot = reinterpret_cast<const uint16_t *>(next_ext + kSweepExt);
+        int off_val = 4 * kSweepHdr + 4 * (nlev + 1) + 4 * npos + 4 * (npos + 1) + 4 * next + 4 * kSweepExt + 2 * nent;
+        off_val = (off_val + 7) & ~7;
+        const double *eval = reinterpret_cast<const double *>(sb + off_val);
+        const double *dg = eval + nent;
+        const bool more = b + 1 < nb;
+        const int64_t noff = off + size;
+        const int np0 = p0 + npos;
+        if (more) {
+            RSILU_LOAD_BATCH(noff, size_next >> 4, np0, npos_next)
+            RSILU_LOAD_EXT(next_ext, nnext)
+        }
+        for (int L = 0; L < nlev; ++L) {
+            // products of the level's entries, one entry per thread
+            const int pa = lev_off[L], pb = lev_off[L + 1];
+            const int ea = eptr[pa], eb = eptr[pb];
+            for (int e = ea + tid; e < eb; e += kSweepThreads) prod[e - ea] = eval[e] * xw[eslot[e]];
+            __syncthreads();
+            // row sums in entry order, one row per thread
+            const int p = pa + tid;
+            if (p < pb) {
+                double s = 0.0;
+                const int e0 = eptr[p] - ea, e1 = eptr[p + 1] - ea;
+#pragma unroll 4
+                for (int e = e0; e < e1; ++e) s += prod[e];
+                double r = rl[p] - s;
+                if (hd) r = r / dg[p];
+                xw[cur + p] = r;
+                const int row = rowid[p];
+                x[row] = r;
+                if (y2) y2[row] = al[p] + r;
+            }
+            __syncthreads();
+        }
+        if (more) {
+            RSILU_STORE_BATCH(size_next >> 4, npos_next)
+            RSILU_STORE_EXT(nnext)
+            off = noff;
+            size = size_next;
+            p0 = np0;
+            __syncthreads();
+        }
+    }
+#undef RSILU_LOAD_BATCH
+#undef RSILU_LOAD_EXT
+#undef RSILU_STORE_BATCH
+#undef RSILU_STORE_EXT
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_lo(int32_t n, const int32_t *__restrict__ rows,
+                                                       const double *__restrict__ src, double *__restrict__ dst,
+                                                       const double *__restrict__ src2, double *__restrict__ dst2,
+                                                       const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int p = blockIdx.x * kBlock + threadIdx.x; p < n; p += gridDim.x * kBlock) {
+        const int r = rows[p];
+        dst[p] = src[r];
+        if (src2) dst2[p] = src2[r];
+    }
+}
+
 // ------------------------------------------------------------------ dense S~ (Section 3.2)
 
 __device__ __forceinline__ long long pk(long long i, long long j) { return i * (i + 1) / 2 + j; }
@@ -634,6 +800,21 @@ void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, c
         break;
     }
 #undef RSILU_TRSVL_CASE
+}
+
+void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
+                       int32_t p0, int32_t nb, const double *rhs_lo, double *x, const double *add_lo, double *y2,
+                       const int32_t *done)
+{
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_trsv_sweep, dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0, nb, rhs_lo,
+                       x, add_lo, y2, done);
+}
+
+void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const double *src, double *dst,
+                      const double *src2, double *dst2, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_gather_lo, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rows, src, dst, src2, dst2, done);
 }
 
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done)

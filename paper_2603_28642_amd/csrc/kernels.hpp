@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "sweep_limits.hpp"
+
 namespace rsilu {
 
 // Device scalars of Algorithm 1 and the stop/breakdown flags.
@@ -70,6 +72,7 @@ enum Fin : int32_t {
 
 constexpr int kBlock = 256;
 
+
 // ---- launchers (all asynchronous on `s`); `done` may be nullptr
 void launch_gather(hipStream_t s, int32_t m, int32_t n, const int32_t *perm, const double *b, double *r,
                    double *xh, const int32_t *done);
@@ -93,6 +96,15 @@ void launch_trsv_syncfree(hipStream_t s, const DTri &t, const double *rhs, doubl
                           double *y2, DevState *st, int ticket, const int32_t *done);
 void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, const double *rhs, double *x,
                        const double *add, double *y2, const int32_t *done);
+// nb consecutive batches of a hybrid sweep by one workgroup, starting with the
+// batch at byte `off` of `blob` (its size and row count given); rhs_lo and
+// add_lo are the right-hand side and addend in level order.
+void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
+                       int32_t p0, int32_t nb, const double *rhs_lo, double *x, const double *add_lo, double *y2,
+                       const int32_t *done);
+// dst[p] = src[rows[p]] (and dst2 from src2 when given)
+void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const double *src, double *dst,
+                      const double *src2, double *dst2, const int32_t *done);
 // w = (L L^T)^{-1} u with L packed lower (k x k), in place on w (w = u on entry)
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done);
 void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);

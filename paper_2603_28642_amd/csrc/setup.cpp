@@ -18,6 +18,7 @@
 #include <functional>
 #include <new>
 #include <queue>
+#include <stdexcept>
 #include <utility>
 
 #include "internal.hpp"
@@ -114,6 +115,201 @@ Chunks make_chunks(const Levels &lv, int32_t cap)
     return ch;
 }
 
+// Byte size of a sweep batch blob (layout in kernels.hip, k_trsv_sweep).
+int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t nent, int64_t next, bool diag, int64_t nnext = kSweepExt)
+{
+    int64_t b = 4 * kSweepHdr + 4 * (nlev + 1) + 4 * npos + 4 * (npos + 1) + 4 * next + 4 * nnext + 2 * nent;
+    b = (b + 7) & ~(int64_t)7;
+    b += 8 * nent + (diag ? 8 * npos : 0);
+    return (b + 15) & ~(int64_t)15;
+}
+
+// Hybrid sweep schedule of the triangular operator T with level sets lv.
+// Runs of levels of at most kSweepRows rows are cut into batches; an input of a
+// row is read from LDS: from the results of the same batch, of the previous
+// batch of the run, or from the batch's gathered older inputs ("ext").
+Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv)
+{
+    Sweep sw;
+    const int32_t n = T.nrows;
+    const bool hd = diag != nullptr;
+    std::vector<int32_t> posof((size_t)n);
+    for (int32_t p = 0; p < n; ++p) posof[lv.rows[p]] = p;
+    std::vector<int32_t> ext_stamp((size_t)n, -1), ext_slot((size_t)n, 0);
+    sw.batch_off.push_back(0);
+    auto nbatches = [&]() { return (int32_t)sw.batch_off.size() - 1; };
+    auto entries = [&](int32_t l) {
+        int64_t ne = 0;
+        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p)
+            ne += T.ptr[(size_t)lv.rows[p] + 1] - T.ptr[lv.rows[p]];
+        return ne;
+    };
+
+    int32_t run_b0 = -1;       // first batch of the open run
+    int32_t prev_p0 = -1, prev_p1 = -1;  // positions of the previous batch of the run
+    int32_t bl0 = -1, bl1 = -1;          // levels of the open batch
+    int64_t bpos = 0, bent = 0, bext = 0;
+    int32_t stamp = 0;
+
+    // older inputs of level l that the open batch would have to gather
+    auto new_ext = [&](int32_t l, int32_t p0) {
+        int64_t k = 0;
+        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) {
+            const int32_t row = lv.rows[p];
+            for (int32_t e = T.ptr[row]; e < T.ptr[(size_t)row + 1]; ++e) {
+                const int32_t c = T.col[e], pc = posof[c];
+                if (pc >= p0 || (pc >= prev_p0 && pc < prev_p1)) continue;
+                if (ext_stamp[c] != stamp) {
+                    ext_stamp[c] = stamp;
+                    ++k;
+                }
+            }
+        }
+        return k;
+    };
+
+    auto serialize = [&](int32_t l0, int32_t l1) {
+        const int32_t p0 = lv.ptr[l0], p1 = lv.ptr[l1], npos = p1 - p0, nlev = l1 - l0;
+        const int32_t bi = nbatches() - run_b0;  // index inside the run
+        const int32_t cur_base = (bi & 1) ? kSweepPos : 0, prev_base = (bi & 1) ? 0 : kSweepPos;
+        // collect the older inputs (fresh stamp)
+        ++stamp;
+        std::vector<int32_t> ext;
+        int64_t nent = 0;
+        for (int32_t p = p0; p < p1; ++p) {
+            const int32_t row = lv.rows[p];
+            for (int32_t e = T.ptr[row]; e < T.ptr[(size_t)row + 1]; ++e, ++nent) {
+                const int32_t c = T.col[e], pc = posof[c];
+                if (pc >= p0 || (pc >= prev_p0 && pc < prev_p1)) continue;
+                if (ext_stamp[c] != stamp) {
+                    ext_stamp[c] = stamp;
+                    ext_slot[c] = (int32_t)ext.size();
+                    ext.push_back(c);
+                }
+            }
+        }
+        const int64_t next = (int64_t)ext.size();
+        const int64_t size = blob_bytes(nlev, npos, nent, next, hd);  // room for the next batch's list
+        if (npos > kSweepPos || next > kSweepExt || size > kSweepBlob || nent > 65535)
+            throw std::length_error("sweep batch exceeds the LDS limits");
+        const size_t base = sw.blob.size();
+        sw.blob.resize(base + (size_t)size, 0);
+        unsigned char *b = sw.blob.data() + base;
+        int32_t *hdr = reinterpret_cast<int32_t *>(b);
+        hdr[0] = nlev;
+        hdr[1] = npos;
+        hdr[2] = (int32_t)nent;
+        hdr[3] = (int32_t)next;
+        hdr[4] = hd ? 1 : 0;
+        hdr[5] = cur_base;
+        hdr[6] = p0;
+        hdr[7] = (int32_t)size;
+        hdr[8] = 0;   // size of the next batch of the run (patched by the next batch)
+        hdr[9] = 0;   // rows of the next batch
+        hdr[10] = 0;  // older inputs of the next batch (their rows follow ext_idx)
+        int32_t *lev_off = hdr + kSweepHdr;
+        int32_t *rowid = lev_off + nlev + 1;
+        int32_t *eptr = rowid + npos;
+        int32_t *ext_idx = eptr + npos + 1;
+        uint16_t *eslot = reinterpret_cast<uint16_t *>(ext_idx + next + kSweepExt);
+        int64_t off_val =
+            4 * kSweepHdr + 4 * (nlev + 1) + 4 * npos + 4 * (npos + 1) + 4 * next + 4 * kSweepExt + 2 * nent;
+        off_val = (off_val + 7) & ~(int64_t)7;
+        double *eval = reinterpret_cast<double *>(b + off_val);
+        double *dg = eval + nent;
+        for (int32_t l = l0; l <= l1; ++l) lev_off[l - l0] = lv.ptr[l] - p0;
+        for (int64_t j = 0; j < next; ++j) ext_idx[j] = ext[(size_t)j];
+        int32_t e = 0;
+        for (int32_t p = p0; p < p1; ++p) {
+            const int32_t row = lv.rows[p];
+            rowid[p - p0] = row;
+            eptr[p - p0] = e;
+            for (int32_t k = T.ptr[row]; k < T.ptr[(size_t)row + 1]; ++k, ++e) {
+                const int32_t c = T.col[k], pc = posof[c];
+                int32_t slot;
+                if (pc >= p0)
+                    slot = cur_base + (pc - p0);
+                else if (pc >= prev_p0 && pc < prev_p1)
+                    slot = prev_base + (pc - prev_p0);
+                else
+                    slot = 2 * kSweepPos + ext_slot[c];
+                eslot[e] = (uint16_t)slot;
+                eval[e] = T.val[k];
+            }
+            if (hd) dg[p - p0] = (*diag)[row];
+        }
+        eptr[npos] = e;
+        // the previous batch of the run learns this batch's size
+        if (bi > 0) {
+            int32_t *ph = reinterpret_cast<int32_t *>(sw.blob.data() + sw.batch_off[(size_t)nbatches() - 1]);
+            ph[8] = (int32_t)size;
+            ph[9] = npos;
+            ph[10] = (int32_t)next;
+            // the previous blob carries this batch's older inputs, so they are
+            // gathered while the previous batch is being solved
+            int32_t *pnext = ph + kSweepHdr + (ph[0] + 1) + ph[1] + (ph[1] + 1) + ph[3];
+            for (int64_t j = 0; j < next; ++j) pnext[j] = ext[(size_t)j];
+        }
+        sw.batch_off.push_back((int64_t)sw.blob.size());
+        prev_p0 = p0;
+        prev_p1 = p1;
+    };
+
+    auto close_batch = [&]() {
+        if (bl0 >= 0) serialize(bl0, bl1);
+        bl0 = -1;
+    };
+    auto close_run = [&]() {
+        close_batch();
+        if (run_b0 >= 0 && nbatches() > run_b0) sw.segs.push_back({-1, run_b0, nbatches()});
+        run_b0 = -1;
+        prev_p0 = prev_p1 = -1;
+    };
+    auto fits = [&](int64_t nlev, int64_t npos, int64_t nent, int64_t next) {
+        return npos <= kSweepPos && next <= kSweepExt && blob_bytes(nlev, npos, nent, next, hd) <= kSweepBlob;
+    };
+    for (int32_t l = 0; l < lv.nlev(); ++l) {
+        const int64_t w = lv.ptr[(size_t)l + 1] - lv.ptr[l];
+        const int64_t ne = entries(l);
+        if (w > kSweepRows || ne > kSweepLevEnt) {
+            close_run();
+            sw.segs.push_back({l, -1, -1});
+            continue;
+        }
+        if (bl0 >= 0) {
+            // extend the open batch with level l if it still fits
+            ++stamp;
+            int64_t ext_now = 0;
+            for (int32_t ll = bl0; ll <= l; ++ll) ext_now += new_ext(ll, lv.ptr[bl0]);
+            if (fits(l - bl0 + 1, bpos + w, bent + ne, ext_now)) {
+                bl1 = l + 1;
+                bpos += w;
+                bent += ne;
+                bext = ext_now;
+                continue;
+            }
+            close_batch();
+        }
+        // start a new batch with level l (the previous batch is now the last closed one)
+        ++stamp;
+        const int64_t e1 = new_ext(l, lv.ptr[l]);
+        if (!fits(1, w, ne, e1)) {
+            close_run();
+            sw.segs.push_back({l, -1, -1});
+            continue;
+        }
+        if (run_b0 < 0) run_b0 = nbatches();
+        bl0 = l;
+        bl1 = l + 1;
+        bpos = w;
+        bent = ne;
+        bext = e1;
+    }
+    close_run();
+    (void)bext;
+    return sw;
+}
+
 int32_t lanes_for(double avg)
 {
     int32_t g = 2;
@@ -185,7 +381,7 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     if (P.p < 0 || !(P.tau >= 0.0) || !(P.mu > 0.0 && P.mu <= 1.0) || !(P.small > 0.0) ||
         !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE) ||
-        (P.trsv != RSILU_TRSV_SYNCFREE && P.trsv != RSILU_TRSV_LEVELS))
+        (P.trsv != RSILU_TRSV_SYNCFREE && P.trsv != RSILU_TRSV_LEVELS && P.trsv != RSILU_TRSV_HYBRID))
         return RSILU_EINVAL;
     if (rowptr[0] != 0 || rowptr[m] > kMaxIdx) return RSILU_EINVAL;
 
@@ -416,6 +612,9 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.chL1 = make_chunks(c.lvL1, 64 / tri_lanes(c.L1));
     c.chL1T = make_chunks(c.lvL1T, 64 / tri_lanes(c.L1T));
     c.chU = make_chunks(c.lvU, 64 / tri_lanes(c.U));
+    c.swL1 = make_sweep(c.L1, nullptr, c.lvL1);
+    c.swL1T = make_sweep(c.L1T, nullptr, c.lvL1T);
+    c.swU = make_sweep(c.U, &c.Udiag, c.lvU);
 
     // ---- S^ (Section 3.2)
     c.smode = P.smode;
@@ -504,9 +703,11 @@ DevPlanOff place_plan(Bump &b, const SpmvPlan &pl)
     return o;
 }
 
-DevTriOff place_tri(Bump &b, const Csr &a, bool diag, const Levels &lv, const Chunks &ch, size_t n)
+DevTriOff place_tri(Bump &b, const Csr &a, bool diag, const Levels &lv, const Chunks &ch, const Sweep &sw,
+                    size_t n)
 {
     DevTriOff o;
+    o.blob = b.take(sw.blob.size());
     o.a = place_csr(b, a);
     o.diag = diag ? b.take(sizeof(double) * n) : 0;
     o.rows = b.take(sizeof(int32_t) * lv.rows.size());
@@ -533,9 +734,9 @@ void plan_layout(Ctx &c)
     L.pAT = place_plan(b, c.plAT);
     L.pL2 = place_plan(b, c.plL2);
     L.pL2T = place_plan(b, c.plL2T);
-    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, n);
-    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, n);
-    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, n);
+    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, n);
+    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, n);
+    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, n);
     L.perm = b.take(sizeof(int32_t) * m);
     L.colnorm = b.take(sizeof(double) * n);
     L.sfac = b.take(sizeof(double) * c.sfac.size());
@@ -543,6 +744,8 @@ void plan_layout(Ctx &c)
     L.r = b.take(sizeof(double) * m);
     L.q = b.take(sizeof(double) * m);
     L.u = b.take(sizeof(double) * std::max<size_t>(k, 1));
+    L.lo_rhs = b.take(sizeof(double) * n);
+    L.lo_add = b.take(sizeof(double) * n);
     // one partial per block of the largest reduction, plus one per long row
     L.npartials = 65536;
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);

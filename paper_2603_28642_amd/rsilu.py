@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "librsilu.so")
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ESTATE, EINTERNAL = -1, -2, -3, -4, -5
 S_AUTO, S_IDENTITY, S_DENSE = -1, 0, 1
-TRSV_SYNCFREE, TRSV_LEVELS = 0, 1
+TRSV_SYNCFREE, TRSV_LEVELS, TRSV_HYBRID = 0, 1, 2
 # factor / level selectors
 L1, L2, U, AHAT, UDIAG = 0, 1, 2, 3, 4
 LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
