@@ -1,10 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark: preconditioned least-squares solves per second on one MI355X.
 
-A step is one whole solve (Algorithm 1 with Algorithm 3, every kernel on the
-GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from b resident in
-HBM to x in HBM with the iteration count and ||A^T r|| on the host. Setup (the
-host ILUP) is done once, outside the timed region.
+A step is one whole solve (Algorithm 1 with its preconditioning step, every
+kernel on the GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from
+b resident in HBM to x in HBM with the iteration count and ||A^T r|| on the
+host. Setup (the host ILUP) is done once, outside the timed region.
+
+The default preconditioning step is Algorithm 2 with k = n on z = A^T r and
+M_a = (L1 U)^T (L1 U) from the ILUP(10, 1e-2) factors (mu = 1), without the
+M_b correction: on this workload it reaches ||A^T r|| <= 1e-8 ||A^T b||,
+whereas Algorithm 3 on the residual stalls near its starting residual
+(--form alg3 runs it; the solve then ends at maxit or on a breakdown).
 
 Prints one JSON line with the throughput, p50/p99 latency, the roofline of the
 dominant kernel (HIP events recorded by the library on the solve's stream over
@@ -38,41 +44,73 @@ def parse():
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--maxit", type=int, default=2000)
-    ap.add_argument("--smode", default="identity", choices=["identity", "dense", "auto"])
+    ap.add_argument("--smode", default="none", choices=["none", "identity", "dense", "auto"])
+    ap.add_argument("--form", default="alg2", choices=["alg2", "alg3"])
     ap.add_argument("--trsv", default="hybrid", choices=["hybrid", "syncfree", "levels"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (three of them) and exit: the known-size "
+                         "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
-def kernel_bytes(st, cls):
-    """Algorithmic HBM bytes of one launch of a kernel class: FP64 values and int32
-    indices streamed once, row pointers and level lists once, every vector read or
-    written once (a gathered vector counted once)."""
+def copy_probe(mib):
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.randn(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "copies": 3}), flush=True)
+
+
+def step_bytes(st):
+    """Algorithmic HBM bytes of one use of each step: stored FP64 values and int32
+    column indices read once, row pointers once, a triangular solve's level list,
+    right-hand side and result once per row (plus its diagonal, and a fused addend
+    and sum), every other vector read or written once."""
     m, n = st.m, st.n
     k = m - n
     a, l1, l2, u = st.nnz_a, st.nnz_l1, st.nnz_l2, st.nnz_u
+    tri = 24 * n  # pointer, level-list entry, rhs, result per row
     return {
         "spmv_A": 12 * a + 4 * (m + 1) + 8 * n + 8 * m,
         "spmv_AT": 12 * a + 4 * (n + 1) + 8 * m + 8 * n + 8 * n,
-        "trsv_L1": 12 * l1 + 4 * (n + 1) + 4 * n + 8 * n * 3,
-        "trsv_L1T": 12 * l1 + 4 * (n + 1) + 4 * n + 8 * n * 3 + 16 * n,
-        "trsv_U": 12 * u + 4 * (n + 1) + 4 * n + 8 * n * 3 + 8 * n,
-        "spmv_L2": 12 * l2 + 4 * (k + 1) + 8 * n + 16 * k,
+        "trsv_L1": 12 * l1 + tri,
+        "trsv_L1T": 12 * l1 + tri,
+        "trsv_L1T_fused": 12 * l1 + tri + 16 * n,
+        "trsv_U": 12 * u + tri + 8 * n,
+        "trsv_UT": 12 * u + tri + 8 * n,
+        "spmv_L2": 12 * l2 + 4 * (k + 1) + 8 * n + 8 * k,
+        "spmv_L2_sub": 12 * l2 + 4 * (k + 1) + 8 * n + 16 * k,
         "spmv_L2T": 12 * l2 + 4 * (n + 1) + 8 * k + 8 * n,
-        "dense_S": 8 * k * (k + 1) + 32 * k,
-    }[cls]
+        "dense_S": 8 * k * (k + 1) + 16 * k,
+        # x += alpha p, r -= alpha q; rho = (z, h); p = h + beta p
+        "vectors": 8 * (3 * n + 3 * m) + 16 * n + 24 * n,
+    }
 
 
-def iteration_bytes(st, dense):
-    """Algorithmic bytes of one iteration: 2 products with A, 3 sweeps of L1, 2 of L2,
-    1 of U, row pointers, level lists and about 32 vector passes."""
-    m, n = st.m, st.n
-    b = 12 * (2 * st.nnz_a + 3 * st.nnz_l1 + 2 * st.nnz_l2 + st.nnz_u) + 4 * (2 * m + 5 * n) + 16 * n \
-        + 8 * (24 * n + 5 * m + 3 * (m - n))
-    if dense:
-        b += 8 * (m - n) * (m - n + 1)
-    return b
+def iteration_bytes(st, form, smode):
+    """Algorithmic bytes of one iteration of Algorithm 1 with the given form."""
+    b = step_bytes(st)
+    k = st.m - st.n
+    it = b["spmv_A"] + b["spmv_AT"] + b["vectors"]
+    corr = k > 0 and smode != "none"
+    if form == "alg3":
+        it += b["trsv_L1"] + b["trsv_U"]
+        if corr:
+            it += b["spmv_L2_sub"] + b["spmv_L2T"] + b["trsv_L1T_fused"] + b["trsv_L1"]
+    else:
+        it += b["trsv_UT"] + b["trsv_L1T"] + b["trsv_L1"] + b["trsv_U"]
+        if corr:
+            it += b["trsv_L1"] + b["spmv_L2"] + b["spmv_L2T"] + b["trsv_L1T_fused"]
+    if corr and smode == "dense":
+        it += b["dense_S"]
+    return it
 
 
 def cpu_baseline(prob, args, iters_per_solve):
@@ -85,15 +123,15 @@ def cpu_baseline(prob, args, iters_per_solve):
 
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu,
-                                  smode="dense" if args.smode == "dense" else "identity")
+        smode = args.smode if args.smode != "auto" else ("dense" if 0 < prob.m - prob.n <= 4096 else "identity")
+        F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
-        oracle.pcgls(F, prob.b, tol=0.0, maxit=2)
+        oracle.pcgls(F, prob.b, tol=0.0, maxit=2, form=args.form)
         est = max((time.perf_counter() - t0) / 2.0, 1e-6)
         k = int(max(2, min(iters_per_solve if iters_per_solve > 0 else 2, args.cpu_seconds / est)))
         t0 = time.perf_counter()
-        res = oracle.pcgls(F, prob.b, tol=0.0, maxit=k)
+        res = oracle.pcgls(F, prob.b, tol=0.0, maxit=k, form=args.form)
         t = time.perf_counter() - t0
     per_iter = t / max(res.iters, 1)
     per_solve = per_iter * max(iters_per_solve, 1)
@@ -111,7 +149,7 @@ def cpu_baseline(prob, args, iters_per_solve):
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "oracle Algorithm 1 + Algorithm 3 (plain C substitutions, numpy vectors, 1 thread) on the same "
+        "sample": "oracle Algorithm 1 + Algorithm " + args.form[-1] + " (plain C substitutions, numpy vectors, 1 thread) on the same "
                   "workload: %d iterations timed (%.1f s, %.1f ms/iteration), scaled to the %d iterations of one "
                   "GPU solve; oracle setup %.1f s not counted; host %s, nproc %d"
                   % (res.iters, t, per_iter * 1e3, iters_per_solve, t_setup, cpu, os.cpu_count() or 0),
@@ -126,6 +164,10 @@ def main():
               "GPUs (independent solves shard with no communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+
     import numpy as np
     import torch
 
@@ -134,10 +176,12 @@ def main():
 
     torch.cuda.set_device(0)
     prob = gen.by_name(args.workload)
-    smode = {"identity": R.S_IDENTITY, "dense": R.S_DENSE, "auto": R.S_AUTO}[args.smode]
+    smode = {"none": R.S_NONE, "identity": R.S_IDENTITY, "dense": R.S_DENSE, "auto": R.S_AUTO}[args.smode]
     trsv = {"hybrid": R.TRSV_HYBRID, "syncfree": R.TRSV_SYNCFREE, "levels": R.TRSV_LEVELS}[args.trsv]
+    form = {"alg2": R.FORM_ALG2, "alg3": R.FORM_ALG3}[args.form]
     t0 = time.perf_counter()
-    S = R.Solver.from_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit, trsv=trsv)
+    S = R.Solver.from_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit, trsv=trsv,
+                              form=form)
     t_setup = time.perf_counter() - t0
     S.upload()
     st = S.stats
@@ -165,14 +209,17 @@ def main():
     R.rsilu_set_profiling(S.h, 0)
     _, code, iters, atr, rel = result
 
-    # dominant kernel by total time in the timed region
-    dom = max(prof, key=lambda k: prof[k][1])
-    launches, ms = prof[dom]
+    # dominant kernel by total time in the timed region (single-kernel classes; the
+    # library adds up the algorithmic bytes of every timed launch)
+    kernels = [k for k in R.PROF_NAMES if k not in R.PROF_STEPS]
+    dom = max(kernels, key=lambda k: prof[k][1])
+    launches, ms, kbytes = prof[dom]
     avg_s = (ms / 1e3) / max(launches, 1)
-    kb = kernel_bytes(st, dom)
+    kb = kbytes / max(launches, 1)
     achieved = kb / avg_s if avg_s > 0 else 0.0
     t_solve = total / args.steps
-    b_solve = (iters + 1) * iteration_bytes(st, st.smode == R.S_DENSE)
+    smode_used = {R.S_NONE: "none", R.S_IDENTITY: "identity", R.S_DENSE: "dense"}[st.smode]
+    b_solve = (iters + 1) * iteration_bytes(st, args.form, smode_used)
     status = {R.OK: "converged", R.NOT_CONVERGED: "not_converged", R.BREAKDOWN: "breakdown"}.get(code, str(code))
 
     out = {
@@ -192,8 +239,8 @@ def main():
             "workload": prob.name + " (%s)" % args.workload,
             "nnz": int(st.nnz_a),
             "ilup": {"p": args.p, "tau": args.tau, "mu": args.mu, "small": 1e-10},
-            "S": "dense" if st.smode == R.S_DENSE else "identity",
-            "krylov": "Algorithm 1 (PCGLS) + Algorithm 3",
+            "S": smode_used,
+            "krylov": "Algorithm 1 (PCGLS) + Algorithm %s" % args.form[-1],
             "trsv": args.trsv,
             "tol": args.tol,
             "maxit": args.maxit,
@@ -202,7 +249,7 @@ def main():
             "atr_rel": rel,
             "factors": {"nnz_l1": int(st.nnz_l1), "nnz_l2": int(st.nnz_l2), "nnz_u": int(st.nnz_u),
                         "levels_l1": int(st.levels_l1), "levels_l1t": int(st.levels_l1t),
-                        "levels_u": int(st.levels_u), "nmod": int(st.nmod)},
+                        "levels_u": int(st.levels_u), "levels_ut": int(st.levels_ut), "nmod": int(st.nmod)},
             "setup_s": t_setup,
         },
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
@@ -219,8 +266,9 @@ def main():
             "bytes_per_launch": kb,
             "avg_launch_us": avg_s * 1e6,
             "launches": launches,
-            "kernel_ms_share": {k: round(v[1] / max(sum(w[1] for w in prof.values()), 1e-12), 4)
-                                for k, v in prof.items() if v[0]},
+            "step_ms_share": {k: round(prof[k][1] / max(sum(prof[w][1] for w in R.PROF_STEPS), 1e-12), 4)
+                              for k in R.PROF_STEPS if prof[k][0]},
+            "kernel_avg_us": {k: round(1e3 * prof[k][1] / prof[k][0], 2) for k in kernels if prof[k][0]},
         },
     }
     if not args.no_cpu:

@@ -10,9 +10,18 @@
  *   P A D ~ [L1; L2] U                                            (3.8)
  * with D the column scaling, L1 unit lower triangular (n x n), L2 (m-n) x n
  * and U upper triangular. The solve (rsilu_solve) runs entirely on the GPU:
- * the left-preconditioned CGLS of Algorithm 1 with the preconditioner applied
- * by Algorithm 3 (u = r2 - Y r1, S^ w = u, y = r1 + Y^T w, L1 v = y, U h = v,
- * Y = L2 L1^{-1} applied implicitly, S^ = I or the dense S~ = I + Y Y^T).
+ * the left-preconditioned CGLS of Algorithm 1. Its preconditioning step
+ * h = M^{-1} A^T r is evaluated in one of two forms (rsilu_params_t.form):
+ *   - Algorithm 3 on the residual components (the default): u = r2 - Y r1,
+ *     S^ w = u, y = r1 + Y^T w, L1 v = y, U h = v, with Y = L2 L1^{-1}
+ *     applied implicitly and S^ = I, the dense S~ = I + Y Y^T, or no
+ *     correction at all;
+ *   - Algorithm 2 with k = n on z = A^T r: M_a = (L1 U)^T (L1 U) stands for
+ *     C1 = A1^T A1 and A2 for its factored image L2 U, so that
+ *     h = U^{-1} L1^{-1} (I - Y^T S^{-1} Y) L1^{-T} U^{-T} z; with the dense
+ *     S~ this is (A~^T A~)^{-1} z for A~ = [L1; L2] U, and without the
+ *     correction it is (L1 U)^{-1} (L1 U)^{-T} z. Either way M^{-1} is
+ *     symmetric positive definite, which Algorithm 1 assumes of it.
  *
  * Conventions for every call
  *   - Indices are 0-based. Host arrays are owned by the caller and only read
@@ -51,11 +60,21 @@ typedef enum {
     RSILU_EINTERNAL = -5     /* a kernel hit its internal wait bound */
 } rsilu_status_t;
 
-/* S^ used in step 2 of Algorithm 3 (Section 3.2). */
+/* S^ used in step 2 of Algorithm 3 / M_b in step 3 of Algorithm 2
+ * (Section 3.2). */
 enum {
     RSILU_S_AUTO = -1,    /* dense when m - n <= 4096, identity otherwise */
     RSILU_S_IDENTITY = 0, /* S^ = I: w = u */
-    RSILU_S_DENSE = 1     /* S~ = I + Y Y^T assembled and Cholesky-factored once */
+    RSILU_S_DENSE = 1,    /* S~ = I + Y Y^T assembled and Cholesky-factored once */
+    RSILU_S_NONE = 2      /* no A2 correction: w = 0, so that Algorithm 3 gives
+                             h = U^{-1} L1^{-1} r1 and Algorithm 2 gives
+                             h = M_a^{-1} z */
+};
+
+/* Form of the preconditioning step of Algorithm 1 (see the top of this file). */
+enum {
+    RSILU_FORM_ALG3 = 0, /* Algorithm 3 on (r1, r2) (default) */
+    RSILU_FORM_ALG2 = 1  /* Algorithm 2, k = n, on z = A^T r */
 };
 
 /* Schedule of the sparse triangular solves with L1, L1^T and U. */
@@ -77,6 +96,7 @@ typedef struct {
     int32_t maxit;    /* Algorithm 1 iteration limit; 2000 (Section 5.1) */
     int32_t trsv;     /* RSILU_TRSV_*; default RSILU_TRSV_HYBRID */
     int32_t poll;     /* iterations enqueued between host polls of the stop flag; 8 */
+    int32_t form;     /* RSILU_FORM_*; default RSILU_FORM_ALG3 */
 } rsilu_params_t;
 
 typedef struct {
@@ -91,7 +111,7 @@ typedef struct {
     int32_t levels_l1t;    /* ... of the L1^T backward solve */
     int32_t levels_u;      /* ... of the U backward solve */
     int32_t levels_ut;     /* ... of the U^T forward solve */
-    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY or RSILU_S_DENSE) */
+    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY, _DENSE or _NONE) */
     int32_t reserved;
     size_t device_bytes;   /* what rsilu_upload needs */
 } rsilu_stats_t;
@@ -100,7 +120,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
- * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8. */
+ * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting
@@ -156,7 +176,7 @@ rsilu_status_t rsilu_get_factor(rsilu_handle_t h, int32_t which, int64_t *rowptr
 rsilu_status_t rsilu_get_levels(rsilu_handle_t h, int32_t which, int32_t *level_ptr,
                                 int32_t *level_rows);
 
-/* Algorithm 1 with Algorithm 3 (after rsilu_upload).
+/* Algorithm 1 with the configured preconditioning form (after rsilu_upload).
  * b_dev[m]: the right-hand side in the original row order (device, read only).
  * x_dev[n]: the solution in the user's coordinates (device, written); must not
  * alias b_dev. Starts from x = 0 and stops when ||A^T r|| <= tol ||A^T b||
@@ -177,33 +197,47 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b_dev, double tol, do
  *                 1  y[n] = A_hat^T x[m]      (Algorithm 1, z = A^T r)
  *                 2  y[m-n] = L2 x[n]         (Algorithm 3, Y r1 = L2 L1^{-1} r1)
  *                 3  y[n] = L2^T x[m-n]       (Algorithm 3, Y^T w = L1^{-T} L2^T w)
- * rsilu_trsv, which: 0  L1 x = rhs   1  L1^T x = rhs   2  U x = rhs   (n-vectors)
- * rsilu_apply: h[n] from the residual r[m] by Algorithm 3.
+ * rsilu_trsv, which: 0  L1 x = rhs   1  L1^T x = rhs   2  U x = rhs
+ *                   3  U^T x = rhs (Algorithm 2, M_a = (L1 U)^T (L1 U))  (n-vectors)
+ * rsilu_apply:   h[n] from the residual r[m] by Algorithm 3.
+ * rsilu_apply_z: h[n] = M^{-1} z[n] by Algorithm 2 (k = n, as above).
+ * Both use the handle's S^ mode, whatever its form.
  * x and y (rhs and x) must not alias. EINVAL for a bad op/which or NULL. */
 rsilu_status_t rsilu_spmv(rsilu_handle_t h, int32_t op, const double *x_dev, double *y_dev,
                           hipStream_t stream);
 rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs_dev, double *x_dev,
                           hipStream_t stream);
 rsilu_status_t rsilu_apply(rsilu_handle_t h, const double *r_dev, double *h_dev, hipStream_t stream);
+rsilu_status_t rsilu_apply_z(rsilu_handle_t h, const double *z_dev, double *h_dev, hipStream_t stream);
 
-/* Kernel timing with HIP events recorded on the solve's stream around every
- * launch of the classes below, accumulated over all rsilu_solve calls made
- * while enabled (rsilu_set_profiling resets the counters). */
+/* Kernel timing with HIP events recorded on the solve's stream, accumulated
+ * over all rsilu_solve calls made while enabled (rsilu_set_profiling resets
+ * the counters). Classes 0-8 time whole steps of an iteration (a triangular
+ * solve is several kernel launches); classes 9-11 time single kernels, one
+ * event pair per launch, and their `bytes` are the algorithmic bytes of the
+ * timed launches: every stored value (8 B) and index (4 B) of the rows they
+ * solve read once, and each row's right-hand side, result (and fused
+ * addend and sum) once. */
 enum {
-    RSILU_PROF_SPMV_A = 0,   /* q = A_hat p (with its norm partials) */
-    RSILU_PROF_SPMV_AT = 1,  /* z = A_hat^T r (with its norm partials) */
-    RSILU_PROF_TRSV_L1 = 2,  /* L1 forward solves (two per iteration) */
-    RSILU_PROF_TRSV_L1T = 3, /* L1^T backward solve fused with y = r1 + g' */
-    RSILU_PROF_TRSV_U = 4,   /* U backward solve */
-    RSILU_PROF_SPMV_L2 = 5,  /* u = r2 - L2 t */
-    RSILU_PROF_SPMV_L2T = 6, /* g = L2^T w */
-    RSILU_PROF_DENSE_S = 7,  /* dense S~ solves */
-    RSILU_PROF_COUNT = 8
+    RSILU_PROF_SPMV_A = 0,    /* q = A_hat p (with its norm partials) */
+    RSILU_PROF_SPMV_AT = 1,   /* z = A_hat^T r (with its norm partials) */
+    RSILU_PROF_TRSV_L1 = 2,   /* L1 forward solves */
+    RSILU_PROF_TRSV_L1T = 3,  /* L1^T backward solves */
+    RSILU_PROF_TRSV_U = 4,    /* U backward solves */
+    RSILU_PROF_SPMV_L2 = 5,   /* products with L2 */
+    RSILU_PROF_SPMV_L2T = 6,  /* products with L2^T */
+    RSILU_PROF_DENSE_S = 7,   /* dense S~ solves */
+    RSILU_PROF_TRSV_UT = 8,   /* U^T forward solves (Algorithm 2 form) */
+    RSILU_PROF_K_SWEEP = 9,   /* launches of the single-workgroup sweep kernel */
+    RSILU_PROF_K_LEVEL = 10,  /* launches of the one-level kernel (hybrid schedule) */
+    RSILU_PROF_K_GATHER = 11, /* level-order gathers ahead of the sweeps */
+    RSILU_PROF_COUNT = 12
 };
 
 typedef struct {
     int64_t launches[RSILU_PROF_COUNT];
     double ms[RSILU_PROF_COUNT];
+    double bytes[RSILU_PROF_COUNT]; /* algorithmic bytes (kernel classes only) */
 } rsilu_profile_t;
 
 rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable);

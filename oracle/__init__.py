@@ -4,6 +4,7 @@ from .reference import (  # noqa: F401
     CSR,
     Factors,
     SolveResult,
+    apply_alg2,
     apply_alg3,
     csr_from_scipy,
     dense_S,

@@ -14,8 +14,12 @@ It follows the paper step by step:
   * dense_S             S~ = I + Y~ Y~^T with Y~ = L2 L1^{-1}, (3.9), factored
                         once by Cholesky (Section 3.2)
   * apply_alg3          Algorithm 3 on the residual components (r1, r2)
+  * apply_alg2          Algorithm 2 with k = n on z = A^T r, M_a = (L1 U)^T
+                        (L1 U) standing for C1 and A2 for its factored image
+                        L2 U (Section 3.3 gives Y~ = L2 L1^{-1} in that sense)
   * pcgls               Algorithm 1 (left-preconditioned, factorization-free
-                        CGLS) with Algorithm 3 in place of h = M^{-1} A^T r
+                        CGLS) with Algorithm 3 (or Algorithm 2) in place of
+                        h = M^{-1} A^T r
 The method does not converge to anything faster than it converges; its limit
 is the least-squares solution, which the tests pin with dense QR.
 """
@@ -312,7 +316,7 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
     }
     if smode == "dense":
         _, F.S_chol = dense_S(L1, L2)
-    elif smode != "identity":
+    elif smode not in ("identity", "none"):
         raise ValueError(smode)
     return F
 
@@ -334,6 +338,9 @@ def apply_alg3(F, r):
     n = F.n
     r1, r2 = r[:n], r[n:]
     t = lower_solve(F.L1, r1)
+    if F.smode == "none" or F.m == n:
+        # no correction (w = 0): y = r1
+        return upper_solve(F.U, t, F.Udiag)
     u = r2 - F.L2.matvec(t)
     if F.smode == "dense":
         w = sla.cho_solve((F.S_chol, True), u)
@@ -343,6 +350,38 @@ def apply_alg3(F, r):
     y = r1 + upper_solve(F.L1T, g)
     v = lower_solve(F.L1, y)
     return upper_solve(F.U, v, F.Udiag)
+
+
+def _ma_solve(F, v):
+    """M_a^{-1} v for M_a = (L1 U)^T (L1 U): U^T s = v, L1^T t = s, L1 w = t, U h = w."""
+    s = lower_solve(F.UT, v, F.Udiag)
+    t = upper_solve(F.L1T, s)
+    w = lower_solve(F.L1, t)
+    return upper_solve(F.U, w, F.Udiag)
+
+
+def apply_alg2(F, z):
+    """Algorithm 2 with k = n on z = A_hat^T r (pivot-order coordinates).
+
+    Step 1 solves M_a u_a = z; step 2 forms w_b = A2 u_a; step 3 solves
+    M_b v_b = w_b; step 4 forms w_a = z - A2^T v_b (the paper's printed
+    "u_a - A2^T v_b" contradicts (3.1)-(3.3); z is what the Woodbury form
+    needs); step 5 solves M_a h = w_a. Here M_a = (L1 U)^T (L1 U), A2 is
+    represented by L2 U (its image under the incomplete factorization, so
+    that A2 M_a^{-1} A2^T = Y~ Y~^T), and M_b is S~ (dense mode), I
+    (identity mode) or absent (none mode: v_b = 0, h = u_a).
+    """
+    ua = _ma_solve(F, z)
+    if F.smode == "none" or F.m == F.n:
+        return ua
+    wb = F.L2.matvec(F.U.matvec(ua) + F.Udiag * ua)
+    if F.smode == "dense":
+        vb = sla.cho_solve((F.S_chol, True), wb)
+    else:
+        vb = wb
+    s = F.L2T.matvec(vb)
+    wa = z - (F.UT.matvec(s) + F.Udiag * s)
+    return _ma_solve(F, wa)
 
 
 @dataclass
@@ -366,8 +405,9 @@ def true_residual(A, b, x):
     return atr, (atr / atb if atb > 0 else 0.0)
 
 
-def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False):
-    """Algorithm 1 on A_hat x_hat ~ P b with h = B(r) from Algorithm 3.
+def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False, form="alg3"):
+    """Algorithm 1 on A_hat x_hat ~ P b with h = B(r) from Algorithm 3
+    (form "alg3"), or h = M^{-1} z from Algorithm 2 (form "alg2").
 
     Initialisation: x0 = 0, r0 = P b, z0 = A_hat^T r0, h0 = B(r0),
     rho0 = (z0, h0), p0 = h0. Iteration i: q = A_hat p, alpha = rho/(q,q),
@@ -376,7 +416,15 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False):
     else h = B(r), rho' = (z,h), beta = rho'/rho, p = h + beta p.
     Breakdown: (q,q) = 0, rho' = 0 or a non-finite scalar.
     """
-    apply = apply or apply_alg3
+    if apply is None:
+        if form == "alg2":
+            def apply(F_, r_, z_):
+                return apply_alg2(F_, z_)
+        elif form == "alg3":
+            def apply(F_, r_, z_):
+                return apply_alg3(F_, r_)
+        else:
+            raise ValueError(form)
     b = _c(b, np.float64)
     n = F.n
     r = b[F.perm.astype(np.int64)].copy()
@@ -390,7 +438,7 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False):
     if nb == 0.0:
         status = "ok"
     else:
-        h = apply(F, r)
+        h = apply(F, r, z)
         rho = float(np.dot(z, h))
         p = h.copy()
         if rho == 0.0 or not math.isfinite(rho):
@@ -417,7 +465,7 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False):
                     break
                 if it == maxit:
                     break
-                h = apply(F, r)
+                h = apply(F, r, z)
                 rho_new = float(np.dot(z, h))
                 if rho_new == 0.0 or not math.isfinite(rho_new):
                     status = "breakdown"

@@ -1,5 +1,5 @@
 // C ABI of the library and the device driver of the solve (Algorithm 1 with
-// Algorithm 3), enqueued on the caller's stream. The host only enqueues work
+// Algorithm 3 or Algorithm 2), enqueued on the caller's stream. The host only enqueues work
 // and polls a stop flag every `poll` iterations; every scalar of the
 // recurrence lives on the device.
 #include <algorithm>
@@ -53,7 +53,7 @@ DTri dtri(const Ctx &c, const DevTriOff &o)
 // HIP events around one launch group of a profiled class (rsilu_set_profiling).
 class ProfScope {
 public:
-    ProfScope(Ctx &c, hipStream_t s, int cls) : c_(c), s_(s), cls_(cls)
+    ProfScope(Ctx &c, hipStream_t s, int cls, double bytes = 0.0) : c_(c), s_(s), cls_(cls), bytes_(bytes)
     {
         if (!c_.prof) return;
         while (c_.ev_next + 2 > c_.ev_pool.size()) {
@@ -72,13 +72,14 @@ public:
     {
         if (idx_ < 0) return;
         if (hipEventRecord(static_cast<hipEvent_t>(c_.ev_pool[(size_t)idx_ + 1]), s_) == hipSuccess)
-            c_.ev_open.push_back({cls_, idx_, c_.ev_iter});
+            c_.ev_open.push_back({cls_, idx_, c_.ev_iter, bytes_});
     }
 
 private:
     Ctx &c_;
     hipStream_t s_;
     int cls_;
+    double bytes_;
     int idx_ = -1;
 };
 
@@ -93,6 +94,7 @@ void prof_collect(Ctx &c, int completed_iters)
                                 static_cast<hipEvent_t>(c.ev_pool[(size_t)r.idx + 1])) == hipSuccess) {
             c.prof_ms[r.cls] += ms;
             c.prof_launches[r.cls] += 1;
+            c.prof_bytes[r.cls] += r.bytes;
         }
     }
     c.ev_open.clear();
@@ -106,10 +108,10 @@ struct Ptrs {
     double *partials, *segpart;
     DCsr A, AT, L2, L2T;
     DPlan pA, pAT, pL2, pL2T;
-    DTri L1f, L1b, Ub;
+    DTri L1f, L1b, Ub, UTf;
     const int32_t *perm;
     const double *colnorm, *sfac;
-    double *xh, *p, *z, *h, *t, *y, *v, *g, *gp, *r, *q, *u;
+    double *xh, *p, *z, *h, *t, *y, *v, *g, *gp, *s2, *c2, *r, *q, *u;
     double *lo_rhs, *lo_add;
 };
 
@@ -132,6 +134,7 @@ Ptrs ptrs(const Ctx &c)
     P.L1f = dtri(c, L.L1f);
     P.L1b = dtri(c, L.L1b);
     P.Ub = dtri(c, L.Ub);
+    P.UTf = dtri(c, L.UTf);
     P.perm = at<int32_t>(c, L.perm);
     P.colnorm = at<double>(c, L.colnorm);
     P.sfac = at<double>(c, L.sfac);
@@ -144,6 +147,8 @@ Ptrs ptrs(const Ctx &c)
     P.v = at<double>(c, L.v);
     P.g = at<double>(c, L.g);
     P.gp = at<double>(c, L.gp);
+    P.s2 = at<double>(c, L.s2);
+    P.c2 = at<double>(c, L.c2);
     P.r = at<double>(c, L.r);
     P.q = at<double>(c, L.q);
     P.u = at<double>(c, L.u);
@@ -162,15 +167,25 @@ void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv,
     if (c.prm.trsv == RSILU_TRSV_HYBRID) {
         const unsigned char *blob = at<unsigned char>(c, o.blob);
         const bool runs = std::any_of(sw.segs.begin(), sw.segs.end(), [](const Sweep::Seg &g) { return g.wide_level < 0; });
-        if (runs) launch_gather_lo(s, (int32_t)c.n, t.rows, rhs, P.lo_rhs, add, y2 ? P.lo_add : nullptr, done);
+        // algorithmic bytes of a launch solving `rows` rows with `nnz` stored entries:
+        // values and column indices once, per row its pointer, level-list entry,
+        // right-hand side and result (plus diagonal, fused addend and sum)
+        const double per_row = 24.0 + (t.diag ? 8.0 : 0.0) + (y2 ? 16.0 : 0.0);
+        auto bytes = [&](int64_t rows, int64_t nnz) { return 12.0 * (double)nnz + per_row * (double)rows; };
+        if (runs) {
+            ProfScope pg(c, s, RSILU_PROF_K_GATHER, (double)c.n * (y2 ? 36.0 : 20.0));
+            launch_gather_lo(s, (int32_t)c.n, t.rows, rhs, P.lo_rhs, add, y2 ? P.lo_add : nullptr, done);
+        }
         for (const Sweep::Seg &g : sw.segs) {
             if (g.wide_level >= 0) {
+                ProfScope pk(c, s, RSILU_PROF_K_LEVEL, bytes(g.rows, g.nnz));
                 launch_trsv_level(s, t, lv.ptr[g.wide_level], lv.ptr[(size_t)g.wide_level + 1], rhs, x, add, y2,
                                   done);
             } else {
                 const int64_t off = sw.batch_off[(size_t)g.b0];
                 const int32_t size = (int32_t)(sw.batch_off[(size_t)g.b0 + 1] - off);
                 const int32_t *h0 = reinterpret_cast<const int32_t *>(sw.blob.data() + off);
+                ProfScope pk(c, s, RSILU_PROF_K_SWEEP, bytes(g.rows, g.nnz));
                 launch_trsv_sweep(s, blob, off, size, h0[1], h0[6], g.b1 - g.b0, P.lo_rhs, x, P.lo_add, y2, done);
             }
         }
@@ -191,8 +206,8 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *h
     const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
     // step 1: u = r2 - Y r1 with Y r1 = L2 (L1^{-1} r1)
     trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, r, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
-    if (k == 0) {
-        // no A2: h = U^{-1} L1^{-1} r1
+    if (k == 0 || c.smode == RSILU_S_NONE) {
+        // no A2 or no correction (w = 0): h = U^{-1} L1^{-1} r1
         trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.t, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
         return;
     }
@@ -216,6 +231,67 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *h
     trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
 }
 
+// Whether Algorithm 2 carries the M_b correction (six triangular sweeps
+// instead of four).
+bool alg2_correction(const Ctx &c) { return c.m > c.n && c.smode != RSILU_S_NONE; }
+
+// Sync-free outputs to sentinel-fill before one preconditioner application.
+void fill_targets(const Ctx &c, const Ptrs &P, double *hout, double *f[4])
+{
+    f[0] = P.t;
+    f[1] = P.gp;
+    f[2] = P.v;
+    f[3] = (c.prm.form == RSILU_FORM_ALG2 && alg2_correction(c)) ? P.c2 : hout;
+}
+
+// Algorithm 2 with k = n on z (pivot-order coordinates) -> hout, with
+// M_a = (L1 U)^T (L1 U) for C1 and A2 represented by L2 U:
+//   step 1  u_a = M_a^{-1} z, kept factored: g = L1^{-T} U^{-T} z, u_a = U^{-1} L1^{-1} g
+//   step 2  w_b = A2 u_a = L2 L1^{-1} g
+//   step 3  M_b v_b = w_b   (S~ dense, S^ = I, or skipped: v_b = 0)
+//   step 4  w_a = z - A2^T v_b = z - U^T L2^T v_b
+//   step 5  h = M_a^{-1} w_a = U^{-1} L1^{-1} (g - L1^{-T} L2^T v_b)
+// so U^{-T} of step 5 cancels the U^T of step 4 and g is shared.
+void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const double *z, double *hout, const int32_t *done)
+{
+    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
+    trsv(c, s, P, P.UTf, c.lvUT, c.swUT, c.lay.UTf, z, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_UT);
+    trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, P.t, P.gp, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_L1T);
+    if (!alg2_correction(c)) {
+        trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.gp, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+        trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+        return;
+    }
+    // step 2: w_b = L2 (L1^{-1} g) into u
+    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.gp, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_L2);
+        launch_spmv(s, P.L2, P.pL2, P.v, P.u, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, done);
+    }
+    // step 3: v_b = M_b^{-1} w_b in place
+    if (c.smode == RSILU_S_DENSE) {
+        ProfScope ps(c, s, RSILU_PROF_DENSE_S);
+        launch_dense_chol_solve(s, k, P.sfac, P.u, done);
+    }
+    // steps 4-5: y = g + L1^{-T} (-L2^T v_b), then L1 s2 = y, U h = s2
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
+        launch_spmv(s, P.L2T, P.pL2T, P.u, P.g, nullptr, EPI_NEG, FIN_NONE, P.partials, P.segpart, P.st, done);
+    }
+    trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, P.g, P.c2, P.gp, P.y, 3, done, RSILU_PROF_TRSV_L1T);
+    if (syncfree(c)) launch_refill(s, n, P.s2, hout, P.st, done);
+    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.y, P.s2, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
+    trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.s2, hout, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_U);
+}
+
+void apply_form(Ctx &c, hipStream_t s, const Ptrs &P, double *hout, const int32_t *done)
+{
+    if (c.prm.form == RSILU_FORM_ALG2)
+        apply_alg2(c, s, P, P.z, hout, done);
+    else
+        apply_alg3(c, s, P, P.r, hout, done);
+}
+
 void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
 {
     const int32_t n = (int32_t)c.n, m = (int32_t)c.m;
@@ -226,14 +302,16 @@ void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
     }
     // x += alpha p, r -= alpha q (and prepare the sync-free outputs)
     const bool sf = syncfree(c);
-    launch_update(s, n, m, P.p, P.xh, P.q, P.r, sf ? P.t : nullptr, P.gp, P.v, P.h, P.st, P.done);
+    double *f[4];
+    fill_targets(c, P, P.h, f);
+    launch_update(s, n, m, P.p, P.xh, P.q, P.r, sf ? f[0] : nullptr, f[1], f[2], f[3], P.st, P.done);
     // z = A^T r, stop test on ||D^{-1} z|| = ||A^T r||
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_AT);
         launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_STOP, P.partials, P.segpart, P.st, P.done);
     }
-    // h = M^{-1} z by Algorithm 3 on (r1, r2)
-    apply_alg3(c, s, P, P.r, P.h, P.done);
+    // h = M^{-1} z by Algorithm 3 on (r1, r2) or Algorithm 2 on z
+    apply_form(c, s, P, P.h, P.done);
     // rho' = (z, h), beta = rho'/rho, p = h + beta p
     launch_dot(s, n, P.z, P.h, FIN_BETA, P.partials, P.st, P.done);
     launch_pupdate(s, n, P.h, P.p, P.st, false, P.done);
@@ -258,6 +336,7 @@ void rsilu_params_default(rsilu_params_t *p)
     p->maxit = 2000;
     p->trsv = RSILU_TRSV_HYBRID;
     p->poll = 8;
+    p->form = RSILU_FORM_ALG3;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)
@@ -442,9 +521,11 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put_tri(L.L1f, c.L1, nullptr, c.lvL1, c.chL1));
     RSILU_HIP(put_tri(L.L1b, c.L1T, nullptr, c.lvL1T, c.chL1T));
     RSILU_HIP(put_tri(L.Ub, c.U, &c.Udiag, c.lvU, c.chU));
+    RSILU_HIP(put_tri(L.UTf, c.UT, &c.Udiag, c.lvUT, c.chUT));
     RSILU_HIP(put_sweep(L.L1f, c.swL1));
     RSILU_HIP(put_sweep(L.L1b, c.swL1T));
     RSILU_HIP(put_sweep(L.Ub, c.swU));
+    RSILU_HIP(put_sweep(L.UTf, c.swUT));
     RSILU_HIP(put(L.perm, c.perm.data(), c.perm.size() * sizeof(int32_t)));
     RSILU_HIP(put(L.colnorm, c.colnorm.data(), c.colnorm.size() * sizeof(double)));
     RSILU_HIP(put(L.sfac, c.sfac.data(), c.sfac.size() * sizeof(double)));
@@ -486,8 +567,12 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
     c.ev_next = 0;
     launch_gather(s, m, n, P.perm, b, P.r, P.xh, nullptr);
     launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_INIT, P.partials, P.segpart, P.st, nullptr);
-    if (sf) launch_fill(s, n, P.t, P.gp, P.v, P.h, P.st);
-    apply_alg3(c, s, P, P.r, P.h, P.done);
+    if (sf) {
+        double *f[4];
+        fill_targets(c, P, P.h, f);
+        launch_fill(s, n, f[0], f[1], f[2], f[3], P.st);
+    }
+    apply_form(c, s, P, P.h, P.done);
     launch_dot(s, n, P.z, P.h, FIN_RHO0, P.partials, P.st, P.done);
     launch_pupdate(s, n, P.h, P.p, P.st, true, P.done);
     RSILU_HIP(hipGetLastError());
@@ -558,6 +643,7 @@ rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs, do
     case 0: trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1); break;
     case 1: trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1T); break;
     case 2: trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_U); break;
+    case 3: trsv(c, s, P, P.UTf, c.lvUT, c.swUT, c.lay.UTf, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_UT); break;
     default: return RSILU_EINVAL;
     }
     RSILU_HIP(hipGetLastError());
@@ -577,6 +663,19 @@ rsilu_status_t rsilu_apply(rsilu_handle_t h, const double *r, double *hout, hipS
     return RSILU_OK;
 }
 
+rsilu_status_t rsilu_apply_z(rsilu_handle_t h, const double *z, double *hout, hipStream_t s)
+{
+    rsilu_status_t rc = check_ready(h);
+    if (rc != RSILU_OK) return rc;
+    if (!z || !hout || static_cast<const void *>(z) == static_cast<const void *>(hout)) return RSILU_EINVAL;
+    Ctx &c = *h;
+    const Ptrs P = ptrs(c);
+    if (syncfree(c)) launch_fill(s, (int32_t)c.n, P.t, P.gp, P.v, alg2_correction(c) ? P.c2 : hout, P.st);
+    apply_alg2(c, s, P, z, hout, nullptr);
+    RSILU_HIP(hipGetLastError());
+    return RSILU_OK;
+}
+
 rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable)
 {
     if (!h) return RSILU_EINVAL;
@@ -586,6 +685,7 @@ rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable)
     for (int i = 0; i < RSILU_PROF_COUNT; ++i) {
         h->prof_launches[i] = 0;
         h->prof_ms[i] = 0.0;
+        h->prof_bytes[i] = 0.0;
     }
     return RSILU_OK;
 }
@@ -596,6 +696,7 @@ rsilu_status_t rsilu_get_profile(rsilu_handle_t h, rsilu_profile_t *out)
     for (int i = 0; i < RSILU_PROF_COUNT; ++i) {
         out->launches[i] = h->prof_launches[i];
         out->ms[i] = h->prof_ms[i];
+        out->bytes[i] = h->prof_bytes[i];
     }
     return RSILU_OK;
 }

@@ -42,6 +42,7 @@ struct Sweep {
     struct Seg {
         int32_t wide_level;  // >= 0: one multi-CU launch for this level
         int32_t b0, b1;      // otherwise: batches [b0, b1) in one single-workgroup launch
+        int64_t rows, nnz;   // rows solved and stored entries read by the launch
     };
     std::vector<Seg> segs;
     std::vector<int64_t> batch_off;  // nbatches + 1 byte offsets into blob
@@ -85,10 +86,10 @@ struct Layout {
     size_t total = 0;
     DevCsrOff A, AT, L2, L2T;
     DevPlanOff pA, pAT, pL2, pL2T;
-    DevTriOff L1f, L1b, Ub;  // L1 forward, L1^T backward, U backward
+    DevTriOff L1f, L1b, Ub, UTf;  // L1 forward, L1^T backward, U backward, U^T forward
     size_t perm = 0, colnorm = 0, sfac = 0;
     // Krylov vectors
-    size_t xh = 0, p = 0, z = 0, h = 0, t = 0, y = 0, v = 0, g = 0, gp = 0;  // n
+    size_t xh = 0, p = 0, z = 0, h = 0, t = 0, y = 0, v = 0, g = 0, gp = 0, s2 = 0, c2 = 0;  // n
     size_t r = 0, q = 0;                                                       // m
     size_t u = 0;                                                              // m - n
     size_t lo_rhs = 0, lo_add = 0;  // level-ordered right-hand side and addend of a sweep (n)
@@ -112,8 +113,8 @@ struct Ctx {
     Csr L1, L1T, L2, L2T, U, UT;   // strictly triangular parts
     std::vector<double> Udiag;
     Levels lvL1, lvL1T, lvU, lvUT;
-    Chunks chL1, chL1T, chU;
-    Sweep swL1, swL1T, swU;
+    Chunks chL1, chL1T, chU, chUT;
+    Sweep swL1, swL1T, swU, swUT;
     SpmvPlan plA, plAT, plL2, plL2T;
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
 
@@ -129,12 +130,14 @@ struct Ctx {
     std::vector<void *> ev_pool;                // hipEvent_t
     struct EvRec {
         int cls, idx, iter;  // class, first of two events, iteration it belongs to (0 = init)
+        double bytes;        // algorithmic bytes of the timed launch (kernel classes)
     };
     std::vector<EvRec> ev_open;                 // recorded, not yet read back
     int ev_iter = 0;                            // iteration being enqueued
     size_t ev_next = 0;
     int64_t prof_launches[RSILU_PROF_COUNT] = {};
     double prof_ms[RSILU_PROF_COUNT] = {};
+    double prof_bytes[RSILU_PROF_COUNT] = {};
 };
 
 // host setup (setup.cpp)

@@ -144,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsr a, int32_t long_thresh, co
     if (own && gl == 0) {
         double out = sum;
         if (EPI == EPI_SUB) out = aux[row] - sum;
+        if (EPI == EPI_NEG) out = -sum;
         y[row] = out;
         if (EPI == EPI_SQ) contrib = out * out;
         if (EPI == EPI_WSQ) {
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, dou
         const int row = pl.long_rows[i];
         double s = 0.0;
         for (int q = pl.seg_ptr[i]; q < pl.seg_ptr[i + 1]; ++q) s += segpart[q];
-        double out = (EPI == EPI_SUB) ? aux[row] - s : s;
+        double out = (EPI == EPI_SUB) ? aux[row] - s : (EPI == EPI_NEG ? -s : s);
         y[row] = out;
         double c = 0.0;
         if (EPI == EPI_SQ) c = out * out;
@@ -276,6 +277,20 @@ __global__ __launch_bounds__(kBlock) void k_fill(int32_t n, double *f0, double *
     }
     if (blockIdx.x == 0 && threadIdx.x < 4) st->ticket[threadIdx.x] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->err = 0;
+}
+
+// Sentinel-fill two more sync-free outputs and clear tickets 0 and 1 (between
+// the sweeps of one preconditioner application that needs more than four).
+__global__ __launch_bounds__(kBlock) void k_refill(int32_t n, double *f0, double *f1, DevState *st,
+                                                    const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double sent = __longlong_as_double((long long)kSentinel);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        f0[i] = sent;
+        f1[i] = sent;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) st->ticket[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_pupdate(int32_t n, const double *__restrict__ h, double *__restrict__ p,
@@ -401,11 +416,12 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(DTri t, int32_t beg, int3
 // lie in batches <= b-1 or earlier launches, so they are final when batch b
 // starts; the list of them travels in batch b's blob.
 // Blob layout: int32 hdr[kSweepHdr] = {nlev, npos, nent, next, has_diag,
-// cur_base, p0, size, next_size, next_npos, next_next, -}, lev_off[nlev+1],
-// rowid[npos], eptr[npos+1], ext_idx[next], next_ext[kSweepExt],
-// uint16 eslot[nent], then (8-aligned) double eval[nent], diag[npos].
-// eslot indexes the LDS window xw = [even batches' results | odd batches'
-// results | older inputs].
+// cur_base, p0, size, next_size, next_npos, next_next, nchunk},
+// lev_off[nlev+1], lev_chunk[nlev+1], rowid[npos], ext_idx[next],
+// next_ext[kSweepExt], uint16 rchunk[npos+1], cstart[nchunk+1], eslot[nent],
+// then (8-aligned) double eval[nent], diag[npos]. A row's entries are cut into
+// chunks of at most kSweepChunk; eslot indexes the LDS window xw = [even
+// batches' results | odd batches' results | older inputs].
 __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned char *__restrict__ blob, int64_t off,
                                                                int32_t size, int32_t npos_first, int32_t p0,
                                                                int32_t nb, const double *__restrict__ rhs_lo,
@@ -416,12 +432,13 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
     constexpr int VP = (kSweepPos + kSweepThreads - 1) / kSweepThreads;
     constexpr int VE = (kSweepExt + kSweepThreads - 1) / kSweepThreads;
     __shared__ __attribute__((aligned(16))) unsigned char sb[kSweepBlob];
-    __shared__ double xw[2 * kSweepPos + kSweepExt];
+    __shared__ double xw[2 * kSweepPos + kSweepExt + 8];
     __shared__ double rl[kSweepPos];
     __shared__ double al[kSweepPos];
     __shared__ double prod[kSweepLevEnt];
     if (stop_now(done)) return;
     const int tid = threadIdx.x;
+    if (tid == 0) xw[kSweepZeroSlot] = 0.0;
     static_assert(VB <= 5 && VP == 2 && VE == 2, "staging registers are written out for these limits");
     // Staging registers for the next batch. Loads are unconditional with
     // clamped indices (always in bounds: a batch has at least one row and one
@@ -480,7 +497,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
     __syncthreads();
     {
         const int32_t *hdr = reinterpret_cast<const int32_t *>(sb);
-        const int32_t *own_ext = hdr + kSweepHdr + (hdr[0] + 1) + hdr[1] + (hdr[1] + 1);
+        const int32_t *own_ext = hdr + kSweepHdr + 2 * (hdr[0] + 1) + hdr[1];
         RSILU_LOAD_EXT(own_ext, hdr[3])
         RSILU_STORE_EXT(hdr[3])
     }
@@ -489,17 +506,23 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
     for (int b = 0; b < nb; ++b) {
         const int32_t *hdr = reinterpret_cast<const int32_t *>(sb);
         const int nlev = hdr[0], npos = hdr[1], nent = hdr[2], next = hdr[3], hd = hdr[4], cur = hdr[5];
-        const int size_next = hdr[8], npos_next = hdr[9], nnext = hdr[10];
+        const int size_next = hdr[8], npos_next = hdr[9], nnext = hdr[10], nchunk = hdr[11];
         const int32_t *lev_off = hdr + kSweepHdr;
-        const int32_t *rowid = lev_off + nlev + 1;
-        const int32_t *eptr = rowid + npos;
-        const int32_t *ext_idx = eptr + npos + 1;
+        const int32_t *lev_chunk = lev_off + nlev + 1;
+        const int32_t *rowid = lev_chunk + nlev + 1;
+        const int32_t *ext_idx = rowid + npos;
         const int32_t *next_ext = ext_idx + next;
-        const uint16_t *eslot = reinterpret_cast<const uint16_t *>(next_ext + kSweepExt);
-        int off_val = 4 * kSweepHdr + 4 * (nlev + 1) + 4 * npos + 4 * (npos + 1) + 4 * next + 4 * kSweepExt + 2 * nent;
-        off_val = (off_val + 7) & ~7;
-        const double *eval = reinterpret_cast<const double *>(sb + off_val);
-        const double *dg = eval + nent;
+        const uint16_t *rchunk = reinterpret_cast<const uint16_t *>(next_ext + kSweepExt);
+        const int o_slot = ((int)(reinterpret_cast<const unsigned char *>(rchunk + npos + 1) - sb) + 7) & ~7;
+        const int o_val = (o_slot + 8 * nchunk + 15) & ~15;
+        const uint2 *eslot4 = reinterpret_cast<const uint2 *>(sb + o_slot);      // 4 uint16 slots per chunk
+        const double2 *eval2 = reinterpret_cast<const double2 *>(sb + o_val);   // 4 values per chunk
+        const double *dg = reinterpret_cast<const double *>(sb + o_val + 32 * nchunk);
+        (void)nent;
+        // level offsets live in the lanes of every wavefront (nlev <= 63)
+        const int lane = tid & 63;
+        const int lo_v = lane <= nlev ? lev_off[lane] : 0;
+        const int lc_v = lane <= nlev ? lev_chunk[lane] : 0;
         const bool more = b + 1 < nb;
         const int64_t noff = off + size;
         const int np0 = p0 + npos;
@@ -507,25 +530,73 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             RSILU_LOAD_BATCH(noff, size_next >> 4, np0, npos_next)
             RSILU_LOAD_EXT(next_ext, nnext)
         }
-        for (int L = 0; L < nlev; ++L) {
-            // products of the level's entries, one entry per thread
-            const int pa = lev_off[L], pb = lev_off[L + 1];
-            const int ea = eptr[pa], eb = eptr[pb];
-            for (int e = ea + tid; e < eb; e += kSweepThreads) prod[e - ea] = eval[e] * xw[eslot[e]];
-            __syncthreads();
-            // row sums in entry order, one row per thread
+        // Level loop: one chunk and one row per thread. Phase 1 forms the
+        // chunk sums (four entries each, padded with the zero slot so the
+        // loads are branch-free); phase 2 adds each row's chunk sums, solves
+        // the row and publishes it in LDS for later levels.
+        struct Meta {
+            int cidx;      // chunk index in the level (-1: none)
+            uint2 sl;      // four LDS slots
+            double2 v01, v23;
+            int pidx;      // row position in the batch (-1: none)
+            int c0, nch;   // the row's chunks, relative to the level
+            double rhs, dg, add;
+            int row;
+        };
+        auto fetch = [&](int L) {
+            Meta m;
+            const int pa = __builtin_amdgcn_readlane(lo_v, L), pb = __builtin_amdgcn_readlane(lo_v, L + 1);
+            const int ca = __builtin_amdgcn_readlane(lc_v, L), cb = __builtin_amdgcn_readlane(lc_v, L + 1);
+            const int c = ca + tid;
+            m.cidx = -1;
+            if (c < cb) {
+                m.cidx = tid;
+                m.sl = eslot4[c];
+                m.v01 = eval2[2 * c];
+                m.v23 = eval2[2 * c + 1];
+            }
             const int p = pa + tid;
+            m.pidx = -1;
             if (p < pb) {
+                m.pidx = p;
+                m.c0 = rchunk[p] - ca;
+                m.nch = rchunk[p + 1] - rchunk[p];
+                m.rhs = rl[p];
+                m.dg = hd ? dg[p] : 1.0;
+                m.add = y2 ? al[p] : 0.0;
+                m.row = rowid[p];
+            }
+            return m;
+        };
+        for (int L = 0; L < nlev; ++L) {
+            const Meta m = fetch(L);
+            // chunk sums: kSweepChunk entries of one row (padded with the zero slot)
+            if (m.cidx >= 0) {
+                double s = m.v01.x * xw[m.sl.x & 0xffffu];
+                s += m.v01.y * xw[m.sl.x >> 16];
+                s += m.v23.x * xw[m.sl.y & 0xffffu];
+                s += m.v23.y * xw[m.sl.y >> 16];
+                prod[m.cidx] = s;
+            }
+            __syncthreads();
+            // row sums over the row's chunk sums (up to four read at once)
+            if (m.pidx >= 0) {
                 double s = 0.0;
-                const int e0 = eptr[p] - ea, e1 = eptr[p + 1] - ea;
-#pragma unroll 4
-                for (int e = e0; e < e1; ++e) s += prod[e];
-                double r = rl[p] - s;
-                if (hd) r = r / dg[p];
-                xw[cur + p] = r;
-                const int row = rowid[p];
-                x[row] = r;
-                if (y2) y2[row] = al[p] + r;
+                if (m.nch > 0) {
+                    const int c0 = m.c0, last = m.c0 + m.nch - 1;
+                    const double a0 = prod[c0], a1 = prod[min(c0 + 1, last)], a2 = prod[min(c0 + 2, last)],
+                                 a3 = prod[min(c0 + 3, last)];
+                    s = a0;
+                    s = m.nch > 1 ? s + a1 : s;
+                    s = m.nch > 2 ? s + a2 : s;
+                    s = m.nch > 3 ? s + a3 : s;
+                    for (int c = c0 + 4; c <= last; ++c) s += prod[c];
+                }
+                double r = m.rhs - s;
+                if (hd) r = r / m.dg;
+                xw[cur + m.pidx] = r;
+                x[m.row] = r;
+                if (y2) y2[m.row] = m.add + r;
             }
             __syncthreads();
         }
@@ -684,6 +755,7 @@ void launch_spmv(hipStream_t s, const DCsr &a, const DPlan &pl, const double *x,
     case EPI_SQ: spmv_dispatch<EPI_SQ>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     case EPI_SUB: spmv_dispatch<EPI_SUB>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     case EPI_WSQ: spmv_dispatch<EPI_WSQ>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_NEG: spmv_dispatch<EPI_NEG>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     }
     if (pl.nseg > 0)
         hipLaunchKernelGGL(k_spmv_seg, dim3(pl.nseg), dim3(kBlock), 0, s, a, pl, x, segpart, done);
@@ -705,6 +777,10 @@ void launch_spmv(hipStream_t s, const DCsr &a, const DPlan &pl, const double *x,
             break;
         case EPI_WSQ:
             hipLaunchKernelGGL(k_finish<EPI_WSQ>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
+                               fin, st, done);
+            break;
+        case EPI_NEG:
+            hipLaunchKernelGGL(k_finish<EPI_NEG>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
                                fin, st, done);
             break;
         }
@@ -729,6 +805,11 @@ void launch_update(hipStream_t s, int32_t n, int32_t m, const double *p, double 
 void launch_fill(hipStream_t s, int32_t n, double *f0, double *f1, double *f2, double *f3, DevState *st)
 {
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, s, n, f0, f1, f2, f3, st);
+}
+
+void launch_refill(hipStream_t s, int32_t n, double *f0, double *f1, DevState *st, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_refill, dim3(grid_for(n)), dim3(kBlock), 0, s, n, f0, f1, st, done);
 }
 
 void launch_pupdate(hipStream_t s, int32_t n, const double *h, double *p, const DevState *st, bool first,

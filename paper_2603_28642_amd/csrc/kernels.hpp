@@ -57,7 +57,8 @@ enum Epi : int32_t {
     EPI_PLAIN = 0,  // y = A x
     EPI_SQ = 1,     // y = A x, partial sums of y^2
     EPI_SUB = 2,    // y = aux - A x
-    EPI_WSQ = 3     // y = A x, partial sums of (aux * y)^2
+    EPI_WSQ = 3,    // y = A x, partial sums of (aux * y)^2
+    EPI_NEG = 4     // y = -A x
 };
 
 enum Fin : int32_t {
@@ -86,6 +87,8 @@ void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin 
 void launch_update(hipStream_t s, int32_t n, int32_t m, const double *p, double *xh, const double *q, double *r,
                    double *f0, double *f1, double *f2, double *f3, DevState *st, const int32_t *done);
 void launch_fill(hipStream_t s, int32_t n, double *f0, double *f1, double *f2, double *f3, DevState *st);
+// sentinel-fill f0, f1 and clear tickets 0 and 1 (honours `done`)
+void launch_refill(hipStream_t s, int32_t n, double *f0, double *f1, DevState *st, const int32_t *done);
 void launch_pupdate(hipStream_t s, int32_t n, const double *h, double *p, const DevState *st, bool first,
                     const int32_t *done);
 void launch_scale_out(hipStream_t s, int32_t n, const double *xh, const double *colnorm, double *x);

@@ -115,19 +115,37 @@ Chunks make_chunks(const Levels &lv, int32_t cap)
     return ch;
 }
 
-// Byte size of a sweep batch blob (layout in kernels.hip, k_trsv_sweep).
-int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t nent, int64_t next, bool diag, int64_t nnext = kSweepExt)
+// Byte offsets inside a sweep batch blob (layout in kernels.hip, k_trsv_sweep).
+struct BlobLayout {
+    int64_t lev, lch, row, ext, next_ext, rch, slot, val, diag, size;
+};
+BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag)
 {
-    int64_t b = 4 * kSweepHdr + 4 * (nlev + 1) + 4 * npos + 4 * (npos + 1) + 4 * next + 4 * nnext + 2 * nent;
-    b = (b + 7) & ~(int64_t)7;
-    b += 8 * nent + (diag ? 8 * npos : 0);
-    return (b + 15) & ~(int64_t)15;
+    BlobLayout o;
+    o.lev = 4 * kSweepHdr;
+    o.lch = o.lev + 4 * (nlev + 1);
+    o.row = o.lch + 4 * (nlev + 1);
+    o.ext = o.row + 4 * npos;
+    o.next_ext = o.ext + 4 * next;
+    o.rch = o.next_ext + 4 * (int64_t)kSweepExt;
+    o.slot = (o.rch + 2 * (npos + 1) + 7) & ~(int64_t)7;
+    o.val = (o.slot + 8 * nchunk + 15) & ~(int64_t)15;
+    o.diag = o.val + 32 * nchunk;
+    o.size = (o.diag + (diag ? 8 * npos : 0) + 15) & ~(int64_t)15;
+    return o;
 }
+int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag)
+{
+    return blob_layout(nlev, npos, next, nchunk, diag).size;
+}
+
+int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
 
 // Hybrid sweep schedule of the triangular operator T with level sets lv.
 // Runs of levels of at most kSweepRows rows are cut into batches; an input of a
 // row is read from LDS: from the results of the same batch, of the previous
-// batch of the run, or from the batch's gathered older inputs ("ext").
+// batch of the run, or from the batch's gathered older inputs ("ext"). Rows
+// are cut into chunks of at most kSweepChunk entries (one thread each).
 Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv)
 {
     Sweep sw;
@@ -138,20 +156,26 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     std::vector<int32_t> ext_stamp((size_t)n, -1), ext_slot((size_t)n, 0);
     sw.batch_off.push_back(0);
     auto nbatches = [&]() { return (int32_t)sw.batch_off.size() - 1; };
+    auto rowlen = [&](int32_t row) { return (int64_t)T.ptr[(size_t)row + 1] - T.ptr[row]; };
     auto entries = [&](int32_t l) {
         int64_t ne = 0;
-        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p)
-            ne += T.ptr[(size_t)lv.rows[p] + 1] - T.ptr[lv.rows[p]];
+        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) ne += rowlen(lv.rows[p]);
         return ne;
     };
+    auto chunks = [&](int32_t l) {
+        int64_t nc = 0;
+        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) nc += chunks_of(rowlen(lv.rows[p]));
+        return nc;
+    };
 
-    int32_t run_b0 = -1;       // first batch of the open run
+    int32_t run_b0 = -1;                 // first batch of the open run
     int32_t prev_p0 = -1, prev_p1 = -1;  // positions of the previous batch of the run
     int32_t bl0 = -1, bl1 = -1;          // levels of the open batch
-    int64_t bpos = 0, bent = 0, bext = 0;
+    int64_t bpos = 0, bent = 0, bchk = 0;
     int32_t stamp = 0;
+    std::vector<int64_t> batch_rows, batch_nnz;  // per serialized batch
 
-    // older inputs of level l that the open batch would have to gather
+    // older inputs of level l that a batch starting at position p0 would gather
     auto new_ext = [&](int32_t l, int32_t p0) {
         int64_t k = 0;
         for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) {
@@ -172,12 +196,12 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         const int32_t p0 = lv.ptr[l0], p1 = lv.ptr[l1], npos = p1 - p0, nlev = l1 - l0;
         const int32_t bi = nbatches() - run_b0;  // index inside the run
         const int32_t cur_base = (bi & 1) ? kSweepPos : 0, prev_base = (bi & 1) ? 0 : kSweepPos;
-        // collect the older inputs (fresh stamp)
         ++stamp;
         std::vector<int32_t> ext;
-        int64_t nent = 0;
+        int64_t nent = 0, nchunk = 0;
         for (int32_t p = p0; p < p1; ++p) {
             const int32_t row = lv.rows[p];
+            nchunk += chunks_of(rowlen(row));
             for (int32_t e = T.ptr[row]; e < T.ptr[(size_t)row + 1]; ++e, ++nent) {
                 const int32_t c = T.col[e], pc = posof[c];
                 if (pc >= p0 || (pc >= prev_p0 && pc < prev_p1)) continue;
@@ -189,8 +213,9 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             }
         }
         const int64_t next = (int64_t)ext.size();
-        const int64_t size = blob_bytes(nlev, npos, nent, next, hd);  // room for the next batch's list
-        if (npos > kSweepPos || next > kSweepExt || size > kSweepBlob || nent > 65535)
+        const BlobLayout lay = blob_layout(nlev, npos, next, nchunk, hd);
+        const int64_t size = lay.size;
+        if (npos > kSweepPos || next > kSweepExt || size > kSweepBlob || nchunk > 65535 || nlev > kSweepLevels)
             throw std::length_error("sweep batch exceeds the LDS limits");
         const size_t base = sw.blob.size();
         sw.blob.resize(base + (size_t)size, 0);
@@ -198,7 +223,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         int32_t *hdr = reinterpret_cast<int32_t *>(b);
         hdr[0] = nlev;
         hdr[1] = npos;
-        hdr[2] = (int32_t)nent;
+        hdr[2] = (int32_t)(kSweepChunk * nchunk);
         hdr[3] = (int32_t)next;
         hdr[4] = hd ? 1 : 0;
         hdr[5] = cur_base;
@@ -207,50 +232,74 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         hdr[8] = 0;   // size of the next batch of the run (patched by the next batch)
         hdr[9] = 0;   // rows of the next batch
         hdr[10] = 0;  // older inputs of the next batch (their rows follow ext_idx)
-        int32_t *lev_off = hdr + kSweepHdr;
-        int32_t *rowid = lev_off + nlev + 1;
-        int32_t *eptr = rowid + npos;
-        int32_t *ext_idx = eptr + npos + 1;
-        uint16_t *eslot = reinterpret_cast<uint16_t *>(ext_idx + next + kSweepExt);
-        int64_t off_val =
-            4 * kSweepHdr + 4 * (nlev + 1) + 4 * npos + 4 * (npos + 1) + 4 * next + 4 * kSweepExt + 2 * nent;
-        off_val = (off_val + 7) & ~(int64_t)7;
-        double *eval = reinterpret_cast<double *>(b + off_val);
-        double *dg = eval + nent;
-        for (int32_t l = l0; l <= l1; ++l) lev_off[l - l0] = lv.ptr[l] - p0;
+        hdr[11] = (int32_t)nchunk;
+        int32_t *lev_off = reinterpret_cast<int32_t *>(b + lay.lev);
+        int32_t *lev_chunk = reinterpret_cast<int32_t *>(b + lay.lch);
+        int32_t *rowid = reinterpret_cast<int32_t *>(b + lay.row);
+        int32_t *ext_idx = reinterpret_cast<int32_t *>(b + lay.ext);
+        uint16_t *rchunk = reinterpret_cast<uint16_t *>(b + lay.rch);
+        uint16_t *eslot = reinterpret_cast<uint16_t *>(b + lay.slot);
+        double *eval = reinterpret_cast<double *>(b + lay.val);
+        double *dg = reinterpret_cast<double *>(b + lay.diag);
         for (int64_t j = 0; j < next; ++j) ext_idx[j] = ext[(size_t)j];
-        int32_t e = 0;
+        int32_t ch = 0;
+        int32_t lvl = l0;
+        lev_off[0] = 0;
+        lev_chunk[0] = 0;
         for (int32_t p = p0; p < p1; ++p) {
+            while (p >= lv.ptr[(size_t)lvl + 1]) {
+                ++lvl;
+                lev_off[lvl - l0] = p - p0;
+                lev_chunk[lvl - l0] = ch;
+            }
             const int32_t row = lv.rows[p];
             rowid[p - p0] = row;
-            eptr[p - p0] = e;
-            for (int32_t k = T.ptr[row]; k < T.ptr[(size_t)row + 1]; ++k, ++e) {
-                const int32_t c = T.col[k], pc = posof[c];
-                int32_t slot;
-                if (pc >= p0)
-                    slot = cur_base + (pc - p0);
-                else if (pc >= prev_p0 && pc < prev_p1)
-                    slot = prev_base + (pc - prev_p0);
-                else
-                    slot = 2 * kSweepPos + ext_slot[c];
-                eslot[e] = (uint16_t)slot;
-                eval[e] = T.val[k];
+            rchunk[p - p0] = (uint16_t)ch;
+            int32_t k = T.ptr[row];
+            while (k < T.ptr[(size_t)row + 1]) {
+                // a chunk holds exactly kSweepChunk entries; padding reads the zero slot
+                for (int32_t q = 0; q < kSweepChunk; ++q) {
+                    const int64_t e = (int64_t)kSweepChunk * ch + q;
+                    if (k < T.ptr[(size_t)row + 1]) {
+                        const int32_t c = T.col[k], pc = posof[c];
+                        int32_t slot;
+                        if (pc >= p0)
+                            slot = cur_base + (pc - p0);
+                        else if (pc >= prev_p0 && pc < prev_p1)
+                            slot = prev_base + (pc - prev_p0);
+                        else
+                            slot = 2 * kSweepPos + ext_slot[c];
+                        eslot[e] = (uint16_t)slot;
+                        eval[e] = T.val[k];
+                        ++k;
+                    } else {
+                        eslot[e] = (uint16_t)kSweepZeroSlot;
+                        eval[e] = 0.0;
+                    }
+                }
+                ++ch;
             }
             if (hd) dg[p - p0] = (*diag)[row];
         }
-        eptr[npos] = e;
-        // the previous batch of the run learns this batch's size
+        while (lvl < l1) {
+            ++lvl;
+            lev_off[lvl - l0] = npos;
+            lev_chunk[lvl - l0] = ch;
+        }
+        rchunk[npos] = (uint16_t)ch;
+        // the previous batch of the run learns this batch's size and older inputs,
+        // so they are gathered while the previous batch is being solved
         if (bi > 0) {
             int32_t *ph = reinterpret_cast<int32_t *>(sw.blob.data() + sw.batch_off[(size_t)nbatches() - 1]);
             ph[8] = (int32_t)size;
             ph[9] = npos;
             ph[10] = (int32_t)next;
-            // the previous blob carries this batch's older inputs, so they are
-            // gathered while the previous batch is being solved
-            int32_t *pnext = ph + kSweepHdr + (ph[0] + 1) + ph[1] + (ph[1] + 1) + ph[3];
+            int32_t *pnext = ph + kSweepHdr + 2 * (ph[0] + 1) + ph[1] + ph[3];  // next_ext of that blob
             for (int64_t j = 0; j < next; ++j) pnext[j] = ext[(size_t)j];
         }
         sw.batch_off.push_back((int64_t)sw.blob.size());
+        batch_rows.push_back(npos);
+        batch_nnz.push_back(nent);
         prev_p0 = p0;
         prev_p1 = p1;
     };
@@ -261,19 +310,28 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     };
     auto close_run = [&]() {
         close_batch();
-        if (run_b0 >= 0 && nbatches() > run_b0) sw.segs.push_back({-1, run_b0, nbatches()});
+        if (run_b0 >= 0 && nbatches() > run_b0) {
+            int64_t rows = 0, nnz = 0;
+            for (int32_t bb = run_b0; bb < nbatches(); ++bb) {
+                rows += batch_rows[(size_t)bb];
+                nnz += batch_nnz[(size_t)bb];
+            }
+            sw.segs.push_back({-1, run_b0, nbatches(), rows, nnz});
+        }
         run_b0 = -1;
         prev_p0 = prev_p1 = -1;
     };
-    auto fits = [&](int64_t nlev, int64_t npos, int64_t nent, int64_t next) {
-        return npos <= kSweepPos && next <= kSweepExt && blob_bytes(nlev, npos, nent, next, hd) <= kSweepBlob;
+    auto fits = [&](int64_t nlev, int64_t npos, int64_t nent, int64_t next, int64_t nchk) {
+        (void)nent;
+        return nlev <= kSweepLevels && npos <= kSweepPos && next <= kSweepExt &&
+               blob_bytes(nlev, npos, next, nchk, hd) <= kSweepBlob;
     };
     for (int32_t l = 0; l < lv.nlev(); ++l) {
         const int64_t w = lv.ptr[(size_t)l + 1] - lv.ptr[l];
-        const int64_t ne = entries(l);
-        if (w > kSweepRows || ne > kSweepLevEnt) {
+        const int64_t ne = entries(l), nc = chunks(l);
+        if (w > kSweepRows || nc > kSweepLevEnt) {
             close_run();
-            sw.segs.push_back({l, -1, -1});
+            sw.segs.push_back({l, -1, -1, w, ne});
             continue;
         }
         if (bl0 >= 0) {
@@ -281,11 +339,11 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             ++stamp;
             int64_t ext_now = 0;
             for (int32_t ll = bl0; ll <= l; ++ll) ext_now += new_ext(ll, lv.ptr[bl0]);
-            if (fits(l - bl0 + 1, bpos + w, bent + ne, ext_now)) {
+            if (fits(l - bl0 + 1, bpos + w, bent + ne, ext_now, bchk + nc)) {
                 bl1 = l + 1;
                 bpos += w;
                 bent += ne;
-                bext = ext_now;
+                bchk += nc;
                 continue;
             }
             close_batch();
@@ -293,9 +351,9 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         // start a new batch with level l (the previous batch is now the last closed one)
         ++stamp;
         const int64_t e1 = new_ext(l, lv.ptr[l]);
-        if (!fits(1, w, ne, e1)) {
+        if (!fits(1, w, ne, e1, nc)) {
             close_run();
-            sw.segs.push_back({l, -1, -1});
+            sw.segs.push_back({l, -1, -1, w, ne});
             continue;
         }
         if (run_b0 < 0) run_b0 = nbatches();
@@ -303,10 +361,9 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         bl1 = l + 1;
         bpos = w;
         bent = ne;
-        bext = e1;
+        bchk = nc;
     }
     close_run();
-    (void)bext;
     return sw;
 }
 
@@ -380,7 +437,9 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
         return RSILU_EINVAL;
     if (P.p < 0 || !(P.tau >= 0.0) || !(P.mu > 0.0 && P.mu <= 1.0) || !(P.small > 0.0) ||
         !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
-        (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE) ||
+        (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
+         P.smode != RSILU_S_NONE) ||
+        (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
         (P.trsv != RSILU_TRSV_SYNCFREE && P.trsv != RSILU_TRSV_LEVELS && P.trsv != RSILU_TRSV_HYBRID))
         return RSILU_EINVAL;
     if (rowptr[0] != 0 || rowptr[m] > kMaxIdx) return RSILU_EINVAL;
@@ -615,6 +674,9 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.swL1 = make_sweep(c.L1, nullptr, c.lvL1);
     c.swL1T = make_sweep(c.L1T, nullptr, c.lvL1T);
     c.swU = make_sweep(c.U, &c.Udiag, c.lvU);
+    // U^T (forward, Udiag on the diagonal) for Algorithm 2's M_a = (L1 U)^T (L1 U)
+    c.chUT = make_chunks(c.lvUT, 64 / tri_lanes(c.UT));
+    c.swUT = make_sweep(c.UT, &c.Udiag, c.lvUT);
 
     // ---- S^ (Section 3.2)
     c.smode = P.smode;
@@ -657,7 +719,7 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
                 c.sfac[at(i, jj)] = s / d;
             }
         }
-    } else {
+    } else if (c.smode != RSILU_S_NONE) {
         c.smode = RSILU_S_IDENTITY;
     }
     return RSILU_OK;
@@ -737,10 +799,12 @@ void plan_layout(Ctx &c)
     L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, n);
     L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, n);
     L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, n);
+    L.UTf = place_tri(b, c.UT, true, c.lvUT, c.chUT, c.swUT, n);
     L.perm = b.take(sizeof(int32_t) * m);
     L.colnorm = b.take(sizeof(double) * n);
     L.sfac = b.take(sizeof(double) * c.sfac.size());
-    for (size_t *o : {&L.xh, &L.p, &L.z, &L.h, &L.t, &L.y, &L.v, &L.g, &L.gp}) *o = b.take(sizeof(double) * n);
+    for (size_t *o : {&L.xh, &L.p, &L.z, &L.h, &L.t, &L.y, &L.v, &L.g, &L.gp, &L.s2, &L.c2})
+        *o = b.take(sizeof(double) * n);
     L.r = b.take(sizeof(double) * m);
     L.q = b.take(sizeof(double) * m);
     L.u = b.take(sizeof(double) * std::max<size_t>(k, 1));

@@ -10,9 +10,13 @@ constexpr int kSweepThreads = 1024;  // one workgroup
 constexpr int kSweepRows = 1024;     // rows per level (one per thread)
 constexpr int kSweepPos = 1536;      // rows per batch
 constexpr int kSweepExt = 2048;      // distinct older inputs per batch
-constexpr int kSweepLevEnt = 4096;   // entries per level (products staged in LDS)
-constexpr int kSweepBlob =
-    163840 - 1024 - (2 * kSweepPos + kSweepExt + 2 * kSweepPos + kSweepLevEnt) * 8;  // 64512 bytes
+constexpr int kSweepLevEnt = 1024;   // chunks per level (one per thread; sums staged in LDS)
+constexpr int kSweepChunk = 4;       // entries per chunk (a row is cut into chunks)
+constexpr int kSweepLevels = 63;     // levels per batch (offsets held in one wavefront's lanes)
+constexpr int kSweepZeroSlot = 2 * kSweepPos + kSweepExt;  // LDS slot that always holds 0.0
+// The blob gets the rest of the LDS, at most 5 16-byte vectors per thread.
+constexpr int kSweepBlobRoom = 163840 - 1024 - (2 * kSweepPos + kSweepExt + 8 + 2 * kSweepPos + kSweepLevEnt) * 8;
+constexpr int kSweepBlob = kSweepBlobRoom < 5 * 16 * kSweepThreads ? (kSweepBlobRoom & ~15) : 5 * 16 * kSweepThreads;
 constexpr int kSweepHdr = 12;        // int32 header words of a batch blob
 
 }  // namespace rsilu

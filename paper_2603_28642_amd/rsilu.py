@@ -16,25 +16,33 @@ LIB_PATH = os.path.join(_HERE, "_lib", "librsilu.so")
 # status codes
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ESTATE, EINTERNAL = -1, -2, -3, -4, -5
-S_AUTO, S_IDENTITY, S_DENSE = -1, 0, 1
+S_AUTO, S_IDENTITY, S_DENSE, S_NONE = -1, 0, 1, 2
+FORM_ALG3, FORM_ALG2 = 0, 1
 TRSV_SYNCFREE, TRSV_LEVELS, TRSV_HYBRID = 0, 1, 2
 # factor / level selectors
 L1, L2, U, AHAT, UDIAG = 0, 1, 2, 3, 4
 LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
+# triangular-solve selectors of rsilu_trsv
+T_L1, T_L1T, T_U, T_UT = 0, 1, 2, 3
 
 EXPORTS = [
     "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_get_stats",
     "rsilu_get_perm", "rsilu_get_colnorm", "rsilu_factor_nnz", "rsilu_get_factor", "rsilu_get_levels",
-    "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_set_profiling", "rsilu_get_profile",
+    "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_apply_z", "rsilu_set_profiling",
+    "rsilu_get_profile",
     "rsilu_destroy", "rsilu_status_string",
 ]
-PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S"]
+PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S", "trsv_UT",
+              "k_trsv_sweep", "k_trsv_level", "k_gather_lo"]
+# classes that time whole steps (the rest time single kernels)
+PROF_STEPS = PROF_NAMES[:9]
 
 
 class rsilu_params_t(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("tau", ctypes.c_double), ("mu", ctypes.c_double),
                 ("small", ctypes.c_double), ("colscale", ctypes.c_int32), ("smode", ctypes.c_int32),
-                ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32)]
+                ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32),
+                ("form", ctypes.c_int32)]
 
 
 class rsilu_stats_t(ctypes.Structure):
@@ -49,7 +57,7 @@ class rsilu_stats_t(ctypes.Structure):
 
 
 class rsilu_profile_t(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
+    _fields_ = [("launches", ctypes.c_int64 * 12), ("ms", ctypes.c_double * 12), ("bytes", ctypes.c_double * 12)]
 
 
 class RsiluError(RuntimeError):
@@ -98,6 +106,8 @@ def lib():
         L.rsilu_trsv.restype = ctypes.c_int
         L.rsilu_apply.argtypes = [P, P, P, P]
         L.rsilu_apply.restype = ctypes.c_int
+        L.rsilu_apply_z.argtypes = [P, P, P, P]
+        L.rsilu_apply_z.restype = ctypes.c_int
         L.rsilu_set_profiling.argtypes = [P, I32]
         L.rsilu_set_profiling.restype = ctypes.c_int
         L.rsilu_get_profile.argtypes = [P, ctypes.POINTER(rsilu_profile_t)]
@@ -243,15 +253,20 @@ def rsilu_apply(h, r_dev, h_dev, stream=None):
     return lib().rsilu_apply(h, _dev(r_dev), _dev(h_dev), _stream(stream))
 
 
+def rsilu_apply_z(h, z_dev, h_dev, stream=None):
+    return lib().rsilu_apply_z(h, _dev(z_dev), _dev(h_dev), _stream(stream))
+
+
 def rsilu_set_profiling(h, enable):
     return lib().rsilu_set_profiling(h, 1 if enable else 0)
 
 
 def rsilu_get_profile(h):
-    """{kernel class: (launches, total ms)} from the HIP events recorded during solves."""
+    """{class: (launches, total ms, algorithmic bytes)} from the HIP events recorded during solves
+    (bytes are reported for the single-kernel classes only)."""
     p = rsilu_profile_t()
     _check(lib().rsilu_get_profile(h, ctypes.byref(p)), "rsilu_get_profile")
-    return {name: (int(p.launches[i]), float(p.ms[i])) for i, name in enumerate(PROF_NAMES)}
+    return {name: (int(p.launches[i]), float(p.ms[i]), float(p.bytes[i])) for i, name in enumerate(PROF_NAMES)}
 
 
 def rsilu_destroy(h):
