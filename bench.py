@@ -113,6 +113,26 @@ def iteration_bytes(st, form, smode):
     return it
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE counter
+    runs (profiles/traffic_<kernel>_<workload>.json, calibrated by a copy of known size),
+    or None when there is no record or the kernel's sources changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for fn in rec["sources"]:
+        with open(os.path.join(ROOT, fn), "rb") as src:
+            h.update(src.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(prob, args, iters_per_solve):
     """The oracle's Algorithm 1 on the same problem, timed on a bounded number of
     iterations and scaled to whole solves of the GPU's iteration count."""
@@ -262,7 +282,7 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK,
-            "traffic": None,
+            "traffic": measured_traffic(dom, args.workload),
             "bytes_per_launch": kb,
             "avg_launch_us": avg_s * 1e6,
             "launches": launches,
