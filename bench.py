@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--smode", default="none", choices=["none", "identity", "dense", "auto"])
     ap.add_argument("--form", default="alg2", choices=["alg2", "alg3"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the preconditioner (factors and Algorithm 2/3); Krylov part is FP64")
     ap.add_argument("--trsv", default="hybrid", choices=["hybrid", "syncfree", "levels"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -68,37 +70,43 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "copies": 3}), flush=True)
 
 
-def step_bytes(st):
-    """Algorithmic HBM bytes of one use of each step: stored FP64 values and int32
-    column indices read once, row pointers once, a triangular solve's level list,
-    right-hand side and result once per row (plus its diagonal, and a fused addend
-    and sum), every other vector read or written once."""
+def step_bytes(st, vb=8):
+    """Algorithmic HBM bytes of one use of each step: stored values (vb bytes: 8 for
+    FP64, 4 for the FP32 preconditioner's factors and vectors) and int32 column indices
+    read once, row pointers once, a triangular solve's level list, right-hand side and
+    result once per row (plus its diagonal, and a fused addend and sum), every other
+    vector read or written once."""
     m, n = st.m, st.n
     k = m - n
     a, l1, l2, u = st.nnz_a, st.nnz_l1, st.nnz_l2, st.nnz_u
-    tri = 24 * n  # pointer, level-list entry, rhs, result per row
+    e = 4 + vb  # one stored entry
+    tri = (8 + 2 * vb) * n  # pointer, level-list entry, rhs, result per row
     return {
         "spmv_A": 12 * a + 4 * (m + 1) + 8 * n + 8 * m,
         "spmv_AT": 12 * a + 4 * (n + 1) + 8 * m + 8 * n + 8 * n,
-        "trsv_L1": 12 * l1 + tri,
-        "trsv_L1T": 12 * l1 + tri,
-        "trsv_L1T_fused": 12 * l1 + tri + 16 * n,
-        "trsv_U": 12 * u + tri + 8 * n,
-        "trsv_UT": 12 * u + tri + 8 * n,
-        "spmv_L2": 12 * l2 + 4 * (k + 1) + 8 * n + 8 * k,
-        "spmv_L2_sub": 12 * l2 + 4 * (k + 1) + 8 * n + 16 * k,
-        "spmv_L2T": 12 * l2 + 4 * (n + 1) + 8 * k + 8 * n,
+        "trsv_L1": e * l1 + tri,
+        "trsv_L1T": e * l1 + tri,
+        "trsv_L1T_fused": e * l1 + tri + 2 * vb * n,
+        "trsv_U": e * u + tri + vb * n,
+        "trsv_UT": e * u + tri + vb * n,
+        "spmv_L2": e * l2 + 4 * (k + 1) + vb * (n + k),
+        "spmv_L2_sub": e * l2 + 4 * (k + 1) + vb * (n + 2 * k),
+        "spmv_L2T": e * l2 + 4 * (n + 1) + vb * (k + n),
         "dense_S": 8 * k * (k + 1) + 16 * k,
         # x += alpha p, r -= alpha q; rho = (z, h); p = h + beta p
         "vectors": 8 * (3 * n + 3 * m) + 16 * n + 24 * n,
+        # FP32 preconditioner: input to FP32 and h back to FP64
+        "convert": 12 * n + 12 * n if vb == 4 else 0,
     }
 
 
-def iteration_bytes(st, form, smode):
+def iteration_bytes(st, form, smode, vb=8):
     """Algorithmic bytes of one iteration of Algorithm 1 with the given form."""
-    b = step_bytes(st)
+    b = step_bytes(st, vb)
     k = st.m - st.n
-    it = b["spmv_A"] + b["spmv_AT"] + b["vectors"]
+    it = b["spmv_A"] + b["spmv_AT"] + b["vectors"] + b["convert"]
+    if vb == 4 and form == "alg3":
+        it += 12 * (st.m - st.n)  # the m-vector r is converted, not only n entries
     corr = k > 0 and smode != "none"
     if form == "alg3":
         it += b["trsv_L1"] + b["trsv_U"]
@@ -200,8 +208,9 @@ def main():
     trsv = {"hybrid": R.TRSV_HYBRID, "syncfree": R.TRSV_SYNCFREE, "levels": R.TRSV_LEVELS}[args.trsv]
     form = {"alg2": R.FORM_ALG2, "alg3": R.FORM_ALG3}[args.form]
     t0 = time.perf_counter()
+    precision = {"fp64": R.PREC_FP64, "fp32": R.PREC_FP32}[args.precision]
     S = R.Solver.from_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit, trsv=trsv,
-                              form=form)
+                              form=form, precision=precision)
     t_setup = time.perf_counter() - t0
     S.upload()
     st = S.stats
@@ -239,7 +248,7 @@ def main():
     achieved = kb / avg_s if avg_s > 0 else 0.0
     t_solve = total / args.steps
     smode_used = {R.S_NONE: "none", R.S_IDENTITY: "identity", R.S_DENSE: "dense"}[st.smode]
-    b_solve = (iters + 1) * iteration_bytes(st, args.form, smode_used)
+    b_solve = (iters + 1) * iteration_bytes(st, args.form, smode_used, 4 if args.precision == "fp32" else 8)
     status = {R.OK: "converged", R.NOT_CONVERGED: "not_converged", R.BREAKDOWN: "breakdown"}.get(code, str(code))
 
     out = {
@@ -253,7 +262,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64 (preconditioner f32)",
         "data": "synthetic",
         "config": {
             "workload": prob.name + " (%s)" % args.workload,
@@ -262,6 +271,7 @@ def main():
             "S": smode_used,
             "krylov": "Algorithm 1 (PCGLS) + Algorithm %s" % args.form[-1],
             "trsv": args.trsv,
+            "precond_precision": args.precision,
             "tol": args.tol,
             "maxit": args.maxit,
             "iters": iters,

@@ -77,6 +77,18 @@ enum {
     RSILU_FORM_ALG2 = 1  /* Algorithm 2, k = n, on z = A^T r */
 };
 
+/* Precision of the preconditioner (rsilu_params_t.precision). With FP32 the
+ * factors L1, L2, U are stored in FP32 on the device and every step of
+ * Algorithm 3 or Algorithm 2 runs in FP32 (its input converted from and its
+ * output back to FP64); the products with A, the Krylov vectors, the
+ * recurrence scalars, the norms and the exit residual stay FP64. FP32 needs
+ * the hybrid or level schedule and S^ = I or none (EINVAL otherwise; AUTO
+ * resolves to I). */
+enum {
+    RSILU_PREC_FP64 = 0,
+    RSILU_PREC_FP32 = 1
+};
+
 /* Schedule of the sparse triangular solves with L1, L1^T and U. */
 enum {
     RSILU_TRSV_SYNCFREE = 0, /* one launch per solve; rows wait on their inputs */
@@ -97,6 +109,7 @@ typedef struct {
     int32_t trsv;     /* RSILU_TRSV_*; default RSILU_TRSV_HYBRID */
     int32_t poll;     /* iterations enqueued between host polls of the stop flag; 8 */
     int32_t form;     /* RSILU_FORM_*; default RSILU_FORM_ALG3 */
+    int32_t precision; /* RSILU_PREC_*; default RSILU_PREC_FP64 */
 } rsilu_params_t;
 
 typedef struct {
@@ -120,7 +133,8 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
- * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3. */
+ * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
+ * precision = FP64. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

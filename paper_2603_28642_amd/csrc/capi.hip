@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 
@@ -157,10 +158,61 @@ Ptrs ptrs(const Ctx &c)
     return P;
 }
 
-// One triangular solve with the configured schedule. Sync-free solves need x
-// sentinel-filled and their ticket cleared beforehand.
-void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv, const Sweep &sw,
-          const DevTriOff &o, const double *rhs, double *x, const double *add, double *y2, int ticket,
+// Operators and work vectors of the preconditioner in its precision T
+// (double, or float for the FP32 preconditioner: the factor operators then
+// hold FP32 values and the work vectors are read as float arrays).
+template <class T>
+struct Pre {
+    DCsrT<T> L2, L2T;
+    DTriT<T> L1f, L1b, Ub, UTf;
+    T *t, *gp, *v, *g, *y, *s2, *c2, *u, *lo_rhs, *lo_add, *segpart;
+};
+
+template <class T>
+DCsrT<T> dcsr_t(const Ctx &c, const DevCsrOff &o)
+{
+    return DCsrT<T>{at<int32_t>(c, o.ptr), at<int32_t>(c, o.col), at<T>(c, o.val), o.nrows};
+}
+
+template <class T>
+DTriT<T> dtri_t(const Ctx &c, const DevTriOff &o)
+{
+    return DTriT<T>{dcsr_t<T>(c, o.a), o.diag ? at<T>(c, o.diag) : nullptr, at<int32_t>(c, o.rows),
+                    at<int32_t>(c, o.chunk), o.nchunks, o.lanes};
+}
+
+template <class T>
+Pre<T> pre(const Ctx &c)
+{
+    const Layout &L = c.lay;
+    Pre<T> W;
+    W.L2 = dcsr_t<T>(c, L.L2);
+    W.L2T = dcsr_t<T>(c, L.L2T);
+    W.L1f = dtri_t<T>(c, L.L1f);
+    W.L1b = dtri_t<T>(c, L.L1b);
+    W.Ub = dtri_t<T>(c, L.Ub);
+    W.UTf = dtri_t<T>(c, L.UTf);
+    W.t = at<T>(c, L.t);
+    W.gp = at<T>(c, L.gp);
+    W.v = at<T>(c, L.v);
+    W.g = at<T>(c, L.g);
+    W.y = at<T>(c, L.y);
+    W.s2 = at<T>(c, L.s2);
+    W.c2 = at<T>(c, L.c2);
+    W.u = at<T>(c, L.u);
+    W.lo_rhs = at<T>(c, L.lo_rhs);
+    W.lo_add = at<T>(c, L.lo_add);
+    W.segpart = at<T>(c, L.segpart);
+    return W;
+}
+
+bool syncfree(const Ctx &c) { return c.prm.trsv == RSILU_TRSV_SYNCFREE; }
+
+// One triangular solve with the configured schedule. Sync-free solves (FP64
+// only) need x sentinel-filled and their ticket cleared beforehand.
+template <class T>
+void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const DTriT<T> &t, const Levels &lv,
+          const Sweep &sw, const DevTriOff &o, const T *rhs, T *x, const T *add, T *y2, int ticket,
           const int32_t *done, int cls)
 {
     ProfScope ps(c, s, cls);
@@ -170,65 +222,68 @@ void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const DTri &t, const Levels &lv,
         // algorithmic bytes of a launch solving `rows` rows with `nnz` stored entries:
         // values and column indices once, per row its pointer, level-list entry,
         // right-hand side and result (plus diagonal, fused addend and sum)
-        const double per_row = 24.0 + (t.diag ? 8.0 : 0.0) + (y2 ? 16.0 : 0.0);
-        auto bytes = [&](int64_t rows, int64_t nnz) { return 12.0 * (double)nnz + per_row * (double)rows; };
+        const double vb = (double)sizeof(T);
+        const double per_row = 8.0 + 2.0 * vb + (t.diag ? vb : 0.0) + (y2 ? 2.0 * vb : 0.0);
+        auto bytes = [&](int64_t rows, int64_t nnz) { return (4.0 + vb) * (double)nnz + per_row * (double)rows; };
         if (runs) {
-            ProfScope pg(c, s, RSILU_PROF_K_GATHER, (double)c.n * (y2 ? 36.0 : 20.0));
-            launch_gather_lo(s, (int32_t)c.n, t.rows, rhs, P.lo_rhs, add, y2 ? P.lo_add : nullptr, done);
+            ProfScope pg(c, s, RSILU_PROF_K_GATHER, (double)c.n * (4.0 + 2.0 * vb) * (y2 ? 2.0 : 1.0));
+            launch_gather_lo<T>(s, (int32_t)c.n, t.rows, rhs, W.lo_rhs, add, y2 ? W.lo_add : nullptr, done);
         }
         for (const Sweep::Seg &g : sw.segs) {
             if (g.wide_level >= 0) {
                 ProfScope pk(c, s, RSILU_PROF_K_LEVEL, bytes(g.rows, g.nnz));
-                launch_trsv_level(s, t, lv.ptr[g.wide_level], lv.ptr[(size_t)g.wide_level + 1], rhs, x, add, y2,
-                                  done);
+                launch_trsv_level<T>(s, t, lv.ptr[g.wide_level], lv.ptr[(size_t)g.wide_level + 1], rhs, x, add, y2,
+                                     done);
             } else {
                 const int64_t off = sw.batch_off[(size_t)g.b0];
                 const int32_t size = (int32_t)(sw.batch_off[(size_t)g.b0 + 1] - off);
                 const int32_t *h0 = reinterpret_cast<const int32_t *>(sw.blob.data() + off);
                 ProfScope pk(c, s, RSILU_PROF_K_SWEEP, bytes(g.rows, g.nnz));
-                launch_trsv_sweep(s, blob, off, size, h0[1], h0[6], g.b1 - g.b0, P.lo_rhs, x, P.lo_add, y2, done);
+                launch_trsv_sweep<T>(s, blob, off, size, h0[1], h0[6], g.b1 - g.b0, W.lo_rhs, x, W.lo_add, y2, done);
             }
         }
     } else if (c.prm.trsv == RSILU_TRSV_LEVELS) {
         for (int32_t l = 0; l < lv.nlev(); ++l)
-            launch_trsv_level(s, t, lv.ptr[l], lv.ptr[(size_t)l + 1], rhs, x, add, y2, done);
+            launch_trsv_level<T>(s, t, lv.ptr[l], lv.ptr[(size_t)l + 1], rhs, x, add, y2, done);
     } else {
-        launch_trsv_syncfree(s, t, rhs, x, add, y2, P.st, ticket, done);
+        if constexpr (std::is_same<T, double>::value) launch_trsv_syncfree(s, t, rhs, x, add, y2, P.st, ticket, done);
     }
 }
 
-bool syncfree(const Ctx &c) { return c.prm.trsv == RSILU_TRSV_SYNCFREE; }
-
-// Algorithm 3 on the residual r (pivot order) -> hout. For sync-free solves the
-// outputs t, gp, v and hout must have been sentinel-filled, tickets cleared.
-void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const double *r, double *hout, const int32_t *done)
+// Algorithm 3 on the residual r (pivot order) -> hout, in precision T. For
+// sync-free solves the outputs t, gp, v and hout must have been
+// sentinel-filled, tickets cleared.
+template <class T>
+void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *r, T *hout, const int32_t *done)
 {
     const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
     // step 1: u = r2 - Y r1 with Y r1 = L2 (L1^{-1} r1)
-    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, r, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
+    trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, r, W.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
     if (k == 0 || c.smode == RSILU_S_NONE) {
         // no A2 or no correction (w = 0): h = U^{-1} L1^{-1} r1
-        trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.t, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+        trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.t, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
         return;
     }
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2);
-        launch_spmv(s, P.L2, P.pL2, P.t, P.u, r + n, EPI_SUB, FIN_NONE, P.partials, P.segpart, P.st, done);
+        launch_spmv<T>(s, W.L2, P.pL2, W.t, W.u, r + n, EPI_SUB, FIN_NONE, P.partials, W.segpart, P.st, done);
     }
     // step 2: S^ w = u (in place in u)
-    if (c.smode == RSILU_S_DENSE) {
-        ProfScope ps(c, s, RSILU_PROF_DENSE_S);
-        launch_dense_chol_solve(s, k, P.sfac, P.u, done);
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.smode == RSILU_S_DENSE) {
+            ProfScope ps(c, s, RSILU_PROF_DENSE_S);
+            launch_dense_chol_solve(s, k, P.sfac, W.u, done);
+        }
     }
     // step 3: y = r1 + Y^T w with Y^T w = L1^{-T} (L2^T w)
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
-        launch_spmv(s, P.L2T, P.pL2T, P.u, P.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, done);
+        launch_spmv<T>(s, W.L2T, P.pL2T, W.u, W.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, done);
     }
-    trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, P.g, P.gp, r, P.y, 1, done, RSILU_PROF_TRSV_L1T);
+    trsv<T>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.g, W.gp, r, W.y, 1, done, RSILU_PROF_TRSV_L1T);
     // step 4: L1 v = y, U h = v
-    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.y, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
-    trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+    trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.y, W.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+    trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
 }
 
 // Whether Algorithm 2 carries the M_b correction (six triangular sweeps
@@ -252,44 +307,77 @@ void fill_targets(const Ctx &c, const Ptrs &P, double *hout, double *f[4])
 //   step 4  w_a = z - A2^T v_b = z - U^T L2^T v_b
 //   step 5  h = M_a^{-1} w_a = U^{-1} L1^{-1} (g - L1^{-T} L2^T v_b)
 // so U^{-T} of step 5 cancels the U^T of step 4 and g is shared.
-void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const double *z, double *hout, const int32_t *done)
+template <class T>
+void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *z, T *hout, const int32_t *done)
 {
     const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
-    trsv(c, s, P, P.UTf, c.lvUT, c.swUT, c.lay.UTf, z, P.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_UT);
-    trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, P.t, P.gp, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_L1T);
+    trsv<T>(c, s, P, W, W.UTf, c.lvUT, c.swUT, c.lay.UTf, z, W.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_UT);
+    trsv<T>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.t, W.gp, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_L1T);
     if (!alg2_correction(c)) {
-        trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.gp, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
-        trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+        trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.gp, W.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+        trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
         return;
     }
     // step 2: w_b = L2 (L1^{-1} g) into u
-    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.gp, P.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+    trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.gp, W.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2);
-        launch_spmv(s, P.L2, P.pL2, P.v, P.u, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, done);
+        launch_spmv<T>(s, W.L2, P.pL2, W.v, W.u, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, done);
     }
     // step 3: v_b = M_b^{-1} w_b in place
-    if (c.smode == RSILU_S_DENSE) {
-        ProfScope ps(c, s, RSILU_PROF_DENSE_S);
-        launch_dense_chol_solve(s, k, P.sfac, P.u, done);
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.smode == RSILU_S_DENSE) {
+            ProfScope ps(c, s, RSILU_PROF_DENSE_S);
+            launch_dense_chol_solve(s, k, P.sfac, W.u, done);
+        }
     }
     // steps 4-5: y = g + L1^{-T} (-L2^T v_b), then L1 s2 = y, U h = s2
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
-        launch_spmv(s, P.L2T, P.pL2T, P.u, P.g, nullptr, EPI_NEG, FIN_NONE, P.partials, P.segpart, P.st, done);
+        launch_spmv<T>(s, W.L2T, P.pL2T, W.u, W.g, nullptr, EPI_NEG, FIN_NONE, P.partials, W.segpart, P.st, done);
     }
-    trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, P.g, P.c2, P.gp, P.y, 3, done, RSILU_PROF_TRSV_L1T);
-    if (syncfree(c)) launch_refill(s, n, P.s2, hout, P.st, done);
-    trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, P.y, P.s2, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
-    trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, P.s2, hout, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_U);
+    trsv<T>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.g, W.c2, W.gp, W.y, 3, done, RSILU_PROF_TRSV_L1T);
+    if constexpr (std::is_same<T, double>::value) {
+        if (syncfree(c)) launch_refill(s, n, W.s2, hout, P.st, done);
+    }
+    trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.y, W.s2, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
+    trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.s2, hout, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_U);
 }
 
+// h = M^{-1} z of one iteration, in the configured form and precision. The
+// FP32 preconditioner converts its input (r or z) to FP32 and h back to FP64.
 void apply_form(Ctx &c, hipStream_t s, const Ptrs &P, double *hout, const int32_t *done)
 {
-    if (c.prm.form == RSILU_FORM_ALG2)
-        apply_alg2(c, s, P, P.z, hout, done);
+    const bool a2 = c.prm.form == RSILU_FORM_ALG2;
+    if (fp32(c)) {
+        const Pre<float> W = pre<float>(c);
+        float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
+        if (a2) {
+            launch_cvt(s, (int32_t)c.n, P.z, in, done);
+            apply_alg2<float>(c, s, P, W, in, out, done);
+        } else {
+            launch_cvt(s, (int32_t)c.m, P.r, in, done);
+            apply_alg3<float>(c, s, P, W, in, out, done);
+        }
+        launch_cvt(s, (int32_t)c.n, out, hout, done);
+        return;
+    }
+    const Pre<double> W = pre<double>(c);
+    if (a2)
+        apply_alg2<double>(c, s, P, W, P.z, hout, done);
     else
-        apply_alg3(c, s, P, P.r, hout, done);
+        apply_alg3<double>(c, s, P, W, P.r, hout, done);
+}
+
+template <class T>
+void trsv_which(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, int32_t which, const T *rhs, T *x)
+{
+    switch (which) {
+    case 0: trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1); break;
+    case 1: trsv<T>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1T); break;
+    case 2: trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_U); break;
+    default: trsv<T>(c, s, P, W, W.UTf, c.lvUT, c.swUT, c.lay.UTf, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_UT); break;
+    }
 }
 
 void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
@@ -298,7 +386,7 @@ void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
     // q = A p, alpha = rho / (q, q)
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_A);
-        launch_spmv(s, P.A, P.pA, P.p, P.q, nullptr, EPI_SQ, FIN_ALPHA, P.partials, P.segpart, P.st, P.done);
+        launch_spmv<double>(s, P.A, P.pA, P.p, P.q, nullptr, EPI_SQ, FIN_ALPHA, P.partials, P.segpart, P.st, P.done);
     }
     // x += alpha p, r -= alpha q (and prepare the sync-free outputs)
     const bool sf = syncfree(c);
@@ -308,7 +396,7 @@ void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
     // z = A^T r, stop test on ||D^{-1} z|| = ||A^T r||
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_AT);
-        launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_STOP, P.partials, P.segpart, P.st, P.done);
+        launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_STOP, P.partials, P.segpart, P.st, P.done);
     }
     // h = M^{-1} z by Algorithm 3 on (r1, r2) or Algorithm 2 on z
     apply_form(c, s, P, P.h, P.done);
@@ -486,10 +574,17 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
         if (nbytes == 0) return hipSuccess;
         return hipMemcpyAsync(static_cast<char *>(c.dev) + off, src, nbytes, hipMemcpyHostToDevice, s);
     };
+    // FP32 copies of factor values live until the copies are done (synchronised below)
+    std::vector<std::vector<float>> f32hold;
+    auto put_vals = [&](size_t off, const std::vector<double> &v, int32_t vbytes) -> hipError_t {
+        if (vbytes == 8) return put(off, v.data(), v.size() * sizeof(double));
+        f32hold.emplace_back(v.begin(), v.end());
+        return put(off, f32hold.back().data(), v.size() * sizeof(float));
+    };
     auto put_csr = [&](const DevCsrOff &o, const Csr &a) -> hipError_t {
         hipError_t e = put(o.ptr, a.ptr.data(), a.ptr.size() * sizeof(int32_t));
         if (e == hipSuccess) e = put(o.col, a.col.data(), a.col.size() * sizeof(int32_t));
-        if (e == hipSuccess) e = put(o.val, a.val.data(), a.val.size() * sizeof(double));
+        if (e == hipSuccess) e = put_vals(o.val, a.val, o.vbytes);
         return e;
     };
     auto put_plan = [&](const DevPlanOff &o, const SpmvPlan &p) -> hipError_t {
@@ -502,7 +597,7 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     auto put_tri = [&](const DevTriOff &o, const Csr &a, const std::vector<double> *diag, const Levels &lv,
                        const Chunks &ch) -> hipError_t {
         hipError_t e = put_csr(o.a, a);
-        if (e == hipSuccess && diag) e = put(o.diag, diag->data(), diag->size() * sizeof(double));
+        if (e == hipSuccess && diag) e = put_vals(o.diag, *diag, o.a.vbytes);
         if (e == hipSuccess) e = put(o.rows, lv.rows.data(), lv.rows.size() * sizeof(int32_t));
         if (e == hipSuccess) e = put(o.chunk, ch.ptr.data(), ch.ptr.size() * sizeof(int32_t));
         return e;
@@ -566,7 +661,7 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
     c.ev_open.clear();
     c.ev_next = 0;
     launch_gather(s, m, n, P.perm, b, P.r, P.xh, nullptr);
-    launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_INIT, P.partials, P.segpart, P.st, nullptr);
+    launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_INIT, P.partials, P.segpart, P.st, nullptr);
     if (sf) {
         double *f[4];
         fill_targets(c, P, P.h, f);
@@ -596,9 +691,9 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
 
     // ---- exit: x = D x_hat; true ||A^T (b - A x)|| recomputed from x_hat
     launch_scale_out(s, n, P.xh, P.colnorm, x);
-    launch_spmv(s, P.A, P.pA, P.xh, P.q, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr);
+    launch_spmv<double>(s, P.A, P.pA, P.xh, P.q, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr);
     launch_residual(s, m, P.perm, b, P.q, P.r);
-    launch_spmv(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_ATR, P.partials, P.segpart, P.st, nullptr);
+    launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_ATR, P.partials, P.segpart, P.st, nullptr);
     RSILU_HIP(hipGetLastError());
     RSILU_HIP(hipMemcpyAsync(&mail->poll, P.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     RSILU_HIP(hipStreamSynchronize(s));
@@ -618,12 +713,31 @@ rsilu_status_t rsilu_spmv(rsilu_handle_t h, int32_t op, const double *xin, doubl
     rsilu_status_t rc = check_ready(h);
     if (rc != RSILU_OK) return rc;
     if (!xin || !y || static_cast<const void *>(xin) == static_cast<const void *>(y)) return RSILU_EINVAL;
-    const Ptrs P = ptrs(*h);
+    Ctx &c = *h;
+    const Ptrs P = ptrs(c);
+    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
     switch (op) {
-    case 0: launch_spmv(s, P.A, P.pA, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
-    case 1: launch_spmv(s, P.AT, P.pAT, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
-    case 2: launch_spmv(s, P.L2, P.pL2, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
-    case 3: launch_spmv(s, P.L2T, P.pL2T, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
+    case 0: launch_spmv<double>(s, P.A, P.pA, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
+    case 1: launch_spmv<double>(s, P.AT, P.pAT, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
+    case 2:
+    case 3: {
+        // products with L2 and L2^T in the preconditioner's precision
+        const bool l2 = op == 2;
+        const int32_t nin = l2 ? n : k, nout = l2 ? k : n;
+        if (fp32(c)) {
+            const Pre<float> W = pre<float>(c);
+            float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
+            launch_cvt(s, nin, xin, in, nullptr);
+            launch_spmv<float>(s, l2 ? W.L2 : W.L2T, l2 ? P.pL2 : P.pL2T, in, out, nullptr, EPI_PLAIN, FIN_NONE,
+                               P.partials, W.segpart, P.st, nullptr);
+            launch_cvt(s, nout, out, y, nullptr);
+        } else {
+            const Pre<double> W = pre<double>(c);
+            launch_spmv<double>(s, l2 ? W.L2 : W.L2T, l2 ? P.pL2 : P.pL2T, xin, y, nullptr, EPI_PLAIN, FIN_NONE,
+                                P.partials, W.segpart, P.st, nullptr);
+        }
+        break;
+    }
     default: return RSILU_EINVAL;
     }
     RSILU_HIP(hipGetLastError());
@@ -635,16 +749,18 @@ rsilu_status_t rsilu_trsv(rsilu_handle_t h, int32_t which, const double *rhs, do
     rsilu_status_t rc = check_ready(h);
     if (rc != RSILU_OK) return rc;
     if (!rhs || !x || static_cast<const void *>(rhs) == static_cast<const void *>(x)) return RSILU_EINVAL;
+    if (which < 0 || which > 3) return RSILU_EINVAL;
     Ctx &c = *h;
     const Ptrs P = ptrs(c);
     const int32_t n = (int32_t)c.n;
-    if (syncfree(c)) launch_fill(s, n, x, nullptr, nullptr, nullptr, P.st);
-    switch (which) {
-    case 0: trsv(c, s, P, P.L1f, c.lvL1, c.swL1, c.lay.L1f, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1); break;
-    case 1: trsv(c, s, P, P.L1b, c.lvL1T, c.swL1T, c.lay.L1b, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_L1T); break;
-    case 2: trsv(c, s, P, P.Ub, c.lvU, c.swU, c.lay.Ub, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_U); break;
-    case 3: trsv(c, s, P, P.UTf, c.lvUT, c.swUT, c.lay.UTf, rhs, x, nullptr, nullptr, 0, nullptr, RSILU_PROF_TRSV_UT); break;
-    default: return RSILU_EINVAL;
+    if (fp32(c)) {
+        float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
+        launch_cvt(s, n, rhs, in, nullptr);
+        trsv_which<float>(c, s, P, pre<float>(c), which, in, out);
+        launch_cvt(s, n, out, x, nullptr);
+    } else {
+        if (syncfree(c)) launch_fill(s, n, x, nullptr, nullptr, nullptr, P.st);
+        trsv_which<double>(c, s, P, pre<double>(c), which, rhs, x);
     }
     RSILU_HIP(hipGetLastError());
     return RSILU_OK;
@@ -657,8 +773,15 @@ rsilu_status_t rsilu_apply(rsilu_handle_t h, const double *r, double *hout, hipS
     if (!r || !hout || static_cast<const void *>(r) == static_cast<const void *>(hout)) return RSILU_EINVAL;
     Ctx &c = *h;
     const Ptrs P = ptrs(c);
-    if (syncfree(c)) launch_fill(s, (int32_t)c.n, P.t, P.gp, P.v, hout, P.st);
-    apply_alg3(c, s, P, r, hout, nullptr);
+    if (fp32(c)) {
+        float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
+        launch_cvt(s, (int32_t)c.m, r, in, nullptr);
+        apply_alg3<float>(c, s, P, pre<float>(c), in, out, nullptr);
+        launch_cvt(s, (int32_t)c.n, out, hout, nullptr);
+    } else {
+        if (syncfree(c)) launch_fill(s, (int32_t)c.n, P.t, P.gp, P.v, hout, P.st);
+        apply_alg3<double>(c, s, P, pre<double>(c), r, hout, nullptr);
+    }
     RSILU_HIP(hipGetLastError());
     return RSILU_OK;
 }
@@ -670,8 +793,15 @@ rsilu_status_t rsilu_apply_z(rsilu_handle_t h, const double *z, double *hout, hi
     if (!z || !hout || static_cast<const void *>(z) == static_cast<const void *>(hout)) return RSILU_EINVAL;
     Ctx &c = *h;
     const Ptrs P = ptrs(c);
-    if (syncfree(c)) launch_fill(s, (int32_t)c.n, P.t, P.gp, P.v, alg2_correction(c) ? P.c2 : hout, P.st);
-    apply_alg2(c, s, P, z, hout, nullptr);
+    if (fp32(c)) {
+        float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
+        launch_cvt(s, (int32_t)c.n, z, in, nullptr);
+        apply_alg2<float>(c, s, P, pre<float>(c), in, out, nullptr);
+        launch_cvt(s, (int32_t)c.n, out, hout, nullptr);
+    } else {
+        if (syncfree(c)) launch_fill(s, (int32_t)c.n, P.t, P.gp, P.v, alg2_correction(c) ? P.c2 : hout, P.st);
+        apply_alg2<double>(c, s, P, pre<double>(c), z, hout, nullptr);
+    }
     RSILU_HIP(hipGetLastError());
     return RSILU_OK;
 }

@@ -65,6 +65,7 @@ struct DevCsrOff {
     size_t ptr = 0, col = 0, val = 0;
     int32_t nrows = 0, ncols = 0;
     int64_t nnz = 0;
+    int32_t vbytes = 8;  // 8: FP64 values, 4: FP32 (factors of the FP32 preconditioner)
 };
 struct DevPlanOff {
     size_t long_rows = 0, seg_ptr = 0, seg_beg = 0, seg_end = 0;
@@ -93,6 +94,7 @@ struct Layout {
     size_t r = 0, q = 0;                                                       // m
     size_t u = 0;                                                              // m - n
     size_t lo_rhs = 0, lo_add = 0;  // level-ordered right-hand side and addend of a sweep (n)
+    size_t f32a = 0, f32b = 0;      // FP32 preconditioner: converted input and output (m floats each)
     size_t partials = 0;  // reduction partials
     int32_t npartials = 0;
     size_t segpart = 0;   // long-row segment partials
@@ -139,6 +141,8 @@ struct Ctx {
     double prof_ms[RSILU_PROF_COUNT] = {};
     double prof_bytes[RSILU_PROF_COUNT] = {};
 };
+
+inline bool fp32(const Ctx &c) { return c.prm.precision == RSILU_PREC_FP32; }
 
 // host setup (setup.cpp)
 rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *rowptr,

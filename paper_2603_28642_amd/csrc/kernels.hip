@@ -17,6 +17,8 @@
 #include <cmath>
 #include <cstdint>
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -33,8 +35,8 @@ constexpr int kSpinLimit = 1 << 20;
 
 __device__ __forceinline__ bool stop_now(const int32_t *done) { return done != nullptr && *done != 0; }
 
-template <int G>
-__device__ __forceinline__ double group_sum(double v)
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v)
 {
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -120,9 +122,9 @@ __device__ void apply_fin(Fin fin, double total, DevState *st)
 
 // ------------------------------------------------------------------ products
 
-template <int G, int EPI>
-__global__ __launch_bounds__(kBlock) void k_spmv(DCsr a, int32_t long_thresh, const double *__restrict__ x,
-                                                  double *__restrict__ y, const double *__restrict__ aux,
+template <int G, int EPI, class T>
+__global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh, const T *__restrict__ x,
+                                                  T *__restrict__ y, const T *__restrict__ aux,
                                                   double *__restrict__ partials, const int32_t *done)
 {
     __shared__ double lds4[4];
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsr a, int32_t long_thresh, co
     constexpr int RPB = kBlock / G;
     const int row = blockIdx.x * RPB + threadIdx.x / G;
     const int gl = threadIdx.x % G;
-    double sum = 0.0;
+    T sum = 0;
     bool own = false;
     if (row < a.nrows) {
         const int b = a.ptr[row], e = a.ptr[row + 1];
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsr a, int32_t long_thresh, co
     sum = group_sum<G>(sum);
     double contrib = 0.0;
     if (own && gl == 0) {
-        double out = sum;
+        T out = sum;
         if (EPI == EPI_SUB) out = aux[row] - sum;
         if (EPI == EPI_NEG) out = -sum;
         y[row] = out;
@@ -152,32 +154,32 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsr a, int32_t long_thresh, co
             contrib = t * t;
         }
     }
-    if (EPI == EPI_SQ || EPI == EPI_WSQ) {
+    if constexpr (EPI == EPI_SQ || EPI == EPI_WSQ) {
         const double s = block_sum256(contrib, lds4);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
 }
 
 // One block per segment of a long row.
-__global__ __launch_bounds__(kBlock) void k_spmv_seg(DCsr a, DPlan pl, const double *__restrict__ x,
-                                                      double *__restrict__ segpart, const int32_t *done)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_seg(DCsrT<T> a, DPlan pl, const T *__restrict__ x,
+                                                      T *__restrict__ segpart, const int32_t *done)
 {
     __shared__ double lds4[4];
     if (stop_now(done)) return;
     const int s = blockIdx.x;
     const int b = pl.seg_beg[s], e = pl.seg_end[s];
-    double sum = 0.0;
+    T sum = 0;
     for (int k = b + threadIdx.x; k < e; k += kBlock) sum += a.val[k] * x[a.col[k]];
-    const double t = block_sum256(sum, lds4);
-    if (threadIdx.x == 0) segpart[s] = t;
+    const double t = block_sum256((double)sum, lds4);
+    if (threadIdx.x == 0) segpart[s] = (T)t;
 }
 
 // Single block: finish the long rows, reduce the partials in index order and
 // take the scalar step of Algorithm 1 selected by `fin`.
-template <int EPI>
-__global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, double *__restrict__ y,
-                                                    const double *__restrict__ aux,
-                                                    const double *__restrict__ segpart,
+template <int EPI, class T>
+__global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, T *__restrict__ y,
+                                                    const T *__restrict__ aux, const T *__restrict__ segpart,
                                                     double *__restrict__ partials, Fin fin, DevState *st,
                                                     const int32_t *done)
 {
@@ -185,9 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, dou
     if (stop_now(done)) return;
     for (int i = threadIdx.x; i < pl.nlong; i += kBlock) {
         const int row = pl.long_rows[i];
-        double s = 0.0;
+        T s = 0;
         for (int q = pl.seg_ptr[i]; q < pl.seg_ptr[i + 1]; ++q) s += segpart[q];
-        double out = (EPI == EPI_SUB) ? aux[row] - s : (EPI == EPI_NEG ? -s : s);
+        T out = (EPI == EPI_SUB) ? aux[row] - s : (EPI == EPI_NEG ? -s : s);
         y[row] = out;
         double c = 0.0;
         if (EPI == EPI_SQ) c = out * out;
@@ -322,6 +324,14 @@ __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const double *__rest
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
 }
 
+template <class A, class B>
+__global__ __launch_bounds__(kBlock) void k_cvt(int32_t n, const A *__restrict__ in, B *__restrict__ out,
+                                                 const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = (B)in[i];
+}
+
 // ------------------------------------------------------------------ triangular solves
 
 template <int G>
@@ -380,10 +390,9 @@ __global__ __launch_bounds__(kBlock) void k_trsv_syncfree(DTri t, const double *
     }
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_trsv_level(DTri t, int32_t beg, int32_t end,
-                                                        const double *__restrict__ rhs, double *x,
-                                                        const double *__restrict__ add, double *__restrict__ y2,
+template <int G, class T>
+__global__ __launch_bounds__(kBlock) void k_trsv_level(DTriT<T> t, int32_t beg, int32_t end, const T *__restrict__ rhs,
+                                                        T *x, const T *__restrict__ add, T *__restrict__ y2,
                                                         const int32_t *done)
 {
     if (stop_now(done)) return;
@@ -392,14 +401,14 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(DTri t, int32_t beg, int3
     const int gl = threadIdx.x % G;
     const bool act = idx < end;
     const int row = act ? t.rows[idx] : 0;
-    double sum = 0.0;
+    T sum = 0;
     if (act) {
         const int b = t.a.ptr[row], e = t.a.ptr[row + 1];
         for (int k = b + gl; k < e; k += G) sum += t.a.val[k] * x[t.a.col[k]];
     }
     sum = group_sum<G>(sum);
     if (act && gl == 0) {
-        double r = rhs[row] - sum;
+        T r = rhs[row] - sum;
         if (t.diag) r = r / t.diag[row];
         x[row] = r;
         if (y2) y2[row] = add[row] + r;
@@ -419,33 +428,59 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(DTri t, int32_t beg, int3
 // cur_base, p0, size, next_size, next_npos, next_next, nchunk},
 // lev_off[nlev+1], lev_chunk[nlev+1], rowid[npos], ext_idx[next],
 // next_ext[kSweepExt], uint16 rchunk[npos+1], cstart[nchunk+1], eslot[nent],
-// then (8-aligned) double eval[nent], diag[npos]. A row's entries are cut into
-// chunks of at most kSweepChunk; eslot indexes the LDS window xw = [even
-// batches' results | odd batches' results | older inputs].
+// then (16-aligned) T eval[nent], diag[npos] (T = double, or float for the
+// FP32 preconditioner). A row's entries are cut into chunks of at most
+// kSweepChunk; eslot indexes the LDS window xw = [even batches' results | odd
+// batches' results | older inputs].
+template <class T>
+__device__ __forceinline__ void load_chunk(const unsigned char *vb, int c, T &a, T &b, T &cc, T &d);
+template <>
+__device__ __forceinline__ void load_chunk<double>(const unsigned char *vb, int c, double &a, double &b, double &cc,
+                                                   double &d)
+{
+    const double2 *v = reinterpret_cast<const double2 *>(vb);
+    const double2 p = v[2 * c], q = v[2 * c + 1];
+    a = p.x;
+    b = p.y;
+    cc = q.x;
+    d = q.y;
+}
+template <>
+__device__ __forceinline__ void load_chunk<float>(const unsigned char *vb, int c, float &a, float &b, float &cc,
+                                                  float &d)
+{
+    const float4 p = reinterpret_cast<const float4 *>(vb)[c];
+    a = p.x;
+    b = p.y;
+    cc = p.z;
+    d = p.w;
+}
+
+template <class T>
 __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned char *__restrict__ blob, int64_t off,
                                                                int32_t size, int32_t npos_first, int32_t p0,
-                                                               int32_t nb, const double *__restrict__ rhs_lo,
-                                                               double *x, const double *__restrict__ add_lo,
-                                                               double *y2, const int32_t *done)
+                                                               int32_t nb, const T *__restrict__ rhs_lo, T *x,
+                                                               const T *__restrict__ add_lo, T *y2,
+                                                               const int32_t *done)
 {
     constexpr int VB = (kSweepBlob / 16 + kSweepThreads - 1) / kSweepThreads;
     constexpr int VP = (kSweepPos + kSweepThreads - 1) / kSweepThreads;
     constexpr int VE = (kSweepExt + kSweepThreads - 1) / kSweepThreads;
     __shared__ __attribute__((aligned(16))) unsigned char sb[kSweepBlob];
-    __shared__ double xw[2 * kSweepPos + kSweepExt + 8];
-    __shared__ double rl[kSweepPos];
-    __shared__ double al[kSweepPos];
-    __shared__ double prod[kSweepLevEnt];
+    __shared__ T xw[2 * kSweepPos + kSweepExt + 8];
+    __shared__ T rl[kSweepPos];
+    __shared__ T al[kSweepPos];
+    __shared__ T prod[kSweepLevEnt];
     if (stop_now(done)) return;
     const int tid = threadIdx.x;
-    if (tid == 0) xw[kSweepZeroSlot] = 0.0;
+    if (tid == 0) xw[kSweepZeroSlot] = 0;
     static_assert(VB <= 5 && VP == 2 && VE == 2, "staging registers are written out for these limits");
     // Staging registers for the next batch. Loads are unconditional with
     // clamped indices (always in bounds: a batch has at least one row and one
     // blob vector) so the values stay in registers; only LDS writes are
     // predicated.
     uint4 rb0, rb1, rb2, rb3, rb4;
-    double rr0, rr1, ra0, ra1, re0, re1;
+    T rr0, rr1, ra0, ra1, re0, re1;
     uint4 *sb4 = reinterpret_cast<uint4 *>(sb);
     const int t0 = tid, t1 = tid + kSweepThreads, t2 = tid + 2 * kSweepThreads, t3 = tid + 3 * kSweepThreads,
               t4 = tid + 4 * kSweepThreads;
@@ -460,14 +495,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
         if (VB > 4) rb4 = src_[min(t4, lastv_)];                                        \
         rr0 = rhs_lo[(BP0) + min(t0, lastp_)];                                          \
         rr1 = rhs_lo[(BP0) + min(t1, lastp_)];                                          \
-        ra0 = y2 ? add_lo[(BP0) + min(t0, lastp_)] : 0.0;                               \
-        ra1 = y2 ? add_lo[(BP0) + min(t1, lastp_)] : 0.0;                               \
+        ra0 = y2 ? add_lo[(BP0) + min(t0, lastp_)] : (T)0;                              \
+        ra1 = y2 ? add_lo[(BP0) + min(t1, lastp_)] : (T)0;                              \
     }
 #define RSILU_LOAD_EXT(LIST, CNT)                                                       \
     {                                                                                   \
         const int lastj_ = (CNT) - 1;                                                   \
-        re0 = (CNT) > 0 ? x[(LIST)[min(t0, lastj_)]] : 0.0;                             \
-        re1 = (CNT) > 0 ? x[(LIST)[min(t1, lastj_)]] : 0.0;                             \
+        re0 = (CNT) > 0 ? x[(LIST)[min(t0, lastj_)]] : (T)0;                            \
+        re1 = (CNT) > 0 ? x[(LIST)[min(t1, lastj_)]] : (T)0;                            \
     }
 #define RSILU_STORE_BATCH(NVEC, BNPOS)                                                  \
     {                                                                                   \
@@ -515,9 +550,9 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
         const uint16_t *rchunk = reinterpret_cast<const uint16_t *>(next_ext + kSweepExt);
         const int o_slot = ((int)(reinterpret_cast<const unsigned char *>(rchunk + npos + 1) - sb) + 7) & ~7;
         const int o_val = (o_slot + 8 * nchunk + 15) & ~15;
-        const uint2 *eslot4 = reinterpret_cast<const uint2 *>(sb + o_slot);      // 4 uint16 slots per chunk
-        const double2 *eval2 = reinterpret_cast<const double2 *>(sb + o_val);   // 4 values per chunk
-        const double *dg = reinterpret_cast<const double *>(sb + o_val + 32 * nchunk);
+        const uint2 *eslot4 = reinterpret_cast<const uint2 *>(sb + o_slot);  // 4 uint16 slots per chunk
+        const unsigned char *evals = sb + o_val;                             // 4 values per chunk
+        const T *dg = reinterpret_cast<const T *>(sb + o_val + 4 * (int)sizeof(T) * nchunk);
         (void)nent;
         // level offsets live in the lanes of every wavefront (nlev <= 63)
         const int lane = tid & 63;
@@ -537,10 +572,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
         struct Meta {
             int cidx;      // chunk index in the level (-1: none)
             uint2 sl;      // four LDS slots
-            double2 v01, v23;
+            T v0, v1, v2, v3;
             int pidx;      // row position in the batch (-1: none)
             int c0, nch;   // the row's chunks, relative to the level
-            double rhs, dg, add;
+            T rhs, dg, add;
             int row;
         };
         auto fetch = [&](int L) {
@@ -552,8 +587,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             if (c < cb) {
                 m.cidx = tid;
                 m.sl = eslot4[c];
-                m.v01 = eval2[2 * c];
-                m.v23 = eval2[2 * c + 1];
+                load_chunk<T>(evals, c, m.v0, m.v1, m.v2, m.v3);
             }
             const int p = pa + tid;
             m.pidx = -1;
@@ -562,8 +596,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                 m.c0 = rchunk[p] - ca;
                 m.nch = rchunk[p + 1] - rchunk[p];
                 m.rhs = rl[p];
-                m.dg = hd ? dg[p] : 1.0;
-                m.add = y2 ? al[p] : 0.0;
+                m.dg = hd ? dg[p] : (T)1;
+                m.add = y2 ? al[p] : (T)0;
                 m.row = rowid[p];
             }
             return m;
@@ -572,27 +606,27 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             const Meta m = fetch(L);
             // chunk sums: kSweepChunk entries of one row (padded with the zero slot)
             if (m.cidx >= 0) {
-                double s = m.v01.x * xw[m.sl.x & 0xffffu];
-                s += m.v01.y * xw[m.sl.x >> 16];
-                s += m.v23.x * xw[m.sl.y & 0xffffu];
-                s += m.v23.y * xw[m.sl.y >> 16];
+                T s = m.v0 * xw[m.sl.x & 0xffffu];
+                s += m.v1 * xw[m.sl.x >> 16];
+                s += m.v2 * xw[m.sl.y & 0xffffu];
+                s += m.v3 * xw[m.sl.y >> 16];
                 prod[m.cidx] = s;
             }
             __syncthreads();
             // row sums over the row's chunk sums (up to four read at once)
             if (m.pidx >= 0) {
-                double s = 0.0;
+                T s = 0;
                 if (m.nch > 0) {
                     const int c0 = m.c0, last = m.c0 + m.nch - 1;
-                    const double a0 = prod[c0], a1 = prod[min(c0 + 1, last)], a2 = prod[min(c0 + 2, last)],
-                                 a3 = prod[min(c0 + 3, last)];
+                    const T a0 = prod[c0], a1 = prod[min(c0 + 1, last)], a2 = prod[min(c0 + 2, last)],
+                            a3 = prod[min(c0 + 3, last)];
                     s = a0;
                     s = m.nch > 1 ? s + a1 : s;
                     s = m.nch > 2 ? s + a2 : s;
                     s = m.nch > 3 ? s + a3 : s;
                     for (int c = c0 + 4; c <= last; ++c) s += prod[c];
                 }
-                double r = m.rhs - s;
+                T r = m.rhs - s;
                 if (hd) r = r / m.dg;
                 xw[cur + m.pidx] = r;
                 x[m.row] = r;
@@ -615,9 +649,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
 #undef RSILU_STORE_EXT
 }
 
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_gather_lo(int32_t n, const int32_t *__restrict__ rows,
-                                                       const double *__restrict__ src, double *__restrict__ dst,
-                                                       const double *__restrict__ src2, double *__restrict__ dst2,
+                                                       const T *__restrict__ src, T *__restrict__ dst,
+                                                       const T *__restrict__ src2, T *__restrict__ dst2,
                                                        const int32_t *done)
 {
     if (stop_now(done)) return;
@@ -713,13 +748,13 @@ int grid_for(long long n, int cap = 8192)
     return (int)g;
 }
 
-template <int EPI>
-void spmv_dispatch(hipStream_t s, int lanes, int blocks, const DCsr &a, int32_t lt, const double *x, double *y,
-                   const double *aux, double *partials, const int32_t *done)
+template <int EPI, class T>
+void spmv_dispatch(hipStream_t s, int lanes, int blocks, const DCsrT<T> &a, int32_t lt, const T *x, T *y,
+                   const T *aux, double *partials, const int32_t *done)
 {
-#define RSILU_SPMV_CASE(G)                                                                                     \
-    case G:                                                                                                    \
-        hipLaunchKernelGGL((k_spmv<G, EPI>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done); \
+#define RSILU_SPMV_CASE(G)                                                                                        \
+    case G:                                                                                                       \
+        hipLaunchKernelGGL((k_spmv<G, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done); \
         break;
     switch (lanes) {
         RSILU_SPMV_CASE(2)
@@ -729,7 +764,7 @@ void spmv_dispatch(hipStream_t s, int lanes, int blocks, const DCsr &a, int32_t 
         RSILU_SPMV_CASE(32)
         RSILU_SPMV_CASE(64)
     default:
-        hipLaunchKernelGGL((k_spmv<64, EPI>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done);
+        hipLaunchKernelGGL((k_spmv<64, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done);
     }
 #undef RSILU_SPMV_CASE
 }
@@ -744,48 +779,60 @@ void launch_gather(hipStream_t s, int32_t m, int32_t n, const int32_t *perm, con
     hipLaunchKernelGGL(k_gather, dim3(grid_for(m)), dim3(kBlock), 0, s, m, n, perm, b, r, xh, done);
 }
 
-void launch_spmv(hipStream_t s, const DCsr &a, const DPlan &pl, const double *x, double *y, const double *aux,
-                 Epi epi, Fin fin, double *partials, double *segpart, DevState *st, const int32_t *done)
+template <class T>
+void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, T *y, const T *aux, Epi epi,
+                 Fin fin, double *partials, T *segpart, DevState *st, const int32_t *done)
 {
     if (a.nrows <= 0) return;
     const int lanes = pl.lanes;
     const int blocks = (int)((a.nrows + (kBlock / lanes) - 1) / (kBlock / lanes));
+    constexpr bool fp64 = std::is_same<T, double>::value;
     switch (epi) {
-    case EPI_PLAIN: spmv_dispatch<EPI_PLAIN>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_SQ: spmv_dispatch<EPI_SQ>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_SUB: spmv_dispatch<EPI_SUB>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_WSQ: spmv_dispatch<EPI_WSQ>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_NEG: spmv_dispatch<EPI_NEG>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_PLAIN: spmv_dispatch<EPI_PLAIN, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_SUB: spmv_dispatch<EPI_SUB, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_NEG: spmv_dispatch<EPI_NEG, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_SQ:
+        if constexpr (fp64) spmv_dispatch<EPI_SQ, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done);
+        break;
+    case EPI_WSQ:
+        if constexpr (fp64) spmv_dispatch<EPI_WSQ, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done);
+        break;
     }
     if (pl.nseg > 0)
-        hipLaunchKernelGGL(k_spmv_seg, dim3(pl.nseg), dim3(kBlock), 0, s, a, pl, x, segpart, done);
+        hipLaunchKernelGGL(k_spmv_seg<T>, dim3(pl.nseg), dim3(kBlock), 0, s, a, pl, x, segpart, done);
     const bool norm = (epi == EPI_SQ || epi == EPI_WSQ);
     if (pl.nlong > 0 || (norm && fin != FIN_NONE)) {
         const int nparts = norm ? blocks : 0;
         switch (epi) {
         case EPI_PLAIN:
-            hipLaunchKernelGGL(k_finish<EPI_PLAIN>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
-                               fin, st, done);
-            break;
-        case EPI_SQ:
-            hipLaunchKernelGGL(k_finish<EPI_SQ>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
-                               fin, st, done);
+            hipLaunchKernelGGL((k_finish<EPI_PLAIN, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
+                               partials, fin, st, done);
             break;
         case EPI_SUB:
-            hipLaunchKernelGGL(k_finish<EPI_SUB>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
-                               fin, st, done);
-            break;
-        case EPI_WSQ:
-            hipLaunchKernelGGL(k_finish<EPI_WSQ>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
-                               fin, st, done);
+            hipLaunchKernelGGL((k_finish<EPI_SUB, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
+                               partials, fin, st, done);
             break;
         case EPI_NEG:
-            hipLaunchKernelGGL(k_finish<EPI_NEG>, dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart, partials,
-                               fin, st, done);
+            hipLaunchKernelGGL((k_finish<EPI_NEG, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
+                               partials, fin, st, done);
+            break;
+        case EPI_SQ:
+            if constexpr (fp64)
+                hipLaunchKernelGGL((k_finish<EPI_SQ, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
+                                   partials, fin, st, done);
+            break;
+        case EPI_WSQ:
+            if constexpr (fp64)
+                hipLaunchKernelGGL((k_finish<EPI_WSQ, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
+                                   partials, fin, st, done);
             break;
         }
     }
 }
+template void launch_spmv<double>(hipStream_t, const DCsrT<double> &, const DPlan &, const double *, double *,
+                                  const double *, Epi, Fin, double *, double *, DevState *, const int32_t *);
+template void launch_spmv<float>(hipStream_t, const DCsrT<float> &, const DPlan &, const float *, float *,
+                                 const float *, Epi, Fin, double *, float *, DevState *, const int32_t *);
 
 void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin fin, double *partials,
                 DevState *st, const int32_t *done)
@@ -859,15 +906,16 @@ void launch_trsv_syncfree(hipStream_t s, const DTri &t, const double *rhs, doubl
 #undef RSILU_TRSV_CASE
 }
 
-void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, const double *rhs, double *x,
-                       const double *add, double *y2, const int32_t *done)
+template <class T>
+void launch_trsv_level(hipStream_t s, const DTriT<T> &t, int32_t beg, int32_t end, const T *rhs, T *x, const T *add,
+                       T *y2, const int32_t *done)
 {
     const int rpb = kBlock / t.lanes;
     const int blocks = (end - beg + rpb - 1) / rpb;
     if (blocks <= 0) return;
 #define RSILU_TRSVL_CASE(G)                                                                                      \
     case G:                                                                                                      \
-        hipLaunchKernelGGL(k_trsv_level<G>, dim3(blocks), dim3(kBlock), 0, s, t, beg, end, rhs, x, add, y2, done); \
+        hipLaunchKernelGGL((k_trsv_level<G, T>), dim3(blocks), dim3(kBlock), 0, s, t, beg, end, rhs, x, add, y2, done); \
         break;
     switch (t.lanes) {
         RSILU_TRSVL_CASE(1)
@@ -882,20 +930,43 @@ void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, c
     }
 #undef RSILU_TRSVL_CASE
 }
+template void launch_trsv_level<double>(hipStream_t, const DTriT<double> &, int32_t, int32_t, const double *, double *,
+                                        const double *, double *, const int32_t *);
+template void launch_trsv_level<float>(hipStream_t, const DTriT<float> &, int32_t, int32_t, const float *, float *,
+                                       const float *, float *, const int32_t *);
 
+template <class T>
 void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
-                       int32_t p0, int32_t nb, const double *rhs_lo, double *x, const double *add_lo, double *y2,
-                       const int32_t *done)
+                       int32_t p0, int32_t nb, const T *rhs_lo, T *x, const T *add_lo, T *y2, const int32_t *done)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_trsv_sweep, dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0, nb, rhs_lo,
-                       x, add_lo, y2, done);
+    hipLaunchKernelGGL(k_trsv_sweep<T>, dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0, nb,
+                       rhs_lo, x, add_lo, y2, done);
+}
+template void launch_trsv_sweep<double>(hipStream_t, const unsigned char *, int64_t, int32_t, int32_t, int32_t, int32_t,
+                                        const double *, double *, const double *, double *, const int32_t *);
+template void launch_trsv_sweep<float>(hipStream_t, const unsigned char *, int64_t, int32_t, int32_t, int32_t, int32_t,
+                                       const float *, float *, const float *, float *, const int32_t *);
+
+template <class T>
+void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const T *src, T *dst, const T *src2, T *dst2,
+                      const int32_t *done)
+{
+    hipLaunchKernelGGL(k_gather_lo<T>, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rows, src, dst, src2, dst2, done);
+}
+template void launch_gather_lo<double>(hipStream_t, int32_t, const int32_t *, const double *, double *, const double *,
+                                       double *, const int32_t *);
+template void launch_gather_lo<float>(hipStream_t, int32_t, const int32_t *, const float *, float *, const float *,
+                                      float *, const int32_t *);
+
+void launch_cvt(hipStream_t s, int32_t n, const double *in, float *out, const int32_t *done)
+{
+    hipLaunchKernelGGL((k_cvt<double, float>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out, done);
 }
 
-void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const double *src, double *dst,
-                      const double *src2, double *dst2, const int32_t *done)
+void launch_cvt(hipStream_t s, int32_t n, const float *in, double *out, const int32_t *done)
 {
-    hipLaunchKernelGGL(k_gather_lo, dim3(grid_for(n)), dim3(kBlock), 0, s, n, rows, src, dst, src2, dst2, done);
+    hipLaunchKernelGGL((k_cvt<float, double>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, in, out, done);
 }
 
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done)

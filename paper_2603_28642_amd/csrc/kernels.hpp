@@ -25,13 +25,16 @@ struct alignas(256) DevState {
     uint32_t ticket[4];  // chunk dispensers of the sync-free solves
 };
 
-// CSR operator in device memory.
-struct DCsr {
+// CSR operator in device memory (values in FP64, or FP32 for the factors of
+// the FP32 preconditioner).
+template <class T>
+struct DCsrT {
     const int32_t *ptr;
     const int32_t *col;
-    const double *val;
+    const T *val;
     int32_t nrows;
 };
+using DCsr = DCsrT<double>;
 
 // Split of long rows into fixed segments (reduced in a fixed order).
 struct DPlan {
@@ -44,14 +47,16 @@ struct DPlan {
 
 // Triangular operator: strictly triangular CSR, optional diagonal, level-ordered rows,
 // chunks of one level each.
-struct DTri {
-    DCsr a;
-    const double *diag;   // nullptr: unit diagonal
+template <class T>
+struct DTriT {
+    DCsrT<T> a;
+    const T *diag;        // nullptr: unit diagonal
     const int32_t *rows;  // rows in level order
     const int32_t *chunk; // nchunks + 1 positions into rows
     int32_t nchunks;
     int32_t lanes;        // lanes per row (64 / chunk capacity)
 };
+using DTri = DTriT<double>;
 
 enum Epi : int32_t {
     EPI_PLAIN = 0,  // y = A x
@@ -60,6 +65,7 @@ enum Epi : int32_t {
     EPI_WSQ = 3,    // y = A x, partial sums of (aux * y)^2
     EPI_NEG = 4     // y = -A x
 };
+// (the FP32 products use EPI_PLAIN, EPI_SUB and EPI_NEG only)
 
 enum Fin : int32_t {
     FIN_NONE = 0,   // long rows only
@@ -79,8 +85,9 @@ void launch_gather(hipStream_t s, int32_t m, int32_t n, const int32_t *perm, con
                    double *xh, const int32_t *done);
 // y = op(A) x with epilogue; long rows through segments; partial sums of the
 // epilogue norm, then the single-block finish (reduction + scalar step).
-void launch_spmv(hipStream_t s, const DCsr &a, const DPlan &pl, const double *x, double *y, const double *aux,
-                 Epi epi, Fin fin, double *partials, double *segpart, DevState *st, const int32_t *done);
+template <class T>
+void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, T *y, const T *aux, Epi epi,
+                 Fin fin, double *partials, T *segpart, DevState *st, const int32_t *done);
 void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin fin, double *partials,
                 DevState *st, const int32_t *done);
 // x_hat += alpha p; r -= alpha q; sentinel-fill the sync-free outputs; reset tickets
@@ -97,17 +104,22 @@ void launch_residual(hipStream_t s, int32_t m, const int32_t *perm, const double
 // Sync-free: x must be sentinel-filled and the ticket zero (launch_fill / launch_update).
 void launch_trsv_syncfree(hipStream_t s, const DTri &t, const double *rhs, double *x, const double *add,
                           double *y2, DevState *st, int ticket, const int32_t *done);
-void launch_trsv_level(hipStream_t s, const DTri &t, int32_t beg, int32_t end, const double *rhs, double *x,
-                       const double *add, double *y2, const int32_t *done);
+template <class T>
+void launch_trsv_level(hipStream_t s, const DTriT<T> &t, int32_t beg, int32_t end, const T *rhs, T *x, const T *add,
+                       T *y2, const int32_t *done);
 // nb consecutive batches of a hybrid sweep by one workgroup, starting with the
 // batch at byte `off` of `blob` (its size and row count given); rhs_lo and
 // add_lo are the right-hand side and addend in level order.
+template <class T>
 void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
-                       int32_t p0, int32_t nb, const double *rhs_lo, double *x, const double *add_lo, double *y2,
-                       const int32_t *done);
+                       int32_t p0, int32_t nb, const T *rhs_lo, T *x, const T *add_lo, T *y2, const int32_t *done);
 // dst[p] = src[rows[p]] (and dst2 from src2 when given)
-void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const double *src, double *dst,
-                      const double *src2, double *dst2, const int32_t *done);
+template <class T>
+void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const T *src, T *dst, const T *src2, T *dst2,
+                      const int32_t *done);
+// out = in converted (FP64 <-> FP32, round to nearest)
+void launch_cvt(hipStream_t s, int32_t n, const double *in, float *out, const int32_t *done);
+void launch_cvt(hipStream_t s, int32_t n, const float *in, double *out, const int32_t *done);
 // w = (L L^T)^{-1} u with L packed lower (k x k), in place on w (w = u on entry)
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done);
 void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);

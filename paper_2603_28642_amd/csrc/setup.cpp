@@ -119,7 +119,7 @@ Chunks make_chunks(const Levels &lv, int32_t cap)
 struct BlobLayout {
     int64_t lev, lch, row, ext, next_ext, rch, slot, val, diag, size;
 };
-BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag)
+BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag, int64_t vb)
 {
     BlobLayout o;
     o.lev = 4 * kSweepHdr;
@@ -130,13 +130,13 @@ BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk,
     o.rch = o.next_ext + 4 * (int64_t)kSweepExt;
     o.slot = (o.rch + 2 * (npos + 1) + 7) & ~(int64_t)7;
     o.val = (o.slot + 8 * nchunk + 15) & ~(int64_t)15;
-    o.diag = o.val + 32 * nchunk;
-    o.size = (o.diag + (diag ? 8 * npos : 0) + 15) & ~(int64_t)15;
+    o.diag = o.val + 4 * vb * nchunk;
+    o.size = (o.diag + (diag ? vb * npos : 0) + 15) & ~(int64_t)15;
     return o;
 }
-int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag)
+int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag, int64_t vb)
 {
-    return blob_layout(nlev, npos, next, nchunk, diag).size;
+    return blob_layout(nlev, npos, next, nchunk, diag, vb).size;
 }
 
 int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
@@ -146,8 +146,12 @@ int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
 // row is read from LDS: from the results of the same batch, of the previous
 // batch of the run, or from the batch's gathered older inputs ("ext"). Rows
 // are cut into chunks of at most kSweepChunk entries (one thread each).
+// V is the value type stored in the blob: double, or float for the FP32
+// preconditioner (values rounded to nearest).
+template <class V>
 Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv)
 {
+    constexpr int64_t vb = (int64_t)sizeof(V);
     Sweep sw;
     const int32_t n = T.nrows;
     const bool hd = diag != nullptr;
@@ -213,7 +217,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             }
         }
         const int64_t next = (int64_t)ext.size();
-        const BlobLayout lay = blob_layout(nlev, npos, next, nchunk, hd);
+        const BlobLayout lay = blob_layout(nlev, npos, next, nchunk, hd, vb);
         const int64_t size = lay.size;
         if (npos > kSweepPos || next > kSweepExt || size > kSweepBlob || nchunk > 65535 || nlev > kSweepLevels)
             throw std::length_error("sweep batch exceeds the LDS limits");
@@ -239,8 +243,8 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         int32_t *ext_idx = reinterpret_cast<int32_t *>(b + lay.ext);
         uint16_t *rchunk = reinterpret_cast<uint16_t *>(b + lay.rch);
         uint16_t *eslot = reinterpret_cast<uint16_t *>(b + lay.slot);
-        double *eval = reinterpret_cast<double *>(b + lay.val);
-        double *dg = reinterpret_cast<double *>(b + lay.diag);
+        V *eval = reinterpret_cast<V *>(b + lay.val);
+        V *dg = reinterpret_cast<V *>(b + lay.diag);
         for (int64_t j = 0; j < next; ++j) ext_idx[j] = ext[(size_t)j];
         int32_t ch = 0;
         int32_t lvl = l0;
@@ -270,16 +274,16 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
                         else
                             slot = 2 * kSweepPos + ext_slot[c];
                         eslot[e] = (uint16_t)slot;
-                        eval[e] = T.val[k];
+                        eval[e] = (V)T.val[k];
                         ++k;
                     } else {
                         eslot[e] = (uint16_t)kSweepZeroSlot;
-                        eval[e] = 0.0;
+                        eval[e] = (V)0;
                     }
                 }
                 ++ch;
             }
-            if (hd) dg[p - p0] = (*diag)[row];
+            if (hd) dg[p - p0] = (V)(*diag)[row];
         }
         while (lvl < l1) {
             ++lvl;
@@ -324,7 +328,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     auto fits = [&](int64_t nlev, int64_t npos, int64_t nent, int64_t next, int64_t nchk) {
         (void)nent;
         return nlev <= kSweepLevels && npos <= kSweepPos && next <= kSweepExt &&
-               blob_bytes(nlev, npos, next, nchk, hd) <= kSweepBlob;
+               blob_bytes(nlev, npos, next, nchk, hd, vb) <= kSweepBlob;
     };
     for (int32_t l = 0; l < lv.nlev(); ++l) {
         const int64_t w = lv.ptr[(size_t)l + 1] - lv.ptr[l];
@@ -440,6 +444,8 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
          P.smode != RSILU_S_NONE) ||
         (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
+        (P.precision != RSILU_PREC_FP64 && P.precision != RSILU_PREC_FP32) ||
+        (P.precision == RSILU_PREC_FP32 && (P.trsv == RSILU_TRSV_SYNCFREE || P.smode == RSILU_S_DENSE)) ||
         (P.trsv != RSILU_TRSV_SYNCFREE && P.trsv != RSILU_TRSV_LEVELS && P.trsv != RSILU_TRSV_HYBRID))
         return RSILU_EINVAL;
     if (rowptr[0] != 0 || rowptr[m] > kMaxIdx) return RSILU_EINVAL;
@@ -671,16 +677,17 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.chL1 = make_chunks(c.lvL1, 64 / tri_lanes(c.L1));
     c.chL1T = make_chunks(c.lvL1T, 64 / tri_lanes(c.L1T));
     c.chU = make_chunks(c.lvU, 64 / tri_lanes(c.U));
-    c.swL1 = make_sweep(c.L1, nullptr, c.lvL1);
-    c.swL1T = make_sweep(c.L1T, nullptr, c.lvL1T);
-    c.swU = make_sweep(c.U, &c.Udiag, c.lvU);
+    const bool f32 = P.precision == RSILU_PREC_FP32;
+    c.swL1 = f32 ? make_sweep<float>(c.L1, nullptr, c.lvL1) : make_sweep<double>(c.L1, nullptr, c.lvL1);
+    c.swL1T = f32 ? make_sweep<float>(c.L1T, nullptr, c.lvL1T) : make_sweep<double>(c.L1T, nullptr, c.lvL1T);
+    c.swU = f32 ? make_sweep<float>(c.U, &c.Udiag, c.lvU) : make_sweep<double>(c.U, &c.Udiag, c.lvU);
     // U^T (forward, Udiag on the diagonal) for Algorithm 2's M_a = (L1 U)^T (L1 U)
     c.chUT = make_chunks(c.lvUT, 64 / tri_lanes(c.UT));
-    c.swUT = make_sweep(c.UT, &c.Udiag, c.lvUT);
+    c.swUT = f32 ? make_sweep<float>(c.UT, &c.Udiag, c.lvUT) : make_sweep<double>(c.UT, &c.Udiag, c.lvUT);
 
     // ---- S^ (Section 3.2)
     c.smode = P.smode;
-    if (c.smode == RSILU_S_AUTO) c.smode = (m - n > 0 && m - n <= 4096) ? RSILU_S_DENSE : RSILU_S_IDENTITY;
+    if (c.smode == RSILU_S_AUTO) c.smode = (m - n > 0 && m - n <= 4096 && !f32) ? RSILU_S_DENSE : RSILU_S_IDENTITY;
     if (c.smode == RSILU_S_DENSE && m > n) {
         const int64_t k = m - n;
         if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
@@ -739,15 +746,16 @@ struct Bump {
     }
 };
 
-DevCsrOff place_csr(Bump &b, const Csr &a)
+DevCsrOff place_csr(Bump &b, const Csr &a, int32_t vbytes = 8)
 {
     DevCsrOff o;
     o.nrows = a.nrows;
     o.ncols = a.ncols;
     o.nnz = a.nnz();
+    o.vbytes = vbytes;
     o.ptr = b.take(sizeof(int32_t) * a.ptr.size());
     o.col = b.take(sizeof(int32_t) * a.col.size());
-    o.val = b.take(sizeof(double) * a.val.size());
+    o.val = b.take((size_t)vbytes * a.val.size());
     return o;
 }
 
@@ -766,12 +774,12 @@ DevPlanOff place_plan(Bump &b, const SpmvPlan &pl)
 }
 
 DevTriOff place_tri(Bump &b, const Csr &a, bool diag, const Levels &lv, const Chunks &ch, const Sweep &sw,
-                    size_t n)
+                    size_t n, int32_t vbytes)
 {
     DevTriOff o;
     o.blob = b.take(sw.blob.size());
-    o.a = place_csr(b, a);
-    o.diag = diag ? b.take(sizeof(double) * n) : 0;
+    o.a = place_csr(b, a, vbytes);
+    o.diag = diag ? b.take((size_t)vbytes * n) : 0;
     o.rows = b.take(sizeof(int32_t) * lv.rows.size());
     o.chunk = b.take(sizeof(int32_t) * ch.ptr.size());
     o.nchunks = (int32_t)ch.ptr.size() - 1;
@@ -790,16 +798,17 @@ void plan_layout(Ctx &c)
     L.state = b.take(4096);
     L.A = place_csr(b, c.Ahat);
     L.AT = place_csr(b, c.AhatT);
-    L.L2 = place_csr(b, c.L2);
-    L.L2T = place_csr(b, c.L2T);
+    const int32_t vb = fp32(c) ? 4 : 8;  // factor values
+    L.L2 = place_csr(b, c.L2, vb);
+    L.L2T = place_csr(b, c.L2T, vb);
     L.pA = place_plan(b, c.plA);
     L.pAT = place_plan(b, c.plAT);
     L.pL2 = place_plan(b, c.plL2);
     L.pL2T = place_plan(b, c.plL2T);
-    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, n);
-    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, n);
-    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, n);
-    L.UTf = place_tri(b, c.UT, true, c.lvUT, c.chUT, c.swUT, n);
+    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, n, vb);
+    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, n, vb);
+    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, n, vb);
+    L.UTf = place_tri(b, c.UT, true, c.lvUT, c.chUT, c.swUT, n, vb);
     L.perm = b.take(sizeof(int32_t) * m);
     L.colnorm = b.take(sizeof(double) * n);
     L.sfac = b.take(sizeof(double) * c.sfac.size());
@@ -810,6 +819,10 @@ void plan_layout(Ctx &c)
     L.u = b.take(sizeof(double) * std::max<size_t>(k, 1));
     L.lo_rhs = b.take(sizeof(double) * n);
     L.lo_add = b.take(sizeof(double) * n);
+    if (fp32(c)) {
+        L.f32a = b.take(sizeof(float) * m);
+        L.f32b = b.take(sizeof(float) * m);
+    }
     // one partial per block of the largest reduction, plus one per long row
     L.npartials = 65536;
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);

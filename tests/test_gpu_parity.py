@@ -338,3 +338,92 @@ def test_solve_alg2_converges_like_oracle(gpu_lib, name):
         name, it, res.iters, np.linalg.norm(e) / np.linalg.norm(res.x)))
     if name == "c1":
         assert np.linalg.norm(e) <= 1e-8 * np.linalg.norm(res.x)
+
+
+# --------------------------------------------------------------- FP32 preconditioner
+
+EPS32 = np.finfo(np.float32).eps / 2
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small", "c3-mini"])
+@pytest.mark.parametrize("mode", ["hybrid", "levels"])
+def test_trsv_fp32(gpu_lib, name, mode):
+    """FP32 triangular solves: componentwise backward error in FP32 with respect to the
+    FP32-rounded factor and right-hand side, |T32 x - rhs32| <= 4 k eps32 (|T32| |x| + |rhs32|),
+    evaluated in FP64 (x is exactly representable there)."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    trsv = {"hybrid": R.TRSV_HYBRID, "levels": R.TRSV_LEVELS}[mode]
+    S = make(R, prob, mu=1.0, smode=R.S_NONE, trsv=trsv, precision=R.PREC_FP32)
+    F = oracle_for(prob, mu=1.0, smode="none")
+    rhs = np.random.default_rng(10).standard_normal(prob.n)
+    rhs32 = rhs.astype(np.float32).astype(np.float64)
+    torch = torch_dev()
+    for which, T, diag in [(R.T_L1, F.L1, None), (R.T_L1T, F.L1T, None), (R.T_U, F.U, F.Udiag),
+                           (R.T_UT, F.UT, F.Udiag)]:
+        x = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        assert R.rsilu_trsv(S.h, which, to_dev(rhs), x) == R.OK
+        got = to_host(x)
+        assert np.array_equal(got, got.astype(np.float32).astype(np.float64))
+        T32 = T.scipy().astype(np.float32).astype(np.float64)
+        d32 = np.ones(prob.n) if diag is None else diag.astype(np.float32).astype(np.float64)
+        resid = T32 @ got + d32 * got - rhs32
+        scale = abs(T32) @ np.abs(got) + np.abs(d32 * got) + np.abs(rhs32)
+        k = np.diff(T.rowptr) + 2
+        assert np.all(np.abs(resid) <= 4 * k * EPS32 * scale), (name, which)
+    S.close()
+
+
+def fp32_apply_error(R, prob, smode, form):
+    """Relative difference of the FP32 application to the FP64 oracle's."""
+    sm = {"none": R.S_NONE, "identity": R.S_IDENTITY}[smode]
+    S = make(R, prob, mu=1.0, smode=sm, precision=R.PREC_FP32)
+    F = oracle_for(prob, mu=1.0, smode=smode)
+    torch = torch_dev()
+    h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(11)
+    if form == "alg2":
+        z = rng.standard_normal(prob.n)
+        assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
+        want = oracle.apply_alg2(F, z)
+    else:
+        r = rng.standard_normal(prob.m)
+        assert R.rsilu_apply(S.h, to_dev(r), h) == R.OK
+        want = oracle.apply_alg3(F, r)
+    got = to_host(h)
+    S.close()
+    return np.linalg.norm(got - want) / np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("name,smode,form", [("c1", "none", "alg2"), ("c1", "identity", "alg2"),
+                                             ("c1", "identity", "alg3"), ("c2-small", "none", "alg2"),
+                                             ("c2-small", "identity", "alg3"), ("long-rows", "none", "alg2")])
+def test_apply_fp32(gpu_lib, name, smode, form):
+    """Stated bound for the FP32 preconditioner against the FP64 oracle: relative error
+    <= 1e-4 (FP32 rounding of the factors and of every operation, eps32 = 6e-8, times the
+    growth through four to six triangular solves of these mu = 1 factors)."""
+    err = fp32_apply_error(gpu_lib, PROBLEMS[name](), smode, form)
+    print("%s %s %s: |h32 - h64| / |h64| = %.2e" % (name, smode, form, err))
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small"])
+def test_solve_fp32_converges(gpu_lib, name):
+    """Whole solves with the FP32 preconditioner (Algorithm 2, no correction): FP64 Krylov
+    recurrences still reach tol = 1e-8 on the true residual; the solution lies in the same
+    stop-test ball as the FP64 oracle's, ||A^T A (x32 - x64)|| <= 4 tol ||A^T b||."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    tol = 1e-8
+    x, code, it, atr, rel = run_solve(R, prob, tol, mu=1.0, smode=R.S_NONE, maxit=2000, form=R.FORM_ALG2,
+                                      precision=R.PREC_FP32)
+    F = oracle.factor_problem(prob, mu=1.0, smode="none")
+    res = oracle.pcgls(F, prob.b, tol=tol, maxit=2000, form="alg2")
+    assert code == R.OK and res.status == "ok"
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    assert np.linalg.norm(A.T @ (prob.b - A @ x)) <= 2 * tol * atb
+    e = x - res.x
+    assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
+    print("%s: fp32-preconditioner its %d, fp64 oracle its %d, |x - x_or|/|x_or| = %.2e" % (
+        name, it, res.iters, np.linalg.norm(e) / np.linalg.norm(res.x)))

@@ -108,7 +108,8 @@ def test_explicit_zeros_are_stripped():
 
 
 @pytest.mark.parametrize("case", ["m<n", "bad col", "unsorted", "duplicate", "nan", "inf", "bad ptr", "bad mu",
-                                  "bad tau", "bad small"])
+                                  "bad tau", "bad small", "bad form", "bad smode", "bad precision",
+                                  "fp32 syncfree", "fp32 dense"])
 def test_invalid_input(case):
     m, n, rp, c, v = dense_problem(np.array([[1.0, 2.0], [3.0, 0.0], [0.0, 4.0]]))
     prm = R.rsilu_params_default()
@@ -138,6 +139,18 @@ def test_invalid_input(case):
             prm.tau = -1.0
         elif case == "bad small":
             prm.small = 0.0
+        elif case == "bad form":
+            prm.form = 2
+        elif case == "bad smode":
+            prm.smode = 3
+        elif case == "bad precision":
+            prm.precision = 2
+        elif case == "fp32 syncfree":
+            prm.precision = R.PREC_FP32
+            prm.trsv = R.TRSV_SYNCFREE
+        elif case == "fp32 dense":
+            prm.precision = R.PREC_FP32
+            prm.smode = R.S_DENSE
         code, h = R.rsilu_factor(m, n, rp, c, v, prm)
     assert code == R.EINVAL and h is None
 
@@ -191,3 +204,21 @@ def test_no_oracle_in_product():
                 with open(os.path.join(dirpath, fn)) as f:
                     src = f.read()
                 assert "oracle" not in src.lower(), fn
+
+
+def test_fp32_auto_resolves_to_identity_and_shrinks_footprint():
+    p = gen.random_sparse(90, 60, k=4, seed=8)
+    code, h64 = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, R.rsilu_params_default(smode=R.S_AUTO, mu=1.0))
+    code2, h32 = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val,
+                                R.rsilu_params_default(smode=R.S_AUTO, mu=1.0, precision=R.PREC_FP32))
+    assert code == R.OK and code2 == R.OK
+    s64, s32 = R.rsilu_get_stats(h64), R.rsilu_get_stats(h32)
+    assert s64.smode == R.S_DENSE and s32.smode == R.S_IDENTITY
+    big = gen.by_name("c2-small")
+    a = R.rsilu_factor(big.m, big.n, big.rowptr, big.col, big.val, R.rsilu_params_default(mu=1.0, smode=R.S_NONE))[1]
+    b = R.rsilu_factor(big.m, big.n, big.rowptr, big.col, big.val,
+                       R.rsilu_params_default(mu=1.0, smode=R.S_NONE, precision=R.PREC_FP32))[1]
+    # factor values and sweep blobs shrink by about a third
+    assert R.rsilu_device_bytes(b) < 0.8 * R.rsilu_device_bytes(a)
+    for hh in (h64, h32, a, b):
+        R.rsilu_destroy(hh)
