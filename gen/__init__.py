@@ -14,4 +14,6 @@ from .workloads import (  # noqa: F401
     paper_shape,
     PAPER_SHAPES,
     by_name,
+    served_request,
+    served_stream,
 )

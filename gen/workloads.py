@@ -216,6 +216,49 @@ def sparse_dense_c3(n=400_000, m_sparse=450_000, n_dense=64, dense_frac=0.3, k=6
 
 
 # ----------------------------------------------------------------------------
+# served requests (a stream of independent problems of uneven size)
+
+
+def served_request(n, m, seed, n_dense=0, dense_frac=0.3):
+    """One request of the served stream: the tiny-case recipe at size m x n with
+    4-8 entries per row (B: diagonal g + 4 sign(g) and 3-7 off-diagonals; R:
+    4-8 random columns), plus n_dense rows holding round(dense_frac * n)
+    random columns. Values N(0,1); b = A x_true + 1e-3 N(0,1).
+    """
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(n)
+    diag = g + 4.0 * np.sign(g)
+    kb = rng.integers(3, 8, size=n)  # off-diagonals of B rows
+    off = _distinct_cols(rng, n, n, 7, exclude=np.arange(n))
+    take_b = np.arange(7)[None, :] < kb[:, None]
+    nr = m - n - n_dense
+    kr = rng.integers(4, 9, size=nr)
+    rr = _distinct_cols(rng, nr, n, 8)
+    take_r = np.arange(8)[None, :] < kr[:, None]
+    nd = int(round(dense_frac * n))
+    dense_cols = [np.sort(rng.choice(n, size=nd, replace=False)) for _ in range(n_dense)]
+    rows = np.concatenate([np.arange(n), np.repeat(np.arange(n), 7)[take_b.ravel()],
+                           n + np.repeat(np.arange(nr), 8)[take_r.ravel()]] +
+                          [np.full(nd, n + nr + d) for d in range(n_dense)])
+    cols = np.concatenate([np.arange(n), off.ravel()[take_b.ravel()], rr.ravel()[take_r.ravel()]] + dense_cols)
+    vals = np.concatenate([diag, rng.standard_normal(rows.size - n)])
+    return _finish(f"served m={m} n={n} dense={n_dense}", rng, m, n, rows, cols, vals)
+
+
+def served_stream(count=512, seed=5, n_lo=2000, n_hi=200_000, dense_share=0.1):
+    """Sizes of the served stream: n log-uniform in [n_lo, n_hi], m = round(n U(1.1, 2.0)),
+    a share of requests with U{8..32} dense rows. Returns (n, m, seed, n_dense) tuples."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        m = int(round(n * rng.uniform(1.1, 2.0)))
+        nd = int(rng.integers(8, 33)) if rng.random() < dense_share else 0
+        out.append((n, m, seed * 100003 + i, nd))
+    return out
+
+
+# ----------------------------------------------------------------------------
 # small generic cases for tests
 
 

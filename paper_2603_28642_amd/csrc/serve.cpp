@@ -1,0 +1,308 @@
+// Serving runtime (rsilu_serve.h): host setup threads, first-come admission by
+// device footprint into one preallocated arena, one stream per solve slot.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "rsilu.h"
+#include "rsilu_serve.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit allocator over [0, size) of the device arena (offsets only).
+class Arena {
+public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    // offset of a block of `bytes`, or SIZE_MAX when no hole is large enough
+    size_t take(size_t bytes)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void give(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;  // offset -> length, non-adjacent holes
+};
+
+struct Job {
+    int64_t id = 0;
+    rsilu_request_t req{};
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val, b;
+    rsilu_handle_t h = nullptr;
+    size_t op_bytes = 0, bytes = 0, off = 0;
+    Clock::time_point t_submit, t_setup_done, t_admit;
+    rsilu_result_t res{};
+};
+
+}  // namespace
+
+struct rsilu_server {
+    rsilu_server_opts_t opts{};
+    void *arena_base = nullptr;
+    Arena *arena = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<int> slot_free;
+
+    std::mutex mu;
+    std::condition_variable cv_setup, cv_ready, cv_done;
+    std::deque<Job *> setup_q, ready_q;
+    std::deque<rsilu_result_t> results;
+    int64_t next_id = 0, completed = 0;
+    bool stopping = false;
+    std::vector<std::thread> threads;
+
+    void finish(Job *j, int32_t status)
+    {
+        const Clock::time_point now = Clock::now();
+        j->res.id = j->id;
+        j->res.user = j->req.user;
+        j->res.status = status;
+        j->res.total_ms = ms_between(j->t_submit, now);
+        if (j->h) rsilu_destroy(j->h);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            results.push_back(j->res);
+            ++completed;
+        }
+        cv_done.notify_all();
+        delete j;
+    }
+
+    void setup_worker()
+    {
+        for (;;) {
+            Job *j = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_setup.wait(lk, [&] { return stopping || !setup_q.empty(); });
+                if (setup_q.empty()) return;
+                j = setup_q.front();
+                setup_q.pop_front();
+            }
+            const Clock::time_point t0 = Clock::now();
+            rsilu_status_t st = rsilu_factor(j->req.m, j->req.n, j->rowptr.data(), j->col.data(), j->val.data(),
+                                             &j->req.params, &j->h);
+            j->t_setup_done = Clock::now();
+            j->res.setup_ms = ms_between(t0, j->t_setup_done);
+            if (st != RSILU_OK) {
+                finish(j, st);
+                continue;
+            }
+            j->op_bytes = round_up(rsilu_device_bytes(j->h));
+            j->bytes = j->op_bytes + round_up(sizeof(double) * (size_t)j->req.m) +
+                       round_up(sizeof(double) * (size_t)j->req.n);
+            j->res.device_bytes = j->bytes;
+            if (j->bytes > opts.hbm_bytes) {
+                finish(j, RSILU_ENOMEM);
+                continue;
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                ready_q.push_back(j);
+            }
+            cv_ready.notify_all();
+        }
+    }
+
+    void slot_worker(int slot)
+    {
+        (void)hipSetDevice(opts.device);
+        hipStream_t s = streams[(size_t)slot];
+        for (;;) {
+            Job *j = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                // first come, first served: only the head of the ready queue is admitted
+                cv_ready.wait(lk, [&] {
+                    if (ready_q.empty()) return stopping;
+                    Job *head = ready_q.front();
+                    head->off = arena->take(head->bytes);
+                    return head->off != SIZE_MAX;
+                });
+                if (ready_q.empty()) return;
+                j = ready_q.front();
+                ready_q.pop_front();
+            }
+            j->t_admit = Clock::now();
+            j->res.wait_ms = ms_between(j->t_setup_done, j->t_admit);
+            char *base = static_cast<char *>(arena_base) + j->off;
+            double *b_dev = reinterpret_cast<double *>(base + j->op_bytes);
+            double *x_dev = reinterpret_cast<double *>(base + j->op_bytes + round_up(sizeof(double) * (size_t)j->req.m));
+            rsilu_status_t st = rsilu_upload(j->h, base, j->op_bytes, s);
+            if (st == RSILU_OK &&
+                hipMemcpyAsync(b_dev, j->b.data(), sizeof(double) * (size_t)j->req.m, hipMemcpyHostToDevice, s) !=
+                    hipSuccess)
+                st = RSILU_EHIP;
+            if (st == RSILU_OK)
+                st = rsilu_solve(j->h, b_dev, j->req.tol, x_dev, &j->res.iters, &j->res.atr_norm, &j->res.atr_rel, s);
+            if (st >= 0 && hipMemcpyAsync(j->req.x, x_dev, sizeof(double) * (size_t)j->req.n, hipMemcpyDeviceToHost,
+                                          s) != hipSuccess)
+                st = RSILU_EHIP;
+            if (hipStreamSynchronize(s) != hipSuccess && st >= 0) st = RSILU_EHIP;
+            j->res.solve_ms = ms_between(j->t_admit, Clock::now());
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                arena->give(j->off, j->bytes);
+            }
+            cv_ready.notify_all();
+            finish(j, st);
+        }
+    }
+};
+
+extern "C" {
+
+rsilu_status_t rsilu_server_create(const rsilu_server_opts_t *opts, rsilu_server_t *out)
+{
+    if (!opts || !out || opts->slots < 1 || opts->setup_threads < 1 || opts->hbm_bytes < kAlign) return RSILU_EINVAL;
+    *out = nullptr;
+    rsilu_server *s = nullptr;
+    try {
+        s = new rsilu_server();
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
+    s->opts = *opts;
+    s->opts.hbm_bytes &= ~(kAlign - 1);
+    if (hipSetDevice(opts->device) != hipSuccess) {
+        delete s;
+        return RSILU_EINVAL;
+    }
+    if (hipMalloc(&s->arena_base, s->opts.hbm_bytes) != hipSuccess) {
+        delete s;
+        return RSILU_ENOMEM;
+    }
+    s->arena = new Arena(s->opts.hbm_bytes);
+    for (int i = 0; i < opts->slots; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+            (void)hipFree(s->arena_base);
+            delete s->arena;
+            delete s;
+            return RSILU_EHIP;
+        }
+        s->streams.push_back(st);
+    }
+    for (int i = 0; i < opts->setup_threads; ++i) s->threads.emplace_back([s] { s->setup_worker(); });
+    for (int i = 0; i < opts->slots; ++i) s->threads.emplace_back([s, i] { s->slot_worker(i); });
+    *out = s;
+    return RSILU_OK;
+}
+
+rsilu_status_t rsilu_server_submit(rsilu_server_t s, const rsilu_request_t *req, int64_t *id)
+{
+    if (!s || !req || !req->rowptr || !req->b || !req->x || req->m < req->n || req->n < 1) return RSILU_EINVAL;
+    const int64_t nnz = req->rowptr[req->m];
+    if (nnz < 0 || (nnz > 0 && (!req->colind || !req->val))) return RSILU_EINVAL;
+    Job *j = nullptr;
+    try {
+        j = new Job();
+        j->req = *req;
+        j->rowptr.assign(req->rowptr, req->rowptr + req->m + 1);
+        j->col.assign(req->colind, req->colind + nnz);
+        j->val.assign(req->val, req->val + nnz);
+        j->b.assign(req->b, req->b + req->m);
+    } catch (const std::bad_alloc &) {
+        delete j;
+        return RSILU_ENOMEM;
+    }
+    j->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) {
+            delete j;
+            return RSILU_ESTATE;
+        }
+        j->id = s->next_id++;
+        s->setup_q.push_back(j);
+    }
+    if (id) *id = j->id;
+    s->cv_setup.notify_one();
+    return RSILU_OK;
+}
+
+int32_t rsilu_server_poll(rsilu_server_t s, rsilu_result_t *out, int32_t max, int32_t wait_ms)
+{
+    if (!s || !out || max < 1) return 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->results.empty() && wait_ms > 0)
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !s->results.empty(); });
+    int32_t k = 0;
+    while (k < max && !s->results.empty()) {
+        out[k++] = s->results.front();
+        s->results.pop_front();
+    }
+    return k;
+}
+
+rsilu_status_t rsilu_server_drain(rsilu_server_t s)
+{
+    if (!s) return RSILU_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->completed == s->next_id; });
+    return RSILU_OK;
+}
+
+void rsilu_server_destroy(rsilu_server_t s)
+{
+    if (!s) return;
+    (void)rsilu_server_drain(s);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_setup.notify_all();
+    s->cv_ready.notify_all();
+    for (std::thread &t : s->threads) t.join();
+    for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+    (void)hipFree(s->arena_base);
+    delete s->arena;
+    delete s;
+}
+
+}  // extern "C"

@@ -32,6 +32,7 @@ EXPORTS = [
     "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_apply_z", "rsilu_set_profiling",
     "rsilu_get_profile",
     "rsilu_destroy", "rsilu_status_string",
+    "rsilu_server_create", "rsilu_server_submit", "rsilu_server_poll", "rsilu_server_drain", "rsilu_server_destroy",
 ]
 PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S", "trsv_UT",
               "k_trsv_sweep", "k_trsv_level", "k_gather_lo"]
@@ -59,6 +60,25 @@ class rsilu_stats_t(ctypes.Structure):
 
 class rsilu_profile_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 12), ("ms", ctypes.c_double * 12), ("bytes", ctypes.c_double * 12)]
+
+
+class rsilu_server_opts_t(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("setup_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hbm_bytes", ctypes.c_size_t)]
+
+
+class rsilu_request_t(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("tol", ctypes.c_double), ("params", rsilu_params_t),
+                ("user", ctypes.c_void_p)]
+
+
+class rsilu_result_t(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("user", ctypes.c_void_p), ("status", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("atr_norm", ctypes.c_double), ("atr_rel", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("wait_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
 
 
 class RsiluError(RuntimeError):
@@ -117,6 +137,16 @@ def lib():
         L.rsilu_destroy.restype = None
         L.rsilu_status_string.argtypes = [ctypes.c_int]
         L.rsilu_status_string.restype = ctypes.c_char_p
+        L.rsilu_server_create.argtypes = [ctypes.POINTER(rsilu_server_opts_t), ctypes.POINTER(P)]
+        L.rsilu_server_create.restype = ctypes.c_int
+        L.rsilu_server_submit.argtypes = [P, ctypes.POINTER(rsilu_request_t), ctypes.POINTER(I64)]
+        L.rsilu_server_submit.restype = ctypes.c_int
+        L.rsilu_server_poll.argtypes = [P, ctypes.POINTER(rsilu_result_t), I32, I32]
+        L.rsilu_server_poll.restype = I32
+        L.rsilu_server_drain.argtypes = [P]
+        L.rsilu_server_drain.restype = ctypes.c_int
+        L.rsilu_server_destroy.argtypes = [P]
+        L.rsilu_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -324,6 +354,59 @@ class Solver:
     def close(self):
         if self.h is not None:
             rsilu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The serving runtime (include/rsilu_serve.h): submit host problems, poll results.
+    Host inputs are copied at submit; each request's x buffer is kept alive here until
+    its result has been polled."""
+
+    def __init__(self, hbm_bytes, slots=4, setup_threads=4, device=0):
+        opts = rsilu_server_opts_t(device=device, slots=slots, setup_threads=setup_threads, reserved=0,
+                                   hbm_bytes=int(hbm_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().rsilu_server_create(ctypes.byref(opts), ctypes.byref(h)), "rsilu_server_create")
+        self.h = h
+        self.pending = {}  # id -> x array (and the problem, for the caller)
+
+    def submit(self, m, n, rowptr, colind, val, b, tol=1e-8, **params):
+        rp, prp = _host(rowptr, np.int64)
+        ci, pci = _host(colind, np.int32)
+        vv, pvv = _host(val, np.float64)
+        bb, pbb = _host(b, np.float64)
+        x = np.zeros(n, dtype=np.float64)
+        req = rsilu_request_t(m=int(m), n=int(n), rowptr=prp, colind=pci, val=pvv, b=pbb,
+                              x=x.ctypes.data_as(ctypes.c_void_p), tol=float(tol),
+                              params=rsilu_params_default(**params), user=None)
+        rid = ctypes.c_int64(-1)
+        _check(lib().rsilu_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid)), "rsilu_server_submit")
+        self.pending[rid.value] = x
+        return rid.value
+
+    def poll(self, max_results=64, wait_ms=0):
+        """[(result dict, x)] of completed requests."""
+        buf = (rsilu_result_t * max_results)()
+        k = lib().rsilu_server_poll(self.h, buf, max_results, int(wait_ms))
+        out = []
+        for i in range(k):
+            r = buf[i]
+            d = {f: getattr(r, f) for f, _ in r._fields_ if f != "user"}
+            out.append((d, self.pending.pop(r.id)))
+        return out
+
+    def drain(self):
+        _check(lib().rsilu_server_drain(self.h), "rsilu_server_drain")
+
+    def close(self):
+        if self.h is not None:
+            lib().rsilu_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -184,9 +184,12 @@ def test_device_calls_need_upload():
 
 
 def test_exports_match_header():
-    """Every function declared in include/rsilu.h is exported by the library."""
-    with open(os.path.join(ROOT, "include", "rsilu.h")) as f:
-        text = f.read()
+    """Every function declared in include/*.h is exported by the library."""
+    text = ""
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            with open(os.path.join(ROOT, "include", fn)) as f:
+                text += f.read()
     declared = sorted(set(re.findall(r"\b(rsilu_[a-z_]+)\s*\(", text)))
     assert declared == sorted(R.EXPORTS)
     for name in declared:
