@@ -66,9 +66,13 @@ enum {
     RSILU_S_AUTO = -1,    /* dense when m - n <= 4096, identity otherwise */
     RSILU_S_IDENTITY = 0, /* S^ = I: w = u */
     RSILU_S_DENSE = 1,    /* S~ = I + Y Y^T assembled and Cholesky-factored once */
-    RSILU_S_NONE = 2      /* no A2 correction: w = 0, so that Algorithm 3 gives
+    RSILU_S_NONE = 2,     /* no A2 correction: w = 0, so that Algorithm 3 gives
                              h = U^{-1} L1^{-1} r1 and Algorithm 2 gives
                              h = M_a^{-1} z */
+    RSILU_S_CG = 3        /* cg_steps steps of conjugate gradients on S~ w = u from
+                             w = 0 (Section 3.2; Table 3(a) uses two), S~ applied
+                             implicitly as d + L2 L1^{-1} L1^{-T} L2^T d; FP64 with the
+                             hybrid or level schedule only */
 };
 
 /* Form of the preconditioning step of Algorithm 1 (see the top of this file). */
@@ -110,6 +114,7 @@ typedef struct {
     int32_t poll;     /* iterations enqueued between host polls of the stop flag; 8 */
     int32_t form;     /* RSILU_FORM_*; default RSILU_FORM_ALG3 */
     int32_t precision; /* RSILU_PREC_*; default RSILU_PREC_FP64 */
+    int32_t cg_steps;  /* CG steps of RSILU_S_CG, 1..64; default 2 */
 } rsilu_params_t;
 
 typedef struct {
@@ -124,7 +129,7 @@ typedef struct {
     int32_t levels_l1t;    /* ... of the L1^T backward solve */
     int32_t levels_u;      /* ... of the U backward solve */
     int32_t levels_ut;     /* ... of the U^T forward solve */
-    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY, _DENSE or _NONE) */
+    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY, _DENSE, _NONE or _CG) */
     int32_t reserved;
     size_t device_bytes;   /* what rsilu_upload needs */
 } rsilu_stats_t;
@@ -134,7 +139,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
- * precision = FP64. */
+ * precision = FP64, cg_steps = 2. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting
@@ -240,7 +245,7 @@ enum {
     RSILU_PROF_TRSV_U = 4,    /* U backward solves */
     RSILU_PROF_SPMV_L2 = 5,   /* products with L2 */
     RSILU_PROF_SPMV_L2T = 6,  /* products with L2^T */
-    RSILU_PROF_DENSE_S = 7,   /* dense S~ solves */
+    RSILU_PROF_DENSE_S = 7,   /* dense S~ solves, or the CG steps on S~ (whole) */
     RSILU_PROF_TRSV_UT = 8,   /* U^T forward solves (Algorithm 2 form) */
     RSILU_PROF_K_SWEEP = 9,   /* launches of the single-workgroup sweep kernel */
     RSILU_PROF_K_LEVEL = 10,  /* launches of the one-level kernel (hybrid schedule) */

@@ -13,6 +13,8 @@ It follows the paper step by step:
   * levels              dependency depths of the triangular factors
   * dense_S             S~ = I + Y~ Y~^T with Y~ = L2 L1^{-1}, (3.9), factored
                         once by Cholesky (Section 3.2)
+  * cg_S                S~ w = u by a fixed number of CG steps, S~ applied
+                        implicitly (Section 3.2, Table 3(a))
   * apply_alg3          Algorithm 3 on the residual components (r1, r2)
   * apply_alg2          Algorithm 2 with k = n on z = A^T r, M_a = (L1 U)^T
                         (L1 U) standing for C1 and A2 for its factored image
@@ -250,6 +252,7 @@ class Factors:
     nmod: int
     smode: str
     S_chol: np.ndarray = field(default=None)  # lower Cholesky factor of S~ (dense mode)
+    cg_steps: int = 2  # CG steps on S~ (cg mode)
     lev: dict = field(default_factory=dict)
 
     @property
@@ -291,7 +294,8 @@ def dense_S(L1, L2):
     return S, np.linalg.cholesky(S)
 
 
-def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=True, smode="identity"):
+def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=True, smode="identity",
+           cg_steps=2):
     """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~."""
     rowptr, col, val = validate(m, n, rowptr, col, val)
     A = CSR(m, n, rowptr, col, val)
@@ -307,7 +311,7 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
     Ahat = csr_from_scipy(scaled[perm.astype(np.int64), :])
     F = Factors(m=m, n=n, perm=perm, colnorm=nrm, A=A, Ahat=Ahat, AhatT=Ahat.transpose(), L1=L1,
                 L1T=L1.transpose(), L2=L2, L2T=L2.transpose(), U=U, Udiag=Udiag, UT=U.transpose(),
-                nmod=res["nmod"], smode=smode)
+                nmod=res["nmod"], smode=smode, cg_steps=cg_steps)
     F.lev = {
         "L1": level_sets(levels(F.L1, True)),
         "L1T": level_sets(levels(F.L1T, False)),
@@ -316,7 +320,7 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
     }
     if smode == "dense":
         _, F.S_chol = dense_S(L1, L2)
-    elif smode not in ("identity", "none"):
+    elif smode not in ("identity", "none", "cg"):
         raise ValueError(smode)
     return F
 
@@ -327,6 +331,35 @@ def factor_problem(prob, **kw):
 
 # ----------------------------------------------------------------------------
 # Algorithm 3 and Algorithm 1
+
+
+def S_product(F, d):
+    """S~ d = d + Y~ Y~^T d with Y~ = L2 L1^{-1} applied implicitly (Section 3.2)."""
+    return d + F.L2.matvec(lower_solve(F.L1, upper_solve(F.L1T, F.L2T.matvec(d))))
+
+
+def cg_S(F, u):
+    """F.cg_steps steps of unpreconditioned conjugate gradients on S~ w = u from
+    w = 0 (Section 3.2; Table 3(a) takes two); stops early on a zero residual."""
+    w = np.zeros_like(u)
+    res = u.copy()
+    p = u.copy()
+    rr = float(np.dot(res, res))
+    for i in range(F.cg_steps):
+        if not rr > 0.0:
+            break
+        q = S_product(F, p)
+        pq = float(np.dot(p, q))
+        if not (pq > 0.0 and math.isfinite(pq)):
+            break
+        alpha = rr / pq
+        w = w + alpha * p
+        res = res - alpha * q
+        if i + 1 < F.cg_steps:
+            rr_new = float(np.dot(res, res))
+            p = res + (rr_new / rr) * p
+            rr = rr_new
+    return w
 
 
 def apply_alg3(F, r):
@@ -344,6 +377,8 @@ def apply_alg3(F, r):
     u = r2 - F.L2.matvec(t)
     if F.smode == "dense":
         w = sla.cho_solve((F.S_chol, True), u)
+    elif F.smode == "cg":
+        w = cg_S(F, u)
     else:
         w = u
     g = F.L2T.matvec(w)
@@ -377,6 +412,8 @@ def apply_alg2(F, z):
     wb = F.L2.matvec(F.U.matvec(ua) + F.Udiag * ua)
     if F.smode == "dense":
         vb = sla.cho_solve((F.S_chol, True), wb)
+    elif F.smode == "cg":
+        vb = cg_S(F, wb)
     else:
         vb = wb
     s = F.L2T.matvec(vb)

@@ -250,6 +250,37 @@ void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const DTriT<T> 
     }
 }
 
+// Step 2 of Algorithm 3 / step 3 of Algorithm 2 with S^ by CG: u <- w after
+// cg_steps steps of unpreconditioned CG on S~ w = u from w = 0, with
+// S~ d = d + L2 (L1^{-1} (L1^{-T} (L2^T d))) (Section 3.2). The scalars stay on
+// the device; a zero residual makes the remaining steps leave w unchanged.
+// Temporaries: g, c2 and s2 (free at this point in both forms).
+void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, const int32_t *done)
+{
+    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
+    double *w = at<double>(c, c.lay.cg_w), *res = at<double>(c, c.lay.cg_r), *p = at<double>(c, c.lay.cg_p),
+           *q = at<double>(c, c.lay.cg_q);
+    ProfScope ps(c, s, RSILU_PROF_DENSE_S);
+    launch_cg_init(s, k, W.u, w, res, p, done);
+    launch_dot(s, k, res, res, FIN_CG_RR0, P.partials, P.st, done);
+    for (int32_t i = 0; i < c.prm.cg_steps; ++i) {
+        launch_spmv<double>(s, W.L2T, P.pL2T, p, W.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, done);
+        trsv<double>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.g, W.c2, nullptr, nullptr, 1, done,
+                     RSILU_PROF_TRSV_L1T);
+        trsv<double>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.c2, W.s2, nullptr, nullptr, 2, done,
+                     RSILU_PROF_TRSV_L1);
+        launch_spmv<double>(s, W.L2, P.pL2, W.s2, q, p, EPI_ADD, FIN_NONE, P.partials, W.segpart, P.st, done);
+        launch_dot(s, k, p, q, FIN_CG_ALPHA, P.partials, P.st, done);
+        launch_cg_update(s, k, p, q, w, res, P.st, done);
+        if (i + 1 < c.prm.cg_steps) {
+            launch_dot(s, k, res, res, FIN_CG_BETA, P.partials, P.st, done);
+            launch_cg_dir(s, k, res, p, P.st, done);
+        }
+    }
+    launch_copy(s, k, w, W.u, done);
+    (void)n;
+}
+
 // Algorithm 3 on the residual r (pivot order) -> hout, in precision T. For
 // sync-free solves the outputs t, gp, v and hout must have been
 // sentinel-filled, tickets cleared.
@@ -273,6 +304,8 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
         if (c.smode == RSILU_S_DENSE) {
             ProfScope ps(c, s, RSILU_PROF_DENSE_S);
             launch_dense_chol_solve(s, k, P.sfac, W.u, done);
+        } else if (c.smode == RSILU_S_CG) {
+            cg_solve_S(c, s, P, W, done);
         }
     }
     // step 3: y = r1 + Y^T w with Y^T w = L1^{-T} (L2^T w)
@@ -329,6 +362,8 @@ void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
         if (c.smode == RSILU_S_DENSE) {
             ProfScope ps(c, s, RSILU_PROF_DENSE_S);
             launch_dense_chol_solve(s, k, P.sfac, W.u, done);
+        } else if (c.smode == RSILU_S_CG) {
+            cg_solve_S(c, s, P, W, done);
         }
     }
     // steps 4-5: y = g + L1^{-T} (-L2^T v_b), then L1 s2 = y, U h = s2
@@ -425,6 +460,8 @@ void rsilu_params_default(rsilu_params_t *p)
     p->trsv = RSILU_TRSV_HYBRID;
     p->poll = 8;
     p->form = RSILU_FORM_ALG3;
+    p->precision = RSILU_PREC_FP64;
+    p->cg_steps = 2;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)

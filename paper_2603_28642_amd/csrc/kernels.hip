@@ -115,6 +115,16 @@ __device__ void apply_fin(Fin fin, double total, DevState *st)
     case FIN_ATR:
         st->atr = sqrt(total);
         break;
+    case FIN_CG_RR0:
+        st->cg_rr = total;
+        break;
+    case FIN_CG_ALPHA:
+        st->cg_alpha = (st->cg_rr > 0.0 && total > 0.0 && isfinite(total) && isfinite(st->cg_rr)) ? st->cg_rr / total : 0.0;
+        break;
+    case FIN_CG_BETA:
+        st->cg_beta = (st->cg_rr > 0.0 && isfinite(total)) ? total / st->cg_rr : 0.0;
+        st->cg_rr = total;
+        break;
     default:
         break;
     }
@@ -147,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh
         T out = sum;
         if (EPI == EPI_SUB) out = aux[row] - sum;
         if (EPI == EPI_NEG) out = -sum;
+        if (EPI == EPI_ADD) out = aux[row] + sum;
         y[row] = out;
         if (EPI == EPI_SQ) contrib = out * out;
         if (EPI == EPI_WSQ) {
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, T *
         const int row = pl.long_rows[i];
         T s = 0;
         for (int q = pl.seg_ptr[i]; q < pl.seg_ptr[i + 1]; ++q) s += segpart[q];
-        T out = (EPI == EPI_SUB) ? aux[row] - s : (EPI == EPI_NEG ? -s : s);
+        T out = (EPI == EPI_SUB) ? aux[row] - s : (EPI == EPI_NEG ? -s : (EPI == EPI_ADD ? aux[row] + s : s));
         y[row] = out;
         double c = 0.0;
         if (EPI == EPI_SQ) c = out * out;
@@ -322,6 +333,39 @@ __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const double *__rest
 {
     if (stop_now(done)) return;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_init(int32_t k, const double *__restrict__ u, double *__restrict__ w,
+                                                    double *__restrict__ res, double *__restrict__ p,
+                                                    const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        w[i] = 0.0;
+        res[i] = u[i];
+        p[i] = u[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update(int32_t k, const double *__restrict__ p,
+                                                      const double *__restrict__ q, double *__restrict__ w,
+                                                      double *__restrict__ res, const DevState *st,
+                                                      const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double a = st->cg_alpha;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        w[i] = w[i] + a * p[i];
+        res[i] = res[i] - a * q[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_dir(int32_t k, const double *__restrict__ res, double *__restrict__ p,
+                                                   const DevState *st, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double bt = st->cg_beta;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) p[i] = res[i] + bt * p[i];
 }
 
 template <class A, class B>
@@ -791,6 +835,7 @@ void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, 
     case EPI_PLAIN: spmv_dispatch<EPI_PLAIN, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     case EPI_SUB: spmv_dispatch<EPI_SUB, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     case EPI_NEG: spmv_dispatch<EPI_NEG, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_ADD: spmv_dispatch<EPI_ADD, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     case EPI_SQ:
         if constexpr (fp64) spmv_dispatch<EPI_SQ, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done);
         break;
@@ -814,6 +859,10 @@ void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, 
             break;
         case EPI_NEG:
             hipLaunchKernelGGL((k_finish<EPI_NEG, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
+                               partials, fin, st, done);
+            break;
+        case EPI_ADD:
+            hipLaunchKernelGGL((k_finish<EPI_ADD, T>), dim3(1), dim3(kBlock), 0, s, pl, nparts, y, aux, segpart,
                                partials, fin, st, done);
             break;
         case EPI_SQ:
@@ -958,6 +1007,22 @@ template void launch_gather_lo<double>(hipStream_t, int32_t, const int32_t *, co
                                        double *, const int32_t *);
 template void launch_gather_lo<float>(hipStream_t, int32_t, const int32_t *, const float *, float *, const float *,
                                       float *, const int32_t *);
+
+void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double *res, double *p, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_cg_init, dim3(grid_for(k)), dim3(kBlock), 0, s, k, u, w, res, p, done);
+}
+
+void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
+                      const DevState *st, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(k)), dim3(kBlock), 0, s, k, p, q, w, res, st, done);
+}
+
+void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(k)), dim3(kBlock), 0, s, k, res, p, st, done);
+}
 
 void launch_cvt(hipStream_t s, int32_t n, const double *in, float *out, const int32_t *done)
 {

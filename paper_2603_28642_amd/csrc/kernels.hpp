@@ -23,6 +23,7 @@ struct alignas(256) DevState {
     int32_t err;     // a sync-free wait exceeded its bound
     int32_t pad0;
     uint32_t ticket[4];  // chunk dispensers of the sync-free solves
+    double cg_rr, cg_alpha, cg_beta;  // scalars of the CG steps on S~
 };
 
 // CSR operator in device memory (values in FP64, or FP32 for the factors of
@@ -63,7 +64,8 @@ enum Epi : int32_t {
     EPI_SQ = 1,     // y = A x, partial sums of y^2
     EPI_SUB = 2,    // y = aux - A x
     EPI_WSQ = 3,    // y = A x, partial sums of (aux * y)^2
-    EPI_NEG = 4     // y = -A x
+    EPI_NEG = 4,    // y = -A x
+    EPI_ADD = 5     // y = aux + A x
 };
 // (the FP32 products use EPI_PLAIN, EPI_SUB and EPI_NEG only)
 
@@ -74,7 +76,10 @@ enum Fin : int32_t {
     FIN_STOP = 3,   // zn = sqrt(sum); ++iter; stop test
     FIN_RHO0 = 4,   // rho = sum
     FIN_BETA = 5,   // beta = sum / rho; rho = sum
-    FIN_ATR = 6     // atr = sqrt(sum)
+    FIN_ATR = 6,    // atr = sqrt(sum)
+    FIN_CG_RR0 = 7, // cg_rr = sum
+    FIN_CG_ALPHA = 8,  // cg_alpha = cg_rr / sum (0 when either is 0 or not finite)
+    FIN_CG_BETA = 9    // cg_beta = sum / cg_rr (0 when cg_rr is 0); cg_rr = sum
 };
 
 constexpr int kBlock = 256;
@@ -123,5 +128,10 @@ void launch_cvt(hipStream_t s, int32_t n, const float *in, double *out, const in
 // w = (L L^T)^{-1} u with L packed lower (k x k), in place on w (w = u on entry)
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done);
 void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);
+// CG on S~: res = p = u, w = 0; then w += alpha p, res -= alpha q; p = res + beta p
+void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double *res, double *p, const int32_t *done);
+void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
+                      const DevState *st, const int32_t *done);
+void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done);
 
 }  // namespace rsilu

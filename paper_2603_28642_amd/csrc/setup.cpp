@@ -442,7 +442,9 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     if (P.p < 0 || !(P.tau >= 0.0) || !(P.mu > 0.0 && P.mu <= 1.0) || !(P.small > 0.0) ||
         !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
-         P.smode != RSILU_S_NONE) ||
+         P.smode != RSILU_S_NONE && P.smode != RSILU_S_CG) ||
+        (P.smode == RSILU_S_CG &&
+         (P.precision != RSILU_PREC_FP64 || P.trsv == RSILU_TRSV_SYNCFREE || P.cg_steps < 1 || P.cg_steps > 64)) ||
         (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
         (P.precision != RSILU_PREC_FP64 && P.precision != RSILU_PREC_FP32) ||
         (P.precision == RSILU_PREC_FP32 && (P.trsv == RSILU_TRSV_SYNCFREE || P.smode == RSILU_S_DENSE)) ||
@@ -726,7 +728,7 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
                 c.sfac[at(i, jj)] = s / d;
             }
         }
-    } else if (c.smode != RSILU_S_NONE) {
+    } else if (c.smode != RSILU_S_NONE && c.smode != RSILU_S_CG) {
         c.smode = RSILU_S_IDENTITY;
     }
     return RSILU_OK;
@@ -823,6 +825,8 @@ void plan_layout(Ctx &c)
         L.f32a = b.take(sizeof(float) * m);
         L.f32b = b.take(sizeof(float) * m);
     }
+    if (c.smode == RSILU_S_CG)
+        for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
     // one partial per block of the largest reduction, plus one per long row
     L.npartials = 65536;
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);

@@ -427,3 +427,42 @@ def test_solve_fp32_converges(gpu_lib, name):
     assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
     print("%s: fp32-preconditioner its %d, fp64 oracle its %d, |x - x_or|/|x_or| = %.2e" % (
         name, it, res.iters, np.linalg.norm(e) / np.linalg.norm(res.x)))
+
+
+# --------------------------------------------------------------- S^ by CG on S~ (Table 3(a))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small", "c3-mini", "long-rows"])
+@pytest.mark.parametrize("form,steps,mode", [("alg3", 2, "hybrid"), ("alg2", 2, "hybrid"), ("alg3", 5, "levels")])
+def test_apply_cg(gpu_lib, name, form, steps, mode):
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    trsv = {"hybrid": R.TRSV_HYBRID, "levels": R.TRSV_LEVELS}[mode]
+    S = make(R, prob, mu=1.0, smode=R.S_CG, cg_steps=steps, trsv=trsv)
+    F = oracle.factor_problem(prob, mu=1.0, smode="cg", cg_steps=steps)
+    torch = torch_dev()
+    h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(12)
+    if form == "alg3":
+        r = rng.standard_normal(prob.m)
+        assert R.rsilu_apply(S.h, to_dev(r), h) == R.OK
+        want = oracle.apply_alg3(F, r)
+    else:
+        z = rng.standard_normal(prob.n)
+        assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
+        want = oracle.apply_alg2(F, z)
+    assert np.linalg.norm(to_host(h) - want) <= 1e-10 * np.linalg.norm(want)
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small"])
+def test_solve_cg_fixed_iterations(gpu_lib, name):
+    """Four iterations of Algorithm 1 with Algorithm 3 and CG(2) on S~ follow the oracle."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    x, code, it, atr, rel = run_solve(R, prob, 1e-14, mu=1.0, smode=R.S_CG, cg_steps=2, maxit=4)
+    F = oracle.factor_problem(prob, mu=1.0, smode="cg", cg_steps=2)
+    res = oracle.pcgls(F, prob.b, tol=1e-14, maxit=4)
+    assert it == res.iters
+    assert np.linalg.norm(x - res.x) <= 1e-8 * np.linalg.norm(res.x)
+    assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm

@@ -109,7 +109,7 @@ def test_explicit_zeros_are_stripped():
 
 @pytest.mark.parametrize("case", ["m<n", "bad col", "unsorted", "duplicate", "nan", "inf", "bad ptr", "bad mu",
                                   "bad tau", "bad small", "bad form", "bad smode", "bad precision",
-                                  "fp32 syncfree", "fp32 dense"])
+                                  "fp32 syncfree", "fp32 dense", "cg fp32", "cg syncfree", "cg steps"])
 def test_invalid_input(case):
     m, n, rp, c, v = dense_problem(np.array([[1.0, 2.0], [3.0, 0.0], [0.0, 4.0]]))
     prm = R.rsilu_params_default()
@@ -142,7 +142,7 @@ def test_invalid_input(case):
         elif case == "bad form":
             prm.form = 2
         elif case == "bad smode":
-            prm.smode = 3
+            prm.smode = 4
         elif case == "bad precision":
             prm.precision = 2
         elif case == "fp32 syncfree":
@@ -151,6 +151,15 @@ def test_invalid_input(case):
         elif case == "fp32 dense":
             prm.precision = R.PREC_FP32
             prm.smode = R.S_DENSE
+        elif case == "cg fp32":
+            prm.smode = R.S_CG
+            prm.precision = R.PREC_FP32
+        elif case == "cg syncfree":
+            prm.smode = R.S_CG
+            prm.trsv = R.TRSV_SYNCFREE
+        elif case == "cg steps":
+            prm.smode = R.S_CG
+            prm.cg_steps = 0
         code, h = R.rsilu_factor(m, n, rp, c, v, prm)
     assert code == R.EINVAL and h is None
 
