@@ -6,11 +6,13 @@ kernel on the GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from
 b resident in HBM to x in HBM with the iteration count and ||A^T r|| on the
 host. Setup (the host ILUP) is done once, outside the timed region.
 
-The default preconditioning step is Algorithm 2 with k = n on z = A^T r and
-M_a = (L1 U)^T (L1 U) from the ILUP(10, 1e-2) factors (mu = 1), without the
-M_b correction: on this workload it reaches ||A^T r|| <= 1e-8 ||A^T b||,
-whereas Algorithm 3 on the residual stalls near its starting residual
-(--form alg3 runs it; the solve then ends at maxit or on a breakdown).
+The default Krylov method is LSQR in the M-inner-product form (--krylov pcgls
+runs Algorithm 1; both give the same iterates in exact arithmetic), with the
+preconditioner applied by Algorithm 2 with k = n and M_a = (L1 U)^T (L1 U)
+from the ILUP(10, 1e-2) factors (mu = 1), without the M_b correction: on this
+workload it reaches ||A^T r|| <= 1e-8 ||A^T b||, whereas Algorithm 3 on the
+residual stalls near its starting residual (--form alg3 --krylov pcgls runs
+it; the solve then ends at maxit or on a breakdown).
 
 Prints one JSON line with the throughput, p50/p99 latency, the roofline of the
 dominant kernel (HIP events recorded by the library on the solve's stream over
@@ -46,6 +48,8 @@ def parse():
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--smode", default="none", choices=["none", "identity", "dense", "auto"])
     ap.add_argument("--form", default="alg2", choices=["alg2", "alg3"])
+    ap.add_argument("--krylov", default="lsqr", choices=["pcgls", "lsqr"],
+                    help="Algorithm 1 (PCGLS) or LSQR in the M-inner-product form (needs --form alg2)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the preconditioner (factors and Algorithm 2/3); Krylov part is FP64")
     ap.add_argument("--trsv", default="hybrid", choices=["hybrid", "syncfree", "levels"])
@@ -155,11 +159,16 @@ def cpu_baseline(prob, args, iters_per_solve):
         F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
-        oracle.pcgls(F, prob.b, tol=0.0, maxit=2, form=args.form)
+        def run(maxit):
+            if args.krylov == "lsqr":
+                return oracle.lsqr_m(F, prob.b, tol=0.0, maxit=maxit)
+            return oracle.pcgls(F, prob.b, tol=0.0, maxit=maxit, form=args.form)
+
+        run(2)
         est = max((time.perf_counter() - t0) / 2.0, 1e-6)
         k = int(max(2, min(iters_per_solve if iters_per_solve > 0 else 2, args.cpu_seconds / est)))
         t0 = time.perf_counter()
-        res = oracle.pcgls(F, prob.b, tol=0.0, maxit=k, form=args.form)
+        res = run(k)
         t = time.perf_counter() - t0
     per_iter = t / max(res.iters, 1)
     per_solve = per_iter * max(iters_per_solve, 1)
@@ -177,7 +186,8 @@ def cpu_baseline(prob, args, iters_per_solve):
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "oracle Algorithm 1 + Algorithm " + args.form[-1] + " (plain C substitutions, numpy vectors, 1 thread) on the same "
+        "sample": "oracle " + ("LSQR" if args.krylov == "lsqr" else "Algorithm 1") + " + Algorithm " + args.form[-1] +
+                  " (plain C substitutions, numpy vectors, 1 thread) on the same "
                   "workload: %d iterations timed (%.1f s, %.1f ms/iteration), scaled to the %d iterations of one "
                   "GPU solve; oracle setup %.1f s not counted; host %s, nproc %d"
                   % (res.iters, t, per_iter * 1e3, iters_per_solve, t_setup, cpu, os.cpu_count() or 0),
@@ -209,8 +219,9 @@ def main():
     form = {"alg2": R.FORM_ALG2, "alg3": R.FORM_ALG3}[args.form]
     t0 = time.perf_counter()
     precision = {"fp64": R.PREC_FP64, "fp32": R.PREC_FP32}[args.precision]
+    krylov = {"pcgls": R.KRYLOV_PCGLS, "lsqr": R.KRYLOV_LSQR}[args.krylov]
     S = R.Solver.from_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit, trsv=trsv,
-                              form=form, precision=precision)
+                              form=form, precision=precision, krylov=krylov)
     t_setup = time.perf_counter() - t0
     S.upload()
     st = S.stats
@@ -269,7 +280,8 @@ def main():
             "nnz": int(st.nnz_a),
             "ilup": {"p": args.p, "tau": args.tau, "mu": args.mu, "small": 1e-10},
             "S": smode_used,
-            "krylov": "Algorithm 1 (PCGLS) + Algorithm %s" % args.form[-1],
+            "krylov": ("LSQR (M-inner-product form)" if args.krylov == "lsqr" else "Algorithm 1 (PCGLS)") +
+                      " + Algorithm %s" % args.form[-1],
             "trsv": args.trsv,
             "precond_precision": args.precision,
             "tol": args.tol,

@@ -81,6 +81,21 @@ enum {
     RSILU_FORM_ALG2 = 1  /* Algorithm 2, k = n, on z = A^T r */
 };
 
+/* Krylov method of rsilu_solve (rsilu_params_t.krylov).
+ *   PCGLS: Algorithm 1.
+ *   LSQR:  LSQR (Paige and Saunders) on A_hat N with N N^T = M^{-1}, written so
+ *          that only M^{-1} is applied; the same iterates as Algorithm 1 with
+ *          that M in exact arithmetic (Section 1 notes the equivalence of CGLS
+ *          and LSQR), usually better behaved in floating point. It needs a
+ *          symmetric positive definite M^{-1}: the Algorithm 2 form with S^
+ *          none or dense (AUTO resolves to dense when m - n <= 4096 in FP64,
+ *          else to none), and the hybrid or level schedule. Its stop test uses
+ *          the recurrence ||A^T r|| = |phibar c| ||D^{-1} s||. */
+enum {
+    RSILU_KRYLOV_PCGLS = 0,
+    RSILU_KRYLOV_LSQR = 1
+};
+
 /* Precision of the preconditioner (rsilu_params_t.precision). With FP32 the
  * factors L1, L2, U are stored in FP32 on the device and every step of
  * Algorithm 3 or Algorithm 2 runs in FP32 (its input converted from and its
@@ -115,6 +130,7 @@ typedef struct {
     int32_t form;     /* RSILU_FORM_*; default RSILU_FORM_ALG3 */
     int32_t precision; /* RSILU_PREC_*; default RSILU_PREC_FP64 */
     int32_t cg_steps;  /* CG steps of RSILU_S_CG, 1..64; default 2 */
+    int32_t krylov;    /* RSILU_KRYLOV_*; default RSILU_KRYLOV_PCGLS */
 } rsilu_params_t;
 
 typedef struct {
@@ -139,7 +155,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
- * precision = FP64, cg_steps = 2. */
+ * precision = FP64, cg_steps = 2, krylov = PCGLS. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

@@ -22,6 +22,11 @@ It follows the paper step by step:
   * pcgls               Algorithm 1 (left-preconditioned, factorization-free
                         CGLS) with Algorithm 3 (or Algorithm 2) in place of
                         h = M^{-1} A^T r
+  * lsqr_m              LSQR (Paige and Saunders) on A_hat N with N N^T = M^{-1}
+                        the SPD Algorithm 2 operator, written so that only
+                        M^{-1} is applied (mathematically the same iterates
+                        as Algorithm 1 with that M, which the paper notes for
+                        CGLS and LSQR in exact arithmetic)
 The method does not converge to anything faster than it converges; its limit
 is the least-squares solution, which the tests pin with dense QR.
 """
@@ -419,6 +424,87 @@ def apply_alg2(F, z):
     s = F.L2T.matvec(vb)
     wa = z - (F.UT.matvec(s) + F.Udiag * s)
     return _ma_solve(F, wa)
+
+
+def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):
+    """LSQR on min || P b - A_hat N y ||, x_hat = N y, with N N^T = M^{-1} the SPD operator
+    of Algorithm 2 (apply_alg2; modes "none" and "dense"), in the M-inner-product form:
+    v = N v_hat, M v = N^{-T} v_hat, so only M^{-1} is ever applied.
+
+    Init: beta1 = ||P b||, u = P b / beta1, s = A_hat^T u, v' = M^{-1} s,
+    alpha = sqrt(s . v'), v = v'/alpha, Mv = s/alpha, w = v, phibar = beta1,
+    rhobar = alpha. Step: t = A_hat v - alpha u, beta = ||t||, u = t/beta;
+    s = A_hat^T u - beta Mv, v' = M^{-1} s, alpha = sqrt(s . v'), v = v'/alpha,
+    Mv = s/alpha; rho = sqrt(rhobar^2 + beta^2), c = rhobar/rho, sn = beta/rho,
+    theta = sn alpha, rhobar = -c alpha, phi = c phibar, phibar = sn phibar;
+    x_hat += (phi/rho) w, w = v - (theta/rho) w.
+    Since A_hat^T r = phibar c s (up to sign) after a step, the stop test is
+    |phibar c| ||D^{-1} s|| <= tol ||A^T b|| with ||A^T b|| = beta1 ||D^{-1} s_1||.
+    Breakdown: s . v' <= 0 or a non-finite scalar.
+    """
+    if F.smode not in ("none", "dense") and F.m > F.n:
+        raise ValueError("LSQR needs a symmetric positive definite M^{-1}")
+    b = _c(b, np.float64)
+    n = F.n
+    r = b[F.perm.astype(np.int64)].copy()
+    xh = np.zeros(n)
+    beta1 = math.sqrt(float(np.dot(r, r)))
+    status = "not_converged"
+    iters = 0
+    hist = []
+    if beta1 == 0.0:
+        status = "ok"
+    else:
+        u = r / beta1
+        s = F.AhatT.matvec(u)
+        s1 = math.sqrt(float(np.dot(F.colnorm * s, F.colnorm * s)))
+        nb = beta1 * s1
+        hist.append(nb)
+        vp = apply_alg2(F, s)
+        sv = float(np.dot(s, vp))
+        if not (sv > 0.0 and math.isfinite(sv)):
+            status = "breakdown" if nb > 0.0 else "ok"
+        else:
+            alpha = math.sqrt(sv)
+            v = vp / alpha
+            Mv = s / alpha
+            w = v.copy()
+            phibar, rhobar = beta1, alpha
+            for it in range(1, maxit + 1):
+                t = F.Ahat.matvec(v) - alpha * u
+                beta = math.sqrt(float(np.dot(t, t)))
+                if not math.isfinite(beta):
+                    status = "breakdown"
+                    break
+                u = t / beta if beta > 0.0 else t
+                s = F.AhatT.matvec(u) - beta * Mv
+                sn_ = math.sqrt(float(np.dot(F.colnorm * s, F.colnorm * s)))
+                vp = apply_alg2(F, s)
+                sv = float(np.dot(s, vp))
+                alpha = math.sqrt(sv) if sv > 0.0 else 0.0
+                rho = math.sqrt(rhobar * rhobar + beta * beta)
+                c, sn = rhobar / rho, beta / rho
+                theta = sn * alpha
+                rhobar = -c * alpha
+                phi = c * phibar
+                phibar = sn * phibar
+                xh = xh + (phi / rho) * w
+                iters = it
+                est = abs(phibar * c) * sn_
+                hist.append(est)
+                if alpha > 0.0:
+                    v = vp / alpha
+                    Mv = s / alpha
+                    w = v - (theta / rho) * w
+                if est <= tol * nb:
+                    status = "ok"
+                    break
+                if alpha == 0.0 or not math.isfinite(sv):
+                    status = "breakdown" if sv < 0.0 or not math.isfinite(sv) else "ok"
+                    break
+    x = xh / F.colnorm
+    atr, rel = true_residual(F.A, b, x)
+    return SolveResult(x=x, iters=iters, status=status, atr_norm=atr, atr_rel=rel, hist=hist)
 
 
 @dataclass

@@ -415,6 +415,49 @@ void trsv_which(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, int32_t w
     }
 }
 
+// LSQR in the M-inner-product form (rsilu.h, RSILU_KRYLOV_LSQR). Vectors: u in r,
+// t in q (m); s in z (the Algorithm 2 input), h in h, x_hat in xh; v, M v and w
+// in their own n-vectors.
+void enqueue_lsqr_init(Ctx &c, hipStream_t s, const Ptrs &P, const double *b)
+{
+    const int32_t n = (int32_t)c.n, m = (int32_t)c.m;
+    double *v = at<double>(c, c.lay.l_v), *Mv = at<double>(c, c.lay.l_mv), *w = at<double>(c, c.lay.l_w);
+    launch_gather(s, m, n, P.perm, b, P.r, P.xh, nullptr);
+    launch_dot(s, m, P.r, P.r, FIN_L_BETA1, P.partials, P.st, P.done);
+    launch_lsqr_scale(s, m, P.r, P.r, P.st, P.done);
+    launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, P.done);
+    launch_lsqr_s(s, n, P.z, nullptr, P.colnorm, FIN_L_S1, P.partials, P.st, P.done);
+    apply_form(c, s, P, P.h, P.done);
+    launch_dot(s, n, P.z, P.h, FIN_L_ALPHA0, P.partials, P.st, P.done);
+    launch_lsqr_v(s, n, P.h, P.z, P.xh, v, Mv, w, true, P.st, P.done);
+}
+
+void enqueue_lsqr_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
+{
+    const int32_t n = (int32_t)c.n, m = (int32_t)c.m;
+    double *v = at<double>(c, c.lay.l_v), *Mv = at<double>(c, c.lay.l_mv), *w = at<double>(c, c.lay.l_w);
+    // t = A_hat v - alpha u, beta = ||t||, u = t / beta
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_A);
+        launch_spmv<double>(s, P.A, P.pA, v, P.q, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, P.done);
+    }
+    launch_lsqr_t(s, m, P.r, P.q, FIN_L_BETA, P.partials, P.st, P.done);
+    launch_lsqr_scale(s, m, P.q, P.r, P.st, P.done);
+    // s = A_hat^T u - beta M v with ||D^{-1} s||
+    {
+        ProfScope ps(c, s, RSILU_PROF_SPMV_AT);
+        launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st,
+                            P.done);
+    }
+    launch_lsqr_s(s, n, P.z, Mv, P.colnorm, FIN_L_SNORM, P.partials, P.st, P.done);
+    // h = M^{-1} s, alpha = sqrt(s . h), the Givens step and the stop test
+    apply_form(c, s, P, P.h, P.done);
+    launch_dot(s, n, P.z, P.h, FIN_L_ALPHA, P.partials, P.st, P.done);
+    // x_hat, v, M v, w; then a requested stop takes effect
+    launch_lsqr_v(s, n, P.h, P.z, P.xh, v, Mv, w, false, P.st, P.done);
+    launch_lsqr_commit(s, P.st);
+}
+
 void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
 {
     const int32_t n = (int32_t)c.n, m = (int32_t)c.m;
@@ -462,6 +505,7 @@ void rsilu_params_default(rsilu_params_t *p)
     p->form = RSILU_FORM_ALG3;
     p->precision = RSILU_PREC_FP64;
     p->cg_steps = 2;
+    p->krylov = RSILU_KRYLOV_PCGLS;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)
@@ -692,21 +736,28 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
     mail->init.maxit = c.prm.maxit;
     RSILU_HIP(hipMemcpyAsync(P.st, &mail->init, sizeof(DevState), hipMemcpyHostToDevice, s));
     const bool sf = syncfree(c);
+    const bool lsqr = c.prm.krylov == RSILU_KRYLOV_LSQR;
 
-    // ---- initialisation: x0 = 0, r0 = P b, z0 = A^T r0, h0 = B(r0), rho0, p0 = h0
+    // ---- initialisation: x0 = 0; PCGLS: r0 = P b, z0 = A^T r0, h0 = B(r0), rho0, p0 = h0
+    // (LSQR: its own start, enqueue_lsqr_init)
     c.ev_iter = 0;
     c.ev_open.clear();
     c.ev_next = 0;
-    launch_gather(s, m, n, P.perm, b, P.r, P.xh, nullptr);
-    launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_INIT, P.partials, P.segpart, P.st, nullptr);
-    if (sf) {
-        double *f[4];
-        fill_targets(c, P, P.h, f);
-        launch_fill(s, n, f[0], f[1], f[2], f[3], P.st);
+    if (lsqr) {
+        enqueue_lsqr_init(c, s, P, b);
+    } else {
+        launch_gather(s, m, n, P.perm, b, P.r, P.xh, nullptr);
+        launch_spmv<double>(s, P.AT, P.pAT, P.r, P.z, P.colnorm, EPI_WSQ, FIN_INIT, P.partials, P.segpart, P.st,
+                            nullptr);
+        if (sf) {
+            double *f[4];
+            fill_targets(c, P, P.h, f);
+            launch_fill(s, n, f[0], f[1], f[2], f[3], P.st);
+        }
+        apply_form(c, s, P, P.h, P.done);
+        launch_dot(s, n, P.z, P.h, FIN_RHO0, P.partials, P.st, P.done);
+        launch_pupdate(s, n, P.h, P.p, P.st, true, P.done);
     }
-    apply_form(c, s, P, P.h, P.done);
-    launch_dot(s, n, P.z, P.h, FIN_RHO0, P.partials, P.st, P.done);
-    launch_pupdate(s, n, P.h, P.p, P.st, true, P.done);
     RSILU_HIP(hipGetLastError());
 
     // ---- iterations, polled every `poll` steps (maxit = 0 stops after the init)
@@ -716,7 +767,10 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
         const int batch = (int)std::min<int64_t>(c.prm.poll, (int64_t)c.prm.maxit - enqueued);
         for (int i = 0; i < batch; ++i) {
             c.ev_iter = (int)(enqueued + i + 1);
-            enqueue_iteration(c, s, P);
+            if (lsqr)
+                enqueue_lsqr_iteration(c, s, P);
+            else
+                enqueue_iteration(c, s, P);
         }
         enqueued += batch;
         RSILU_HIP(hipGetLastError());

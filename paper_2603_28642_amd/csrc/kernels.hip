@@ -118,6 +118,85 @@ __device__ void apply_fin(Fin fin, double total, DevState *st)
     case FIN_CG_RR0:
         st->cg_rr = total;
         break;
+    case FIN_L_BETA1: {
+        const double b1 = sqrt(total);
+        st->lb = b1;
+        st->phibar = b1;
+        st->nb = 0.0;
+        if (b1 == 0.0) {
+            st->done = 1;
+            st->status = 0;
+        } else if (!isfinite(b1)) {
+            st->done = 1;
+            st->status = 2;
+        }
+        break;
+    }
+    case FIN_L_S1:
+        st->snorm = sqrt(total);
+        st->nb = st->lb * st->snorm;
+        st->zn = st->nb;
+        if (st->nb == 0.0) {
+            st->done = 1;
+            st->status = 0;
+        } else if (!isfinite(st->nb)) {
+            st->done = 1;
+            st->status = 2;
+        }
+        break;
+    case FIN_L_ALPHA0:
+        if (!(total > 0.0) || !isfinite(total)) {
+            st->done = 1;
+            st->status = 2;
+        } else {
+            st->la = sqrt(total);
+            st->rhobar = st->la;
+        }
+        if (st->maxit == 0 && !st->done) {
+            st->done = 1;
+            st->status = 1;
+        }
+        break;
+    case FIN_L_BETA:
+        st->lb = sqrt(total);
+        if (!isfinite(st->lb)) {
+            st->done = 1;
+            st->status = 2;
+        }
+        break;
+    case FIN_L_SNORM:
+        st->snorm = sqrt(total);
+        break;
+    case FIN_L_ALPHA: {
+        const double la = total > 0.0 ? sqrt(total) : 0.0;
+        const double rho = sqrt(st->rhobar * st->rhobar + st->lb * st->lb);
+        const double c = st->rhobar / rho, sn = st->lb / rho;
+        const double theta = sn * la;
+        st->rhobar = -c * la;
+        const double phi = c * st->phibar;
+        st->phibar = sn * st->phibar;
+        st->phi_rho = phi / rho;
+        st->theta_rho = theta / rho;
+        st->la = la;
+        st->iter += 1;
+        const double est = fabs(st->phibar * c) * st->snorm;
+        st->zn = est;
+        st->lstop = 0;
+        if (!isfinite(est) || !isfinite(total) || !isfinite(rho)) {
+            st->lstop = 1;
+            st->lstop_status = 2;
+        } else if (est <= st->tol * st->nb) {
+            st->lstop = 1;
+            st->lstop_status = 0;
+        } else if (la == 0.0) {
+            st->lstop = 1;
+            st->lstop_status = total < 0.0 ? 2 : 0;
+        } else if (st->iter >= st->maxit) {
+            st->lstop = 1;
+            st->lstop_status = 1;
+        }
+        break;
+    }
     case FIN_CG_ALPHA:
         st->cg_alpha = (st->cg_rr > 0.0 && total > 0.0 && isfinite(total) && isfinite(st->cg_rr)) ? st->cg_rr / total : 0.0;
         break;
@@ -333,6 +412,84 @@ __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const double *__rest
 {
     if (stop_now(done)) return;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lsqr_t(int32_t m, const double *__restrict__ u, double *__restrict__ t,
+                                                   double *__restrict__ partials, const DevState *st,
+                                                   const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    const double a = st->la;
+    double sq = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+        const double v = t[i] - a * u[i];
+        t[i] = v;
+        sq += v * v;
+    }
+    const double tot = block_sum256(sq, lds4);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_lsqr_scale(int32_t m, const double *__restrict__ in,
+                                                       double *__restrict__ out, const DevState *st,
+                                                       const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double d = st->lb;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) out[i] = d > 0.0 ? in[i] / d : in[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lsqr_s(int32_t n, double *__restrict__ sv, const double *__restrict__ Mv,
+                                                   const double *__restrict__ colnorm, double *__restrict__ partials,
+                                                   const DevState *st, const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    const double b = st->lb;
+    double sq = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double v = Mv ? sv[i] - b * Mv[i] : sv[i];
+        sv[i] = v;
+        const double w = colnorm[i] * v;
+        sq += w * w;
+    }
+    const double tot = block_sum256(sq, lds4);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_lsqr_v(int32_t n, const double *__restrict__ h, const double *__restrict__ sv,
+                                                   double *__restrict__ xh, double *__restrict__ v,
+                                                   double *__restrict__ Mv, double *__restrict__ w, int32_t init,
+                                                   const DevState *st, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    const double la = st->la, pr = st->phi_rho, tr = st->theta_rho;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        if (init) {
+            const double vi = h[i] / la;
+            v[i] = vi;
+            Mv[i] = sv[i] / la;
+            w[i] = vi;
+            continue;
+        }
+        const double wo = w[i];
+        xh[i] = xh[i] + pr * wo;
+        if (la > 0.0) {
+            const double vi = h[i] / la;
+            v[i] = vi;
+            Mv[i] = sv[i] / la;
+            w[i] = vi - tr * wo;
+        }
+    }
+}
+
+__global__ void k_lsqr_commit(DevState *st)
+{
+    if (threadIdx.x == 0 && st->done == 0 && st->lstop) {
+        st->status = st->lstop_status;
+        st->done = 1;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t k, const double *__restrict__ u, double *__restrict__ w,
@@ -1007,6 +1164,40 @@ template void launch_gather_lo<double>(hipStream_t, int32_t, const int32_t *, co
                                        double *, const int32_t *);
 template void launch_gather_lo<float>(hipStream_t, int32_t, const int32_t *, const float *, float *, const float *,
                                       float *, const int32_t *);
+
+void launch_lsqr_t(hipStream_t s, int32_t m, const double *u, double *t, Fin fin, double *partials, DevState *st,
+                   const int32_t *done)
+{
+    const int g = grid_for(m, 2048);
+    hipLaunchKernelGGL(k_lsqr_t, dim3(g), dim3(kBlock), 0, s, m, u, t, partials, st, done);
+    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+}
+
+void launch_lsqr_scale(hipStream_t s, int32_t m, const double *in, double *out, const DevState *st,
+                       const int32_t *done)
+{
+    hipLaunchKernelGGL(k_lsqr_scale, dim3(grid_for(m)), dim3(kBlock), 0, s, m, in, out, st, done);
+}
+
+void launch_lsqr_s(hipStream_t s, int32_t n, double *sv, const double *Mv, const double *colnorm, Fin fin,
+                   double *partials, DevState *st, const int32_t *done)
+{
+    const int g = grid_for(n, 2048);
+    hipLaunchKernelGGL(k_lsqr_s, dim3(g), dim3(kBlock), 0, s, n, sv, Mv, colnorm, partials, st, done);
+    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+}
+
+void launch_lsqr_v(hipStream_t s, int32_t n, const double *h, const double *sv, double *xh, double *v, double *Mv,
+                   double *w, bool init, const DevState *st, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_lsqr_v, dim3(grid_for(n)), dim3(kBlock), 0, s, n, h, sv, xh, v, Mv, w, init ? 1 : 0, st,
+                       done);
+}
+
+void launch_lsqr_commit(hipStream_t s, DevState *st)
+{
+    hipLaunchKernelGGL(k_lsqr_commit, dim3(1), dim3(64), 0, s, st);
+}
 
 void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double *res, double *p, const int32_t *done)
 {

@@ -24,6 +24,10 @@ struct alignas(256) DevState {
     int32_t pad0;
     uint32_t ticket[4];  // chunk dispensers of the sync-free solves
     double cg_rr, cg_alpha, cg_beta;  // scalars of the CG steps on S~
+    // LSQR: alpha, beta, the Givens rotation's state and step coefficients, ||D^{-1} s||,
+    // and a stop requested by the scalar step, committed after the x update
+    double la, lb, rhobar, phibar, phi_rho, theta_rho, snorm;
+    int32_t lstop, lstop_status;
 };
 
 // CSR operator in device memory (values in FP64, or FP32 for the factors of
@@ -79,7 +83,13 @@ enum Fin : int32_t {
     FIN_ATR = 6,    // atr = sqrt(sum)
     FIN_CG_RR0 = 7, // cg_rr = sum
     FIN_CG_ALPHA = 8,  // cg_alpha = cg_rr / sum (0 when either is 0 or not finite)
-    FIN_CG_BETA = 9    // cg_beta = sum / cg_rr (0 when cg_rr is 0); cg_rr = sum
+    FIN_CG_BETA = 9,   // cg_beta = sum / cg_rr (0 when cg_rr is 0); cg_rr = sum
+    FIN_L_BETA1 = 10,  // LSQR init: lb = phibar = sqrt(sum) (= ||P b||); 0 -> done, converged
+    FIN_L_S1 = 11,     // LSQR init: snorm = sqrt(sum); nb = zn = lb snorm (= ||A^T b||)
+    FIN_L_ALPHA0 = 12, // LSQR init: la = rhobar = sqrt(sum); <= 0 or not finite -> breakdown
+    FIN_L_BETA = 13,   // LSQR: lb = sqrt(sum)
+    FIN_L_SNORM = 14,  // LSQR: snorm = sqrt(sum)
+    FIN_L_ALPHA = 15   // LSQR: la = sqrt(sum), Givens step, ++iter, stop test (requested in lstop)
 };
 
 constexpr int kBlock = 256;
@@ -124,6 +134,21 @@ void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const T *sr
                       const int32_t *done);
 // out = in converted (FP64 <-> FP32, round to nearest)
 void launch_cvt(hipStream_t s, int32_t n, const double *in, float *out, const int32_t *done);
+// LSQR steps (device scalars in st):
+// t -= la u with the partial sums of t^2, then the single-block finish (fin)
+void launch_lsqr_t(hipStream_t s, int32_t m, const double *u, double *t, Fin fin, double *partials, DevState *st,
+                   const int32_t *done);
+// out = in / lb (in when lb = 0)
+void launch_lsqr_scale(hipStream_t s, int32_t m, const double *in, double *out, const DevState *st,
+                       const int32_t *done);
+// sv -= lb Mv with the partial sums of (colnorm s)^2, then the finish (fin)
+void launch_lsqr_s(hipStream_t s, int32_t n, double *sv, const double *Mv, const double *colnorm, Fin fin,
+                   double *partials, DevState *st, const int32_t *done);
+// x_hat += phi_rho w; when la > 0: v = h / la, Mv = s / la, w = v - theta_rho w (init: w = v)
+void launch_lsqr_v(hipStream_t s, int32_t n, const double *h, const double *sv, double *xh, double *v, double *Mv,
+                   double *w, bool init, const DevState *st, const int32_t *done);
+// a stop requested by FIN_L_ALPHA takes effect
+void launch_lsqr_commit(hipStream_t s, DevState *st);
 void launch_cvt(hipStream_t s, int32_t n, const float *in, double *out, const int32_t *done);
 // w = (L L^T)^{-1} u with L packed lower (k x k), in place on w (w = u on entry)
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done);

@@ -443,6 +443,10 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
         !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
          P.smode != RSILU_S_NONE && P.smode != RSILU_S_CG) ||
+        (P.krylov != RSILU_KRYLOV_PCGLS && P.krylov != RSILU_KRYLOV_LSQR) ||
+        (P.krylov == RSILU_KRYLOV_LSQR &&
+         (P.form != RSILU_FORM_ALG2 || P.trsv == RSILU_TRSV_SYNCFREE ||
+          (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_NONE && P.smode != RSILU_S_DENSE))) ||
         (P.smode == RSILU_S_CG &&
          (P.precision != RSILU_PREC_FP64 || P.trsv == RSILU_TRSV_SYNCFREE || P.cg_steps < 1 || P.cg_steps > 64)) ||
         (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
@@ -689,7 +693,10 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
 
     // ---- S^ (Section 3.2)
     c.smode = P.smode;
-    if (c.smode == RSILU_S_AUTO) c.smode = (m - n > 0 && m - n <= 4096 && !f32) ? RSILU_S_DENSE : RSILU_S_IDENTITY;
+    if (c.smode == RSILU_S_AUTO)
+        c.smode = (m - n > 0 && m - n <= 4096 && !f32)
+                      ? RSILU_S_DENSE
+                      : (P.krylov == RSILU_KRYLOV_LSQR ? RSILU_S_NONE : RSILU_S_IDENTITY);
     if (c.smode == RSILU_S_DENSE && m > n) {
         const int64_t k = m - n;
         if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
@@ -827,6 +834,8 @@ void plan_layout(Ctx &c)
     }
     if (c.smode == RSILU_S_CG)
         for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
+    if (c.prm.krylov == RSILU_KRYLOV_LSQR)
+        for (size_t *o : {&L.l_v, &L.l_mv, &L.l_w}) *o = b.take(sizeof(double) * n);
     // one partial per block of the largest reduction, plus one per long row
     L.npartials = 65536;
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);

@@ -19,6 +19,7 @@ EINVAL, ENOMEM, EHIP, ESTATE, EINTERNAL = -1, -2, -3, -4, -5
 S_AUTO, S_IDENTITY, S_DENSE, S_NONE, S_CG = -1, 0, 1, 2, 3
 FORM_ALG3, FORM_ALG2 = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
+KRYLOV_PCGLS, KRYLOV_LSQR = 0, 1
 TRSV_SYNCFREE, TRSV_LEVELS, TRSV_HYBRID = 0, 1, 2
 # factor / level selectors
 L1, L2, U, AHAT, UDIAG = 0, 1, 2, 3, 4
@@ -44,7 +45,8 @@ class rsilu_params_t(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("tau", ctypes.c_double), ("mu", ctypes.c_double),
                 ("small", ctypes.c_double), ("colscale", ctypes.c_int32), ("smode", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32)]
+                ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
+                ("krylov", ctypes.c_int32)]
 
 
 class rsilu_stats_t(ctypes.Structure):

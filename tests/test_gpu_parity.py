@@ -466,3 +466,47 @@ def test_solve_cg_fixed_iterations(gpu_lib, name):
     assert it == res.iters
     assert np.linalg.norm(x - res.x) <= 1e-8 * np.linalg.norm(res.x)
     assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm
+
+
+# --------------------------------------------------------------- LSQR (M-inner-product form)
+
+
+@pytest.mark.parametrize("name,smode", [("c1", "none"), ("c1", "dense"), ("c2-small", "none"), ("long-rows", "none")])
+@pytest.mark.parametrize("mode", ["hybrid", "levels"])
+def test_lsqr_fixed_iterations(gpu_lib, name, smode, mode):
+    """Four LSQR steps follow the oracle's lsqr_m."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    sm = {"none": R.S_NONE, "dense": R.S_DENSE}[smode]
+    trsv = {"hybrid": R.TRSV_HYBRID, "levels": R.TRSV_LEVELS}[mode]
+    x, code, it, atr, rel = run_solve(R, prob, 1e-14, mu=1.0, smode=sm, maxit=4, trsv=trsv, form=R.FORM_ALG2,
+                                      krylov=R.KRYLOV_LSQR)
+    F = oracle.factor_problem(prob, mu=1.0, smode=smode)
+    res = oracle.lsqr_m(F, prob.b, tol=1e-14, maxit=4)
+    assert it == res.iters == 4 and code == R.NOT_CONVERGED
+    assert np.linalg.norm(x - res.x) <= 1e-8 * np.linalg.norm(res.x)
+    assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm
+
+
+@pytest.mark.parametrize("name,precision", [("c1", 0), ("c2-small", 0), ("c2-small", 1)])
+def test_lsqr_converges_like_oracle(gpu_lib, name, precision):
+    """Whole LSQR solves to tol = 1e-8: iteration counts within 2% (at least one) of the
+    oracle's for the FP64 preconditioner; the true ||A^T r|| at the tolerance (the stop test
+    uses the recurrence estimate, so 2 tol is allowed) and the solution in the oracle's
+    stop-test ball, ||A^T A (x - x_or)|| <= 4 tol ||A^T b||."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    tol = 1e-8
+    x, code, it, atr, rel = run_solve(R, prob, tol, mu=1.0, smode=R.S_NONE, maxit=2000, form=R.FORM_ALG2,
+                                      krylov=R.KRYLOV_LSQR, precision=precision)
+    F = oracle.factor_problem(prob, mu=1.0, smode="none")
+    res = oracle.lsqr_m(F, prob.b, tol=tol, maxit=2000)
+    assert code == R.OK and res.status == "ok"
+    if precision == 0:
+        assert abs(it - res.iters) <= max(1, int(0.02 * res.iters))
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    assert np.linalg.norm(A.T @ (prob.b - A @ x)) <= 2 * tol * atb
+    e = x - res.x
+    assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
+    print("%s precision %d: LSQR its %d, oracle its %d" % (name, precision, it, res.iters))

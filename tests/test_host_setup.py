@@ -109,7 +109,8 @@ def test_explicit_zeros_are_stripped():
 
 @pytest.mark.parametrize("case", ["m<n", "bad col", "unsorted", "duplicate", "nan", "inf", "bad ptr", "bad mu",
                                   "bad tau", "bad small", "bad form", "bad smode", "bad precision",
-                                  "fp32 syncfree", "fp32 dense", "cg fp32", "cg syncfree", "cg steps"])
+                                  "fp32 syncfree", "fp32 dense", "cg fp32", "cg syncfree", "cg steps",
+                                  "lsqr alg3", "lsqr identity", "lsqr syncfree", "bad krylov"])
 def test_invalid_input(case):
     m, n, rp, c, v = dense_problem(np.array([[1.0, 2.0], [3.0, 0.0], [0.0, 4.0]]))
     prm = R.rsilu_params_default()
@@ -160,6 +161,18 @@ def test_invalid_input(case):
         elif case == "cg steps":
             prm.smode = R.S_CG
             prm.cg_steps = 0
+        elif case == "lsqr alg3":
+            prm.krylov = R.KRYLOV_LSQR
+        elif case == "lsqr identity":
+            prm.krylov = R.KRYLOV_LSQR
+            prm.form = R.FORM_ALG2
+            prm.smode = R.S_IDENTITY
+        elif case == "lsqr syncfree":
+            prm.krylov = R.KRYLOV_LSQR
+            prm.form = R.FORM_ALG2
+            prm.trsv = R.TRSV_SYNCFREE
+        elif case == "bad krylov":
+            prm.krylov = 2
         code, h = R.rsilu_factor(m, n, rp, c, v, prm)
     assert code == R.EINVAL and h is None
 
@@ -234,3 +247,14 @@ def test_fp32_auto_resolves_to_identity_and_shrinks_footprint():
     assert R.rsilu_device_bytes(b) < 0.8 * R.rsilu_device_bytes(a)
     for hh in (h64, h32, a, b):
         R.rsilu_destroy(hh)
+
+
+def test_lsqr_auto_resolves_to_spd_modes():
+    small = gen.random_sparse(90, 60, k=4, seed=8)
+    big = gen.by_name("c2-small")
+    for p, want in [(small, R.S_DENSE), (big, R.S_NONE)]:
+        prm = R.rsilu_params_default(mu=1.0, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR, smode=R.S_AUTO)
+        code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+        assert code == R.OK
+        assert R.rsilu_get_stats(h).smode == want
+        R.rsilu_destroy(h)
