@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark: preconditioned least-squares solves per second on one MI355X.
 
-A step is one whole solve (Algorithm 1 with its preconditioning step, every
-kernel on the GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from
+A step is one whole preconditioned solve (LSQR or Algorithm 1, every kernel
+on the GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from
 b resident in HBM to x in HBM with the iteration count and ||A^T r|| on the
 host. Setup (the host ILUP) is done once, outside the timed region.
 
