@@ -131,6 +131,10 @@ typedef struct {
     int32_t precision; /* RSILU_PREC_*; default RSILU_PREC_FP64 */
     int32_t cg_steps;  /* CG steps of RSILU_S_CG, 1..64; default 2 */
     int32_t krylov;    /* RSILU_KRYLOV_*; default RSILU_KRYLOV_PCGLS */
+    int32_t graph;     /* 1: the `poll` iterations between two polls are captured once
+                          into a HIP graph (per upload) and replayed, one launch instead
+                          of some 30 kernel launches per iteration; 0: launched one by
+                          one. Profiling runs always launch one by one. Default 1. */
 } rsilu_params_t;
 
 typedef struct {
@@ -155,7 +159,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
- * precision = FP64, cg_steps = 2, krylov = PCGLS. */
+ * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

@@ -483,7 +483,45 @@ void enqueue_iteration(Ctx &c, hipStream_t s, const Ptrs &P)
     launch_pupdate(s, n, P.h, P.p, P.st, false, P.done);
 }
 
+// Capture `poll` iterations of the configured solver into a graph (on the
+// handle's own stream, thread-local capture mode), for replay by rsilu_solve.
+hipError_t capture_iterations(Ctx &c, const Ptrs &P)
+{
+    hipError_t e = hipSuccess;
+    if (!c.cap_stream) {
+        hipStream_t cs;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        c.cap_stream = cs;
+    }
+    hipStream_t cs = static_cast<hipStream_t>(c.cap_stream);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < c.prm.poll; ++i) {
+        if (c.prm.krylov == RSILU_KRYLOV_LSQR)
+            enqueue_lsqr_iteration(c, cs, P);
+        else
+            enqueue_iteration(c, cs, P);
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess) return e;
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    c.graph_exec = x;
+    return hipSuccess;
+}
+
 }  // namespace
+
+void release_graph(Ctx &c)
+{
+    if (c.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(c.graph_exec));
+    c.graph_exec = nullptr;
+}
+
 }  // namespace rsilu
 
 using namespace rsilu;
@@ -506,6 +544,7 @@ void rsilu_params_default(rsilu_params_t *p)
     p->precision = RSILU_PREC_FP64;
     p->cg_steps = 2;
     p->krylov = RSILU_KRYLOV_PCGLS;
+    p->graph = 1;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)
@@ -643,6 +682,7 @@ rsilu_status_t rsilu_get_levels(rsilu_handle_t h, int32_t which, int32_t *level_
 rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipStream_t s)
 {
     if (!h || !dev_buf) return RSILU_EINVAL;
+    release_graph(*h);  // a captured graph holds the previous buffer's addresses
     if ((reinterpret_cast<uintptr_t>(dev_buf) & 255u) != 0) return RSILU_EINVAL;
     if (bytes < h->lay.total) return RSILU_ENOMEM;
     Ctx &c = *h;
@@ -760,19 +800,28 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b, double tol, double
     }
     RSILU_HIP(hipGetLastError());
 
-    // ---- iterations, polled every `poll` steps (maxit = 0 stops after the init)
+    // ---- iterations, polled every `poll` steps (maxit = 0 stops after the init). With
+    // graphs, `poll` iterations are captured once per upload and replayed; iterations
+    // past maxit or past convergence return at once on the device's stop flag.
+    const bool use_graph = c.prm.graph && !c.prof;
+    if (use_graph && !c.graph_exec) RSILU_HIP(capture_iterations(c, P));
     int64_t enqueued = 0;
     bool stop = c.prm.maxit == 0;
     while (!stop) {
-        const int batch = (int)std::min<int64_t>(c.prm.poll, (int64_t)c.prm.maxit - enqueued);
-        for (int i = 0; i < batch; ++i) {
-            c.ev_iter = (int)(enqueued + i + 1);
-            if (lsqr)
-                enqueue_lsqr_iteration(c, s, P);
-            else
-                enqueue_iteration(c, s, P);
+        if (use_graph) {
+            RSILU_HIP(hipGraphLaunch(static_cast<hipGraphExec_t>(c.graph_exec), s));
+            enqueued += c.prm.poll;
+        } else {
+            const int batch = (int)std::min<int64_t>(c.prm.poll, (int64_t)c.prm.maxit - enqueued);
+            for (int i = 0; i < batch; ++i) {
+                c.ev_iter = (int)(enqueued + i + 1);
+                if (lsqr)
+                    enqueue_lsqr_iteration(c, s, P);
+                else
+                    enqueue_iteration(c, s, P);
+            }
+            enqueued += batch;
         }
-        enqueued += batch;
         RSILU_HIP(hipGetLastError());
         RSILU_HIP(hipMemcpyAsync(&mail->poll, P.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         RSILU_HIP(hipStreamSynchronize(s));
@@ -925,6 +974,8 @@ rsilu_status_t rsilu_get_profile(rsilu_handle_t h, rsilu_profile_t *out)
 void rsilu_destroy(rsilu_handle_t h)
 {
     if (!h) return;
+    release_graph(*h);
+    if (h->cap_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(h->cap_stream));
     if (h->pinned) (void)hipHostFree(h->pinned);
     for (void *e : h->ev_pool) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     delete h;

@@ -128,6 +128,8 @@ struct Ctx {
     size_t dev_bytes = 0;
     int device = -1;
     void *pinned = nullptr;  // small host-pinned mailbox for polling
+    void *graph_exec = nullptr;  // hipGraphExec_t of `poll` captured iterations (per upload)
+    void *cap_stream = nullptr;  // hipStream_t the iterations are captured on
 
     // kernel timing (rsilu_set_profiling)
     bool prof = false;
@@ -150,5 +152,7 @@ inline bool fp32(const Ctx &c) { return c.prm.precision == RSILU_PREC_FP32; }
 rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *rowptr,
                                    const int32_t *colind, const double *val);
 void plan_layout(Ctx &c);
+// device driver (capi.hip): drop a captured iteration graph
+void release_graph(Ctx &c);
 
 }  // namespace rsilu

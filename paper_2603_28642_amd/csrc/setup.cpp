@@ -443,7 +443,7 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
         !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
          P.smode != RSILU_S_NONE && P.smode != RSILU_S_CG) ||
-        (P.krylov != RSILU_KRYLOV_PCGLS && P.krylov != RSILU_KRYLOV_LSQR) ||
+        (P.krylov != RSILU_KRYLOV_PCGLS && P.krylov != RSILU_KRYLOV_LSQR) || (P.graph != 0 && P.graph != 1) ||
         (P.krylov == RSILU_KRYLOV_LSQR &&
          (P.form != RSILU_FORM_ALG2 || P.trsv == RSILU_TRSV_SYNCFREE ||
           (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_NONE && P.smode != RSILU_S_DENSE))) ||

@@ -46,7 +46,7 @@ class rsilu_params_t(ctypes.Structure):
                 ("small", ctypes.c_double), ("colscale", ctypes.c_int32), ("smode", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
-                ("krylov", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class rsilu_stats_t(ctypes.Structure):

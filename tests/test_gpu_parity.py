@@ -510,3 +510,37 @@ def test_lsqr_converges_like_oracle(gpu_lib, name, precision):
     e = x - res.x
     assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
     print("%s precision %d: LSQR its %d, oracle its %d" % (name, precision, it, res.iters))
+
+
+# --------------------------------------------------------------- captured iteration graphs
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small", "long-rows"])
+@pytest.mark.parametrize("cfg", ["pcgls-alg3", "lsqr-alg2", "pcgls-syncfree"])
+def test_graph_replays_equal_eager(gpu_lib, name, cfg):
+    """Solves that replay the captured iteration graph (several replays per solve, eager
+    work and synchronisations in between, three solves, then a re-upload to a new buffer)
+    give bit for bit the results of solves launched kernel by kernel."""
+    R = gpu_lib
+    torch = torch_dev()
+    prob = PROBLEMS[name]()
+    kw = {"pcgls-alg3": dict(smode=R.S_IDENTITY),
+          "lsqr-alg2": dict(smode=R.S_NONE, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR),
+          "pcgls-syncfree": dict(smode=R.S_NONE, form=R.FORM_ALG2, trsv=R.TRSV_SYNCFREE)}[cfg]
+    b = to_dev(prob.b)
+    eager = make(R, prob, mu=1.0, maxit=60, graph=0, **kw)
+    xe, ce, ie, ae, re_ = eager.solve(b, tol=1e-10)
+    want = to_host(xe)
+    eager.close()
+    S = make(R, prob, mu=1.0, maxit=60, graph=1, **kw)
+    for rep in range(4):
+        if rep == 3:
+            S.upload()  # new buffer: the graph is captured again
+        x, code, it, atr, rel = S.solve(b, tol=1e-10)
+        got = to_host(x)
+        assert code == ce and it == ie, (rep, code, ce, it, ie)
+        assert np.array_equal(got.view(np.int64), want.view(np.int64)), rep
+        # eager work on the same stream between replays
+        torch.cuda.synchronize()
+        _ = (b * 2.0).sum().item()
+    S.close()
