@@ -1,0 +1,112 @@
+"""Parity at the full sizes of the benchmarked configurations, in the launch
+configuration bench.py times (hybrid schedule, Algorithm 2 without correction, LSQR).
+
+* grid workload, 600000 x 400000: every triangular solve against the oracle's
+  substitutions (componentwise backward error, forward difference); four LSQR steps
+  against the oracle's; the whole solve against the oracle's (iteration counts within 2%,
+  both solutions in the same stop-test ball);
+* the same generator at 1500000 x 1000000 with the FP32 preconditioner: the whole solve
+  reaches the tolerance on the true residual, and lies in the stop-test ball of the FP64
+  path on the same GPU.
+"""
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps / 2
+PARAMS = dict(mu=1.0, smode=2, form=1, krylov=1)  # S^ none, Algorithm 2 form, LSQR
+
+
+@pytest.fixture(scope="module")
+def c2():
+    prob = gen.by_name("c2")
+    F = oracle.factor_problem(prob, mu=1.0, smode="none")
+    return prob, F
+
+
+def test_c2_triangular_solves(gpu_lib, c2):
+    R = gpu_lib
+    import torch
+
+    prob, F = c2
+    S = R.Solver.from_problem(prob, **PARAMS).upload()
+    rhs = np.random.default_rng(21).standard_normal(prob.n)
+    for which, T, diag, lower in [(R.T_L1, F.L1, None, True), (R.T_L1T, F.L1T, None, False),
+                                  (R.T_U, F.U, F.Udiag, False), (R.T_UT, F.UT, F.Udiag, True)]:
+        x = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        assert R.rsilu_trsv(S.h, which, torch.from_numpy(rhs).cuda(), x) == R.OK
+        got = x.cpu().numpy()
+        want = oracle.lower_solve(T, rhs, diag) if lower else oracle.upper_solve(T, rhs, diag)
+        Td = T.scipy()
+        d = np.ones(prob.n) if diag is None else diag
+        resid = Td @ got + d * got - rhs
+        scale = abs(Td) @ np.abs(got) + np.abs(d * got) + np.abs(rhs)
+        k = np.diff(T.rowptr) + 2
+        assert np.all(np.abs(resid) <= 4 * k * EPS * scale), which
+        assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want), which
+    S.close()
+
+
+def test_c2_four_lsqr_steps(gpu_lib, c2):
+    R = gpu_lib
+    import torch
+
+    prob, F = c2
+    S = R.Solver.from_problem(prob, maxit=4, **PARAMS).upload()
+    x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=1e-14)
+    got = x.cpu().numpy()
+    S.close()
+    res = oracle.lsqr_m(F, prob.b, tol=1e-14, maxit=4)
+    assert it == res.iters == 4
+    assert np.linalg.norm(got - res.x) <= 1e-8 * np.linalg.norm(res.x)
+    assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm
+
+
+def test_c2_whole_solve(gpu_lib, c2):
+    R = gpu_lib
+    import torch
+
+    prob, F = c2
+    tol = 1e-8
+    S = R.Solver.from_problem(prob, maxit=2000, **PARAMS).upload()
+    x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=tol)
+    got = x.cpu().numpy()
+    S.close()
+    res = oracle.lsqr_m(F, prob.b, tol=tol, maxit=2000)
+    assert code == R.OK and res.status == "ok"
+    assert abs(it - res.iters) <= max(1, int(0.02 * res.iters)), (it, res.iters)
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    assert np.linalg.norm(A.T @ (prob.b - A @ got)) <= 2 * tol * atb
+    e = got - res.x
+    assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
+    print("grid 600000 x 400000: gpu its %d, oracle its %d, ||A^T A e|| / ||A^T b|| = %.2e" % (
+        it, res.iters, np.linalg.norm(A.T @ (A @ e)) / atb))
+
+
+def test_c4_fp32_preconditioner(gpu_lib):
+    R = gpu_lib
+    import torch
+
+    prob = gen.by_name("c4")
+    tol = 1e-8
+    b = torch.from_numpy(prob.b).cuda()
+    out = {}
+    for prec in (R.PREC_FP64, R.PREC_FP32):
+        S = R.Solver.from_problem(prob, maxit=2000, precision=prec, **PARAMS).upload()
+        x, code, it, atr, rel = S.solve(b, tol=tol)
+        out[prec] = (x.cpu().numpy(), code, it)
+        S.close()
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    for prec, (x, code, it) in out.items():
+        assert code == R.OK, prec
+        assert np.linalg.norm(A.T @ (prob.b - A @ x)) <= 2 * tol * atb, prec
+    e = out[R.PREC_FP32][0] - out[R.PREC_FP64][0]
+    assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
+    print("grid 1500000 x 1000000: its fp64 %d, fp32-preconditioner %d" % (out[R.PREC_FP64][2], out[R.PREC_FP32][2]))

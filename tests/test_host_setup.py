@@ -258,3 +258,24 @@ def test_lsqr_auto_resolves_to_spd_modes():
         assert code == R.OK
         assert R.rsilu_get_stats(h).smode == want
         R.rsilu_destroy(h)
+
+
+def test_full_size_grid_setup_bit_exact():
+    """The grid workload at its full size (600000 x 400000): permutation, factors and level
+    schedules bit-identical to the oracle's."""
+    p = gen.by_name("c2")
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_NONE)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    F = oracle.factor_problem(p, mu=1.0, smode="none")
+    st = R.rsilu_get_stats(h)
+    assert np.array_equal(R.rsilu_get_perm(h, p.m), F.perm)
+    for which, C in [(R.L1, F.L1), (R.L2, F.L2), (R.U, F.U)]:
+        rp, col, val = R.rsilu_get_factor(h, which, C.nrows)
+        assert np.array_equal(rp, C.rowptr) and np.array_equal(col, C.col) and np.array_equal(bits(val), bits(C.val))
+    assert np.array_equal(bits(R.rsilu_get_factor(h, R.UDIAG, p.n)), bits(F.Udiag))
+    for which, key, nl in [(R.LEV_L1, "L1", st.levels_l1), (R.LEV_U, "U", st.levels_u)]:
+        ptr, rows = R.rsilu_get_levels(h, which, p.n, nl)
+        want_ptr, want_rows = F.lev[key]
+        assert np.array_equal(ptr, want_ptr) and np.array_equal(rows, want_rows)
+    R.rsilu_destroy(h)
