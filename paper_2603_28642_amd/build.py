@@ -2,7 +2,8 @@
 
 The host setup (setup.cpp) is compiled by g++ with -ffp-contract=off so the
 factorization's floating-point decisions are reproducible; the kernels, the
-C ABI (*.hip) and the serving runtime (serve.cpp) by hipcc for gfx950.
+C ABI, the batched persistent solves (*.hip) and the serving runtime (serve.cpp)
+by hipcc for gfx950.
 """
 
 import os
@@ -40,7 +41,7 @@ def build(quiet=False):
           "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include")] + INCLUDES +
          ["-c", os.path.join(CSRC, "setup.cpp"), "-o", setup_o], quiet)
     objs.append(setup_o)
-    for name in ("kernels.hip", "capi.hip", "serve.cpp"):
+    for name in ("kernels.hip", "capi.hip", "batch.hip", "serve.cpp"):
         o = os.path.join(OUT_DIR, name.rsplit(".", 1)[0] + ".o")
         _run([HIPCC] + HIP_FLAGS + INCLUDES + ["-c", os.path.join(CSRC, name), "-o", o], quiet)
         objs.append(o)

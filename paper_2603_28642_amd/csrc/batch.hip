@@ -1,0 +1,872 @@
+// Batched persistent solves (rsilu_batch.h): one workgroup owns one problem and
+// runs its whole preconditioned LSQR inside one launch; the autotuner picks the
+// tile of that kernel, or the plain multi-kernel path, per problem signature.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <type_traits>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "rsilu_batch.h"
+
+namespace rsilu {
+namespace {
+
+// ------------------------------------------------------------------ descriptors
+
+// CSR product operand; rows longer than long_thresh (listed in long_rows) are
+// summed by the whole workgroup.
+struct BOp {
+    const int32_t *ptr, *col;
+    const double *val;
+    const int32_t *long_rows;
+    int32_t nrows, nlong, long_thresh, pad;
+};
+
+// Triangular factor in level order: position p of level l (lev[l] <= p <
+// lev[l+1]) solves row rows[p] with the entries lptr[p]..lptr[p+1] of
+// lcol/lval and divides by ldiag[p] (null: unit diagonal). Values in the
+// preconditioner's precision.
+struct BTri {
+    const int32_t *lev, *rows, *lptr, *lcol;
+    const void *lval, *ldiag;
+    int32_t nlev, pad;
+};
+
+struct BOut {
+    double atr, nb;
+    int32_t iters, status;
+    int32_t pad[2];
+};
+
+// One problem of a launch: its operators and work vectors inside its handle's
+// device buffer, the caller's b and x, and its outcome slot.
+struct BDesc {
+    BOp A, AT;
+    BTri tri[4];  // applied in this order: U^T (forward), L1^T (backward), L1 (forward), U (backward)
+    const int32_t *perm;
+    const double *colnorm, *b;
+    double *x;
+    double *xh, *z, *h, *r, *q, *v, *Mv, *w;
+    void *pin, *pt0, *pt1, *pt2, *pout;  // preconditioner input, temporaries, output (its precision)
+    double tol;
+    int32_t maxit, m, n, pad;
+    BOut *out;
+};
+
+// ------------------------------------------------------------------ device code
+
+template <int G, class T>
+__device__ __forceinline__ T lane_sum(T v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum over the workgroup of one value per thread. Within a wavefront the xor
+// butterfly leaves every lane with the same bits (each step adds the same two
+// operands, commuted); the wavefront sums are then added in index order by
+// every thread, so all threads return identical values and the scalar
+// recurrences that follow stay uniform.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double *red)
+{
+    v = lane_sum<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+
+// y = A x by one workgroup: G lanes per row, two row groups in flight per
+// thread; rows longer than long_thresh are then summed by the whole workgroup.
+// The caller separates it from the producers of x and the readers of y with
+// workgroup barriers.
+template <int NT, int G>
+__device__ void wg_spmv(const BOp &a, const double *x, double *y, double *red)
+{
+    constexpr int RPP = NT / G;
+    constexpr int U = 2;
+    const int gl = threadIdx.x % G, slot = threadIdx.x / G;
+    for (int base = 0; base < a.nrows; base += U * RPP) {
+        int rb[U], re[U];
+        bool own[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = base + u * RPP + slot;
+            rb[u] = 0;
+            re[u] = 0;
+            own[u] = false;
+            if (row < a.nrows) {
+                rb[u] = a.ptr[row];
+                re[u] = a.ptr[row + 1];
+                if (re[u] - rb[u] > a.long_thresh)
+                    re[u] = rb[u];
+                else
+                    own[u] = true;
+            }
+        }
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s[u] = 0.0;
+            for (int k = rb[u] + gl; k < re[u]; k += G) s[u] += a.val[k] * x[a.col[k]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s[u] = lane_sum<G>(s[u]);
+            if (own[u] && gl == 0) y[base + u * RPP + slot] = s[u];
+        }
+    }
+    for (int i = 0; i < a.nlong; ++i) {
+        const int row = a.long_rows[i];
+        const int b = a.ptr[row], e = a.ptr[row + 1];
+        double s = 0.0;
+        for (int k = b + (int)threadIdx.x; k < e; k += NT) s += a.val[k] * x[a.col[k]];
+        s = wg_sum<NT>(s, red);
+        if (threadIdx.x == 0) y[row] = s;
+    }
+}
+
+// T x = rhs by one workgroup, level by level with one barrier per level; G
+// lanes per row. The static data of a thread's first row of the next level
+// (position, entry range, the first E entries of each lane, right-hand side
+// and diagonal) is loaded while the current level is solved, so a level waits
+// only for the x values of its entries. Every x store of a level precedes the
+// barrier that ends it.
+template <class T, int NT, int G>
+__device__ void wg_trsv(const BTri &t, const T *rhs, T *x)
+{
+    constexpr int RPP = NT / G;
+    constexpr int E = G >= 4 ? 1 : 4 / G;
+    const T *lval = static_cast<const T *>(t.lval);
+    const T *ldiag = static_cast<const T *>(t.ldiag);
+    const int gl = threadIdx.x % G, slot = threadIdx.x / G;
+    struct Pf {
+        int row, k0, k1;
+        int c[E];
+        T v[E];
+        T r, d;
+    };
+    auto fetch = [&](int beg, int end) {
+        Pf f;
+        const int p = beg + slot;
+        f.row = -1;
+        f.k0 = 0;
+        f.k1 = 0;
+        f.r = T(0);
+        f.d = T(1);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            f.c[i] = -1;
+            f.v[i] = T(0);
+        }
+        if (p < end) {
+            f.row = t.rows[p];
+            f.k0 = t.lptr[p];
+            f.k1 = t.lptr[p + 1];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int k = f.k0 + gl + i * G;
+                if (k < f.k1) {
+                    f.c[i] = t.lcol[k];
+                    f.v[i] = lval[k];
+                }
+            }
+            f.r = rhs[f.row];
+            if (ldiag) f.d = ldiag[p];
+        }
+        return f;
+    };
+    __syncthreads();  // rhs complete
+    const int nlev = t.nlev;
+    if (nlev == 0) return;
+    int end = t.lev[1];
+    Pf cur = fetch(0, end);
+    for (int l = 0; l < nlev; ++l) {
+        const int beg = t.lev[l];
+        const int nend = l + 2 <= nlev ? t.lev[l + 2] : end;
+        T s = T(0);
+        if (cur.row >= 0) {
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+                if (cur.c[i] >= 0) s += cur.v[i] * x[cur.c[i]];
+            for (int k = cur.k0 + gl + E * G; k < cur.k1; k += G) s += lval[k] * x[t.lcol[k]];
+        }
+        const Pf nxt = fetch(end, l + 1 < nlev ? nend : end);
+        s = lane_sum<G>(s);
+        if (cur.row >= 0 && gl == 0) {
+            T r = cur.r - s;
+            if (ldiag) r = r / cur.d;
+            x[cur.row] = r;
+        }
+        // further rows of a level wider than one pass
+        for (int base = beg + RPP; base < end; base += RPP) {
+            const int p = base + slot;
+            T s2 = T(0);
+            int row = -1;
+            if (p < end) {
+                row = t.rows[p];
+                const int k1 = t.lptr[p + 1];
+                for (int k = t.lptr[p] + gl; k < k1; k += G) s2 += lval[k] * x[t.lcol[k]];
+            }
+            s2 = lane_sum<G>(s2);
+            if (row >= 0 && gl == 0) {
+                T r = rhs[row] - s2;
+                if (ldiag) r = r / ldiag[p];
+                x[row] = r;
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+        end = nend;
+    }
+}
+
+// h = M^{-1} z with M^{-1} = (L1 U)^{-1} (L1 U)^{-T} (Algorithm 2, k = n, no M_b
+// correction): U^T t0 = z, L1^T t1 = t0, L1 t2 = t1, U h = t2. In FP32 the input
+// is rounded to FP32 first and h converted back.
+template <class T, int NT, int G>
+__device__ void wg_precond(const BDesc &d)
+{
+    const int n = d.n;
+    T *t0 = static_cast<T *>(d.pt0), *t1 = static_cast<T *>(d.pt1), *t2 = static_cast<T *>(d.pt2);
+    const T *in;
+    T *out;
+    if constexpr (std::is_same<T, float>::value) {
+        float *fi = static_cast<float *>(d.pin);
+        for (int i = threadIdx.x; i < n; i += NT) fi[i] = (float)d.z[i];
+        in = fi;
+        out = static_cast<float *>(d.pout);
+    } else {
+        in = d.z;
+        out = d.h;
+    }
+    wg_trsv<T, NT, G>(d.tri[0], in, t0);
+    wg_trsv<T, NT, G>(d.tri[1], t0, t1);
+    wg_trsv<T, NT, G>(d.tri[2], t1, t2);
+    wg_trsv<T, NT, G>(d.tri[3], t2, out);
+    __syncthreads();
+    if constexpr (std::is_same<T, float>::value)
+        for (int i = threadIdx.x; i < n; i += NT) d.h[i] = (double)out[i];
+}
+
+// The whole LSQR solve of problem blockIdx.x (M-inner-product form): init,
+// iterations until the stop test or maxit, then x = D x_hat and the true
+// ||A^T (b - A x)||. Every scalar is computed identically by every thread.
+template <class T, int NT, int GS, int GT>
+__global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ descs)
+{
+    __shared__ double red[NT / 64];
+    const BDesc &d = descs[blockIdx.x];
+    const int tid = threadIdx.x, m = d.m, n = d.n;
+    double *r = d.r, *q = d.q, *z = d.z, *h = d.h, *xh = d.xh, *v = d.v, *Mv = d.Mv, *w = d.w;
+
+    // u = P b / beta1 (u kept in r), x_hat = 0
+    double sq = 0.0;
+    for (int i = tid; i < m; i += NT) {
+        const double bi = d.b[d.perm[i]];
+        r[i] = bi;
+        sq += bi * bi;
+    }
+    for (int i = tid; i < n; i += NT) xh[i] = 0.0;
+    const double b1 = sqrt(wg_sum<NT>(sq, red));
+    int done = 0, status = 0, iter = 0;
+    double nb = 0.0, lb = b1, la = 0.0, phibar = b1, rhobar = 0.0, snorm = 0.0;
+    if (b1 == 0.0) {
+        done = 1;
+    } else if (!isfinite(b1)) {
+        done = 1;
+        status = 2;
+    }
+    // s = A_hat^T u, ||D^{-1} s|| gives ||A^T b|| = beta1 ||D^{-1} s||
+    if (!done) {
+        for (int i = tid; i < m; i += NT) r[i] = r[i] / lb;
+        __syncthreads();
+        wg_spmv<NT, GS>(d.AT, r, z, red);
+        __syncthreads();
+        sq = 0.0;
+        for (int i = tid; i < n; i += NT) {
+            const double c = d.colnorm[i] * z[i];
+            sq += c * c;
+        }
+        snorm = sqrt(wg_sum<NT>(sq, red));
+        nb = lb * snorm;
+        if (nb == 0.0) {
+            done = 1;
+        } else if (!isfinite(nb)) {
+            done = 1;
+            status = 2;
+        }
+    }
+    // h = M^{-1} s, alpha = sqrt(s . h), v = h / alpha, M v = s / alpha, w = v
+    if (!done) {
+        wg_precond<T, NT, GT>(d);
+        sq = 0.0;
+        for (int i = tid; i < n; i += NT) sq += z[i] * h[i];
+        const double tot = wg_sum<NT>(sq, red);
+        if (!(tot > 0.0) || !isfinite(tot)) {
+            done = 1;
+            status = 2;
+        } else {
+            la = sqrt(tot);
+            rhobar = la;
+        }
+        if (d.maxit == 0 && !done) {
+            done = 1;
+            status = 1;
+        }
+    }
+    if (!done)
+        for (int i = tid; i < n; i += NT) {
+            const double vi = h[i] / la;
+            v[i] = vi;
+            Mv[i] = z[i] / la;
+            w[i] = vi;
+        }
+
+    while (!done) {
+        // t = A_hat v - alpha u, beta = ||t||, u = t / beta (t kept in q)
+        __syncthreads();
+        wg_spmv<NT, GS>(d.A, v, q, red);
+        __syncthreads();
+        sq = 0.0;
+        for (int i = tid; i < m; i += NT) {
+            const double ti = q[i] - la * r[i];
+            q[i] = ti;
+            sq += ti * ti;
+        }
+        lb = sqrt(wg_sum<NT>(sq, red));
+        if (!isfinite(lb)) {
+            status = 2;
+            break;
+        }
+        for (int i = tid; i < m; i += NT) r[i] = lb > 0.0 ? q[i] / lb : q[i];
+        // s = A_hat^T u - beta M v with ||D^{-1} s||
+        __syncthreads();
+        wg_spmv<NT, GS>(d.AT, r, z, red);
+        __syncthreads();
+        sq = 0.0;
+        for (int i = tid; i < n; i += NT) {
+            const double si = z[i] - lb * Mv[i];
+            z[i] = si;
+            const double c = d.colnorm[i] * si;
+            sq += c * c;
+        }
+        snorm = sqrt(wg_sum<NT>(sq, red));
+        // h = M^{-1} s, alpha = sqrt(s . h)
+        wg_precond<T, NT, GT>(d);
+        sq = 0.0;
+        for (int i = tid; i < n; i += NT) sq += z[i] * h[i];
+        const double tot = wg_sum<NT>(sq, red);
+        // plane rotation and the stop test on |phibar c| ||D^{-1} s||
+        const double lan = tot > 0.0 ? sqrt(tot) : 0.0;
+        const double rho = sqrt(rhobar * rhobar + lb * lb);
+        const double c = rhobar / rho, sn = lb / rho;
+        const double theta = sn * lan;
+        rhobar = -c * lan;
+        const double phi = c * phibar;
+        phibar = sn * phibar;
+        const double phi_rho = phi / rho, theta_rho = theta / rho;
+        la = lan;
+        iter += 1;
+        const double est = fabs(phibar * c) * snorm;
+        int lstop = 0, lstatus = 0;
+        if (!isfinite(est) || !isfinite(tot) || !isfinite(rho)) {
+            lstop = 1;
+            lstatus = 2;
+        } else if (est <= d.tol * nb) {
+            lstop = 1;
+        } else if (la == 0.0) {
+            lstop = 1;
+            lstatus = tot < 0.0 ? 2 : 0;
+        } else if (iter >= d.maxit) {
+            lstop = 1;
+            lstatus = 1;
+        }
+        // x_hat += (phi / rho) w; v = h / alpha, M v = s / alpha, w = v - (theta / rho) w
+        for (int i = tid; i < n; i += NT) {
+            const double wo = w[i];
+            xh[i] = xh[i] + phi_rho * wo;
+            if (la > 0.0) {
+                const double vi = h[i] / la;
+                v[i] = vi;
+                Mv[i] = z[i] / la;
+                w[i] = vi - theta_rho * wo;
+            }
+        }
+        if (lstop) {
+            done = 1;
+            status = lstatus;
+        }
+    }
+
+    // x = D x_hat; true ||A^T (b - A x)|| = ||D^{-1} A_hat^T (P b - A_hat x_hat)||
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) d.x[i] = xh[i] / d.colnorm[i];
+    wg_spmv<NT, GS>(d.A, xh, q, red);
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) r[i] = d.b[d.perm[i]] - q[i];
+    __syncthreads();
+    wg_spmv<NT, GS>(d.AT, r, z, red);
+    __syncthreads();
+    sq = 0.0;
+    for (int i = tid; i < n; i += NT) {
+        const double c = d.colnorm[i] * z[i];
+        sq += c * c;
+    }
+    const double atr = sqrt(wg_sum<NT>(sq, red));
+    if (tid == 0) {
+        d.out->atr = atr;
+        d.out->nb = nb;
+        d.out->iters = iter;
+        d.out->status = status;
+    }
+}
+
+// ------------------------------------------------------------------ compiled tiles
+
+struct TileEntry {
+    rsilu_tile_t tile;
+    const void *f64, *f32;
+};
+
+template <int NT, int GS, int GT>
+TileEntry tile_entry()
+{
+    return TileEntry{{NT, GS, GT, 0}, reinterpret_cast<const void *>(&k_batch_lsqr<double, NT, GS, GT>),
+                     reinterpret_cast<const void *>(&k_batch_lsqr<float, NT, GS, GT>)};
+}
+
+const std::vector<TileEntry> &tiles()
+{
+    static const std::vector<TileEntry> t = {
+        tile_entry<256, 4, 1>(),  tile_entry<256, 4, 4>(),  tile_entry<256, 8, 1>(),  tile_entry<256, 8, 4>(),
+        tile_entry<512, 4, 1>(),  tile_entry<512, 4, 4>(),  tile_entry<512, 8, 1>(),  tile_entry<512, 8, 4>(),
+        tile_entry<1024, 4, 1>(), tile_entry<1024, 4, 4>(), tile_entry<1024, 8, 1>(), tile_entry<1024, 8, 4>(),
+    };
+    return t;
+}
+
+const TileEntry *find_tile(const rsilu_tile_t &t)
+{
+    for (const TileEntry &e : tiles())
+        if (e.tile.threads == t.threads && e.tile.spmv_lanes == t.spmv_lanes && e.tile.tri_lanes == t.tri_lanes &&
+            t.reserved == 0)
+            return &e;
+    return nullptr;
+}
+
+constexpr rsilu_tile_t kDefaultTile = {256, 8, 1, 0};
+
+// ------------------------------------------------------------------ host side
+
+template <class T>
+T *at(const Ctx &c, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(c.dev) + off);
+}
+
+BOp bop(const Ctx &c, const DevCsrOff &o, const DevPlanOff &p)
+{
+    return BOp{at<int32_t>(c, o.ptr), at<int32_t>(c, o.col), at<double>(c, o.val), at<int32_t>(c, p.long_rows),
+               o.nrows, p.nlong, p.long_thresh, 0};
+}
+
+BTri btri(const Ctx &c, const DevTriOff &o)
+{
+    return BTri{at<int32_t>(c, o.lev), at<int32_t>(c, o.rows), at<int32_t>(c, o.lo.ptr), at<int32_t>(c, o.lo.col),
+                at<void>(c, o.lo.val), o.ldiag ? at<void>(c, o.ldiag) : nullptr, o.nlev, 0};
+}
+
+// Whether a handle can be solved by the batched kernel.
+rsilu_status_t check_handle(const Ctx &c)
+{
+    if (!c.dev) return RSILU_EINVAL;
+    if (c.prm.krylov != RSILU_KRYLOV_LSQR || c.prm.form != RSILU_FORM_ALG2) return RSILU_EINVAL;
+    if (c.m > c.n && c.smode != RSILU_S_NONE) return RSILU_EINVAL;
+    return RSILU_OK;
+}
+
+BDesc make_desc(const Ctx &c, const double *b, double *x, double tol, int32_t maxit, BOut *out)
+{
+    const Layout &L = c.lay;
+    BDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.A = bop(c, L.A, L.pA);
+    d.AT = bop(c, L.AT, L.pAT);
+    d.tri[0] = btri(c, L.UTf);
+    d.tri[1] = btri(c, L.L1b);
+    d.tri[2] = btri(c, L.L1f);
+    d.tri[3] = btri(c, L.Ub);
+    d.perm = at<int32_t>(c, L.perm);
+    d.colnorm = at<double>(c, L.colnorm);
+    d.b = b;
+    d.x = x;
+    d.xh = at<double>(c, L.xh);
+    d.z = at<double>(c, L.z);
+    d.h = at<double>(c, L.h);
+    d.r = at<double>(c, L.r);
+    d.q = at<double>(c, L.q);
+    d.v = at<double>(c, L.l_v);
+    d.Mv = at<double>(c, L.l_mv);
+    d.w = at<double>(c, L.l_w);
+    // preconditioner vectors: the same buffers as the multi-kernel path's Algorithm 2
+    d.pt0 = at<void>(c, L.t);
+    d.pt1 = at<void>(c, L.gp);
+    d.pt2 = at<void>(c, L.v);
+    if (fp32(c)) {
+        d.pin = at<void>(c, L.f32a);
+        d.pout = at<void>(c, L.f32b);
+    }
+    d.tol = tol;
+    d.maxit = maxit;
+    d.m = (int32_t)c.m;
+    d.n = (int32_t)c.n;
+    d.out = out;
+    return d;
+}
+
+// Rough work of one problem (entries streamed per iteration plus the levels,
+// which cost a barrier each): problems are ordered by it, largest first, so the
+// longest workgroups start first.
+double work_of(const Ctx &c)
+{
+    return 2.0 * (double)c.nnz_a + (double)(c.L1.nnz() * 2 + c.U.nnz() * 2) +
+           2000.0 * (double)(c.lvL1.nlev() * 2 + c.lvU.nlev() + c.lvUT.nlev());
+}
+
+rsilu_status_t map_status(const BOut &o, int32_t maxit)
+{
+    if (o.status == 2) return RSILU_BREAKDOWN;
+    if (maxit == 0 && o.nb > 0.0) return RSILU_NOT_CONVERGED;
+    if (o.status == 1) return RSILU_NOT_CONVERGED;
+    return RSILU_OK;
+}
+
+}  // namespace
+}  // namespace rsilu
+
+using namespace rsilu;
+
+struct rsilu_batch {
+    int32_t cap = 0;
+    int device = -1;
+    BDesc *d_desc = nullptr;
+    BOut *d_out = nullptr;
+    BDesc *h_desc = nullptr;  // pinned
+    BOut *h_out = nullptr;    // pinned
+    hipStream_t cap_stream = nullptr;
+    std::map<std::pair<int32_t, const void *>, hipGraphExec_t> graphs;  // (count, kernel)
+    std::mutex mu;  // one launch at a time per batch object
+};
+
+namespace rsilu {
+namespace {
+
+#define RSILU_HIPB(call)                               \
+    do {                                               \
+        if ((call) != hipSuccess) return RSILU_EHIP;   \
+    } while (0)
+
+// Descriptor upload, kernel, outcome download: enqueued directly, or captured
+// once per (count, kernel) and replayed.
+rsilu_status_t run_batch(rsilu_batch &bt, int32_t count, const void *fn, int32_t threads, bool use_graph, hipStream_t s)
+{
+    const size_t db = sizeof(BDesc) * (size_t)count, ob = sizeof(BOut) * (size_t)count;
+    auto enqueue = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(bt.d_desc, bt.h_desc, db, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        BDesc *arg = bt.d_desc;
+        void *args[] = {&arg};
+        e = hipLaunchKernel(fn, dim3((unsigned)count), dim3((unsigned)threads), args, 0, st);
+        if (e != hipSuccess) return e;
+        return hipMemcpyAsync(bt.h_out, bt.d_out, ob, hipMemcpyDeviceToHost, st);
+    };
+    if (!use_graph) {
+        RSILU_HIPB(enqueue(s));
+        RSILU_HIPB(hipStreamSynchronize(s));
+        return RSILU_OK;
+    }
+    const auto key = std::make_pair(count, fn);
+    auto it = bt.graphs.find(key);
+    if (it == bt.graphs.end()) {
+        if (!bt.cap_stream) RSILU_HIPB(hipStreamCreateWithFlags(&bt.cap_stream, hipStreamNonBlocking));
+        RSILU_HIPB(hipStreamBeginCapture(bt.cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t ce = enqueue(bt.cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(bt.cap_stream, &g);
+        if (ce != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return RSILU_EHIP;
+        }
+        hipGraphExec_t x = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return RSILU_EHIP;
+        it = bt.graphs.emplace(key, x).first;
+    }
+    RSILU_HIPB(hipGraphLaunch(it->second, s));
+    RSILU_HIPB(hipStreamSynchronize(s));
+    return RSILU_OK;
+}
+
+// Batched solve with an optional maxit override (>= 0) used by the autotuner.
+rsilu_status_t batch_solve(rsilu_batch &bt, int32_t count, const rsilu_handle_t *hs, const double *const *b,
+                           const double *tol, double *const *x, const rsilu_tile_t *tile, rsilu_batch_result_t *res,
+                           hipStream_t s, int32_t maxit_override)
+{
+    if (count < 0 || count > bt.cap) return RSILU_EINVAL;
+    if (count == 0) return RSILU_OK;
+    if (!hs || !b || !tol || !x || !res) return RSILU_EINVAL;
+    const TileEntry *te = find_tile(tile ? *tile : kDefaultTile);
+    if (!te) return RSILU_EINVAL;
+    bool any32 = false, any64 = false;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!hs[i] || !b[i] || !x[i] || static_cast<const void *>(b[i]) == static_cast<const void *>(x[i]))
+            return RSILU_EINVAL;
+        if (!(tol[i] >= 0.0) || !std::isfinite(tol[i])) return RSILU_EINVAL;
+        const rsilu_status_t st = check_handle(*hs[i]);
+        if (st != RSILU_OK) return st;
+        if (hs[i]->device != bt.device) return RSILU_ESTATE;
+        (fp32(*hs[i]) ? any32 : any64) = true;
+        for (int32_t j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return RSILU_EINVAL;
+    }
+    // FP64 and FP32 preconditioners are different kernels: one launch each
+    std::vector<int32_t> order((size_t)count);
+    for (int32_t i = 0; i < count; ++i) order[i] = i;
+    std::vector<double> work((size_t)count);
+    for (int32_t i = 0; i < count; ++i) work[i] = work_of(*hs[i]);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
+    std::lock_guard<std::mutex> lk(bt.mu);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fp = pass == 1;
+        if ((fp && !any32) || (!fp && !any64)) continue;
+        std::vector<int32_t> idx;
+        for (int32_t i : order)
+            if (fp32(*hs[i]) == fp) idx.push_back(i);
+        const int32_t k = (int32_t)idx.size();
+        for (int32_t j = 0; j < k; ++j) {
+            const Ctx &c = *hs[idx[j]];
+            const int32_t mi = maxit_override >= 0 ? maxit_override : c.prm.maxit;
+            bt.h_desc[j] = make_desc(c, b[idx[j]], x[idx[j]], tol[idx[j]], mi, bt.d_out + j);
+        }
+        const rsilu_status_t rc = run_batch(bt, k, fp ? te->f32 : te->f64, te->tile.threads, maxit_override < 0, s);
+        if (rc != RSILU_OK) return rc;
+        for (int32_t j = 0; j < k; ++j) {
+            const BOut &o = bt.h_out[j];
+            const Ctx &c = *hs[idx[j]];
+            rsilu_batch_result_t &r = res[idx[j]];
+            r.iters = o.iters;
+            r.atr_norm = o.atr;
+            r.atr_rel = o.nb > 0.0 ? o.atr / o.nb : 0.0;
+            r.status = map_status(o, maxit_override >= 0 ? maxit_override : c.prm.maxit);
+        }
+    }
+    return RSILU_OK;
+}
+
+}  // namespace
+}  // namespace rsilu
+
+// ------------------------------------------------------------------ autotuner
+
+struct rsilu_tuner {
+    double slack = 1.0;
+    int32_t iters = 8;
+    rsilu_batch_t bt = nullptr;  // single-problem batch object for timing
+    std::map<std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t>, rsilu_tune_result_t> cache;
+    std::mutex mu;
+};
+
+namespace rsilu {
+namespace {
+
+int32_t log2_class(double v) { return v <= 1.0 ? 0 : (int32_t)std::floor(std::log2(v)); }
+
+// Signature of a problem: precision, size class, density class, level class
+// and whether long rows are present.
+std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> signature(const Ctx &c)
+{
+    const double nnz_per_row = c.m ? (double)c.nnz_a / (double)c.m : 0.0;
+    const int32_t levels = c.lvL1.nlev() + c.lvL1T.nlev() + c.lvU.nlev() + c.lvUT.nlev();
+    return std::make_tuple((int32_t)fp32(c), log2_class((double)c.n), log2_class(4.0 * nnz_per_row),
+                           log2_class((double)levels), (int32_t)(c.plA.long_rows.size() > 0));
+}
+
+double elapsed_ms(std::chrono::steady_clock::time_point a)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+}
+
+}  // namespace
+}  // namespace rsilu
+
+extern "C" {
+
+int32_t rsilu_batch_tiles(rsilu_tile_t *out, int32_t max)
+{
+    const auto &t = tiles();
+    if (out)
+        for (int32_t i = 0; i < max && i < (int32_t)t.size(); ++i) out[i] = t[(size_t)i].tile;
+    return (int32_t)t.size();
+}
+
+rsilu_status_t rsilu_batch_create(int32_t capacity, rsilu_batch_t *out)
+{
+    if (!out || capacity < 1 || capacity > 65535) return RSILU_EINVAL;
+    *out = nullptr;
+    rsilu_batch *bt = nullptr;
+    try {
+        bt = new rsilu_batch();
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
+    bt->cap = capacity;
+    if (hipGetDevice(&bt->device) != hipSuccess) {
+        delete bt;
+        return RSILU_EHIP;
+    }
+    const size_t db = sizeof(BDesc) * (size_t)capacity, ob = sizeof(BOut) * (size_t)capacity;
+    if (hipMalloc(&bt->d_desc, db) != hipSuccess || hipMalloc(&bt->d_out, ob) != hipSuccess ||
+        hipHostMalloc(&bt->h_desc, db, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&bt->h_out, ob, hipHostMallocDefault) != hipSuccess) {
+        rsilu_batch_destroy(bt);
+        return RSILU_ENOMEM;
+    }
+    std::memset(bt->h_desc, 0, db);
+    std::memset(bt->h_out, 0, ob);
+    *out = bt;
+    return RSILU_OK;
+}
+
+rsilu_status_t rsilu_batch_solve(rsilu_batch_t bt, int32_t count, const rsilu_handle_t *hs, const double *const *b,
+                                 const double *tol, double *const *x, const rsilu_tile_t *tile,
+                                 rsilu_batch_result_t *res, hipStream_t s)
+{
+    if (!bt) return RSILU_EINVAL;
+    try {
+        return batch_solve(*bt, count, hs, b, tol, x, tile, res, s, -1);
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
+}
+
+void rsilu_batch_destroy(rsilu_batch_t bt)
+{
+    if (!bt) return;
+    for (auto &kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+    if (bt->d_desc) (void)hipFree(bt->d_desc);
+    if (bt->d_out) (void)hipFree(bt->d_out);
+    if (bt->h_desc) (void)hipHostFree(bt->h_desc);
+    if (bt->h_out) (void)hipHostFree(bt->h_out);
+    delete bt;
+}
+
+rsilu_status_t rsilu_tuner_create(double slack, int32_t iters, rsilu_tuner_t *out)
+{
+    if (!out || !std::isfinite(slack) || !(slack > 0.0) || iters < 2) return RSILU_EINVAL;
+    *out = nullptr;
+    rsilu_tuner *t = nullptr;
+    try {
+        t = new rsilu_tuner();
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
+    t->slack = slack;
+    t->iters = iters;
+    const rsilu_status_t rc = rsilu_batch_create(1, &t->bt);
+    if (rc != RSILU_OK) {
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return RSILU_OK;
+}
+
+rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev, double *x_dev,
+                          rsilu_tune_result_t *res, hipStream_t s)
+{
+    if (!t || !h || !b_dev || !x_dev || !res) return RSILU_EINVAL;
+    rsilu_status_t rc = check_handle(*h);
+    if (rc != RSILU_OK) return rc;
+    std::lock_guard<std::mutex> lk(t->mu);
+    const auto key = signature(*h);
+    auto it = t->cache.find(key);
+    if (it != t->cache.end()) {
+        *res = it->second;
+        res->from_cache = 1;
+        return RSILU_OK;
+    }
+    const int32_t K = std::min<int32_t>(t->iters, std::max<int32_t>(h->prm.maxit, 2));
+    const double zero = 0.0;
+    rsilu_batch_result_t br;
+    // candidates of the batched kernel: one untimed run, then the timed one
+    double best = 1e300;
+    rsilu_tile_t best_tile = kDefaultTile;
+    for (const TileEntry &e : tiles()) {
+        for (int rep = 0; rep < 2; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &e.tile, &br, s, K);
+            if (rc != RSILU_OK) return rc;
+            const double ms = elapsed_ms(t0);
+            if (rep == 1 && ms < best) {
+                best = ms;
+                best_tile = e.tile;
+            }
+        }
+    }
+    // the plain path with the same iteration count
+    const int32_t saved = h->prm.maxit;
+    h->prm.maxit = K;
+    double plain = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+        const auto t0 = std::chrono::steady_clock::now();
+        int32_t it_ = 0;
+        double a = 0.0, ar = 0.0;
+        rc = rsilu_solve(h, b_dev, 0.0, x_dev, &it_, &a, &ar, s);
+        if (rc < 0) break;
+        if (rep == 1) plain = elapsed_ms(t0);
+    }
+    h->prm.maxit = saved;
+    if (rc < 0) return rc;
+    rsilu_tune_result_t r{};
+    r.tile = best_tile;
+    r.batched_ms_per_iter = best / K;
+    r.plain_ms_per_iter = plain / K;
+    r.path = best <= t->slack * plain ? 0 : 1;
+    r.from_cache = 0;
+    t->cache.emplace(key, r);
+    *res = r;
+    return RSILU_OK;
+}
+
+int32_t rsilu_tuner_size(rsilu_tuner_t t)
+{
+    if (!t) return 0;
+    std::lock_guard<std::mutex> lk(t->mu);
+    return (int32_t)t->cache.size();
+}
+
+void rsilu_tuner_destroy(rsilu_tuner_t t)
+{
+    if (!t) return;
+    rsilu_batch_destroy(t->bt);
+    delete t;
+}
+
+}  // extern "C"

@@ -13,8 +13,6 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 
-struct rsilu_ctx : rsilu::Ctx {};
-
 namespace rsilu {
 namespace {
 
@@ -716,11 +714,14 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
         return e;
     };
     auto put_tri = [&](const DevTriOff &o, const Csr &a, const std::vector<double> *diag, const Levels &lv,
-                       const Chunks &ch) -> hipError_t {
+                       const Chunks &ch, const LoTri &lo) -> hipError_t {
         hipError_t e = put_csr(o.a, a);
         if (e == hipSuccess && diag) e = put_vals(o.diag, *diag, o.a.vbytes);
         if (e == hipSuccess) e = put(o.rows, lv.rows.data(), lv.rows.size() * sizeof(int32_t));
         if (e == hipSuccess) e = put(o.chunk, ch.ptr.data(), ch.ptr.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = put(o.lev, lv.ptr.data(), lv.ptr.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = put_csr(o.lo, lo.a);
+        if (e == hipSuccess && o.ldiag) e = put_vals(o.ldiag, lo.diag, o.lo.vbytes);
         return e;
     };
     auto put_sweep = [&](const DevTriOff &o, const Sweep &sw) -> hipError_t {
@@ -734,10 +735,10 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put_plan(L.pAT, c.plAT));
     RSILU_HIP(put_plan(L.pL2, c.plL2));
     RSILU_HIP(put_plan(L.pL2T, c.plL2T));
-    RSILU_HIP(put_tri(L.L1f, c.L1, nullptr, c.lvL1, c.chL1));
-    RSILU_HIP(put_tri(L.L1b, c.L1T, nullptr, c.lvL1T, c.chL1T));
-    RSILU_HIP(put_tri(L.Ub, c.U, &c.Udiag, c.lvU, c.chU));
-    RSILU_HIP(put_tri(L.UTf, c.UT, &c.Udiag, c.lvUT, c.chUT));
+    RSILU_HIP(put_tri(L.L1f, c.L1, nullptr, c.lvL1, c.chL1, c.loL1));
+    RSILU_HIP(put_tri(L.L1b, c.L1T, nullptr, c.lvL1T, c.chL1T, c.loL1T));
+    RSILU_HIP(put_tri(L.Ub, c.U, &c.Udiag, c.lvU, c.chU, c.loU));
+    RSILU_HIP(put_tri(L.UTf, c.UT, &c.Udiag, c.lvUT, c.chUT, c.loUT));
     RSILU_HIP(put_sweep(L.L1f, c.swL1));
     RSILU_HIP(put_sweep(L.L1b, c.swL1T));
     RSILU_HIP(put_sweep(L.Ub, c.swU));

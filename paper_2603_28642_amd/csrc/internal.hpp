@@ -49,6 +49,15 @@ struct Sweep {
     std::vector<unsigned char> blob;
 };
 
+// A triangular factor with its rows stored in level order (position p holds
+// row Levels::rows[p]); diag is the diagonal in the same order (empty: unit).
+// Read by the batched persistent solves: one load of the row pointer per
+// position instead of the row index, then its pointer.
+struct LoTri {
+    Csr a;
+    std::vector<double> diag;
+};
+
 // Work plan for a CSR product: rows with more than `long_thresh` entries are
 // split into segments of at most `seg` entries, reduced in a fixed order.
 struct SpmvPlan {
@@ -81,6 +90,10 @@ struct DevTriOff {
     int32_t lanes = 8;
     int32_t nlev = 0;
     size_t blob = 0;  // hybrid sweep: batch blobs
+    // level pointer and the level-ordered copy (LoTri) of the batched solves
+    size_t lev = 0;
+    DevCsrOff lo;
+    size_t ldiag = 0;  // 0 = unit diagonal
 };
 
 struct Layout {
@@ -119,6 +132,7 @@ struct Ctx {
     Levels lvL1, lvL1T, lvU, lvUT;
     Chunks chL1, chL1T, chU, chUT;
     Sweep swL1, swL1T, swU, swUT;
+    LoTri loL1, loL1T, loU, loUT;
     SpmvPlan plA, plAT, plL2, plL2T;
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
 
@@ -156,3 +170,6 @@ void plan_layout(Ctx &c);
 void release_graph(Ctx &c);
 
 }  // namespace rsilu
+
+// The opaque handle of the C ABI (rsilu.h) is the context itself.
+struct rsilu_ctx : rsilu::Ctx {};

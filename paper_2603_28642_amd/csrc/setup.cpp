@@ -139,6 +139,28 @@ int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, boo
     return blob_layout(nlev, npos, next, nchunk, diag, vb).size;
 }
 
+LoTri level_ordered(const Csr &T, const std::vector<double> *diag, const Levels &lv)
+{
+    LoTri o;
+    const int32_t n = T.nrows;
+    o.a.nrows = n;
+    o.a.ncols = T.ncols;
+    o.a.ptr.assign((size_t)n + 1, 0);
+    o.a.col.reserve(T.col.size());
+    o.a.val.reserve(T.val.size());
+    if (diag) o.diag.resize((size_t)n);
+    for (int32_t p = 0; p < n; ++p) {
+        const int32_t row = lv.rows[p];
+        for (int32_t e = T.ptr[row]; e < T.ptr[(size_t)row + 1]; ++e) {
+            o.a.col.push_back(T.col[e]);
+            o.a.val.push_back(T.val[e]);
+        }
+        o.a.ptr[(size_t)p + 1] = (int32_t)o.a.col.size();
+        if (diag) o.diag[p] = (*diag)[row];
+    }
+    return o;
+}
+
 int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
 
 // Hybrid sweep schedule of the triangular operator T with level sets lv.
@@ -691,6 +713,11 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.chUT = make_chunks(c.lvUT, 64 / tri_lanes(c.UT));
     c.swUT = f32 ? make_sweep<float>(c.UT, &c.Udiag, c.lvUT) : make_sweep<double>(c.UT, &c.Udiag, c.lvUT);
 
+    c.loL1 = level_ordered(c.L1, nullptr, c.lvL1);
+    c.loL1T = level_ordered(c.L1T, nullptr, c.lvL1T);
+    c.loU = level_ordered(c.U, &c.Udiag, c.lvU);
+    c.loUT = level_ordered(c.UT, &c.Udiag, c.lvUT);
+
     // ---- S^ (Section 3.2)
     c.smode = P.smode;
     if (c.smode == RSILU_S_AUTO)
@@ -783,9 +810,12 @@ DevPlanOff place_plan(Bump &b, const SpmvPlan &pl)
 }
 
 DevTriOff place_tri(Bump &b, const Csr &a, bool diag, const Levels &lv, const Chunks &ch, const Sweep &sw,
-                    size_t n, int32_t vbytes)
+                    const LoTri &lo, size_t n, int32_t vbytes)
 {
     DevTriOff o;
+    o.lev = b.take(sizeof(int32_t) * lv.ptr.size());
+    o.lo = place_csr(b, lo.a, vbytes);
+    o.ldiag = diag ? b.take((size_t)vbytes * n) : 0;
     o.blob = b.take(sw.blob.size());
     o.a = place_csr(b, a, vbytes);
     o.diag = diag ? b.take((size_t)vbytes * n) : 0;
@@ -814,10 +844,10 @@ void plan_layout(Ctx &c)
     L.pAT = place_plan(b, c.plAT);
     L.pL2 = place_plan(b, c.plL2);
     L.pL2T = place_plan(b, c.plL2T);
-    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, n, vb);
-    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, n, vb);
-    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, n, vb);
-    L.UTf = place_tri(b, c.UT, true, c.lvUT, c.chUT, c.swUT, n, vb);
+    L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, c.loL1, n, vb);
+    L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, c.loL1T, n, vb);
+    L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, c.loU, n, vb);
+    L.UTf = place_tri(b, c.UT, true, c.lvUT, c.chUT, c.swUT, c.loUT, n, vb);
     L.perm = b.take(sizeof(int32_t) * m);
     L.colnorm = b.take(sizeof(double) * n);
     L.sfac = b.take(sizeof(double) * c.sfac.size());

@@ -34,6 +34,8 @@ EXPORTS = [
     "rsilu_get_profile",
     "rsilu_destroy", "rsilu_status_string",
     "rsilu_server_create", "rsilu_server_submit", "rsilu_server_poll", "rsilu_server_drain", "rsilu_server_destroy",
+    "rsilu_batch_tiles", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_destroy", "rsilu_tuner_create",
+    "rsilu_tune", "rsilu_tuner_size", "rsilu_tuner_destroy",
 ]
 PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S", "trsv_UT",
               "k_trsv_sweep", "k_trsv_level", "k_gather_lo"]
@@ -81,6 +83,24 @@ class rsilu_result_t(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("atr_norm", ctypes.c_double), ("atr_rel", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("wait_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+
+class rsilu_tile_t(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("spmv_lanes", ctypes.c_int32), ("tri_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.threads, self.spmv_lanes, self.tri_lanes)
+
+
+class rsilu_batch_result_t(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("atr_norm", ctypes.c_double),
+                ("atr_rel", ctypes.c_double)]
+
+
+class rsilu_tune_result_t(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("tile", rsilu_tile_t),
+                ("batched_ms_per_iter", ctypes.c_double), ("plain_ms_per_iter", ctypes.c_double)]
 
 
 class RsiluError(RuntimeError):
@@ -149,6 +169,23 @@ def lib():
         L.rsilu_server_drain.restype = ctypes.c_int
         L.rsilu_server_destroy.argtypes = [P]
         L.rsilu_server_destroy.restype = None
+        L.rsilu_batch_tiles.argtypes = [ctypes.POINTER(rsilu_tile_t), I32]
+        L.rsilu_batch_tiles.restype = I32
+        L.rsilu_batch_create.argtypes = [I32, ctypes.POINTER(P)]
+        L.rsilu_batch_create.restype = ctypes.c_int
+        L.rsilu_batch_solve.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(rsilu_tile_t),
+                                        ctypes.POINTER(rsilu_batch_result_t), P]
+        L.rsilu_batch_solve.restype = ctypes.c_int
+        L.rsilu_batch_destroy.argtypes = [P]
+        L.rsilu_batch_destroy.restype = None
+        L.rsilu_tuner_create.argtypes = [D, I32, ctypes.POINTER(P)]
+        L.rsilu_tuner_create.restype = ctypes.c_int
+        L.rsilu_tune.argtypes = [P, P, P, P, ctypes.POINTER(rsilu_tune_result_t), P]
+        L.rsilu_tune.restype = ctypes.c_int
+        L.rsilu_tuner_size.argtypes = [P]
+        L.rsilu_tuner_size.restype = I32
+        L.rsilu_tuner_destroy.argtypes = [P]
+        L.rsilu_tuner_destroy.restype = None
         _lib = L
     return _lib
 
@@ -409,6 +446,105 @@ class Server:
     def close(self):
         if self.h is not None:
             lib().rsilu_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batched persistent solves
+
+
+def rsilu_batch_tiles():
+    """The compiled tiles of the persistent kernel, as (threads, spmv_lanes, tri_lanes)."""
+    k = lib().rsilu_batch_tiles(None, 0)
+    buf = (rsilu_tile_t * k)()
+    lib().rsilu_batch_tiles(buf, k)
+    return [buf[i].as_tuple() for i in range(k)]
+
+
+def make_tile(tile):
+    if tile is None:
+        return None
+    t, s_, r = tile
+    return rsilu_tile_t(threads=t, spmv_lanes=s_, tri_lanes=r, reserved=0)
+
+
+class Batch:
+    """A batch object (include/rsilu_batch.h): solves many uploaded handles in one launch."""
+
+    def __init__(self, capacity):
+        h = ctypes.c_void_p()
+        _check(lib().rsilu_batch_create(int(capacity), ctypes.byref(h)), "rsilu_batch_create")
+        self.h = h
+        self.capacity = int(capacity)
+
+    def solve_raw(self, handles, b_devs, tols, x_devs, tile=None, stream=None):
+        """Returns (status code of the call, [result dicts])."""
+        k = len(handles)
+        hs = (ctypes.c_void_p * max(k, 1))(*[h if isinstance(h, int) else h.value for h in handles])
+        bs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in b_devs])
+        xs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in x_devs])
+        ts = (ctypes.c_double * max(k, 1))(*[float(t) for t in tols])
+        res = (rsilu_batch_result_t * max(k, 1))()
+        tl = make_tile(tile)
+        code = lib().rsilu_batch_solve(self.h, k, hs, bs, ts, xs, ctypes.byref(tl) if tl is not None else None,
+                                       res, _stream(stream))
+        out = [{f: getattr(res[i], f) for f, _ in res[i]._fields_} for i in range(k)]
+        return code, out
+
+    def solve(self, solvers, b_devs, tols, x_devs=None, tile=None, stream=None):
+        """Solve the problems of `solvers` (uploaded Solver objects); returns (xs, results)."""
+        import torch
+
+        if x_devs is None:
+            x_devs = [torch.empty(S.n, dtype=torch.float64, device=b.device) for S, b in zip(solvers, b_devs)]
+        if not isinstance(tols, (list, tuple)):
+            tols = [tols] * len(solvers)
+        code, res = self.solve_raw([S.h for S in solvers], b_devs, tols, x_devs, tile, stream)
+        _check(code, "rsilu_batch_solve")
+        return x_devs, res
+
+    def close(self):
+        if self.h is not None:
+            lib().rsilu_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tuner:
+    """The autotuner (include/rsilu_batch.h): per problem signature, the batched tile or the plain path."""
+
+    def __init__(self, slack=1.0, iters=8):
+        h = ctypes.c_void_p()
+        _check(lib().rsilu_tuner_create(float(slack), int(iters), ctypes.byref(h)), "rsilu_tuner_create")
+        self.h = h
+
+    def tune(self, solver, b_dev, x_dev=None, stream=None):
+        import torch
+
+        if x_dev is None:
+            x_dev = torch.empty(solver.n, dtype=torch.float64, device=b_dev.device)
+        r = rsilu_tune_result_t()
+        _check(lib().rsilu_tune(self.h, solver.h, _dev(b_dev), _dev(x_dev), ctypes.byref(r), _stream(stream)),
+               "rsilu_tune")
+        return {"path": r.path, "from_cache": r.from_cache, "tile": r.tile.as_tuple(),
+                "batched_ms_per_iter": r.batched_ms_per_iter, "plain_ms_per_iter": r.plain_ms_per_iter}
+
+    def size(self):
+        return lib().rsilu_tuner_size(self.h)
+
+    def close(self):
+        if self.h is not None:
+            lib().rsilu_tuner_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,240 @@
+"""Batched persistent solves (include/rsilu_batch.h) through the C ABI.
+
+* several problems in one launch follow the oracle's LSQR (lsqr_m) step for step
+  (four iterations: x to 1e-8 relative, ||A^T r|| to 1e-6) and, run to tol = 1e-8,
+  converge like it (iteration counts within 2%, the true ||A^T r|| at 2 tol, the
+  solution in the oracle's stop-test ball ||A^T A (x - x_or)|| <= 4 tol ||A^T b||);
+* every compiled tile, FP64 and FP32 preconditioners;
+* a problem's result in a mixed launch equals its result alone, bit for bit;
+* graph replays of the same batch equal the first call;
+* invalid calls are rejected;
+* the autotuner's choice is a compiled tile or the plain path, cached per signature.
+"""
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+LSQR = dict(mu=1.0, form=1, krylov=1, smode=2)  # Algorithm 2 form, LSQR, S^ none
+
+
+def to_dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def long_rows():
+    return gen.random_sparse(3000, 2500, k=4, seed=17, n_dense=3, dense_len=2400)
+
+
+PROBLEMS = {
+    "c1": lambda: gen.tiny_c1(),
+    "c2-small": lambda: gen.by_name("c2-small"),
+    "long-rows": long_rows,
+    "served-dense": lambda: gen.served_request(3000, 4500, 31, n_dense=12),
+    "served": lambda: gen.served_request(5000, 6000, 32),
+}
+
+
+def solvers(R, names, **kw):
+    probs = [PROBLEMS[n]() for n in names]
+    return probs, [R.Solver.from_problem(p, **dict(LSQR, **kw)).upload() for p in probs]
+
+
+def test_batch_four_steps_follow_oracle(gpu_lib):
+    R = gpu_lib
+    names = list(PROBLEMS)
+    probs, S = solvers(R, names, maxit=4)
+    bt = R.Batch(8)
+    xs, res = bt.solve(S, [to_dev(p.b) for p in probs], 1e-14)
+    for name, p, x, r in zip(names, probs, xs, res):
+        F = oracle.factor_problem(p, mu=1.0, smode="none")
+        o = oracle.lsqr_m(F, p.b, tol=1e-14, maxit=4)
+        got = x.cpu().numpy()
+        assert r["iters"] == o.iters == 4 and r["status"] == R.NOT_CONVERGED, name
+        assert np.linalg.norm(got - o.x) <= 1e-8 * np.linalg.norm(o.x), name
+        assert abs(r["atr_norm"] - o.atr_norm) <= 1e-6 * o.atr_norm, name
+    bt.close()
+    for s in S:
+        s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_converges_like_oracle(gpu_lib, precision):
+    R = gpu_lib
+    names = ["c1", "c2-small", "served-dense", "served"]
+    tol = 1e-8
+    probs, S = solvers(R, names, maxit=2000, precision=precision)
+    bt = R.Batch(4)
+    xs, res = bt.solve(S, [to_dev(p.b) for p in probs], tol)
+    for name, p, x, r in zip(names, probs, xs, res):
+        F = oracle.factor_problem(p, mu=1.0, smode="none")
+        o = oracle.lsqr_m(F, p.b, tol=tol, maxit=2000)
+        got = x.cpu().numpy()
+        assert r["status"] == R.OK and o.status == "ok", name
+        if precision == 0:
+            assert abs(r["iters"] - o.iters) <= max(1, int(0.02 * o.iters)), (name, r["iters"], o.iters)
+        A = p.scipy()
+        atb = np.linalg.norm(A.T @ p.b)
+        assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2 * tol * atb, name
+        assert np.linalg.norm(A.T @ (A @ (got - o.x))) <= 4 * tol * atb, name
+        print("%s precision %d: batched its %d, oracle its %d" % (name, precision, r["iters"], o.iters))
+    bt.close()
+    for s in S:
+        s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_tile(gpu_lib, precision):
+    """Each compiled tile: four steps against the oracle on problems with and without
+    long rows (FP64), or convergence to the tolerance (FP32)."""
+    R = gpu_lib
+    # FP32: problems on which the FP32 preconditioner reaches 1e-8 (long rows in FP64)
+    names = ["c1", "long-rows"] if precision == 0 else ["c1", "served-dense"]
+    maxit = 4 if precision == 0 else 2000
+    probs, S = solvers(R, names, maxit=maxit, precision=precision)
+    Fs = [oracle.factor_problem(p, mu=1.0, smode="none") for p in probs]
+    tol = 1e-14 if precision == 0 else 1e-8
+    want = [oracle.lsqr_m(F, p.b, tol=tol, maxit=maxit) for F, p in zip(Fs, probs)]
+    bt = R.Batch(2)
+    for tile in R.rsilu_batch_tiles():
+        xs, res = bt.solve(S, [to_dev(p.b) for p in probs], tol, tile=tile)
+        for name, p, x, r, o in zip(names, probs, xs, res, want):
+            got = x.cpu().numpy()
+            if precision == 0:
+                assert r["iters"] == 4, (tile, name)
+                assert np.linalg.norm(got - o.x) <= 1e-8 * np.linalg.norm(o.x), (tile, name)
+            else:
+                A = p.scipy()
+                atb = np.linalg.norm(A.T @ p.b)
+                assert r["status"] == R.OK, (tile, name)
+                assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2 * tol * atb, (tile, name)
+    bt.close()
+    for s in S:
+        s.close()
+
+
+def test_alone_equals_mixed(gpu_lib):
+    """A problem's result does not depend on the other problems of its launch."""
+    import torch
+
+    R = gpu_lib
+    sizes = [(2000, 2600, 0), (6000, 9000, 16), (3000, 5500, 0), (9000, 12000, 8), (2500, 3000, 0)]
+    probs = [gen.served_request(n, m, 40 + i, n_dense=nd) for i, (n, m, nd) in enumerate(sizes)]
+    tile = (256, 8, 1)
+    for prec in (0, 1):
+        S = [R.Solver.from_problem(p, maxit=2000, precision=prec, **LSQR).upload() for p in probs]
+        bs = [to_dev(p.b) for p in probs]
+        bt = R.Batch(len(probs))
+        xs, res = bt.solve(S, bs, 1e-8, tile=tile)
+        mixed = [x.cpu().numpy() for x in xs]
+        for i in range(len(probs)):
+            x1, r1 = bt.solve([S[i]], [bs[i]], 1e-8, tile=tile)
+            assert r1[0]["iters"] == res[i]["iters"] and r1[0]["status"] == res[i]["status"] == R.OK
+            assert np.array_equal(x1[0].cpu().numpy().view(np.int64), mixed[i].view(np.int64)), (prec, i)
+        # the same problems in another order
+        xr, rr = bt.solve(S[::-1], bs[::-1], 1e-8, tile=tile)
+        for i, x in enumerate(xr[::-1]):
+            assert np.array_equal(x.cpu().numpy().view(np.int64), mixed[i].view(np.int64))
+        torch.cuda.synchronize()
+        bt.close()
+        for s in S:
+            s.close()
+
+
+def test_graph_replays(gpu_lib):
+    """Calls of one batch object replay captured graphs (one per count and kernel);
+    eager work and other counts in between; every replay equals the first call."""
+    import torch
+
+    R = gpu_lib
+    probs, S = solvers(R, ["c1", "served", "long-rows"], maxit=2000)
+    bs = [to_dev(p.b) for p in probs]
+    bt = R.Batch(3)
+    first, r0 = bt.solve(S, bs, 1e-8)
+    first = [x.cpu().numpy() for x in first]
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        _ = (junk * 2).sum().item()
+        if rep % 2:
+            bt.solve(S[:1], bs[:1], 1e-8)
+        xs, r = bt.solve(S, bs, 1e-8)
+        torch.cuda.synchronize()
+        for a, b_, ra, rb in zip(first, xs, r0, r):
+            assert np.array_equal(a.view(np.int64), b_.cpu().numpy().view(np.int64)), rep
+            assert ra["iters"] == rb["iters"]
+    bt.close()
+    for s in S:
+        s.close()
+
+
+def test_batch_rejects_invalid(gpu_lib):
+    import torch
+
+    R = gpu_lib
+    p = PROBLEMS["c1"]()
+    good = R.Solver.from_problem(p, **LSQR).upload()
+    pcgls = R.Solver.from_problem(p, mu=1.0, smode=R.S_IDENTITY).upload()
+    ident = R.Solver.from_problem(p, mu=1.0, smode=R.S_DENSE, form=1, krylov=1).upload()
+    not_up = R.Solver.from_problem(p, **LSQR)
+    b = to_dev(p.b)
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    bt = R.Batch(2)
+    assert bt.solve_raw([pcgls.h], [b], [1e-8], [x])[0] == R.EINVAL
+    assert bt.solve_raw([ident.h], [b], [1e-8], [x])[0] == R.EINVAL
+    assert bt.solve_raw([not_up.h], [b], [1e-8], [x])[0] == R.EINVAL
+    assert bt.solve_raw([good.h, good.h], [b, b], [1e-8, 1e-8], [x, x])[0] == R.EINVAL
+    assert bt.solve_raw([good.h] * 3, [b] * 3, [1e-8] * 3, [x] * 3)[0] == R.EINVAL  # over capacity
+    assert bt.solve_raw([good.h], [b], [-1.0], [x])[0] == R.EINVAL
+    assert bt.solve_raw([good.h], [b], [float("nan")], [x])[0] == R.EINVAL
+    assert bt.solve_raw([good.h], [b], [1e-8], [b])[0] == R.EINVAL  # x aliases b
+    assert bt.solve_raw([good.h], [b], [1e-8], [x], tile=(128, 8, 1))[0] == R.EINVAL
+    assert bt.solve_raw([], [], [], [])[0] == R.OK
+    code, res = bt.solve_raw([good.h], [b], [1e-8], [x])
+    assert code == R.OK and res[0]["status"] == R.OK
+    bt.close()
+    for s in (good, pcgls, ident, not_up):
+        s.close()
+
+
+def test_tuner_choice_and_cache(gpu_lib):
+    R = gpu_lib
+    tiles = R.rsilu_batch_tiles()
+    import copy
+
+    p1 = gen.served_request(4500, 6000, 51)
+    # same pattern, other values and right-hand side: the same signature class
+    p2 = copy.copy(p1)
+    p2.val = 3.0 * p1.val
+    p2.b = np.random.default_rng(52).standard_normal(p1.m)
+    S1 = R.Solver.from_problem(p1, maxit=2000, **LSQR).upload()
+    S2 = R.Solver.from_problem(p2, maxit=2000, **LSQR).upload()
+    tu = R.Tuner(slack=2.0, iters=6)
+    r1 = tu.tune(S1, to_dev(p1.b))
+    assert r1["from_cache"] == 0 and r1["path"] in (0, 1) and r1["tile"] in tiles
+    assert r1["batched_ms_per_iter"] > 0 and r1["plain_ms_per_iter"] > 0
+    assert (r1["path"] == 0) == (r1["batched_ms_per_iter"] <= 2.0 * r1["plain_ms_per_iter"])
+    r2 = tu.tune(S2, to_dev(p2.b))
+    assert r2["from_cache"] == 1 and r2["tile"] == r1["tile"] and tu.size() == 1
+    print("tuned: tile %s, batched %.3f ms/it, plain %.3f ms/it, path %d" % (
+        r1["tile"], r1["batched_ms_per_iter"], r1["plain_ms_per_iter"], r1["path"]))
+    # the tuned tile solves both to the tolerance
+    bt = R.Batch(2)
+    xs, res = bt.solve([S1, S2], [to_dev(p1.b), to_dev(p2.b)], 1e-8, tile=r1["tile"])
+    for p, x, r in zip((p1, p2), xs, res):
+        A = p.scipy()
+        got = x.cpu().numpy()
+        assert r["status"] == R.OK
+        assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2e-8 * np.linalg.norm(A.T @ p.b)
+    # the handle's own settings are unchanged by tuning
+    x, code, it, atr, rel = S1.solve(to_dev(p1.b), tol=1e-8)
+    assert code == R.OK and it > 6
+    bt.close()
+    tu.close()
+    S1.close()
+    S2.close()

@@ -279,3 +279,25 @@ def test_full_size_grid_setup_bit_exact():
         want_ptr, want_rows = F.lev[key]
         assert np.array_equal(ptr, want_ptr) and np.array_equal(rows, want_rows)
     R.rsilu_destroy(h)
+
+
+def test_batch_api_host_checks():
+    """Argument checks of the batched-solve and autotuner entry points that need no device."""
+    L = R.lib()
+    tiles = R.rsilu_batch_tiles()
+    assert len(tiles) == 12 and len(set(tiles)) == 12
+    assert all(t in {256, 512, 1024} and s in {4, 8} and g in {1, 4} for t, s, g in tiles)
+    h = ctypes.c_void_p()
+    assert L.rsilu_batch_create(0, ctypes.byref(h)) == R.EINVAL
+    assert L.rsilu_batch_create(70000, ctypes.byref(h)) == R.EINVAL
+    assert L.rsilu_batch_create(4, None) == R.EINVAL
+    assert L.rsilu_tuner_create(0.0, 8, ctypes.byref(h)) == R.EINVAL
+    assert L.rsilu_tuner_create(float("inf"), 8, ctypes.byref(h)) == R.EINVAL
+    assert L.rsilu_tuner_create(1.0, 1, ctypes.byref(h)) == R.EINVAL
+    res = (R.rsilu_batch_result_t * 1)()
+    assert L.rsilu_batch_solve(None, 0, None, None, None, None, None, res, None) == R.EINVAL
+    tr = R.rsilu_tune_result_t()
+    assert L.rsilu_tune(None, None, None, None, ctypes.byref(tr), None) == R.EINVAL
+    assert L.rsilu_tuner_size(None) == 0
+    L.rsilu_batch_destroy(None)
+    L.rsilu_tuner_destroy(None)
