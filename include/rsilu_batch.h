@@ -81,7 +81,7 @@ rsilu_status_t rsilu_batch_create(int32_t capacity, rsilu_batch_t *out);
  *   b[i]    device pointer to the m_i right-hand-side values (user row order);
  *   tol[i]  stop when the LSQR estimate of ||A^T r|| <= tol[i] ||A^T b||;
  *   x[i]    device pointer receiving the n_i solution values (may not alias b[i]);
- *   tile    a compiled tile (rsilu_batch_tiles); NULL picks 256 threads, 8 and 1 lanes;
+ *   tile    a compiled tile (rsilu_batch_tiles); NULL picks 1024 threads, 4 and 4 lanes;
  *   res[i]  host outcome of problem i.
  * Each handle's maxit bounds its iterations. A handle's work vectors are used, so
  * a handle may not be solved elsewhere while the call runs.
@@ -118,7 +118,9 @@ rsilu_status_t rsilu_tuner_create(double slack, int32_t iters, rsilu_tuner_t *ou
  * rsilu_batch_solve), timing candidates on stream s with the right-hand side
  * b_dev (m values) and writing scratch solutions into x_dev (n values). A problem
  * whose signature was tuned before reuses that choice (from_cache = 1) without
- * running anything. Thread-safe. Errors as rsilu_batch_solve. */
+ * running anything. Calls on one tuner are serialised; h itself may not be in use
+ * elsewhere during the call (its maxit is lowered while the plain path is
+ * timed). Errors as rsilu_batch_solve. */
 rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev, double *x_dev,
                           rsilu_tune_result_t *res, hipStream_t s);
 

@@ -8,13 +8,29 @@
  * its b and x) fits in what is left of the server's HBM arena. Admission is
  * first come, first served in order of setup completion. An admitted request
  * is uploaded into the arena (allocated once, at rsilu_server_create; no
- * device allocation happens while serving), solved by rsilu_solve on its
- * slot's stream and copied back; then its bytes and its slot return to the
- * pool at once, so requests that arrived meanwhile join while the others are
- * still on the GPU. Solves on different slots overlap on the device (the
- * single-workgroup sweeps of one solve leave almost every compute unit free).
- * The per-request arithmetic is exactly that of a lone rsilu_solve call, so a
- * result does not depend on what else was in flight.
+ * device allocation happens while serving), solved on its slot's stream and
+ * copied back; then its bytes and its slot return to the pool at once, so
+ * requests that arrived meanwhile join while the others are still on the GPU.
+ *
+ * With batch_max = 0 every admitted request is solved alone by rsilu_solve.
+ * With batch_max >= 1 a free slot admits, first come first served, up to
+ * batch_max ready requests that fit in the arena together, and solves those
+ * that the batched kernel accepts (LSQR, Algorithm 2 form, S^ none) in one
+ * persistent launch per tile (rsilu_batch.h), the others by rsilu_solve. With
+ * the autotuner (tune_slack > 0) each accepted request gets its signature's
+ * tile, and goes to the batched kernel only when its measured time per
+ * iteration there is at most min(tune_slack, k) times that of the plain path,
+ * k being the number of accepted requests admitted with it (on the plain path
+ * those k would run one after another); a lone request (k = 1) takes the plain
+ * path without tuning. Under light load requests thus keep the plain path's
+ * latency, and a burst shares launches. Slots run their launches
+ * concurrently, so a launch of new arrivals overlaps the launches already on
+ * the device.
+ *
+ * A result does not depend on what else was in flight: it is bit for bit the
+ * result of a lone rsilu_solve (path 1) or of a lone rsilu_batch_solve with
+ * the reported tile (path 0). With the autotuner, a problem signature keeps the
+ * tile and times of its first tuning for the server's lifetime.
  *
  * All calls are thread-safe. No call throws.
  */
@@ -25,6 +41,7 @@
 #include <stdint.h>
 
 #include "rsilu.h"
+#include "rsilu_batch.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -36,8 +53,11 @@ typedef struct {
     int32_t device;        /* HIP device ordinal */
     int32_t slots;         /* solves on the device at once (one stream each), >= 1 */
     int32_t setup_threads; /* host threads running rsilu_factor, >= 1 */
-    int32_t reserved;
+    int32_t batch_max;     /* 0: one rsilu_solve per request; >= 1: requests per launch (<= 65535) */
     size_t hbm_bytes;      /* size of the device arena holding every admitted request */
+    double tune_slack;     /* > 0: autotuner with this slack (rsilu_tuner_create) picks each
+                              request's path and tile; 0: the batched kernel with 1024 threads,
+                              4 and 4 lanes for every request it accepts */
 } rsilu_server_opts_t;
 
 typedef struct {
@@ -64,11 +84,17 @@ typedef struct {
     double solve_ms;          /* admitted -> x copied back (upload, solve, copy) */
     double total_ms;          /* submit -> done */
     size_t device_bytes;      /* arena bytes the request held */
+    int32_t path;             /* 0: batched persistent kernel, 1: rsilu_solve, -1: not solved */
+    int32_t launch_size;      /* requests solved by the same launch (1 on path 1) */
+    rsilu_tile_t tile;        /* path 0: the tile of the launch */
 } rsilu_result_t;
 
 /* Start a server: allocates the arena (hbm_bytes) on `device`, creates one
- * stream per slot and starts the threads. EINVAL for bad options, ENOMEM if
- * the arena cannot be allocated, EHIP for other runtime errors. */
+ * stream (and, with batch_max >= 1, one batch object) per slot and the
+ * autotuner, and starts the threads. EINVAL for bad options (slots or
+ * setup_threads < 1, batch_max outside [0, 65535], tune_slack negative or not
+ * finite), ENOMEM if the arena cannot be allocated, EHIP for other runtime
+ * errors. */
 rsilu_status_t rsilu_server_create(const rsilu_server_opts_t *opts, rsilu_server_t *out);
 
 /* Queue one request. Host inputs are copied before the call returns; *id (may

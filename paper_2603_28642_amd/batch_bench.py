@@ -93,7 +93,7 @@ def main():
             A = p.scipy()
             e = c.cpu().numpy() - a.cpu().numpy()
             dev = max(dev, float(np.linalg.norm(A.T @ (A @ e)) / np.linalg.norm(A.T @ p.b)))
-        out[label] = {"tile": list(tile) if tile else [256, 8, 1], "solves_per_s": len(S) / min(times),
+        out[label] = {"tile": list(tile) if tile else [1024, 4, 4], "solves_per_s": len(S) / min(times),
                       "s_per_set": min(times), "ok": ok, "max_iters": max(r["iters"] for r in res),
                       "max_ball_vs_plain": dev}
         print("%s: %.3f s per set" % (label, min(times)), file=sys.stderr, flush=True)

@@ -469,7 +469,7 @@ const TileEntry *find_tile(const rsilu_tile_t &t)
     return nullptr;
 }
 
-constexpr rsilu_tile_t kDefaultTile = {256, 8, 1, 0};
+constexpr rsilu_tile_t kDefaultTile = {1024, 4, 4, 0};
 
 // ------------------------------------------------------------------ host side
 
@@ -815,19 +815,20 @@ rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev
     const int32_t K = std::min<int32_t>(t->iters, std::max<int32_t>(h->prm.maxit, 2));
     const double zero = 0.0;
     rsilu_batch_result_t br;
-    // candidates of the batched kernel: one untimed run, then the timed one
+    // candidates of the batched kernel: one untimed run (first touch of the
+    // problem's data), then one timed run per compiled tile
     double best = 1e300;
     rsilu_tile_t best_tile = kDefaultTile;
+    rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &kDefaultTile, &br, s, K);
+    if (rc != RSILU_OK) return rc;
     for (const TileEntry &e : tiles()) {
-        for (int rep = 0; rep < 2; ++rep) {
-            const auto t0 = std::chrono::steady_clock::now();
-            rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &e.tile, &br, s, K);
-            if (rc != RSILU_OK) return rc;
-            const double ms = elapsed_ms(t0);
-            if (rep == 1 && ms < best) {
-                best = ms;
-                best_tile = e.tile;
-            }
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &e.tile, &br, s, K);
+        if (rc != RSILU_OK) return rc;
+        const double ms = elapsed_ms(t0);
+        if (ms < best) {
+            best = ms;
+            best_tile = e.tile;
         }
     }
     // the plain path with the same iteration count

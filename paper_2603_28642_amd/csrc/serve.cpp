@@ -1,7 +1,10 @@
 // Serving runtime (rsilu_serve.h): host setup threads, first-come admission by
-// device footprint into one preallocated arena, one stream per solve slot.
+// device footprint into one preallocated arena, one stream per solve slot; a
+// slot solves the requests it admitted together in batched persistent launches
+// (rsilu_batch.h) or one by one.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -14,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rsilu.h"
+#include "rsilu_batch.h"
 #include "rsilu_serve.h"
 
 namespace {
@@ -85,7 +89,8 @@ struct rsilu_server {
     void *arena_base = nullptr;
     Arena *arena = nullptr;
     std::vector<hipStream_t> streams;
-    std::vector<int> slot_free;
+    std::vector<rsilu_batch_t> batches;  // one per slot when batch_max >= 1
+    rsilu_tuner_t tuner = nullptr;       // when tune_slack > 0
 
     std::mutex mu;
     std::condition_variable cv_setup, cv_ready, cv_done;
@@ -94,6 +99,21 @@ struct rsilu_server {
     int64_t next_id = 0, completed = 0;
     bool stopping = false;
     std::vector<std::thread> threads;
+
+    // streams, batch objects, tuner, arena
+    void release_device()
+    {
+        if (tuner) rsilu_tuner_destroy(tuner);
+        tuner = nullptr;
+        for (rsilu_batch_t b : batches) rsilu_batch_destroy(b);
+        batches.clear();
+        for (hipStream_t t : streams) (void)hipStreamDestroy(t);
+        streams.clear();
+        if (arena_base) (void)hipFree(arena_base);
+        arena_base = nullptr;
+        delete arena;
+        arena = nullptr;
+    }
 
     void finish(Job *j, int32_t status)
     {
@@ -148,15 +168,27 @@ struct rsilu_server {
         }
     }
 
+    // Whether the batched kernel accepts a request (LSQR, Algorithm 2 form, S^ none).
+    static bool batchable(const Job &j)
+    {
+        if (j.req.params.krylov != RSILU_KRYLOV_LSQR || j.req.params.form != RSILU_FORM_ALG2) return false;
+        if (j.req.m == j.req.n) return true;
+        rsilu_stats_t st;
+        return rsilu_get_stats(j.h, &st) == RSILU_OK && st.smode == RSILU_S_NONE;
+    }
+
     void slot_worker(int slot)
     {
         (void)hipSetDevice(opts.device);
         hipStream_t s = streams[(size_t)slot];
+        rsilu_batch_t bt = batches.empty() ? nullptr : batches[(size_t)slot];
+        const size_t cap = opts.batch_max > 0 ? (size_t)opts.batch_max : 1;
         for (;;) {
-            Job *j = nullptr;
+            std::vector<Job *> jobs;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                // first come, first served: only the head of the ready queue is admitted
+                // first come, first served: only the head of the ready queue is admitted,
+                // then the requests behind it while they fit (up to batch_max)
                 cv_ready.wait(lk, [&] {
                     if (ready_q.empty()) return stopping;
                     Job *head = ready_q.front();
@@ -164,32 +196,134 @@ struct rsilu_server {
                     return head->off != SIZE_MAX;
                 });
                 if (ready_q.empty()) return;
-                j = ready_q.front();
+                jobs.push_back(ready_q.front());
                 ready_q.pop_front();
+                while (jobs.size() < cap && !ready_q.empty()) {
+                    Job *nx = ready_q.front();
+                    const size_t off = arena->take(nx->bytes);
+                    if (off == SIZE_MAX) break;
+                    nx->off = off;
+                    jobs.push_back(nx);
+                    ready_q.pop_front();
+                }
             }
-            j->t_admit = Clock::now();
-            j->res.wait_ms = ms_between(j->t_setup_done, j->t_admit);
-            char *base = static_cast<char *>(arena_base) + j->off;
-            double *b_dev = reinterpret_cast<double *>(base + j->op_bytes);
-            double *x_dev = reinterpret_cast<double *>(base + j->op_bytes + round_up(sizeof(double) * (size_t)j->req.m));
-            rsilu_status_t st = rsilu_upload(j->h, base, j->op_bytes, s);
-            if (st == RSILU_OK &&
-                hipMemcpyAsync(b_dev, j->b.data(), sizeof(double) * (size_t)j->req.m, hipMemcpyHostToDevice, s) !=
-                    hipSuccess)
-                st = RSILU_EHIP;
-            if (st == RSILU_OK)
-                st = rsilu_solve(j->h, b_dev, j->req.tol, x_dev, &j->res.iters, &j->res.atr_norm, &j->res.atr_rel, s);
-            if (st >= 0 && hipMemcpyAsync(j->req.x, x_dev, sizeof(double) * (size_t)j->req.n, hipMemcpyDeviceToHost,
-                                          s) != hipSuccess)
-                st = RSILU_EHIP;
-            if (hipStreamSynchronize(s) != hipSuccess && st >= 0) st = RSILU_EHIP;
-            j->res.solve_ms = ms_between(j->t_admit, Clock::now());
+            const size_t k = jobs.size();
+            std::vector<rsilu_status_t> st(k, RSILU_OK);
+            std::vector<double *> bdev(k), xdev(k);
+            for (size_t i = 0; i < k; ++i) {
+                Job *j = jobs[i];
+                j->t_admit = Clock::now();
+                j->res.wait_ms = ms_between(j->t_setup_done, j->t_admit);
+                char *base = static_cast<char *>(arena_base) + j->off;
+                bdev[i] = reinterpret_cast<double *>(base + j->op_bytes);
+                xdev[i] = reinterpret_cast<double *>(base + j->op_bytes + round_up(sizeof(double) * (size_t)j->req.m));
+                st[i] = rsilu_upload(j->h, base, j->op_bytes, s);
+                if (st[i] == RSILU_OK && hipMemcpyAsync(bdev[i], j->b.data(), sizeof(double) * (size_t)j->req.m,
+                                                        hipMemcpyHostToDevice, s) != hipSuccess)
+                    st[i] = RSILU_EHIP;
+            }
+            // path and tile of every request; batched ones grouped by tile
+            // With the autotuner a request takes the batched kernel when its time per
+            // iteration there is at most min(tune_slack, kb) times the plain path's,
+            // kb being the batchable requests of this admission: on the plain path
+            // they would run one after another on this slot's stream.
+            // A lone request (kb = 1) would need a batched time at most equal to the plain
+            // one, which the tuned classes rarely show: it takes the plain path untuned.
+            std::vector<int32_t> can(k, 0);
+            std::vector<rsilu_tune_result_t> tr(k);
+            size_t kb = 0;
+            for (size_t i = 0; i < k; ++i) {
+                if (st[i] != RSILU_OK || !bt || !batchable(*jobs[i])) continue;
+                can[i] = 1;
+                ++kb;
+            }
+            for (size_t i = 0; i < k; ++i) {
+                if (can[i] != 1 || !tuner) continue;
+                if (kb < 2 || rsilu_tune(tuner, jobs[i]->h, bdev[i], xdev[i], &tr[i], s) != RSILU_OK) can[i] = 2;
+            }
+            const double slack = std::min(opts.tune_slack, (double)kb);
+            std::vector<std::vector<size_t>> groups;
+            std::vector<rsilu_tile_t> group_tile;
+            std::vector<size_t> plain;
+            for (size_t i = 0; i < k; ++i) {
+                if (st[i] != RSILU_OK) continue;
+                Job *j = jobs[i];
+                int32_t path = 1;
+                rsilu_tile_t tile = {1024, 4, 4, 0};
+                if (can[i] == 1) {
+                    path = 0;
+                    if (tuner) {
+                        tile = tr[i].tile;
+                        if (!(tr[i].batched_ms_per_iter <= slack * tr[i].plain_ms_per_iter)) path = 1;
+                    }
+                }
+                j->res.path = path;
+                j->res.launch_size = 1;
+                if (path == 1) {
+                    plain.push_back(i);
+                    continue;
+                }
+                j->res.tile = tile;
+                size_t g = 0;
+                while (g < groups.size() && !(group_tile[g].threads == tile.threads &&
+                                              group_tile[g].spmv_lanes == tile.spmv_lanes &&
+                                              group_tile[g].tri_lanes == tile.tri_lanes))
+                    ++g;
+                if (g == groups.size()) {
+                    groups.emplace_back();
+                    group_tile.push_back(tile);
+                }
+                groups[g].push_back(i);
+            }
+            for (size_t g = 0; g < groups.size(); ++g) {
+                const size_t kg = groups[g].size();
+                std::vector<rsilu_handle_t> hs(kg);
+                std::vector<const double *> bb(kg);
+                std::vector<double *> xx(kg);
+                std::vector<double> tt(kg);
+                std::vector<rsilu_batch_result_t> rr(kg);
+                for (size_t q = 0; q < kg; ++q) {
+                    const size_t i = groups[g][q];
+                    hs[q] = jobs[i]->h;
+                    bb[q] = bdev[i];
+                    xx[q] = xdev[i];
+                    tt[q] = jobs[i]->req.tol;
+                }
+                const rsilu_status_t rc = rsilu_batch_solve(bt, (int32_t)kg, hs.data(), bb.data(), tt.data(),
+                                                            xx.data(), &group_tile[g], rr.data(), s);
+                for (size_t q = 0; q < kg; ++q) {
+                    Job *j = jobs[groups[g][q]];
+                    j->res.launch_size = (int32_t)kg;
+                    if (rc != RSILU_OK) {
+                        st[groups[g][q]] = rc;
+                        continue;
+                    }
+                    st[groups[g][q]] = (rsilu_status_t)rr[q].status;
+                    j->res.iters = rr[q].iters;
+                    j->res.atr_norm = rr[q].atr_norm;
+                    j->res.atr_rel = rr[q].atr_rel;
+                }
+            }
+            for (size_t i : plain) {
+                Job *j = jobs[i];
+                st[i] = rsilu_solve(j->h, bdev[i], j->req.tol, xdev[i], &j->res.iters, &j->res.atr_norm,
+                                    &j->res.atr_rel, s);
+            }
+            for (size_t i = 0; i < k; ++i)
+                if (st[i] >= 0 && hipMemcpyAsync(jobs[i]->req.x, xdev[i], sizeof(double) * (size_t)jobs[i]->req.n,
+                                                 hipMemcpyDeviceToHost, s) != hipSuccess)
+                    st[i] = RSILU_EHIP;
+            const bool sync_ok = hipStreamSynchronize(s) == hipSuccess;
+            const Clock::time_point t_end = Clock::now();
             {
                 std::lock_guard<std::mutex> lk(mu);
-                arena->give(j->off, j->bytes);
+                for (Job *j : jobs) arena->give(j->off, j->bytes);
             }
             cv_ready.notify_all();
-            finish(j, st);
+            for (size_t i = 0; i < k; ++i) {
+                jobs[i]->res.solve_ms = ms_between(jobs[i]->t_admit, t_end);
+                finish(jobs[i], (!sync_ok && st[i] >= 0) ? RSILU_EHIP : st[i]);
+            }
         }
     }
 };
@@ -198,7 +332,9 @@ extern "C" {
 
 rsilu_status_t rsilu_server_create(const rsilu_server_opts_t *opts, rsilu_server_t *out)
 {
-    if (!opts || !out || opts->slots < 1 || opts->setup_threads < 1 || opts->hbm_bytes < kAlign) return RSILU_EINVAL;
+    if (!opts || !out || opts->slots < 1 || opts->setup_threads < 1 || opts->hbm_bytes < kAlign ||
+        opts->batch_max < 0 || opts->batch_max > 65535 || !std::isfinite(opts->tune_slack) || opts->tune_slack < 0.0)
+        return RSILU_EINVAL;
     *out = nullptr;
     rsilu_server *s = nullptr;
     try {
@@ -220,13 +356,23 @@ rsilu_status_t rsilu_server_create(const rsilu_server_opts_t *opts, rsilu_server
     for (int i = 0; i < opts->slots; ++i) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
-            (void)hipFree(s->arena_base);
-            delete s->arena;
+            s->release_device();
             delete s;
             return RSILU_EHIP;
         }
         s->streams.push_back(st);
+    }
+    rsilu_status_t rc = RSILU_OK;
+    for (int i = 0; i < opts->slots && opts->batch_max > 0 && rc == RSILU_OK; ++i) {
+        rsilu_batch_t bt = nullptr;
+        rc = rsilu_batch_create(opts->batch_max, &bt);
+        if (rc == RSILU_OK) s->batches.push_back(bt);
+    }
+    if (rc == RSILU_OK && opts->batch_max > 0 && opts->tune_slack > 0.0) rc = rsilu_tuner_create(opts->tune_slack, 4, &s->tuner);
+    if (rc != RSILU_OK) {
+        s->release_device();
+        delete s;
+        return rc;
     }
     for (int i = 0; i < opts->setup_threads; ++i) s->threads.emplace_back([s] { s->setup_worker(); });
     for (int i = 0; i < opts->slots; ++i) s->threads.emplace_back([s, i] { s->slot_worker(i); });
@@ -252,6 +398,7 @@ rsilu_status_t rsilu_server_submit(rsilu_server_t s, const rsilu_request_t *req,
         return RSILU_ENOMEM;
     }
     j->t_submit = Clock::now();
+    j->res.path = -1;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) {
@@ -299,9 +446,7 @@ void rsilu_server_destroy(rsilu_server_t s)
     s->cv_setup.notify_all();
     s->cv_ready.notify_all();
     for (std::thread &t : s->threads) t.join();
-    for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
-    (void)hipFree(s->arena_base);
-    delete s->arena;
+    s->release_device();
     delete s;
 }
 

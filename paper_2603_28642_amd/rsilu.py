@@ -66,9 +66,17 @@ class rsilu_profile_t(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 12), ("ms", ctypes.c_double * 12), ("bytes", ctypes.c_double * 12)]
 
 
+class rsilu_tile_t(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("spmv_lanes", ctypes.c_int32), ("tri_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.threads, self.spmv_lanes, self.tri_lanes)
+
+
 class rsilu_server_opts_t(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("setup_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("hbm_bytes", ctypes.c_size_t)]
+                ("batch_max", ctypes.c_int32), ("hbm_bytes", ctypes.c_size_t), ("tune_slack", ctypes.c_double)]
 
 
 class rsilu_request_t(ctypes.Structure):
@@ -82,15 +90,8 @@ class rsilu_result_t(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("user", ctypes.c_void_p), ("status", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("atr_norm", ctypes.c_double), ("atr_rel", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("wait_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
-
-
-class rsilu_tile_t(ctypes.Structure):
-    _fields_ = [("threads", ctypes.c_int32), ("spmv_lanes", ctypes.c_int32), ("tri_lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
-
-    def as_tuple(self):
-        return (self.threads, self.spmv_lanes, self.tri_lanes)
+                ("total_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t), ("path", ctypes.c_int32),
+                ("launch_size", ctypes.c_int32), ("tile", rsilu_tile_t)]
 
 
 class rsilu_batch_result_t(ctypes.Structure):
@@ -407,9 +408,9 @@ class Server:
     Host inputs are copied at submit; each request's x buffer is kept alive here until
     its result has been polled."""
 
-    def __init__(self, hbm_bytes, slots=4, setup_threads=4, device=0):
-        opts = rsilu_server_opts_t(device=device, slots=slots, setup_threads=setup_threads, reserved=0,
-                                   hbm_bytes=int(hbm_bytes))
+    def __init__(self, hbm_bytes, slots=4, setup_threads=4, device=0, batch_max=0, tune_slack=0.0):
+        opts = rsilu_server_opts_t(device=device, slots=slots, setup_threads=setup_threads, batch_max=int(batch_max),
+                                   hbm_bytes=int(hbm_bytes), tune_slack=float(tune_slack))
         h = ctypes.c_void_p()
         _check(lib().rsilu_server_create(ctypes.byref(opts), ctypes.byref(h)), "rsilu_server_create")
         self.h = h
@@ -436,7 +437,8 @@ class Server:
         out = []
         for i in range(k):
             r = buf[i]
-            d = {f: getattr(r, f) for f, _ in r._fields_ if f != "user"}
+            d = {f: getattr(r, f) for f, _ in r._fields_ if f not in ("user", "tile")}
+            d["tile"] = r.tile.as_tuple()
             out.append((d, self.pending.pop(r.id)))
         return out
 

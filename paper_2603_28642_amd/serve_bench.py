@@ -5,7 +5,9 @@ with dense rows) arrive as a Poisson process and go through the serving runtime
 (include/rsilu_serve.h): host setup threads, admission by device footprint into one
 HBM arena, concurrent solves on per-slot streams. The plain path handles the same
 requests one at a time (setup, upload, solve). Prints one JSON line with solves/s and
-p50/p99 latency of both, and how many served results equal the plain ones bit for bit.
+p50/p99 latency of both, how many served results equal the plain ones bit for bit, and
+the largest ||A^T A (x_served - x_plain)|| / ||A^T b|| (batched launches sum in another
+order than the plain path).
 
 Usage: python -m paper_2603_28642_amd.serve_bench [--requests 128] [--slots 8] ...
 """
@@ -33,6 +35,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--batch-max", type=int, default=32, help="requests per batched launch (0: rsilu_solve each)")
+    ap.add_argument("--tune-slack", type=float, default=8.0, help="autotuner slack (0: default tile, no tuning)")
     args = ap.parse_args()
     # one hardware queue per solve slot (the runtime's default is 4)
     os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(max(args.slots, 4), 32)))
@@ -44,7 +48,7 @@ def main():
     from paper_2603_28642_amd import rsilu as R
 
     prec = {"fp32": R.PREC_FP32, "fp64": R.PREC_FP64}[args.precision]
-    params = dict(mu=1.0, form=R.FORM_ALG2, smode=R.S_NONE, precision=prec)
+    params = dict(mu=1.0, form=R.FORM_ALG2, smode=R.S_NONE, krylov=R.KRYLOV_LSQR, precision=prec)
     sizes = gen.served_stream(args.requests, seed=args.seed, n_lo=args.n_lo, n_hi=args.n_hi)
     probs = [gen.served_request(n, m, s, n_dense=nd) for n, m, s, nd in sizes]
     print("generated %d requests" % len(probs), file=sys.stderr, flush=True)
@@ -70,7 +74,8 @@ def main():
     rate = args.load * capacity
     rng = np.random.default_rng(args.seed + 1)
     gaps = rng.exponential(1.0 / rate, size=len(probs))
-    srv = R.Server(hbm_bytes=int(args.hbm_gb * (1 << 30)), slots=args.slots, setup_threads=args.setup_threads)
+    srv = R.Server(hbm_bytes=int(args.hbm_gb * (1 << 30)), slots=args.slots, setup_threads=args.setup_threads,
+                   batch_max=args.batch_max, tune_slack=args.tune_slack)
     results = {}
     ids = {}
     t_start = time.perf_counter()
@@ -94,6 +99,9 @@ def main():
     lat = np.array([results[i][0]["total_ms"] for i in range(len(probs))])
     ok = sum(1 for i in range(len(probs)) if results[i][0]["status"] == R.OK)
     same = sum(1 for i in range(len(probs)) if np.array_equal(results[i][1].view(np.int64), plain_x[i].view(np.int64)))
+    # batched results differ from the plain ones in the order of sums only: both in the stop-test ball
+    ball = max(float(np.linalg.norm(probs[i].scipy().T @ (probs[i].scipy() @ (results[i][1] - plain_x[i]))) /
+                     np.linalg.norm(probs[i].scipy().T @ probs[i].b)) for i in range(len(probs)))
     solve_ms = np.array([results[i][0]["solve_ms"] for i in range(len(probs))])
     setup_ms = np.array([results[i][0]["setup_ms"] for i in range(len(probs))])
     wait_ms = np.array([results[i][0]["wait_ms"] for i in range(len(probs))])
@@ -103,6 +111,11 @@ def main():
         "n_range": [args.n_lo, args.n_hi],
         "precision": args.precision,
         "slots": args.slots,
+        "batch_max": args.batch_max,
+        "tune_slack": args.tune_slack,
+        "paths": {"batched": sum(1 for i in range(len(probs)) if results[i][0]["path"] == 0),
+                  "plain": sum(1 for i in range(len(probs)) if results[i][0]["path"] == 1)},
+        "median_launch_size": float(np.median([results[i][0]["launch_size"] for i in range(len(probs))])),
         "setup_threads": args.setup_threads,
         "offered_rate_per_s": rate,
         "served": {"solves_per_s": len(probs) / served_total, "p50_ms": float(np.percentile(lat, 50)),
@@ -113,6 +126,7 @@ def main():
                   "p99_ms": 1e3 * float(np.percentile(plain_lat, 99)),
                   "median_setup_ms": 1e3 * float(np.median(plain_setup))},
         "identical_to_plain": same,
+        "max_ball_vs_plain": ball,
     }
     print(json.dumps(out), flush=True)
 
