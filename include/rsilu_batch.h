@@ -124,6 +124,24 @@ rsilu_status_t rsilu_tuner_create(double slack, int32_t iters, rsilu_tuner_t *ou
 rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev, double *x_dev,
                           rsilu_tune_result_t *res, hipStream_t s);
 
+/* Solve `count` problems with the autotuner's schedule, on stream s, and wait.
+ * Every problem the batched kernel accepts is tuned (rsilu_tune, cached per
+ * signature); the accepted problems start on one batched launch, which lasts as
+ * long as its slowest problem, and the plain path (rsilu_solve, one problem after
+ * another on a second stream of the batch object, beside the launch) takes the
+ * rest. The slowest batched problem moves to the plain path while that shortens
+ * the estimated makespan max(slowest batched time, sum of plain times), per
+ * iteration (equal iteration counts assumed). The launch uses the tuned tile of
+ * its slowest problem (*tile_used, may be NULL). Problems the batched kernel does
+ * not accept go to the plain path. path[i] receives 0 (batched) or 1 (plain),
+ * res[i] the outcome (status as rsilu_solve). Arguments and errors as
+ * rsilu_batch_solve (handles need not be configured for the batched kernel);
+ * a plain solve's runtime error is returned after all problems ran. */
+rsilu_status_t rsilu_batch_solve_auto(rsilu_batch_t bt, rsilu_tuner_t t, int32_t count, const rsilu_handle_t *hs,
+                                      const double *const *b, const double *tol, double *const *x,
+                                      rsilu_batch_result_t *res, int32_t *path, rsilu_tile_t *tile_used,
+                                      hipStream_t s);
+
 /* Number of cached signatures. */
 int32_t rsilu_tuner_size(rsilu_tuner_t t);
 

@@ -6,9 +6,10 @@ uploaded (outside every timed region):
   * mixed: K problems of the served-stream recipe, n log-uniform in [n_lo, n_hi],
     m = n U(1.1, 2.0), a tenth with 8-32 dense rows.
 Each set is solved to ||A^T r|| <= tol ||A^T b|| (LSQR, Algorithm 2 form without the
-M_b correction) three ways: one rsilu_solve after another (the plain multi-kernel
-path), one rsilu_batch_solve launch with the default tile, and one launch with the
-tile the autotuner picked for the set's first problem. Prints one JSON line with
+M_b correction) four ways: one rsilu_solve after another (the plain multi-kernel
+path), one rsilu_batch_solve launch with the default tile, one launch with the tile
+the autotuner picked for the set's first problem, and rsilu_batch_solve_auto (every
+signature tuned, the slowest problems moved to the plain path beside the launch). Prints one JSON line with
 solves/s of each, the tuner's choice and the largest deviation of a batched solution
 from its plain one, relative to the stop-test ball ||A^T A e|| / ||A^T b||.
 
@@ -97,6 +98,25 @@ def main():
                       "s_per_set": min(times), "ok": ok, "max_iters": max(r["iters"] for r in res),
                       "max_ball_vs_plain": dev}
         print("%s: %.3f s per set" % (label, min(times)), file=sys.stderr, flush=True)
+    # the autotuner's split: one batched launch beside the plain path
+    tu2 = R.Tuner(slack=1.0, iters=4)
+    xs, res, paths, tile = bt.solve_auto(tu2, S, bs, args.tol, x_devs=xb)  # tunes every signature once
+    times = []
+    for _ in range(args.reps):
+        t1 = time.perf_counter()
+        xs, res, paths, tile = bt.solve_auto(tu2, S, bs, args.tol, x_devs=xb)
+        times.append(time.perf_counter() - t1)
+    dev = 0.0
+    for p, a, c in zip(probs, xp, xb):
+        A = p.scipy()
+        e = c.cpu().numpy() - a.cpu().numpy()
+        dev = max(dev, float(np.linalg.norm(A.T @ (A @ e)) / np.linalg.norm(A.T @ p.b)))
+    out["auto"] = {"tile": list(tile), "solves_per_s": len(S) / min(times), "s_per_set": min(times),
+                   "ok": sum(r["status"] == R.OK for r in res), "batched": int(sum(1 for q in paths if q == 0)),
+                   "plain": int(sum(1 for q in paths if q == 1)), "signatures": tu2.size(), "max_ball_vs_plain": dev}
+    print("auto: %.3f s per set (%d batched, %d plain)" % (min(times), out["auto"]["batched"], out["auto"]["plain"]),
+          file=sys.stderr, flush=True)
+    tu2.close()
     line = {
         "metric": "independent least-squares solves/s, one launch (batched persistent) vs one solve at a time",
         "set": args.set, "k": len(S), "precision": args.precision, "tol": args.tol,

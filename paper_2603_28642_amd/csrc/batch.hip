@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -64,6 +65,16 @@ struct BDesc {
 
 // ------------------------------------------------------------------ device code
 
+// Every pointer of a descriptor addresses device memory; viewing it in the
+// global address space makes its accesses global instructions (flat ones would
+// also count against the LDS counter and serialise with LDS traffic).
+#define RSILU_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RSILU_GLOBAL T *gm(T *p)
+{
+    return (RSILU_GLOBAL T *)p;
+}
+
 template <int G, class T>
 __device__ __forceinline__ T lane_sum(T v)
 {
@@ -95,10 +106,15 @@ __device__ __forceinline__ double wg_sum(double v, double *red)
 // The caller separates it from the producers of x and the readers of y with
 // workgroup barriers.
 template <int NT, int G>
-__device__ void wg_spmv(const BOp &a, const double *x, double *y, double *red)
+__device__ __forceinline__ void wg_spmv(const BOp &a, const double *xp, double *yp, double *red)
 {
     constexpr int RPP = NT / G;
     constexpr int U = 2;
+    const auto ptr = gm(a.ptr);
+    const auto col = gm(a.col);
+    const auto val = gm(a.val);
+    const auto x = gm(xp);
+    const auto y = gm(yp);
     const int gl = threadIdx.x % G, slot = threadIdx.x / G;
     for (int base = 0; base < a.nrows; base += U * RPP) {
         int rb[U], re[U];
@@ -110,8 +126,8 @@ __device__ void wg_spmv(const BOp &a, const double *x, double *y, double *red)
             re[u] = 0;
             own[u] = false;
             if (row < a.nrows) {
-                rb[u] = a.ptr[row];
-                re[u] = a.ptr[row + 1];
+                rb[u] = ptr[row];
+                re[u] = ptr[row + 1];
                 if (re[u] - rb[u] > a.long_thresh)
                     re[u] = rb[u];
                 else
@@ -122,7 +138,7 @@ __device__ void wg_spmv(const BOp &a, const double *x, double *y, double *red)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             s[u] = 0.0;
-            for (int k = rb[u] + gl; k < re[u]; k += G) s[u] += a.val[k] * x[a.col[k]];
+            for (int k = rb[u] + gl; k < re[u]; k += G) s[u] += val[k] * x[col[k]];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -130,11 +146,12 @@ __device__ void wg_spmv(const BOp &a, const double *x, double *y, double *red)
             if (own[u] && gl == 0) y[base + u * RPP + slot] = s[u];
         }
     }
+    const auto longr = gm(a.long_rows);
     for (int i = 0; i < a.nlong; ++i) {
-        const int row = a.long_rows[i];
-        const int b = a.ptr[row], e = a.ptr[row + 1];
+        const int row = longr[i];
+        const int b = ptr[row], e = ptr[row + 1];
         double s = 0.0;
-        for (int k = b + (int)threadIdx.x; k < e; k += NT) s += a.val[k] * x[a.col[k]];
+        for (int k = b + (int)threadIdx.x; k < e; k += NT) s += val[k] * x[col[k]];
         s = wg_sum<NT>(s, red);
         if (threadIdx.x == 0) y[row] = s;
     }
@@ -145,14 +162,19 @@ __device__ void wg_spmv(const BOp &a, const double *x, double *y, double *red)
 // (position, entry range, the first E entries of each lane, right-hand side
 // and diagonal) is loaded while the current level is solved, so a level waits
 // only for the x values of its entries. Every x store of a level precedes the
-// barrier that ends it.
-template <class T, int NT, int G>
-__device__ void wg_trsv(const BTri &t, const T *rhs, T *x)
+// barrier that ends it. rhs and x are global-memory views or LDS arrays.
+template <class T, int NT, int G, class RP, class XP>
+__device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
 {
     constexpr int RPP = NT / G;
     constexpr int E = G >= 4 ? 1 : 4 / G;
-    const T *lval = static_cast<const T *>(t.lval);
-    const T *ldiag = static_cast<const T *>(t.ldiag);
+    const auto lev = gm(t.lev);
+    const auto rows = gm(t.rows);
+    const auto lptr = gm(t.lptr);
+    const auto lcol = gm(t.lcol);
+    const auto lval = gm(static_cast<const T *>(t.lval));
+    const auto ldiag = gm(static_cast<const T *>(t.ldiag));
+    const bool has_diag = t.ldiag != nullptr;
     const int gl = threadIdx.x % G, slot = threadIdx.x / G;
     struct Pf {
         int row, k0, k1;
@@ -174,42 +196,42 @@ __device__ void wg_trsv(const BTri &t, const T *rhs, T *x)
             f.v[i] = T(0);
         }
         if (p < end) {
-            f.row = t.rows[p];
-            f.k0 = t.lptr[p];
-            f.k1 = t.lptr[p + 1];
+            f.row = rows[p];
+            f.k0 = lptr[p];
+            f.k1 = lptr[p + 1];
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const int k = f.k0 + gl + i * G;
                 if (k < f.k1) {
-                    f.c[i] = t.lcol[k];
+                    f.c[i] = lcol[k];
                     f.v[i] = lval[k];
                 }
             }
             f.r = rhs[f.row];
-            if (ldiag) f.d = ldiag[p];
+            if (has_diag) f.d = ldiag[p];
         }
         return f;
     };
     __syncthreads();  // rhs complete
     const int nlev = t.nlev;
     if (nlev == 0) return;
-    int end = t.lev[1];
+    int end = lev[1];
     Pf cur = fetch(0, end);
     for (int l = 0; l < nlev; ++l) {
-        const int beg = t.lev[l];
-        const int nend = l + 2 <= nlev ? t.lev[l + 2] : end;
+        const int beg = lev[l];
+        const int nend = l + 2 <= nlev ? lev[l + 2] : end;
         T s = T(0);
         if (cur.row >= 0) {
 #pragma unroll
             for (int i = 0; i < E; ++i)
                 if (cur.c[i] >= 0) s += cur.v[i] * x[cur.c[i]];
-            for (int k = cur.k0 + gl + E * G; k < cur.k1; k += G) s += lval[k] * x[t.lcol[k]];
+            for (int k = cur.k0 + gl + E * G; k < cur.k1; k += G) s += lval[k] * x[lcol[k]];
         }
         const Pf nxt = fetch(end, l + 1 < nlev ? nend : end);
         s = lane_sum<G>(s);
         if (cur.row >= 0 && gl == 0) {
             T r = cur.r - s;
-            if (ldiag) r = r / cur.d;
+            if (has_diag) r = r / cur.d;
             x[cur.row] = r;
         }
         // further rows of a level wider than one pass
@@ -218,14 +240,14 @@ __device__ void wg_trsv(const BTri &t, const T *rhs, T *x)
             T s2 = T(0);
             int row = -1;
             if (p < end) {
-                row = t.rows[p];
-                const int k1 = t.lptr[p + 1];
-                for (int k = t.lptr[p] + gl; k < k1; k += G) s2 += lval[k] * x[t.lcol[k]];
+                row = rows[p];
+                const int k1 = lptr[p + 1];
+                for (int k = lptr[p] + gl; k < k1; k += G) s2 += lval[k] * x[lcol[k]];
             }
             s2 = lane_sum<G>(s2);
             if (row >= 0 && gl == 0) {
                 T r = rhs[row] - s2;
-                if (ldiag) r = r / ldiag[p];
+                if (has_diag) r = r / ldiag[p];
                 x[row] = r;
             }
         }
@@ -237,47 +259,78 @@ __device__ void wg_trsv(const BTri &t, const T *rhs, T *x)
 
 // h = M^{-1} z with M^{-1} = (L1 U)^{-1} (L1 U)^{-T} (Algorithm 2, k = n, no M_b
 // correction): U^T t0 = z, L1^T t1 = t0, L1 t2 = t1, U h = t2. In FP32 the input
-// is rounded to FP32 first and h converted back.
-template <class T, int NT, int G>
-__device__ void wg_precond(const BDesc &d)
+// is rounded to FP32 first and h converted back. With XL the four solution
+// vectors live in LDS (two arrays of n values, used alternately; xl holds 2n
+// values), so a level reads its inputs from LDS instead of through the caches.
+template <class T, int NT, int G, bool XL>
+__device__ __forceinline__ void wg_precond_in(const BDesc &d, T *xl)
 {
     const int n = d.n;
-    T *t0 = static_cast<T *>(d.pt0), *t1 = static_cast<T *>(d.pt1), *t2 = static_cast<T *>(d.pt2);
-    const T *in;
-    T *out;
+    const auto z = gm(d.z);
+    const auto h = gm(d.h);
     if constexpr (std::is_same<T, float>::value) {
-        float *fi = static_cast<float *>(d.pin);
-        for (int i = threadIdx.x; i < n; i += NT) fi[i] = (float)d.z[i];
-        in = fi;
-        out = static_cast<float *>(d.pout);
-    } else {
-        in = d.z;
-        out = d.h;
+        const auto fi = gm(static_cast<float *>(d.pin));
+        for (int i = threadIdx.x; i < n; i += NT) fi[i] = (float)z[i];
     }
-    wg_trsv<T, NT, G>(d.tri[0], in, t0);
-    wg_trsv<T, NT, G>(d.tri[1], t0, t1);
-    wg_trsv<T, NT, G>(d.tri[2], t1, t2);
-    wg_trsv<T, NT, G>(d.tri[3], t2, out);
-    __syncthreads();
-    if constexpr (std::is_same<T, float>::value)
-        for (int i = threadIdx.x; i < n; i += NT) d.h[i] = (double)out[i];
+    const auto in = gm(std::is_same<T, float>::value ? static_cast<const T *>(d.pin)
+                                                     : reinterpret_cast<const T *>(d.z));
+    if constexpr (XL) {
+        T *xa = xl, *xb = xl + n;
+        wg_trsv<T, NT, G>(d.tri[0], in, xa);
+        wg_trsv<T, NT, G>(d.tri[1], xa, xb);
+        wg_trsv<T, NT, G>(d.tri[2], xb, xa);
+        wg_trsv<T, NT, G>(d.tri[3], xa, xb);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += NT) h[i] = (double)xb[i];
+        __syncthreads();
+    } else {
+        const auto t0 = gm(static_cast<T *>(d.pt0));
+        const auto t1 = gm(static_cast<T *>(d.pt1));
+        const auto t2 = gm(static_cast<T *>(d.pt2));
+        const auto out = gm(std::is_same<T, float>::value ? static_cast<T *>(d.pout) : reinterpret_cast<T *>(d.h));
+        wg_trsv<T, NT, G>(d.tri[0], in, t0);
+        wg_trsv<T, NT, G>(d.tri[1], t0, t1);
+        wg_trsv<T, NT, G>(d.tri[2], t1, t2);
+        wg_trsv<T, NT, G>(d.tri[3], t2, out);
+        __syncthreads();
+        if constexpr (std::is_same<T, float>::value)
+            for (int i = threadIdx.x; i < n; i += NT) h[i] = (double)out[i];
+    }
+}
+
+// The preconditioner of one problem: its solution vectors in LDS when 2 n values
+// fit in the launch's dynamic LDS (xl_bytes), else in global memory.
+template <class T, int NT, int G>
+__device__ __forceinline__ void wg_precond(const BDesc &d, T *xl, uint32_t xl_bytes)
+{
+    if (2 * (uint64_t)d.n * sizeof(T) <= xl_bytes)
+        wg_precond_in<T, NT, G, true>(d, xl);
+    else
+        wg_precond_in<T, NT, G, false>(d, xl);
 }
 
 // The whole LSQR solve of problem blockIdx.x (M-inner-product form): init,
 // iterations until the stop test or maxit, then x = D x_hat and the true
 // ||A^T (b - A x)||. Every scalar is computed identically by every thread.
 template <class T, int NT, int GS, int GT>
-__global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ descs)
+__global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ descs, uint32_t xl_bytes)
 {
     __shared__ double red[NT / 64];
+    extern __shared__ __attribute__((aligned(16))) unsigned char xl_lds[];  // xl_bytes: 2 n values of T
+    T *xl = reinterpret_cast<T *>(xl_lds);
     const BDesc &d = descs[blockIdx.x];
     const int tid = threadIdx.x, m = d.m, n = d.n;
-    double *r = d.r, *q = d.q, *z = d.z, *h = d.h, *xh = d.xh, *v = d.v, *Mv = d.Mv, *w = d.w;
+    const auto r = gm(d.r), q = gm(d.q), z = gm(d.z), h = gm(d.h), xh = gm(d.xh), v = gm(d.v), Mv = gm(d.Mv),
+               w = gm(d.w);
+    const auto bb = gm(d.b);
+    const auto perm = gm(d.perm);
+    const auto colnorm = gm(d.colnorm);
+    const auto xo = gm(d.x);
 
     // u = P b / beta1 (u kept in r), x_hat = 0
     double sq = 0.0;
     for (int i = tid; i < m; i += NT) {
-        const double bi = d.b[d.perm[i]];
+        const double bi = bb[perm[i]];
         r[i] = bi;
         sq += bi * bi;
     }
@@ -295,11 +348,11 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
     if (!done) {
         for (int i = tid; i < m; i += NT) r[i] = r[i] / lb;
         __syncthreads();
-        wg_spmv<NT, GS>(d.AT, r, z, red);
+        wg_spmv<NT, GS>(d.AT, d.r, d.z, red);
         __syncthreads();
         sq = 0.0;
         for (int i = tid; i < n; i += NT) {
-            const double c = d.colnorm[i] * z[i];
+            const double c = colnorm[i] * z[i];
             sq += c * c;
         }
         snorm = sqrt(wg_sum<NT>(sq, red));
@@ -313,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
     }
     // h = M^{-1} s, alpha = sqrt(s . h), v = h / alpha, M v = s / alpha, w = v
     if (!done) {
-        wg_precond<T, NT, GT>(d);
+        wg_precond<T, NT, GT>(d, xl, xl_bytes);
         sq = 0.0;
         for (int i = tid; i < n; i += NT) sq += z[i] * h[i];
         const double tot = wg_sum<NT>(sq, red);
@@ -340,7 +393,7 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
     while (!done) {
         // t = A_hat v - alpha u, beta = ||t||, u = t / beta (t kept in q)
         __syncthreads();
-        wg_spmv<NT, GS>(d.A, v, q, red);
+        wg_spmv<NT, GS>(d.A, d.v, d.q, red);
         __syncthreads();
         sq = 0.0;
         for (int i = tid; i < m; i += NT) {
@@ -356,18 +409,18 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
         for (int i = tid; i < m; i += NT) r[i] = lb > 0.0 ? q[i] / lb : q[i];
         // s = A_hat^T u - beta M v with ||D^{-1} s||
         __syncthreads();
-        wg_spmv<NT, GS>(d.AT, r, z, red);
+        wg_spmv<NT, GS>(d.AT, d.r, d.z, red);
         __syncthreads();
         sq = 0.0;
         for (int i = tid; i < n; i += NT) {
             const double si = z[i] - lb * Mv[i];
             z[i] = si;
-            const double c = d.colnorm[i] * si;
+            const double c = colnorm[i] * si;
             sq += c * c;
         }
         snorm = sqrt(wg_sum<NT>(sq, red));
         // h = M^{-1} s, alpha = sqrt(s . h)
-        wg_precond<T, NT, GT>(d);
+        wg_precond<T, NT, GT>(d, xl, xl_bytes);
         sq = 0.0;
         for (int i = tid; i < n; i += NT) sq += z[i] * h[i];
         const double tot = wg_sum<NT>(sq, red);
@@ -415,16 +468,16 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
 
     // x = D x_hat; true ||A^T (b - A x)|| = ||D^{-1} A_hat^T (P b - A_hat x_hat)||
     __syncthreads();
-    for (int i = tid; i < n; i += NT) d.x[i] = xh[i] / d.colnorm[i];
-    wg_spmv<NT, GS>(d.A, xh, q, red);
+    for (int i = tid; i < n; i += NT) xo[i] = xh[i] / colnorm[i];
+    wg_spmv<NT, GS>(d.A, d.xh, d.q, red);
     __syncthreads();
-    for (int i = tid; i < m; i += NT) r[i] = d.b[d.perm[i]] - q[i];
+    for (int i = tid; i < m; i += NT) r[i] = bb[perm[i]] - q[i];
     __syncthreads();
-    wg_spmv<NT, GS>(d.AT, r, z, red);
+    wg_spmv<NT, GS>(d.AT, d.r, d.z, red);
     __syncthreads();
     sq = 0.0;
     for (int i = tid; i < n; i += NT) {
-        const double c = d.colnorm[i] * z[i];
+        const double c = colnorm[i] * z[i];
         sq += c * c;
     }
     const double atr = sqrt(wg_sum<NT>(sq, red));
@@ -438,17 +491,24 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
 
 // ------------------------------------------------------------------ compiled tiles
 
+// Kernels of one tile: [precision FP64 / FP32].
 struct TileEntry {
     rsilu_tile_t tile;
-    const void *f64, *f32;
+    const void *fn[2];
 };
 
 template <int NT, int GS, int GT>
 TileEntry tile_entry()
 {
-    return TileEntry{{NT, GS, GT, 0}, reinterpret_cast<const void *>(&k_batch_lsqr<double, NT, GS, GT>),
-                     reinterpret_cast<const void *>(&k_batch_lsqr<float, NT, GS, GT>)};
+    TileEntry e{{NT, GS, GT, 0}, {}};
+    e.fn[0] = reinterpret_cast<const void *>(&k_batch_lsqr<double, NT, GS, GT>);
+    e.fn[1] = reinterpret_cast<const void *>(&k_batch_lsqr<float, NT, GS, GT>);
+    return e;
 }
+
+// Dynamic LDS of a launch for the triangular-solve vectors: 2 n values of its
+// largest problem that fits in this bound; problems above it use global memory.
+constexpr size_t kXlBytes = 64 * 1024;
 
 const std::vector<TileEntry> &tiles()
 {
@@ -569,7 +629,8 @@ struct rsilu_batch {
     BDesc *h_desc = nullptr;  // pinned
     BOut *h_out = nullptr;    // pinned
     hipStream_t cap_stream = nullptr;
-    std::map<std::pair<int32_t, const void *>, hipGraphExec_t> graphs;  // (count, kernel)
+    hipStream_t aux_stream = nullptr;  // plain-path solves of rsilu_batch_solve_auto
+    std::map<std::tuple<int32_t, const void *, size_t>, hipGraphExec_t> graphs;  // (count, kernel, LDS)
     std::mutex mu;  // one launch at a time per batch object
 };
 
@@ -582,25 +643,28 @@ namespace {
     } while (0)
 
 // Descriptor upload, kernel, outcome download: enqueued directly, or captured
-// once per (count, kernel) and replayed.
-rsilu_status_t run_batch(rsilu_batch &bt, int32_t count, const void *fn, int32_t threads, bool use_graph, hipStream_t s)
+// once per (count, kernel, dynamic LDS) and replayed.
+rsilu_status_t run_batch(rsilu_batch &bt, int32_t count, const void *fn, int32_t threads, size_t shmem,
+                         bool use_graph, hipStream_t s, const std::function<void()> &during)
 {
     const size_t db = sizeof(BDesc) * (size_t)count, ob = sizeof(BOut) * (size_t)count;
     auto enqueue = [&](hipStream_t st) -> hipError_t {
         hipError_t e = hipMemcpyAsync(bt.d_desc, bt.h_desc, db, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return e;
         BDesc *arg = bt.d_desc;
-        void *args[] = {&arg};
-        e = hipLaunchKernel(fn, dim3((unsigned)count), dim3((unsigned)threads), args, 0, st);
+        uint32_t xlb = (uint32_t)shmem;
+        void *args[] = {&arg, &xlb};
+        e = hipLaunchKernel(fn, dim3((unsigned)count), dim3((unsigned)threads), args, shmem, st);
         if (e != hipSuccess) return e;
         return hipMemcpyAsync(bt.h_out, bt.d_out, ob, hipMemcpyDeviceToHost, st);
     };
     if (!use_graph) {
         RSILU_HIPB(enqueue(s));
+        if (during) during();
         RSILU_HIPB(hipStreamSynchronize(s));
         return RSILU_OK;
     }
-    const auto key = std::make_pair(count, fn);
+    const auto key = std::make_tuple(count, fn, shmem);
     auto it = bt.graphs.find(key);
     if (it == bt.graphs.end()) {
         if (!bt.cap_stream) RSILU_HIPB(hipStreamCreateWithFlags(&bt.cap_stream, hipStreamNonBlocking));
@@ -619,14 +683,16 @@ rsilu_status_t run_batch(rsilu_batch &bt, int32_t count, const void *fn, int32_t
         it = bt.graphs.emplace(key, x).first;
     }
     RSILU_HIPB(hipGraphLaunch(it->second, s));
+    if (during) during();
     RSILU_HIPB(hipStreamSynchronize(s));
     return RSILU_OK;
 }
 
-// Batched solve with an optional maxit override (>= 0) used by the autotuner.
+// Batched solve with an optional maxit override (>= 0) used by the autotuner;
+// `during` runs on the host while the first launch is on the device.
 rsilu_status_t batch_solve(rsilu_batch &bt, int32_t count, const rsilu_handle_t *hs, const double *const *b,
                            const double *tol, double *const *x, const rsilu_tile_t *tile, rsilu_batch_result_t *res,
-                           hipStream_t s, int32_t maxit_override)
+                           hipStream_t s, int32_t maxit_override, std::function<void()> during = nullptr)
 {
     if (count < 0 || count > bt.cap) return RSILU_EINVAL;
     if (count == 0) return RSILU_OK;
@@ -659,12 +725,18 @@ rsilu_status_t batch_solve(rsilu_batch &bt, int32_t count, const rsilu_handle_t 
         for (int32_t i : order)
             if (fp32(*hs[i]) == fp) idx.push_back(i);
         const int32_t k = (int32_t)idx.size();
+        const size_t vb = fp ? sizeof(float) : sizeof(double);
+        size_t xl = 0;
         for (int32_t j = 0; j < k; ++j) {
             const Ctx &c = *hs[idx[j]];
             const int32_t mi = maxit_override >= 0 ? maxit_override : c.prm.maxit;
             bt.h_desc[j] = make_desc(c, b[idx[j]], x[idx[j]], tol[idx[j]], mi, bt.d_out + j);
+            const size_t need = 2 * (size_t)c.n * vb;
+            if (need <= kXlBytes) xl = std::max(xl, need);
         }
-        const rsilu_status_t rc = run_batch(bt, k, fp ? te->f32 : te->f64, te->tile.threads, maxit_override < 0, s);
+        const rsilu_status_t rc =
+            run_batch(bt, k, te->fn[fp ? 1 : 0], te->tile.threads, xl, maxit_override < 0, s, during);
+        during = nullptr;
         if (rc != RSILU_OK) return rc;
         for (int32_t j = 0; j < k; ++j) {
             const BOut &o = bt.h_out[j];
@@ -770,6 +842,7 @@ void rsilu_batch_destroy(rsilu_batch_t bt)
     if (!bt) return;
     for (auto &kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
     if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+    if (bt->aux_stream) (void)hipStreamDestroy(bt->aux_stream);
     if (bt->d_desc) (void)hipFree(bt->d_desc);
     if (bt->d_out) (void)hipFree(bt->d_out);
     if (bt->h_desc) (void)hipHostFree(bt->h_desc);
@@ -854,6 +927,97 @@ rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev
     t->cache.emplace(key, r);
     *res = r;
     return RSILU_OK;
+}
+
+rsilu_status_t rsilu_batch_solve_auto(rsilu_batch_t bt, rsilu_tuner_t t, int32_t count, const rsilu_handle_t *hs,
+                                      const double *const *b, const double *tol, double *const *x,
+                                      rsilu_batch_result_t *res, int32_t *path, rsilu_tile_t *tile_used,
+                                      hipStream_t s)
+{
+    if (!bt || !t || count < 0 || count > bt->cap) return RSILU_EINVAL;
+    if (count == 0) return RSILU_OK;
+    if (!hs || !b || !tol || !x || !res || !path) return RSILU_EINVAL;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!hs[i] || !b[i] || !x[i] || static_cast<const void *>(b[i]) == static_cast<const void *>(x[i]) ||
+            !hs[i]->dev)
+            return RSILU_EINVAL;
+        if (!(tol[i] >= 0.0) || !std::isfinite(tol[i])) return RSILU_EINVAL;
+        for (int32_t j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return RSILU_EINVAL;
+    }
+    try {
+        // times per iteration of every accepted problem (cached per signature)
+        std::vector<rsilu_tune_result_t> tr((size_t)count);
+        std::vector<int32_t> acc;
+        for (int32_t i = 0; i < count; ++i) {
+            path[i] = 1;
+            if (check_handle(*hs[i]) != RSILU_OK) continue;
+            const rsilu_status_t rc = rsilu_tune(t, hs[i], b[i], x[i], &tr[(size_t)i], s);
+            if (rc != RSILU_OK) return rc;
+            acc.push_back(i);
+        }
+        // All accepted problems start on the batched launch, which lasts as long as
+        // its slowest problem; the plain path runs its problems one after another
+        // beside it. Move the slowest batched problem to the plain path while that
+        // shortens max(slowest batched, sum of plain) (equal iteration counts assumed).
+        std::stable_sort(acc.begin(), acc.end(), [&](int32_t a, int32_t c) {
+            return tr[(size_t)a].batched_ms_per_iter > tr[(size_t)c].batched_ms_per_iter;
+        });
+        double sum_p = 0.0;
+        size_t top = 0;
+        while (top < acc.size()) {
+            const rsilu_tune_result_t &r = tr[(size_t)acc[top]];
+            const double now = std::max(r.batched_ms_per_iter, sum_p);
+            const double next_b = top + 1 < acc.size() ? tr[(size_t)acc[top + 1]].batched_ms_per_iter : 0.0;
+            if (std::max(next_b, sum_p + r.plain_ms_per_iter) >= now) break;
+            sum_p += r.plain_ms_per_iter;
+            ++top;
+        }
+        std::vector<int32_t> plain;
+        for (int32_t i = 0; i < count; ++i)
+            if (check_handle(*hs[i]) != RSILU_OK) plain.push_back(i);
+        for (size_t q = 0; q < top; ++q) plain.push_back(acc[q]);
+        std::vector<int32_t> batched(acc.begin() + (ptrdiff_t)top, acc.end());
+        // one tile for the launch: the tuned tile of its slowest problem
+        rsilu_tile_t tile = batched.empty() ? kDefaultTile : tr[(size_t)batched.front()].tile;
+        if (tile_used) *tile_used = tile;
+        rsilu_status_t plain_rc = RSILU_OK;
+        auto run_plain = [&](hipStream_t ps) {
+            for (int32_t i : plain) {
+                rsilu_batch_result_t &r = res[i];
+                const rsilu_status_t rc = rsilu_solve(hs[i], b[i], tol[i], x[i], &r.iters, &r.atr_norm, &r.atr_rel, ps);
+                r.status = rc;
+                if (rc < 0) plain_rc = rc;
+            }
+        };
+        if (batched.empty()) {
+            run_plain(s);
+            return plain_rc;
+        }
+        if (!plain.empty() && !bt->aux_stream &&
+            hipStreamCreateWithFlags(&bt->aux_stream, hipStreamNonBlocking) != hipSuccess)
+            return RSILU_EHIP;
+        std::vector<rsilu_handle_t> bh;
+        std::vector<const double *> bb;
+        std::vector<double> bt_tol;
+        std::vector<double *> bx;
+        for (int32_t i : batched) {
+            path[i] = 0;
+            bh.push_back(hs[i]);
+            bb.push_back(b[i]);
+            bt_tol.push_back(tol[i]);
+            bx.push_back(x[i]);
+        }
+        std::vector<rsilu_batch_result_t> br(batched.size());
+        const rsilu_status_t rc =
+            batch_solve(*bt, (int32_t)batched.size(), bh.data(), bb.data(), bt_tol.data(), bx.data(), &tile, br.data(),
+                        s, -1, plain.empty() ? std::function<void()>() : std::function<void()>([&] { run_plain(bt->aux_stream); }));
+        if (rc != RSILU_OK) return rc;
+        for (size_t q = 0; q < batched.size(); ++q) res[batched[q]] = br[q];
+        return plain_rc;
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
 }
 
 int32_t rsilu_tuner_size(rsilu_tuner_t t)

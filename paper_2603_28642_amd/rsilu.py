@@ -34,7 +34,8 @@ EXPORTS = [
     "rsilu_get_profile",
     "rsilu_destroy", "rsilu_status_string",
     "rsilu_server_create", "rsilu_server_submit", "rsilu_server_poll", "rsilu_server_drain", "rsilu_server_destroy",
-    "rsilu_batch_tiles", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_destroy", "rsilu_tuner_create",
+    "rsilu_batch_tiles", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_solve_auto", "rsilu_batch_destroy",
+    "rsilu_tuner_create",
     "rsilu_tune", "rsilu_tuner_size", "rsilu_tuner_destroy",
 ]
 PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S", "trsv_UT",
@@ -177,6 +178,9 @@ def lib():
         L.rsilu_batch_solve.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(rsilu_tile_t),
                                         ctypes.POINTER(rsilu_batch_result_t), P]
         L.rsilu_batch_solve.restype = ctypes.c_int
+        L.rsilu_batch_solve_auto.argtypes = [P, P, I32, P, P, P, P, ctypes.POINTER(rsilu_batch_result_t),
+                                             ctypes.POINTER(I32), ctypes.POINTER(rsilu_tile_t), P]
+        L.rsilu_batch_solve_auto.restype = ctypes.c_int
         L.rsilu_batch_destroy.argtypes = [P]
         L.rsilu_batch_destroy.restype = None
         L.rsilu_tuner_create.argtypes = [D, I32, ctypes.POINTER(P)]
@@ -509,6 +513,28 @@ class Batch:
         code, res = self.solve_raw([S.h for S in solvers], b_devs, tols, x_devs, tile, stream)
         _check(code, "rsilu_batch_solve")
         return x_devs, res
+
+    def solve_auto(self, tuner, solvers, b_devs, tols, x_devs=None, stream=None):
+        """The autotuner's split between one batched launch and the plain path
+        (rsilu_batch_solve_auto); returns (xs, results, paths, tile)."""
+        import torch
+
+        k = len(solvers)
+        if x_devs is None:
+            x_devs = [torch.empty(S.n, dtype=torch.float64, device=b.device) for S, b in zip(solvers, b_devs)]
+        if not isinstance(tols, (list, tuple)):
+            tols = [tols] * k
+        hs = (ctypes.c_void_p * max(k, 1))(*[S.h.value for S in solvers])
+        bs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in b_devs])
+        xs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in x_devs])
+        ts = (ctypes.c_double * max(k, 1))(*[float(t) for t in tols])
+        res = (rsilu_batch_result_t * max(k, 1))()
+        paths = (ctypes.c_int32 * max(k, 1))()
+        tile = rsilu_tile_t()
+        _check(lib().rsilu_batch_solve_auto(self.h, tuner.h, k, hs, bs, ts, xs, res, paths, ctypes.byref(tile),
+                                            _stream(stream)), "rsilu_batch_solve_auto")
+        out = [{f: getattr(res[i], f) for f, _ in res[i]._fields_} for i in range(k)]
+        return x_devs, out, [paths[i] for i in range(k)], tile.as_tuple()
 
     def close(self):
         if self.h is not None:

@@ -238,3 +238,41 @@ def test_tuner_choice_and_cache(gpu_lib):
     tu.close()
     S1.close()
     S2.close()
+
+
+def test_solve_auto_split(gpu_lib):
+    """rsilu_batch_solve_auto: every problem reaches the tolerance on the path it was
+    given; a handle the batched kernel does not take runs on the plain path; batched
+    results equal a lone launch with the reported tile and plain ones a lone
+    rsilu_solve, bit for bit."""
+    R = gpu_lib
+    probs = [gen.served_request(n, m, 60 + i, n_dense=nd)
+             for i, (n, m, nd) in enumerate([(2000, 2600, 0), (3000, 4000, 8), (40000, 60000, 0), (2500, 3000, 0)])]
+    probs.append(PROBLEMS["c1"]())
+    S = [R.Solver.from_problem(p, maxit=2000, **LSQR).upload() for p in probs[:-1]]
+    # Algorithm 1 (PCGLS) with the Algorithm 2 form: converges, but only the plain path takes it
+    S.append(R.Solver.from_problem(probs[-1], mu=1.0, smode=R.S_NONE, form=1, krylov=0, maxit=2000).upload())
+    bs = [to_dev(p.b) for p in probs]
+    bt = R.Batch(8)
+    tu = R.Tuner(slack=1.0, iters=4)
+    xs, res, paths, tile = bt.solve_auto(tu, S, bs, 1e-8)
+    assert paths[-1] == 1 and set(paths) <= {0, 1} and tile in R.rsilu_batch_tiles()
+    print("paths", paths, "tile", tile)
+    one = R.Batch(1)
+    for i, (p, x, r) in enumerate(zip(probs, xs, res)):
+        got = x.cpu().numpy()
+        assert r["status"] == R.OK, (i, r)
+        A = p.scipy()
+        assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2e-8 * np.linalg.norm(A.T @ p.b), i
+        if paths[i] == 0:
+            x1, r1 = one.solve([S[i]], [bs[i]], 1e-8, tile=tile)
+            lone, it = x1[0].cpu().numpy(), r1[0]["iters"]
+        else:
+            xl, code, it, atr, rel = S[i].solve(bs[i], tol=1e-8)
+            lone = xl.cpu().numpy()
+        assert it == r["iters"] and np.array_equal(lone.view(np.int64), got.view(np.int64)), i
+    one.close()
+    bt.close()
+    tu.close()
+    for s in S:
+        s.close()
