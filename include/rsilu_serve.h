@@ -14,23 +14,22 @@
  *
  * With batch_max = 0 every admitted request is solved alone by rsilu_solve.
  * With batch_max >= 1 a free slot admits, first come first served, up to
- * batch_max ready requests that fit in the arena together, and solves those
- * that the batched kernel accepts (LSQR, Algorithm 2 form, S^ none) in one
- * persistent launch per tile (rsilu_batch.h), the others by rsilu_solve. With
- * the autotuner (tune_slack > 0) each accepted request gets its signature's
- * tile, and goes to the batched kernel only when its measured time per
- * iteration there is at most min(tune_slack, k) times that of the plain path,
- * k being the number of accepted requests admitted with it (on the plain path
- * those k would run one after another); a lone request (k = 1) takes the plain
- * path without tuning. Under light load requests thus keep the plain path's
- * latency, and a burst shares launches. Slots run their launches
- * concurrently, so a launch of new arrivals overlaps the launches already on
- * the device.
+ * batch_max ready requests that fit in the arena together. Without the
+ * autotuner (tune_slack = 0) those the batched kernel accepts (LSQR,
+ * Algorithm 2 form, S^ none) share one persistent launch with 1024 threads, 4
+ * and 4 lanes (rsilu_batch.h), the others take rsilu_solve. With the autotuner
+ * (tune_slack > 0) an admission holding at least two accepted requests is
+ * scheduled by rsilu_batch_solve_auto (one batched launch, the slowest requests
+ * on the plain path beside it), and a lone request takes the plain path
+ * untuned, so under light load requests keep the plain path's latency and a
+ * burst shares launches. Slots run their launches concurrently, so a launch of
+ * new arrivals overlaps the launches already on the device.
  *
  * A result does not depend on what else was in flight: it is bit for bit the
  * result of a lone rsilu_solve (path 1) or of a lone rsilu_batch_solve with
  * the reported tile (path 0). With the autotuner, a problem signature keeps the
- * tile and times of its first tuning for the server's lifetime.
+ * tile and times of its first tuning for the server's lifetime (tune_slack only
+ * enables it: the split needs no slack).
  *
  * All calls are thread-safe. No call throws.
  */
@@ -55,9 +54,9 @@ typedef struct {
     int32_t setup_threads; /* host threads running rsilu_factor, >= 1 */
     int32_t batch_max;     /* 0: one rsilu_solve per request; >= 1: requests per launch (<= 65535) */
     size_t hbm_bytes;      /* size of the device arena holding every admitted request */
-    double tune_slack;     /* > 0: autotuner with this slack (rsilu_tuner_create) picks each
-                              request's path and tile; 0: the batched kernel with 1024 threads,
-                              4 and 4 lanes for every request it accepts */
+    double tune_slack;     /* > 0: schedule admissions with the autotuner (rsilu_tuner_create
+                              with this slack); 0: the batched kernel with 1024 threads, 4 and
+                              4 lanes for every request it accepts */
 } rsilu_server_opts_t;
 
 typedef struct {

@@ -508,7 +508,9 @@ TileEntry tile_entry()
 
 // Dynamic LDS of a launch for the triangular-solve vectors: 2 n values of its
 // largest problem that fits in this bound; problems above it use global memory.
-constexpr size_t kXlBytes = 64 * 1024;
+// A 1024-thread workgroup has its compute unit to itself and takes most of the
+// 160 KiB; smaller workgroups keep 64 KiB so that several share a compute unit.
+constexpr size_t xl_bound(int32_t threads) { return threads >= 1024 ? 144 * 1024 : 64 * 1024; }
 
 const std::vector<TileEntry> &tiles()
 {
@@ -732,7 +734,7 @@ rsilu_status_t batch_solve(rsilu_batch &bt, int32_t count, const rsilu_handle_t 
             const int32_t mi = maxit_override >= 0 ? maxit_override : c.prm.maxit;
             bt.h_desc[j] = make_desc(c, b[idx[j]], x[idx[j]], tol[idx[j]], mi, bt.d_out + j);
             const size_t need = 2 * (size_t)c.n * vb;
-            if (need <= kXlBytes) xl = std::max(xl, need);
+            if (need <= xl_bound(te->tile.threads)) xl = std::max(xl, need);
         }
         const rsilu_status_t rc =
             run_batch(bt, k, te->fn[fp ? 1 : 0], te->tile.threads, xl, maxit_override < 0, s, during);

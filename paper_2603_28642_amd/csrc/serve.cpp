@@ -223,86 +223,88 @@ struct rsilu_server {
                     st[i] = RSILU_EHIP;
             }
             // path and tile of every request; batched ones grouped by tile
-            // With the autotuner a request takes the batched kernel when its time per
-            // iteration there is at most min(tune_slack, kb) times the plain path's,
-            // kb being the batchable requests of this admission: on the plain path
-            // they would run one after another on this slot's stream.
-            // A lone request (kb = 1) would need a batched time at most equal to the plain
-            // one, which the tuned classes rarely show: it takes the plain path untuned.
-            std::vector<int32_t> can(k, 0);
-            std::vector<rsilu_tune_result_t> tr(k);
-            size_t kb = 0;
-            for (size_t i = 0; i < k; ++i) {
-                if (st[i] != RSILU_OK || !bt || !batchable(*jobs[i])) continue;
-                can[i] = 1;
-                ++kb;
-            }
-            for (size_t i = 0; i < k; ++i) {
-                if (can[i] != 1 || !tuner) continue;
-                if (kb < 2 || rsilu_tune(tuner, jobs[i]->h, bdev[i], xdev[i], &tr[i], s) != RSILU_OK) can[i] = 2;
-            }
-            const double slack = std::min(opts.tune_slack, (double)kb);
-            std::vector<std::vector<size_t>> groups;
-            std::vector<rsilu_tile_t> group_tile;
-            std::vector<size_t> plain;
+            // Paths: with the autotuner and at least two requests the batched kernel
+            // accepts, rsilu_batch_solve_auto splits the admission between one batched
+            // launch and the plain path beside it; without the tuner every accepted
+            // request shares one launch with the default tile; a lone request, and
+            // every request the batched kernel does not accept, takes rsilu_solve.
+            std::vector<size_t> ok_idx, acc_idx;
             for (size_t i = 0; i < k; ++i) {
                 if (st[i] != RSILU_OK) continue;
-                Job *j = jobs[i];
-                int32_t path = 1;
-                rsilu_tile_t tile = {1024, 4, 4, 0};
-                if (can[i] == 1) {
-                    path = 0;
-                    if (tuner) {
-                        tile = tr[i].tile;
-                        if (!(tr[i].batched_ms_per_iter <= slack * tr[i].plain_ms_per_iter)) path = 1;
-                    }
-                }
-                j->res.path = path;
-                j->res.launch_size = 1;
-                if (path == 1) {
-                    plain.push_back(i);
-                    continue;
-                }
-                j->res.tile = tile;
-                size_t g = 0;
-                while (g < groups.size() && !(group_tile[g].threads == tile.threads &&
-                                              group_tile[g].spmv_lanes == tile.spmv_lanes &&
-                                              group_tile[g].tri_lanes == tile.tri_lanes))
-                    ++g;
-                if (g == groups.size()) {
-                    groups.emplace_back();
-                    group_tile.push_back(tile);
-                }
-                groups[g].push_back(i);
+                ok_idx.push_back(i);
+                jobs[i]->res.path = 1;
+                jobs[i]->res.launch_size = 1;
+                if (bt && batchable(*jobs[i])) acc_idx.push_back(i);
             }
-            for (size_t g = 0; g < groups.size(); ++g) {
-                const size_t kg = groups[g].size();
-                std::vector<rsilu_handle_t> hs(kg);
-                std::vector<const double *> bb(kg);
-                std::vector<double *> xx(kg);
-                std::vector<double> tt(kg);
-                std::vector<rsilu_batch_result_t> rr(kg);
-                for (size_t q = 0; q < kg; ++q) {
-                    const size_t i = groups[g][q];
-                    hs[q] = jobs[i]->h;
-                    bb[q] = bdev[i];
-                    xx[q] = xdev[i];
-                    tt[q] = jobs[i]->req.tol;
+            std::vector<size_t> plain;
+            auto gather = [&](const std::vector<size_t> &ids, std::vector<rsilu_handle_t> &hs,
+                              std::vector<const double *> &bb, std::vector<double> &tt, std::vector<double *> &xx) {
+                for (size_t i : ids) {
+                    hs.push_back(jobs[i]->h);
+                    bb.push_back(bdev[i]);
+                    tt.push_back(jobs[i]->req.tol);
+                    xx.push_back(xdev[i]);
                 }
-                const rsilu_status_t rc = rsilu_batch_solve(bt, (int32_t)kg, hs.data(), bb.data(), tt.data(),
-                                                            xx.data(), &group_tile[g], rr.data(), s);
-                for (size_t q = 0; q < kg; ++q) {
-                    Job *j = jobs[groups[g][q]];
-                    j->res.launch_size = (int32_t)kg;
-                    if (rc != RSILU_OK) {
-                        st[groups[g][q]] = rc;
+            };
+            if (tuner && acc_idx.size() >= 2) {
+                std::vector<rsilu_handle_t> hs;
+                std::vector<const double *> bb;
+                std::vector<double> tt;
+                std::vector<double *> xx;
+                gather(ok_idx, hs, bb, tt, xx);
+                std::vector<rsilu_batch_result_t> rr(ok_idx.size());
+                for (rsilu_batch_result_t &r : rr) r.status = RSILU_EINTERNAL;  // overwritten by every problem that ran
+                std::vector<int32_t> path(ok_idx.size(), 1);
+                rsilu_tile_t tile{};
+                const rsilu_status_t rc = rsilu_batch_solve_auto(bt, tuner, (int32_t)ok_idx.size(), hs.data(), bb.data(),
+                                                                 tt.data(), xx.data(), rr.data(), path.data(), &tile, s);
+                int32_t nb = 0;
+                for (int32_t p : path) nb += p == 0;
+                for (size_t q = 0; q < ok_idx.size(); ++q) {
+                    Job *j = jobs[ok_idx[q]];
+                    if (rr[q].status == RSILU_EINTERNAL && rc < 0) {
+                        st[ok_idx[q]] = rc;
                         continue;
                     }
-                    st[groups[g][q]] = (rsilu_status_t)rr[q].status;
+                    st[ok_idx[q]] = (rsilu_status_t)rr[q].status;
+                    j->res.iters = rr[q].iters;
+                    j->res.atr_norm = rr[q].atr_norm;
+                    j->res.atr_rel = rr[q].atr_rel;
+                    j->res.path = path[q];
+                    if (path[q] == 0) {
+                        j->res.launch_size = nb;
+                        j->res.tile = tile;
+                    }
+                }
+            } else if (!tuner && !acc_idx.empty()) {
+                std::vector<rsilu_handle_t> hs;
+                std::vector<const double *> bb;
+                std::vector<double> tt;
+                std::vector<double *> xx;
+                gather(acc_idx, hs, bb, tt, xx);
+                std::vector<rsilu_batch_result_t> rr(acc_idx.size());
+                const rsilu_tile_t tile = {1024, 4, 4, 0};
+                const rsilu_status_t rc =
+                    rsilu_batch_solve(bt, (int32_t)acc_idx.size(), hs.data(), bb.data(), tt.data(), xx.data(), &tile,
+                                      rr.data(), s);
+                for (size_t q = 0; q < acc_idx.size(); ++q) {
+                    Job *j = jobs[acc_idx[q]];
+                    j->res.path = 0;
+                    j->res.launch_size = (int32_t)acc_idx.size();
+                    j->res.tile = tile;
+                    if (rc != RSILU_OK) {
+                        st[acc_idx[q]] = rc;
+                        continue;
+                    }
+                    st[acc_idx[q]] = (rsilu_status_t)rr[q].status;
                     j->res.iters = rr[q].iters;
                     j->res.atr_norm = rr[q].atr_norm;
                     j->res.atr_rel = rr[q].atr_rel;
                 }
+                for (size_t i : ok_idx)
+                    if (jobs[i]->res.path == 1) plain.push_back(i);
+            } else {
+                plain = ok_idx;
             }
             for (size_t i : plain) {
                 Job *j = jobs[i];
