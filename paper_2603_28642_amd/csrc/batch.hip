@@ -39,6 +39,7 @@ struct BOp {
 struct BTri {
     const int32_t *lev, *rows, *lptr, *lcol;
     const void *lval, *ldiag;
+    const void *lrec;  // LevelRec<T> per position
     int32_t nlev, pad;
 };
 
@@ -158,29 +159,35 @@ __device__ __forceinline__ void wg_spmv(const BOp &a, const double *xp, double *
 }
 
 // T x = rhs by one workgroup, level by level with one barrier per level; G
-// lanes per row. The static data of a thread's first row of the next level
-// (position, entry range, the first E entries of each lane, right-hand side
-// and diagonal) is loaded while the current level is solved, so a level waits
-// only for the x values of its entries. Every x store of a level precedes the
-// barrier that ends it. rhs and x are global-memory views or LDS arrays.
+// lanes per row (G <= kRecEntries). A row's first kRecEntries entries, its
+// position data and diagonal come from its LevelRec, loaded (independent loads,
+// one round trip) while the previous level is solved; the two levels in flight
+// alternate between two register sets, so nothing waits for those loads before
+// the barrier. A level then waits only for its right-hand-side and x values.
+// Entries past the record are read from the level-ordered CSR. The per-lane
+// summation order is that of a plain strided loop over the row. rhs and x are
+// global-memory views or LDS arrays; every x store of a level precedes the
+// barrier that ends it.
 template <class T, int NT, int G, class RP, class XP>
 __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
 {
+    static_assert(G <= kRecEntries && kRecEntries % G == 0, "a lane's record entries");
     constexpr int RPP = NT / G;
-    constexpr int E = G >= 4 ? 1 : 4 / G;
+    constexpr int E = kRecEntries / G;
     const auto lev = gm(t.lev);
     const auto rows = gm(t.rows);
     const auto lptr = gm(t.lptr);
     const auto lcol = gm(t.lcol);
     const auto lval = gm(static_cast<const T *>(t.lval));
     const auto ldiag = gm(static_cast<const T *>(t.ldiag));
+    const auto rec = gm(static_cast<const LevelRec<T> *>(t.lrec));
     const bool has_diag = t.ldiag != nullptr;
     const int gl = threadIdx.x % G, slot = threadIdx.x / G;
     struct Pf {
         int row, k0, k1;
         int c[E];
         T v[E];
-        T r, d;
+        T d;
     };
     auto fetch = [&](int beg, int end) {
         Pf f;
@@ -188,7 +195,6 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
         f.row = -1;
         f.k0 = 0;
         f.k1 = 0;
-        f.r = T(0);
         f.d = T(1);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -196,41 +202,31 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
             f.v[i] = T(0);
         }
         if (p < end) {
-            f.row = rows[p];
-            f.k0 = lptr[p];
-            f.k1 = lptr[p + 1];
+            const auto &r = rec[p];
+            f.row = r.row;
+            f.k0 = r.k0;
+            f.k1 = r.k1;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                const int k = f.k0 + gl + i * G;
-                if (k < f.k1) {
-                    f.c[i] = lcol[k];
-                    f.v[i] = lval[k];
-                }
+                f.c[i] = r.col[gl + i * G];
+                f.v[i] = r.val[gl + i * G];
             }
-            f.r = rhs[f.row];
-            if (has_diag) f.d = ldiag[p];
+            f.d = r.diag;
         }
         return f;
     };
-    __syncthreads();  // rhs complete
-    const int nlev = t.nlev;
-    if (nlev == 0) return;
-    int end = lev[1];
-    Pf cur = fetch(0, end);
-    for (int l = 0; l < nlev; ++l) {
-        const int beg = lev[l];
-        const int nend = l + 2 <= nlev ? lev[l + 2] : end;
-        T s = T(0);
+    auto solve = [&](const Pf &cur, int beg, int end) {
+        T s = T(0), rv = T(0);
         if (cur.row >= 0) {
+            rv = rhs[cur.row];
 #pragma unroll
             for (int i = 0; i < E; ++i)
                 if (cur.c[i] >= 0) s += cur.v[i] * x[cur.c[i]];
-            for (int k = cur.k0 + gl + E * G; k < cur.k1; k += G) s += lval[k] * x[lcol[k]];
+            for (int k = cur.k0 + kRecEntries + gl; k < cur.k1; k += G) s += lval[k] * x[lcol[k]];
         }
-        const Pf nxt = fetch(end, l + 1 < nlev ? nend : end);
         s = lane_sum<G>(s);
         if (cur.row >= 0 && gl == 0) {
-            T r = cur.r - s;
+            T r = rv - s;
             if (has_diag) r = r / cur.d;
             x[cur.row] = r;
         }
@@ -251,9 +247,27 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
                 x[row] = r;
             }
         }
+    };
+    __syncthreads();  // rhs complete
+    const int nlev = t.nlev;
+    if (nlev == 0) return;
+    int b0 = 0, b1 = lev[1];
+    Pf A = fetch(b0, b1), B;
+    for (int l = 0;;) {
+        int b2 = l + 2 <= nlev ? lev[l + 2] : b1;
+        B = fetch(b1, b2);
+        solve(A, b0, b1);
         __syncthreads();
-        cur = nxt;
-        end = nend;
+        if (++l == nlev) break;
+        b0 = b1;
+        b1 = b2;
+        b2 = l + 2 <= nlev ? lev[l + 2] : b1;
+        A = fetch(b1, b2);
+        solve(B, b0, b1);
+        __syncthreads();
+        if (++l == nlev) break;
+        b0 = b1;
+        b1 = b2;
     }
 }
 
@@ -550,7 +564,7 @@ BOp bop(const Ctx &c, const DevCsrOff &o, const DevPlanOff &p)
 BTri btri(const Ctx &c, const DevTriOff &o)
 {
     return BTri{at<int32_t>(c, o.lev), at<int32_t>(c, o.rows), at<int32_t>(c, o.lo.ptr), at<int32_t>(c, o.lo.col),
-                at<void>(c, o.lo.val), o.ldiag ? at<void>(c, o.ldiag) : nullptr, o.nlev, 0};
+                at<void>(c, o.lo.val), o.ldiag ? at<void>(c, o.ldiag) : nullptr, at<void>(c, o.lrec), o.nlev, 0};
 }
 
 // Whether a handle can be solved by the batched kernel.

@@ -722,6 +722,7 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
         if (e == hipSuccess) e = put(o.lev, lv.ptr.data(), lv.ptr.size() * sizeof(int32_t));
         if (e == hipSuccess) e = put_csr(o.lo, lo.a);
         if (e == hipSuccess && o.ldiag) e = put_vals(o.ldiag, lo.diag, o.lo.vbytes);
+        if (e == hipSuccess) e = put(o.lrec, lo.rec.data(), lo.rec.size());
         return e;
     };
     auto put_sweep = [&](const DevTriOff &o, const Sweep &sw) -> hipError_t {

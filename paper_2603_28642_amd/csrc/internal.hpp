@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "rsilu.h"
+#include "level_rec.hpp"
 #include "sweep_limits.hpp"
 
 namespace rsilu {
@@ -56,6 +57,7 @@ struct Sweep {
 struct LoTri {
     Csr a;
     std::vector<double> diag;
+    std::vector<unsigned char> rec;  // LevelRec<V> per position (V: the factor value type)
 };
 
 // Work plan for a CSR product: rows with more than `long_thresh` entries are
@@ -94,6 +96,7 @@ struct DevTriOff {
     size_t lev = 0;
     DevCsrOff lo;
     size_t ldiag = 0;  // 0 = unit diagonal
+    size_t lrec = 0;   // LevelRec per position
 };
 
 struct Layout {

@@ -139,6 +139,7 @@ int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, boo
     return blob_layout(nlev, npos, next, nchunk, diag, vb).size;
 }
 
+template <class V>
 LoTri level_ordered(const Csr &T, const std::vector<double> *diag, const Levels &lv)
 {
     LoTri o;
@@ -157,6 +158,20 @@ LoTri level_ordered(const Csr &T, const std::vector<double> *diag, const Levels 
         }
         o.a.ptr[(size_t)p + 1] = (int32_t)o.a.col.size();
         if (diag) o.diag[p] = (*diag)[row];
+    }
+    o.rec.assign(sizeof(LevelRec<V>) * (size_t)n, 0);
+    LevelRec<V> *rec = reinterpret_cast<LevelRec<V> *>(o.rec.data());
+    for (int32_t p = 0; p < n; ++p) {
+        LevelRec<V> &r = rec[p];
+        r.row = lv.rows[p];
+        r.k0 = o.a.ptr[p];
+        r.k1 = o.a.ptr[(size_t)p + 1];
+        for (int j = 0; j < kRecEntries; ++j) {
+            const bool in = r.k0 + j < r.k1;
+            r.col[j] = in ? o.a.col[(size_t)r.k0 + j] : -1;
+            r.val[j] = in ? (V)o.a.val[(size_t)r.k0 + j] : (V)0;
+        }
+        r.diag = diag ? (V)o.diag[p] : (V)1;
     }
     return o;
 }
@@ -713,10 +728,13 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.chUT = make_chunks(c.lvUT, 64 / tri_lanes(c.UT));
     c.swUT = f32 ? make_sweep<float>(c.UT, &c.Udiag, c.lvUT) : make_sweep<double>(c.UT, &c.Udiag, c.lvUT);
 
-    c.loL1 = level_ordered(c.L1, nullptr, c.lvL1);
-    c.loL1T = level_ordered(c.L1T, nullptr, c.lvL1T);
-    c.loU = level_ordered(c.U, &c.Udiag, c.lvU);
-    c.loUT = level_ordered(c.UT, &c.Udiag, c.lvUT);
+    auto lo = [&](const Csr &T, const std::vector<double> *diag, const Levels &lv) {
+        return f32 ? level_ordered<float>(T, diag, lv) : level_ordered<double>(T, diag, lv);
+    };
+    c.loL1 = lo(c.L1, nullptr, c.lvL1);
+    c.loL1T = lo(c.L1T, nullptr, c.lvL1T);
+    c.loU = lo(c.U, &c.Udiag, c.lvU);
+    c.loUT = lo(c.UT, &c.Udiag, c.lvUT);
 
     // ---- S^ (Section 3.2)
     c.smode = P.smode;
@@ -816,6 +834,7 @@ DevTriOff place_tri(Bump &b, const Csr &a, bool diag, const Levels &lv, const Ch
     o.lev = b.take(sizeof(int32_t) * lv.ptr.size());
     o.lo = place_csr(b, lo.a, vbytes);
     o.ldiag = diag ? b.take((size_t)vbytes * n) : 0;
+    o.lrec = b.take(lo.rec.size());
     o.blob = b.take(sw.blob.size());
     o.a = place_csr(b, a, vbytes);
     o.diag = diag ? b.take((size_t)vbytes * n) : 0;
@@ -866,8 +885,18 @@ void plan_layout(Ctx &c)
         for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
     if (c.prm.krylov == RSILU_KRYLOV_LSQR)
         for (size_t *o : {&L.l_v, &L.l_mv, &L.l_w}) *o = b.take(sizeof(double) * n);
-    // one partial per block of the largest reduction, plus one per long row
-    L.npartials = 65536;
+    // one partial per block of the largest reduction (a product's blocks hold
+    // kBlock / lanes rows; dot products use at most 2048 blocks), plus one per long row
+    auto blocks = [](int64_t rows, int32_t lanes) {
+        const int64_t per = 256 / std::max<int32_t>(lanes, 1);
+        return (rows + per - 1) / per;
+    };
+    const int64_t nparts = std::max<int64_t>({(int64_t)2048, blocks(c.Ahat.nrows, c.plA.lanes),
+                                              blocks(c.AhatT.nrows, c.plAT.lanes), blocks(c.L2.nrows, c.plL2.lanes),
+                                              blocks(c.L2T.nrows, c.plL2T.lanes)});
+    const int64_t nlong = std::max<int64_t>({(int64_t)c.plA.long_rows.size(), (int64_t)c.plAT.long_rows.size(),
+                                             (int64_t)c.plL2.long_rows.size(), (int64_t)c.plL2T.long_rows.size()});
+    L.npartials = (int32_t)(nparts + nlong + 64);
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);
     int32_t nseg = std::max({(int32_t)c.plA.seg_beg.size(), (int32_t)c.plAT.seg_beg.size(),
                              (int32_t)c.plL2.seg_beg.size(), (int32_t)c.plL2T.seg_beg.size(), 1});
