@@ -76,11 +76,36 @@ __device__ __forceinline__ RSILU_GLOBAL T *gm(T *p)
     return (RSILU_GLOBAL T *)p;
 }
 
+// Value of lane (lane ^ X) within each quad of lanes, X in {1, 2}, by a DPP move
+// (quad_perm [1,0,3,2] or [2,3,0,1]); no LDS round trip.
+template <int X>
+__device__ __forceinline__ int quad_xor(int v)
+{
+    static_assert(X == 1 || X == 2, "quad lanes");
+    return __builtin_amdgcn_mov_dpp(v, X == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int X>
+__device__ __forceinline__ double quad_xor(double v)
+{
+    const int lo = quad_xor<X>(__double2loint(v)), hi = quad_xor<X>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int X>
+__device__ __forceinline__ float quad_xor(float v)
+{
+    return __int_as_float(quad_xor<X>(__float_as_int(v)));
+}
+
+// Sum over aligned groups of G lanes by an xor butterfly: every lane of a group
+// ends with the same bits (each step adds the same two operands, commuted). The
+// steps inside a quad use DPP moves, wider ones cross-lane shuffles.
 template <int G, class T>
 __device__ __forceinline__ T lane_sum(T v)
 {
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    for (int off = G / 2; off > 2; off >>= 1) v += __shfl_xor(v, off);
+    if constexpr (G >= 4) v += quad_xor<2>(v);
+    if constexpr (G >= 2) v += quad_xor<1>(v);
     return v;
 }
 
@@ -251,17 +276,30 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
     __syncthreads();  // rhs complete
     const int nlev = t.nlev;
     if (nlev == 0) return;
-    int b0 = 0, b1 = lev[1];
+    // Level pointers come from a window of 64 held in the lanes of every
+    // wavefront (vector loads, read out with readlane): a scalar load in flight
+    // would be waited for at every barrier with the LDS operations.
+    const int lane = threadIdx.x & 63;
+    int wbase = 0;
+    int win = lev[min(lane, nlev)];
+    auto lev_at = [&](int i) {
+        if (i - wbase >= 64) {
+            wbase = i;
+            win = lev[min(wbase + lane, nlev)];
+        }
+        return __builtin_amdgcn_readlane(win, i - wbase);
+    };
+    int b0 = 0, b1 = lev_at(1);
     Pf A = fetch(b0, b1), B;
     for (int l = 0;;) {
-        int b2 = l + 2 <= nlev ? lev[l + 2] : b1;
+        int b2 = l + 2 <= nlev ? lev_at(l + 2) : b1;
         B = fetch(b1, b2);
         solve(A, b0, b1);
         __syncthreads();
         if (++l == nlev) break;
         b0 = b1;
         b1 = b2;
-        b2 = l + 2 <= nlev ? lev[l + 2] : b1;
+        b2 = l + 2 <= nlev ? lev_at(l + 2) : b1;
         A = fetch(b1, b2);
         solve(B, b0, b1);
         __syncthreads();
