@@ -188,6 +188,24 @@ size_t rsilu_device_bytes(rsilu_handle_t h);
  * small), EHIP (runtime error). May be called again with another buffer. */
 rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipStream_t stream);
 
+/* Append `count` rows to A without refactoring (Section 3.4, adding rows). The
+ * rows (host CSR: rowptr[count + 1] from 0, sorted unique column indices in
+ * [0, n), finite values; explicit zeros are stripped; copied) become rows
+ * m, ..., m + count - 1 of A and join A2 at the end of the row order. L1, U and
+ * the level schedules are kept; each new row a gets the L2 row l that solves
+ * U^T l^T = (a D)^T (D the setup's column scaling) by forward substitution,
+ * with entries |l_j| < tau or zero dropped. The products' plans and, in dense
+ * mode, S~ are rebuilt. The device layout grows: the handle has no device
+ * buffer afterwards, so call rsilu_device_bytes and rsilu_upload again before
+ * the next solve (solves return ESTATE until then); b then has m + count
+ * values. Errors: EINVAL (NULL handle, bad rows, too many rows or entries, or
+ * dense S~ beyond its size limit; the handle is unchanged), ENOMEM, BREAKDOWN
+ * (the rebuilt dense S~ is not positive definite; destroy the handle). The
+ * update is only as good as the kept factorization: a row that makes A rank
+ * deficient is not detected. */
+rsilu_status_t rsilu_add_rows(rsilu_handle_t h, int64_t count, const int64_t *rowptr, const int32_t *colind,
+                              const double *val);
+
 /* Setup statistics (Tables 2 and 3 report psize and nmod). */
 rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *stats);
 

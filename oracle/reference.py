@@ -148,13 +148,14 @@ def upper_solve(U, b, diag=None):
 # Section 5.1 and the problem statement (1.1)
 
 
-def validate(m, n, rowptr, col, val):
-    """Check CSR input of A (m x n, m >= n) and strip explicit zeros."""
+def validate(m, n, rowptr, col, val, appended=False):
+    """Check CSR input of A (m x n, m >= n; or, appended, m >= 1 rows of n columns to add)
+    and strip explicit zeros."""
     rowptr = _c(rowptr, np.int64)
     col = _c(col, np.int64)
     val = _c(val, np.float64)
-    if n < 1 or m < n:
-        raise ValueError("need m >= n >= 1")
+    if n < 1 or (m < 1 if appended else m < n):
+        raise ValueError("need m >= n >= 1" if not appended else "need at least one row")
     if rowptr.shape != (m + 1,) or rowptr[0] != 0 or np.any(np.diff(rowptr) < 0):
         raise ValueError("bad row pointer")
     nnz = int(rowptr[-1])
@@ -332,6 +333,42 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
 
 def factor_problem(prob, **kw):
     return factor(prob.m, prob.n, prob.rowptr, prob.col, prob.val, **kw)
+
+
+def add_rows(F, rowptr, col, val, tau=1e-2):
+    """Section 3.4, adding rows: the factorization of A is kept (L1, U, the pivot order of
+    A1) and each new row a, prescaled with the setup's column norms (a_hat = a D), becomes
+    a row of A2 at the end of the row order with the L2 row l that solves (U)^T l^T =
+    a_hat^T by forward substitution; entries with |l_j| < tau (or zero) are dropped, as in
+    the ILUP's dropping of L. Dense S~ is recomputed. Returns new Factors."""
+    import dataclasses
+
+    count = len(rowptr) - 1
+    rowptr, col, val = validate(count, F.n, rowptr, col, val, appended=True)
+    n, m0 = F.n, F.m
+    new = sp.csr_matrix((val, col, rowptr), shape=(count, n))
+    A = csr_from_scipy(sp.vstack([F.A.scipy(), new]).tocsr())
+    scaled = sp.csr_matrix((val / F.colnorm[col], col, rowptr), shape=(count, n))
+    Ahat = csr_from_scipy(sp.vstack([F.Ahat.scipy(), scaled]).tocsr())
+    rows, cols, vals = [], [], []
+    for i in range(count):
+        ahat = np.zeros(n)
+        e0, e1 = int(rowptr[i]), int(rowptr[i + 1])
+        ahat[col[e0:e1]] = val[e0:e1] / F.colnorm[col[e0:e1]]
+        l = lower_solve(F.UT, ahat, F.Udiag)  # U^T l^T = a_hat^T
+        keep = np.nonzero((l != 0.0) & (np.abs(l) >= tau))[0]
+        rows.append(np.full(keep.size, F.L2.nrows + i))
+        cols.append(keep)
+        vals.append(l[keep])
+    L2 = csr_from_scipy(sp.vstack([F.L2.scipy(), sp.csr_matrix(
+        (np.concatenate(vals), (np.concatenate(rows) - F.L2.nrows, np.concatenate(cols))),
+        shape=(count, n))]).tocsr())
+    perm = np.concatenate([F.perm, np.arange(m0, m0 + count, dtype=F.perm.dtype)])
+    G = dataclasses.replace(F, m=m0 + count, perm=perm, A=A, Ahat=Ahat, AhatT=Ahat.transpose(), L2=L2,
+                            L2T=L2.transpose())
+    if F.smode == "dense":
+        _, G.S_chol = dense_S(F.L1, L2)
+    return G
 
 
 # ----------------------------------------------------------------------------

@@ -754,6 +754,24 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     return RSILU_OK;
 }
 
+rsilu_status_t rsilu_add_rows(rsilu_handle_t h, int64_t count, const int64_t *rowptr, const int32_t *colind,
+                              const double *val)
+{
+    if (!h) return RSILU_EINVAL;
+    Ctx &c = *h;
+    try {
+        const rsilu_status_t rc = append_rows(c, count, rowptr, colind, val);
+        if (rc != RSILU_OK) return rc;
+        plan_layout(c);
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
+    release_graph(c);  // the captured iterations hold the old layout's addresses
+    c.dev = nullptr;   // the layout grew: upload again before the next solve
+    c.dev_bytes = 0;
+    return RSILU_OK;
+}
+
 static rsilu_status_t check_ready(rsilu_handle_t h)
 {
     if (!h) return RSILU_EINVAL;

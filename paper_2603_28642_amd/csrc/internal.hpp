@@ -169,6 +169,7 @@ inline bool fp32(const Ctx &c) { return c.prm.precision == RSILU_PREC_FP32; }
 rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *rowptr,
                                    const int32_t *colind, const double *val);
 void plan_layout(Ctx &c);
+rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const int32_t *colind, const double *val);
 // device driver (capi.hip): drop a captured iteration graph
 void release_graph(Ctx &c);
 

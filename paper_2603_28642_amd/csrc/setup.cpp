@@ -470,6 +470,51 @@ double modified_pivot(int64_t j1, int64_t n, double colmax, double small)
 
 }  // namespace
 
+// S~ = I + Y~ Y~^T with Y~^T = L1^{-T} L2^T, factored by Cholesky (Section 3.2),
+// packed lower factor by rows.
+rsilu_status_t build_dense_S(Ctx &c)
+{
+    const int64_t m = c.m, n = c.n;
+    const int64_t k = m - n;
+    if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
+    // Y^T = L1^{-T} L2^T, one column (row of Y) per row of L2
+    std::vector<double> Y((size_t)(k * n), 0.0);  // row-major k x n
+    for (int64_t i = 0; i < k; ++i) {
+        double *y = &Y[(size_t)(i * n)];
+        for (int32_t e = c.L2.ptr[i]; e < c.L2.ptr[(size_t)i + 1]; ++e) y[c.L2.col[e]] = c.L2.val[e];
+        for (int64_t r = n - 1; r >= 0; --r) {  // L1^T y = l2_i, backward
+            double s = y[r];
+            for (int32_t e = c.L1T.ptr[r]; e < c.L1T.ptr[(size_t)r + 1]; ++e) s -= c.L1T.val[e] * y[c.L1T.col[e]];
+            y[r] = s;
+        }
+    }
+    // S~ = I + Y Y^T, lower Cholesky factor, packed by rows
+    c.sfac.assign((size_t)(k * (k + 1) / 2), 0.0);
+    auto at = [](int64_t i, int64_t jj) { return (size_t)(i * (i + 1) / 2 + jj); };
+    for (int64_t i = 0; i < k; ++i) {
+        const double *yi = &Y[(size_t)(i * n)];
+        for (int64_t jj = 0; jj <= i; ++jj) {
+            const double *yj = &Y[(size_t)(jj * n)];
+            double s = (i == jj) ? 1.0 : 0.0;
+            for (int64_t t = 0; t < n; ++t) s += yi[t] * yj[t];
+            c.sfac[at(i, jj)] = s;
+        }
+    }
+    for (int64_t jj = 0; jj < k; ++jj) {
+        double d = c.sfac[at(jj, jj)];
+        for (int64_t t = 0; t < jj; ++t) d -= c.sfac[at(jj, t)] * c.sfac[at(jj, t)];
+        if (!(d > 0.0) || !std::isfinite(d)) return RSILU_BREAKDOWN;
+        d = std::sqrt(d);
+        c.sfac[at(jj, jj)] = d;
+        for (int64_t i = jj + 1; i < k; ++i) {
+            double s = c.sfac[at(i, jj)];
+            for (int64_t t = 0; t < jj; ++t) s -= c.sfac[at(i, t)] * c.sfac[at(jj, t)];
+            c.sfac[at(i, jj)] = s / d;
+        }
+    }
+    return RSILU_OK;
+}
+
 rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *rowptr,
                                    const int32_t *colind, const double *val)
 {
@@ -743,46 +788,88 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
                       ? RSILU_S_DENSE
                       : (P.krylov == RSILU_KRYLOV_LSQR ? RSILU_S_NONE : RSILU_S_IDENTITY);
     if (c.smode == RSILU_S_DENSE && m > n) {
-        const int64_t k = m - n;
-        if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
-        // Y^T = L1^{-T} L2^T, one column (row of Y) per row of L2
-        std::vector<double> Y((size_t)(k * n), 0.0);  // row-major k x n
-        for (int64_t i = 0; i < k; ++i) {
-            double *y = &Y[(size_t)(i * n)];
-            for (int32_t e = c.L2.ptr[i]; e < c.L2.ptr[(size_t)i + 1]; ++e) y[c.L2.col[e]] = c.L2.val[e];
-            for (int64_t r = n - 1; r >= 0; --r) {  // L1^T y = l2_i, backward
-                double s = y[r];
-                for (int32_t e = c.L1T.ptr[r]; e < c.L1T.ptr[(size_t)r + 1]; ++e) s -= c.L1T.val[e] * y[c.L1T.col[e]];
-                y[r] = s;
-            }
-        }
-        // S~ = I + Y Y^T, lower Cholesky factor, packed by rows
-        c.sfac.assign((size_t)(k * (k + 1) / 2), 0.0);
-        auto at = [](int64_t i, int64_t jj) { return (size_t)(i * (i + 1) / 2 + jj); };
-        for (int64_t i = 0; i < k; ++i) {
-            const double *yi = &Y[(size_t)(i * n)];
-            for (int64_t jj = 0; jj <= i; ++jj) {
-                const double *yj = &Y[(size_t)(jj * n)];
-                double s = (i == jj) ? 1.0 : 0.0;
-                for (int64_t t = 0; t < n; ++t) s += yi[t] * yj[t];
-                c.sfac[at(i, jj)] = s;
-            }
-        }
-        for (int64_t jj = 0; jj < k; ++jj) {
-            double d = c.sfac[at(jj, jj)];
-            for (int64_t t = 0; t < jj; ++t) d -= c.sfac[at(jj, t)] * c.sfac[at(jj, t)];
-            if (!(d > 0.0) || !std::isfinite(d)) return RSILU_BREAKDOWN;
-            d = std::sqrt(d);
-            c.sfac[at(jj, jj)] = d;
-            for (int64_t i = jj + 1; i < k; ++i) {
-                double s = c.sfac[at(i, jj)];
-                for (int64_t t = 0; t < jj; ++t) s -= c.sfac[at(i, t)] * c.sfac[at(jj, t)];
-                c.sfac[at(i, jj)] = s / d;
-            }
-        }
+        const rsilu_status_t rc = build_dense_S(c);
+        if (rc != RSILU_OK) return rc;
     } else if (c.smode != RSILU_S_NONE && c.smode != RSILU_S_CG) {
         c.smode = RSILU_S_IDENTITY;
     }
+    return RSILU_OK;
+}
+
+// Section 3.4, adding rows: the factorization of A is kept (L1, U and the pivot
+// order of A1). Each new row a, prescaled with the setup's column norms (a_hat =
+// a D), joins A2 at the end of the row order, and its L2 row l solves
+// U^T l^T = a_hat^T by forward substitution (products summed in entry order,
+// separately rounded, then subtracted and divided by the diagonal); entries with
+// |l_j| < tau, or zero, are dropped as in the ILUP's dropping of L. The products'
+// plans, the transposes and, in dense mode, S~ are rebuilt. Every argument is
+// checked before the handle changes.
+rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const int32_t *colind, const double *val)
+{
+    const int64_t n = c.n, m0 = c.m;
+    if (count < 1 || !rowptr || rowptr[0] != 0 || m0 + count > kMaxIdx) return RSILU_EINVAL;
+    if (rowptr[count] > 0 && (!colind || !val)) return RSILU_EINVAL;
+    for (int64_t i = 0; i < count; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) return RSILU_EINVAL;
+        int32_t prev = -1;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int32_t cc = colind[e];
+            if (cc < 0 || cc >= n || cc <= prev || !std::isfinite(val[e])) return RSILU_EINVAL;
+            prev = cc;
+        }
+    }
+    if (c.A.nnz() + rowptr[count] > kMaxIdx) return RSILU_EINVAL;
+    if (c.smode == RSILU_S_DENSE) {
+        const int64_t k = m0 + count - n;
+        if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
+    }
+    const bool scale = c.prm.colscale != 0;
+    std::vector<double> y((size_t)n);
+    for (int64_t i = 0; i < count; ++i) {
+        std::fill(y.begin(), y.end(), 0.0);
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (val[e] == 0.0) continue;
+            const int32_t cc = colind[e];
+            const double ah = scale ? val[e] / c.colnorm[cc] : val[e];
+            c.A.col.push_back(cc);
+            c.A.val.push_back(val[e]);
+            c.Ahat.col.push_back(cc);
+            c.Ahat.val.push_back(ah);
+            y[cc] = ah;
+        }
+        c.A.ptr.push_back((int32_t)c.A.col.size());
+        c.A.nrows++;
+        c.Ahat.ptr.push_back((int32_t)c.Ahat.col.size());
+        c.Ahat.nrows++;
+        // U^T l^T = a_hat^T: row j of U^T holds the entries U(i, j), i < j
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int32_t e = c.UT.ptr[j]; e < c.UT.ptr[(size_t)j + 1]; ++e) {
+                const double prod = c.UT.val[e] * y[c.UT.col[e]];
+                s = s + prod;
+            }
+            const double r = y[j] - s;
+            y[j] = r / c.Udiag[j];
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            if (y[j] != 0.0 && std::fabs(y[j]) >= c.prm.tau) {
+                c.L2.col.push_back((int32_t)j);
+                c.L2.val.push_back(y[j]);
+            }
+        }
+        c.L2.ptr.push_back((int32_t)c.L2.col.size());
+        c.L2.nrows++;
+        c.perm.push_back((int32_t)(m0 + i));
+    }
+    c.m = m0 + count;
+    c.nnz_a = c.A.nnz();
+    c.AhatT = transpose(c.Ahat);
+    c.L2T = transpose(c.L2);
+    c.plA = plan_spmv(c.Ahat);
+    c.plAT = plan_spmv(c.AhatT);
+    c.plL2 = plan_spmv(c.L2);
+    c.plL2T = plan_spmv(c.L2T);
+    if (c.smode == RSILU_S_DENSE) return build_dense_S(c);
     return RSILU_OK;
 }
 

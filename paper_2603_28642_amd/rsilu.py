@@ -28,7 +28,7 @@ LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
 T_L1, T_L1T, T_U, T_UT = 0, 1, 2, 3
 
 EXPORTS = [
-    "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_get_stats",
+    "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_add_rows", "rsilu_get_stats",
     "rsilu_get_perm", "rsilu_get_colnorm", "rsilu_factor_nnz", "rsilu_get_factor", "rsilu_get_levels",
     "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_apply_z", "rsilu_set_profiling",
     "rsilu_get_profile",
@@ -131,6 +131,8 @@ def lib():
         L.rsilu_device_bytes.restype = ctypes.c_size_t
         L.rsilu_upload.argtypes = [P, P, ctypes.c_size_t, P]
         L.rsilu_upload.restype = ctypes.c_int
+        L.rsilu_add_rows.argtypes = [P, I64, P, P, P]
+        L.rsilu_add_rows.restype = ctypes.c_int
         L.rsilu_get_stats.argtypes = [P, ctypes.POINTER(rsilu_stats_t)]
         L.rsilu_get_stats.restype = ctypes.c_int
         L.rsilu_get_perm.argtypes = [P, P]
@@ -258,6 +260,14 @@ def rsilu_device_bytes(h):
 def rsilu_upload(h, dev_buf, stream=None):
     nbytes = dev_buf.numel() * dev_buf.element_size()
     return lib().rsilu_upload(h, _dev(dev_buf), nbytes, _stream(stream))
+
+
+def rsilu_add_rows(h, rowptr, colind, val):
+    """Append rows (host CSR) to the handle's A; the handle must be uploaded again."""
+    rp, prp = _host(rowptr, np.int64)
+    ci, pci = _host(colind, np.int32)
+    vv, pvv = _host(val, np.float64)
+    return lib().rsilu_add_rows(h, len(rp) - 1, prp, pci, pvv)
 
 
 def rsilu_get_stats(h):
@@ -391,6 +401,13 @@ class Solver:
         code, it, atr, rel = rsilu_solve(self.h, b_dev, tol, x_dev, stream)
         _check(code, "rsilu_solve")
         return x_dev, code, it, atr, rel
+
+    def add_rows(self, rowptr, colind, val, stream=None):
+        """Append rows (Section 3.4) and upload the grown layout to a new buffer."""
+        _check(rsilu_add_rows(self.h, rowptr, colind, val), "rsilu_add_rows")
+        self.m += len(rowptr) - 1
+        self.stats = rsilu_get_stats(self.h)
+        return self.upload(stream)
 
     def perm(self):
         return rsilu_get_perm(self.h, self.m)

@@ -301,3 +301,51 @@ def test_batch_api_host_checks():
     assert L.rsilu_tuner_size(None) == 0
     L.rsilu_batch_destroy(None)
     L.rsilu_tuner_destroy(None)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_add_rows_bit_exact(precision):
+    """rsilu_add_rows against the oracle's add_rows: row order, A_hat and every L2 entry
+    bit-identical; L1, U and the level schedules unchanged; the device layout must be
+    uploaded again."""
+    p = gen.by_name("c2-small")
+    q = gen.random_sparse(300, p.n, k=5, seed=71, transversal=False)
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_NONE, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR, precision=precision)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    before = R.rsilu_device_bytes(h)
+    assert R.rsilu_add_rows(h, q.rowptr, q.col, q.val) == R.OK
+    F = oracle.add_rows(oracle.factor_problem(p, mu=1.0, smode="none"), q.rowptr, q.col, q.val, tau=1e-2)
+    st = R.rsilu_get_stats(h)
+    assert st.m == p.m + 300 and st.nnz_a == p.nnz + q.nnz and R.rsilu_device_bytes(h) > before
+    assert np.array_equal(R.rsilu_get_perm(h, st.m), F.perm)
+    for which, C in [(R.L1, F.L1), (R.L2, F.L2), (R.U, F.U), (R.AHAT, F.Ahat)]:
+        rp, cc, vv = R.rsilu_get_factor(h, which, C.nrows)
+        assert np.array_equal(rp, C.rowptr) and np.array_equal(cc, C.col), which
+        assert np.array_equal(bits(vv), bits(C.val)), which
+    for which, key, nl in [(R.LEV_L1, "L1", st.levels_l1), (R.LEV_U, "U", st.levels_u)]:
+        ptr, rows = R.rsilu_get_levels(h, which, p.n, nl)
+        assert np.array_equal(ptr, F.lev[key][0]) and np.array_equal(rows, F.lev[key][1])
+    R.rsilu_destroy(h)
+
+
+def test_add_rows_rejects_bad_rows():
+    p = gen.tiny_c1()
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_NONE)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    st0 = R.rsilu_get_stats(h)
+    bad = [
+        ([0, 2], [5, 3], [1.0, 2.0]),          # unsorted
+        ([0, 2], [3, 3], [1.0, 2.0]),          # repeated
+        ([0, 1], [p.n], [1.0]),                # out of range
+        ([0, 1], [-1], [1.0]),
+        ([0, 1], [4], [float("nan")]),
+        ([1, 2], [4, 5], [1.0, 1.0]),          # pointer not from 0
+        ([0], [], []),                         # no row
+    ]
+    for rp, cc, vv in bad:
+        assert R.rsilu_add_rows(h, np.array(rp), np.array(cc, dtype=np.int32), np.array(vv)) == R.EINVAL, rp
+    st = R.rsilu_get_stats(h)
+    assert st.m == st0.m and st.nnz_a == st0.nnz_a and R.rsilu_device_bytes(h) == st0.device_bytes
+    assert R.lib().rsilu_add_rows(None, 1, None, None, None) == R.EINVAL
+    R.rsilu_destroy(h)
