@@ -629,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(DTriT<T> t, int32_t beg, 
 // cur_base, p0, size, next_size, next_npos, next_next, nchunk},
 // lev_off[nlev+1], lev_chunk[nlev+1], rowid[npos], ext_idx[next],
 // next_ext[kSweepExt], uint16 rchunk[npos+1], cstart[nchunk+1], eslot[nent],
-// then (16-aligned) T eval[nent], diag[npos] (T = double, or float for the
+// then (16-aligned) T eval[nent], rdiag[npos] (reciprocal diagonal; T = double, or float for the
 // FP32 preconditioner). A row's entries are cut into chunks of at most
 // kSweepChunk; eslot indexes the LDS window xw = [even batches' results | odd
 // batches' results | older inputs].
@@ -828,7 +828,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                     for (int c = c0 + 4; c <= last; ++c) s += prod[c];
                 }
                 T r = m.rhs - s;
-                if (hd) r = r / m.dg;
+                if (hd) r = r * m.dg;  // reciprocal of the diagonal, stored by the setup
                 xw[cur + m.pidx] = r;
                 x[m.row] = r;
                 if (y2) y2[m.row] = m.add + r;

@@ -320,7 +320,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
                 }
                 ++ch;
             }
-            if (hd) dg[p - p0] = (V)(*diag)[row];
+            if (hd) dg[p - p0] = (V)(1.0 / (*diag)[row]);  // the sweep multiplies by the reciprocal
         }
         while (lvl < l1) {
             ++lvl;
