@@ -34,7 +34,7 @@ struct BOp {
 
 // Triangular factor in level order: position p of level l (lev[l] <= p <
 // lev[l+1]) solves row rows[p] with the entries lptr[p]..lptr[p+1] of
-// lcol/lval and divides by ldiag[p] (null: unit diagonal). Values in the
+// lcol/lval and multiplies by ldiag[p], the reciprocal diagonal (null: unit). Values in the
 // preconditioner's precision.
 struct BTri {
     const int32_t *lev, *rows, *lptr, *lcol;
@@ -236,7 +236,7 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
                 f.c[i] = r.col[gl + i * G];
                 f.v[i] = r.val[gl + i * G];
             }
-            f.d = r.diag;
+            f.d = r.rdiag;
         }
         return f;
     };
@@ -252,7 +252,7 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
         s = lane_sum<G>(s);
         if (cur.row >= 0 && gl == 0) {
             T r = rv - s;
-            if (has_diag) r = r / cur.d;
+            if (has_diag) r = r * cur.d;
             x[cur.row] = r;
         }
         // further rows of a level wider than one pass
@@ -268,7 +268,7 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
             s2 = lane_sum<G>(s2);
             if (row >= 0 && gl == 0) {
                 T r = rhs[row] - s2;
-                if (has_diag) r = r / ldiag[p];
+                if (has_diag) r = r * ldiag[p];
                 x[row] = r;
             }
         }

@@ -51,7 +51,8 @@ struct Sweep {
 };
 
 // A triangular factor with its rows stored in level order (position p holds
-// row Levels::rows[p]); diag is the diagonal in the same order (empty: unit).
+// row Levels::rows[p]); diag is the reciprocal of the diagonal in the same order
+// (empty: unit).
 // Read by the batched persistent solves: one load of the row pointer per
 // position instead of the row index, then its pointer.
 struct LoTri {

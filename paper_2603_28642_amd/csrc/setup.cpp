@@ -157,7 +157,7 @@ LoTri level_ordered(const Csr &T, const std::vector<double> *diag, const Levels 
             o.a.val.push_back(T.val[e]);
         }
         o.a.ptr[(size_t)p + 1] = (int32_t)o.a.col.size();
-        if (diag) o.diag[p] = (*diag)[row];
+        if (diag) o.diag[p] = 1.0 / (*diag)[row];  // reciprocal: the batched solves multiply
     }
     o.rec.assign(sizeof(LevelRec<V>) * (size_t)n, 0);
     LevelRec<V> *rec = reinterpret_cast<LevelRec<V> *>(o.rec.data());
@@ -171,7 +171,7 @@ LoTri level_ordered(const Csr &T, const std::vector<double> *diag, const Levels 
             r.col[j] = in ? o.a.col[(size_t)r.k0 + j] : -1;
             r.val[j] = in ? (V)o.a.val[(size_t)r.k0 + j] : (V)0;
         }
-        r.diag = diag ? (V)o.diag[p] : (V)1;
+        r.rdiag = diag ? (V)o.diag[p] : (V)1;
     }
     return o;
 }
