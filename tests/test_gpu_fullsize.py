@@ -7,7 +7,8 @@ configuration bench.py times (hybrid schedule, Algorithm 2 without correction, L
   both solutions in the same stop-test ball);
 * the same generator at 1500000 x 1000000 with the FP32 preconditioner: the whole solve
   reaches the tolerance on the true residual, and lies in the stop-test ball of the FP64
-  path on the same GPU.
+  path on the same GPU and of the FP64 oracle (whose iteration count the FP64 path matches
+  within 2%).
 """
 
 import numpy as np
@@ -109,4 +110,16 @@ def test_c4_fp32_preconditioner(gpu_lib):
         assert np.linalg.norm(A.T @ (prob.b - A @ x)) <= 2 * tol * atb, prec
     e = out[R.PREC_FP32][0] - out[R.PREC_FP64][0]
     assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
-    print("grid 1500000 x 1000000: its fp64 %d, fp32-preconditioner %d" % (out[R.PREC_FP64][2], out[R.PREC_FP32][2]))
+    # both against the FP64 oracle's solution (its stop-test ball) and its iteration count
+    o = oracle.lsqr_m(oracle.factor_problem(prob, mu=1.0, smode="none"), prob.b, tol=tol, maxit=2000)
+    assert o.status == "ok"
+    assert abs(out[R.PREC_FP64][2] - o.iters) <= max(1, int(0.02 * o.iters))
+    ball = {}
+    for prec, (x, code, it) in out.items():
+        ball[prec] = np.linalg.norm(A.T @ (A @ (x - o.x))) / atb
+        assert ball[prec] <= 4 * tol, prec
+    rel = {prec: np.linalg.norm(x - o.x) / np.linalg.norm(o.x) for prec, (x, code, it) in out.items()}
+    print("grid 1500000 x 1000000: its fp64 %d, fp32-preconditioner %d, oracle %d; ||A^T A (x - x_or)|| / ||A^T b||"
+          " fp64 %.1e, fp32 %.1e; ||x - x_or|| / ||x_or|| fp64 %.1e, fp32 %.1e" % (
+              out[R.PREC_FP64][2], out[R.PREC_FP32][2], o.iters, ball[R.PREC_FP64], ball[R.PREC_FP32],
+              rel[R.PREC_FP64], rel[R.PREC_FP32]))
