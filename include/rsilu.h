@@ -206,6 +206,25 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
 rsilu_status_t rsilu_add_rows(rsilu_handle_t h, int64_t count, const int64_t *rowptr, const int32_t *colind,
                               const double *val);
 
+/* Remove `count` rows of A without refactoring (Section 3.4, removing rows).
+ * rows: host array of distinct row indices in the current numbering (copied);
+ * the remaining rows keep their order and are numbered 0 .. m - count - 1, so b
+ * has m - count values afterwards. The factorization is kept: removed rows of A2
+ * leave L2 and S~ is refactored; removed rows of A1 join R, and the
+ * preconditioner becomes the Woodbury update M^{-1} + M^{-1} R^T W^{-1} R M^{-1},
+ * W = I - R M^{-1} R^T, over every A1 row removed so far (M^{-1} the Algorithm 2
+ * operator; each application then costs two of them, a product with R and R^T
+ * and a dense solve with W's Cholesky factor). Needs form ALG2, FP64, the dense
+ * S~ and a level or hybrid schedule (the mode in which M approximates A^T A, not
+ * only its A1 part). The handle has no device buffer afterwards: upload again
+ * before the next solve. The batched kernel does not take such a handle.
+ * Errors: EINVAL (NULL handle or rows, another configuration, a bad or repeated
+ * index, fewer than n rows left, more than 4096 removed A1 rows; the handle is
+ * unchanged), ENOMEM, BREAKDOWN (S~ or W not positive definite: the removal
+ * leaves the kept factorization without a usable preconditioner; destroy the
+ * handle). */
+rsilu_status_t rsilu_remove_rows(rsilu_handle_t h, int64_t count, const int64_t *rows);
+
 /* Setup statistics (Tables 2 and 3 report psize and nmod). */
 rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *stats);
 

@@ -258,6 +258,8 @@ class Factors:
     nmod: int
     smode: str
     S_chol: np.ndarray = field(default=None)  # lower Cholesky factor of S~ (dense mode)
+    R: "CSR" = None  # removed rows of A_hat that were in A1 (Section 3.4), or None
+    W_chol: np.ndarray = field(default=None)  # lower Cholesky factor of I - R M^{-1} R^T
     cg_steps: int = 2  # CG steps on S~ (cg mode)
     lev: dict = field(default_factory=dict)
 
@@ -340,7 +342,8 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
     A1) and each new row a, prescaled with the setup's column norms (a_hat = a D), becomes
     a row of A2 at the end of the row order with the L2 row l that solves (U)^T l^T =
     a_hat^T by forward substitution; entries with |l_j| < tau (or zero) are dropped, as in
-    the ILUP's dropping of L. Dense S~ is recomputed. Returns new Factors."""
+    the ILUP's dropping of L. Dense S~ is recomputed, and so is W after earlier removals.
+    Returns new Factors."""
     import dataclasses
 
     count = len(rowptr) - 1
@@ -368,6 +371,8 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
                             L2T=L2.transpose())
     if F.smode == "dense":
         _, G.S_chol = dense_S(F.L1, L2)
+    if F.R is not None:
+        G.W_chol = _woodbury_chol(G)
     return G
 
 
@@ -448,6 +453,8 @@ def apply_alg2(F, z):
     that A2 M_a^{-1} A2^T = Y~ Y~^T), and M_b is S~ (dense mode), I
     (identity mode) or absent (none mode: v_b = 0, h = u_a).
     """
+    if F.R is not None:
+        return _apply_removed(F, z)
     ua = _ma_solve(F, z)
     if F.smode == "none" or F.m == F.n:
         return ua
@@ -461,6 +468,74 @@ def apply_alg2(F, z):
     s = F.L2T.matvec(vb)
     wa = z - (F.UT.matvec(s) + F.Udiag * s)
     return _ma_solve(F, wa)
+
+
+def _woodbury_chol(G):
+    """Cholesky factor of W = I - R M^{-1} R^T with the kept operator M^{-1} of G."""
+    import dataclasses
+
+    base = dataclasses.replace(G, R=None, W_chol=None)
+    Rd = G.R.dense()
+    MRt = np.column_stack([apply_alg2(base, Rd[i]) for i in range(G.R.nrows)])
+    W = np.eye(G.R.nrows) - Rd @ MRt
+    return np.linalg.cholesky(0.5 * (W + W.T))
+
+
+def _apply_removed(F, z):
+    """Section 3.4, removing rows R (Woodbury): C1^{-1} = C^{-1} + C^{-1} R^T (I - R C^{-1} R^T)^{-1}
+    R C^{-1}, with C^{-1} the Algorithm 2 operator of the kept factorization."""
+    import dataclasses
+
+    base = dataclasses.replace(F, R=None, W_chol=None)
+    g = apply_alg2(base, z)
+    w = sla.cho_solve((F.W_chol, True), F.R.matvec(g))
+    return g + apply_alg2(base, F.R.transpose().matvec(w))
+
+
+def remove_rows(F, rows):
+    """Section 3.4, removing rows (original row indices, unique). The factorization is kept.
+    Removed rows of A2 leave L2 (S~ is refactored); removed rows of A1 (now absent from A_hat)
+    enter R, and the preconditioner becomes the Woodbury update of the Algorithm 2 operator
+    M^{-1} for C1 = C - R^T R: M^{-1} + M^{-1} R^T W^{-1} R M^{-1}, W = I - R M^{-1} R^T (with
+    the refactored S~ and every A1 row removed so far in R). Requires the dense S~ (the only
+    mode in which M approximates A^T A and not only its A1 part). The remaining rows are
+    renumbered in their order. Returns new Factors."""
+    import dataclasses
+
+    if F.smode != "dense":
+        raise ValueError("removing rows needs the dense S~")
+    rows = np.asarray(rows, dtype=np.int64)
+    if rows.size == 0 or np.unique(rows).size != rows.size or rows.min() < 0 or rows.max() >= F.m:
+        raise ValueError("bad row list")
+    if F.m - rows.size < F.n:
+        raise ValueError("fewer rows than columns would remain")
+    m, n = F.m, F.n
+    perm = F.perm.astype(np.int64)
+    pos = np.empty(m, dtype=np.int64)
+    pos[perm] = np.arange(m)
+    gone = np.zeros(m, dtype=bool)
+    gone[pos[rows]] = True  # by position
+    a1 = np.nonzero(gone[:n])[0]
+    keep2 = ~gone[n:]
+    Ahs = F.Ahat.scipy()
+    Rnew = csr_from_scipy(Ahs[a1])
+    R = Rnew if F.R is None else csr_from_scipy(sp.vstack([F.R.scipy(), Rnew.scipy()]).tocsr())
+    L2 = csr_from_scipy(F.L2.scipy()[np.nonzero(keep2)[0]])
+    renum = np.cumsum(~np.isin(np.arange(m), rows)) - 1  # new index of a kept original row
+    keep_pos = np.nonzero(~gone)[0]
+    kept_rows = np.setdiff1d(np.arange(m), rows)
+    G = dataclasses.replace(F, m=m - rows.size, perm=renum[perm[keep_pos]].astype(F.perm.dtype),
+                            A=csr_from_scipy(F.A.scipy()[kept_rows]), Ahat=csr_from_scipy(Ahs[keep_pos]),
+                            L2=L2, L2T=L2.transpose(), R=None, W_chol=None)
+    G.AhatT = G.Ahat.transpose()
+    if G.m > n:
+        _, G.S_chol = dense_S(G.L1, G.L2)
+    else:
+        G.S_chol = None
+    if R.nrows:
+        G.R = R
+        G.W_chol = _woodbury_chol(G)
+    return G
 
 
 def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):

@@ -611,6 +611,7 @@ rsilu_status_t check_handle(const Ctx &c)
     if (!c.dev) return RSILU_EINVAL;
     if (c.prm.krylov != RSILU_KRYLOV_LSQR || c.prm.form != RSILU_FORM_ALG2) return RSILU_EINVAL;
     if (c.m > c.n && c.smode != RSILU_S_NONE) return RSILU_EINVAL;
+    if (c.R.nrows > 0) return RSILU_EINVAL;  // removed rows change the preconditioner
     return RSILU_OK;
 }
 

@@ -255,7 +255,7 @@ void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const DTriT<T> 
 // Temporaries: g, c2 and s2 (free at this point in both forms).
 void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, const int32_t *done)
 {
-    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
+    const int32_t n = (int32_t)c.n, k = c.L2.nrows;
     double *w = at<double>(c, c.lay.cg_w), *res = at<double>(c, c.lay.cg_r), *p = at<double>(c, c.lay.cg_p),
            *q = at<double>(c, c.lay.cg_q);
     ProfScope ps(c, s, RSILU_PROF_DENSE_S);
@@ -285,7 +285,7 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
 template <class T>
 void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *r, T *hout, const int32_t *done)
 {
-    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
+    const int32_t n = (int32_t)c.n, k = c.L2.nrows;
     // step 1: u = r2 - Y r1 with Y r1 = L2 (L1^{-1} r1)
     trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, r, W.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
     if (k == 0 || c.smode == RSILU_S_NONE) {
@@ -319,7 +319,7 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
 
 // Whether Algorithm 2 carries the M_b correction (six triangular sweeps
 // instead of four).
-bool alg2_correction(const Ctx &c) { return c.m > c.n && c.smode != RSILU_S_NONE; }
+bool alg2_correction(const Ctx &c) { return c.L2.nrows > 0 && c.smode != RSILU_S_NONE; }
 
 // Sync-free outputs to sentinel-fill before one preconditioner application.
 void fill_targets(const Ctx &c, const Ptrs &P, double *hout, double *f[4])
@@ -341,7 +341,7 @@ void fill_targets(const Ctx &c, const Ptrs &P, double *hout, double *f[4])
 template <class T>
 void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *z, T *hout, const int32_t *done)
 {
-    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
+    const int32_t n = (int32_t)c.n, k = c.L2.nrows;
     trsv<T>(c, s, P, W, W.UTf, c.lvUT, c.swUT, c.lay.UTf, z, W.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_UT);
     trsv<T>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.t, W.gp, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_L1T);
     if (!alg2_correction(c)) {
@@ -396,10 +396,23 @@ void apply_form(Ctx &c, hipStream_t s, const Ptrs &P, double *hout, const int32_
         return;
     }
     const Pre<double> W = pre<double>(c);
-    if (a2)
+    if (a2) {
         apply_alg2<double>(c, s, P, W, P.z, hout, done);
-    else
+        if (c.R.nrows > 0) {
+            // removed rows (Section 3.4): h = g + M^{-1} R^T W^{-1} R g with g = M^{-1} z
+            const Layout &L = c.lay;
+            double *wr = at<double>(c, L.wr), *wz = at<double>(c, L.wz), *wh = at<double>(c, L.wh);
+            launch_spmv<double>(s, dcsr(c, L.R), dplan(c, L.pR), hout, wr, nullptr, EPI_PLAIN, FIN_NONE, P.partials,
+                                P.segpart, P.st, done);
+            launch_dense_chol_solve(s, c.R.nrows, at<double>(c, L.wfac), wr, done);
+            launch_spmv<double>(s, dcsr(c, L.RT), dplan(c, L.pRT), wr, wz, nullptr, EPI_PLAIN, FIN_NONE, P.partials,
+                                P.segpart, P.st, done);
+            apply_alg2<double>(c, s, P, W, wz, wh, done);
+            launch_add(s, (int32_t)c.n, wh, hout, done);
+        }
+    } else {
         apply_alg3<double>(c, s, P, W, P.r, hout, done);
+    }
 }
 
 template <class T>
@@ -601,7 +614,7 @@ rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *s)
     s->nnz_l1 = h->L1.nnz();
     s->nnz_l2 = h->L2.nnz();
     s->nnz_u = h->U.nnz();
-    const int64_t k = h->m - h->n;
+    const int64_t k = h->L2.nrows;
     s->psize = s->nnz_l1 + s->nnz_l2 + s->nnz_u + h->n + (h->smode == RSILU_S_DENSE ? k * (k + 1) / 2 : 0);
     s->nmod = h->nmod;
     s->levels_l1 = h->lvL1.nlev();
@@ -747,6 +760,13 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put(L.perm, c.perm.data(), c.perm.size() * sizeof(int32_t)));
     RSILU_HIP(put(L.colnorm, c.colnorm.data(), c.colnorm.size() * sizeof(double)));
     RSILU_HIP(put(L.sfac, c.sfac.data(), c.sfac.size() * sizeof(double)));
+    if (c.R.nrows > 0) {
+        RSILU_HIP(put_csr(L.R, c.R));
+        RSILU_HIP(put_csr(L.RT, c.RT));
+        RSILU_HIP(put_plan(L.pR, c.plR));
+        RSILU_HIP(put_plan(L.pRT, c.plRT));
+        RSILU_HIP(put(L.wfac, c.wfac.data(), c.wfac.size() * sizeof(double)));
+    }
     PinnedMail *mail = static_cast<PinnedMail *>(c.pinned);
     std::memset(&mail->init, 0, sizeof(DevState));
     RSILU_HIP(hipMemcpyAsync(at<DevState>(c, L.state), &mail->init, sizeof(DevState), hipMemcpyHostToDevice, s));
@@ -768,6 +788,23 @@ rsilu_status_t rsilu_add_rows(rsilu_handle_t h, int64_t count, const int64_t *ro
     }
     release_graph(c);  // the captured iterations hold the old layout's addresses
     c.dev = nullptr;   // the layout grew: upload again before the next solve
+    c.dev_bytes = 0;
+    return RSILU_OK;
+}
+
+rsilu_status_t rsilu_remove_rows(rsilu_handle_t h, int64_t count, const int64_t *rows)
+{
+    if (!h) return RSILU_EINVAL;
+    Ctx &c = *h;
+    try {
+        const rsilu_status_t rc = remove_rows(c, count, rows);
+        if (rc != RSILU_OK) return rc;
+        plan_layout(c);
+    } catch (const std::bad_alloc &) {
+        return RSILU_ENOMEM;
+    }
+    release_graph(c);  // the captured iterations hold the old layout's addresses
+    c.dev = nullptr;   // the layout changed: upload again before the next solve
     c.dev_bytes = 0;
     return RSILU_OK;
 }
@@ -875,7 +912,7 @@ rsilu_status_t rsilu_spmv(rsilu_handle_t h, int32_t op, const double *xin, doubl
     if (!xin || !y || static_cast<const void *>(xin) == static_cast<const void *>(y)) return RSILU_EINVAL;
     Ctx &c = *h;
     const Ptrs P = ptrs(c);
-    const int32_t n = (int32_t)c.n, k = (int32_t)(c.m - c.n);
+    const int32_t n = (int32_t)c.n, k = c.L2.nrows;
     switch (op) {
     case 0: launch_spmv<double>(s, P.A, P.pA, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
     case 1: launch_spmv<double>(s, P.AT, P.pAT, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;

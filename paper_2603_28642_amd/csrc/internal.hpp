@@ -106,6 +106,10 @@ struct Layout {
     DevPlanOff pA, pAT, pL2, pL2T;
     DevTriOff L1f, L1b, Ub, UTf;  // L1 forward, L1^T backward, U backward, U^T forward
     size_t perm = 0, colnorm = 0, sfac = 0;
+    // removed rows (present when R has rows): R, R^T, W's factor, and work vectors
+    DevCsrOff R, RT;
+    DevPlanOff pR, pRT;
+    size_t wfac = 0, wr = 0, wz = 0, wh = 0;
     // Krylov vectors
     size_t xh = 0, p = 0, z = 0, h = 0, t = 0, y = 0, v = 0, g = 0, gp = 0, s2 = 0, c2 = 0;  // n
     size_t r = 0, q = 0;                                                       // m
@@ -139,6 +143,11 @@ struct Ctx {
     LoTri loL1, loL1T, loU, loUT;
     SpmvPlan plA, plAT, plL2, plL2T;
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
+    // Section 3.4, removed rows: R = the removed rows of A_hat that were in A1, and the packed
+    // lower Cholesky factor of W = I - R M^{-1} R^T (Woodbury update of the preconditioner)
+    Csr R, RT;
+    SpmvPlan plR, plRT;
+    std::vector<double> wfac;
 
     Layout lay;
     // device side
@@ -171,6 +180,8 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
                                    const int32_t *colind, const double *val);
 void plan_layout(Ctx &c);
 rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const int32_t *colind, const double *val);
+rsilu_status_t remove_rows(Ctx &c, int64_t count, const int64_t *rows);
+rsilu_status_t build_woodbury(Ctx &c);
 // device driver (capi.hip): drop a captured iteration graph
 void release_graph(Ctx &c);
 

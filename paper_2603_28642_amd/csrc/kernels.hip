@@ -414,6 +414,13 @@ __global__ __launch_bounds__(kBlock) void k_copy(int32_t n, const double *__rest
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[i];
 }
 
+__global__ __launch_bounds__(kBlock) void k_add(int32_t n, const double *__restrict__ src, double *__restrict__ dst,
+                                                 const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = dst[i] + src[i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_lsqr_t(int32_t m, const double *__restrict__ u, double *__restrict__ t,
                                                    double *__restrict__ partials, const DevState *st,
                                                    const int32_t *done)
@@ -1084,6 +1091,11 @@ void launch_residual(hipStream_t s, int32_t m, const int32_t *perm, const double
 void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done)
 {
     hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, n, src, dst, done);
+}
+
+void launch_add(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(kBlock), 0, s, n, src, dst, done);
 }
 
 void launch_trsv_syncfree(hipStream_t s, const DTri &t, const double *rhs, double *x, const double *add,

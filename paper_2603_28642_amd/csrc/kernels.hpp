@@ -153,6 +153,8 @@ void launch_cvt(hipStream_t s, int32_t n, const float *in, double *out, const in
 // w = (L L^T)^{-1} u with L packed lower (k x k), in place on w (w = u on entry)
 void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, double *w, const int32_t *done);
 void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);
+// dst += src
+void launch_add(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);
 // CG on S~: res = p = u, w = 0; then w += alpha p, res -= alpha q; p = res + beta p
 void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double *res, double *p, const int32_t *done);
 void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,

@@ -474,8 +474,8 @@ double modified_pivot(int64_t j1, int64_t n, double colmax, double small)
 // packed lower factor by rows.
 rsilu_status_t build_dense_S(Ctx &c)
 {
-    const int64_t m = c.m, n = c.n;
-    const int64_t k = m - n;
+    const int64_t n = c.n;
+    const int64_t k = c.L2.nrows;  // rows of A2 (m - n, less the removed rows of A1)
     if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
     // Y^T = L1^{-T} L2^T, one column (row of Y) per row of L2
     std::vector<double> Y((size_t)(k * n), 0.0);  // row-major k x n
@@ -820,7 +820,7 @@ rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const i
     }
     if (c.A.nnz() + rowptr[count] > kMaxIdx) return RSILU_EINVAL;
     if (c.smode == RSILU_S_DENSE) {
-        const int64_t k = m0 + count - n;
+        const int64_t k = (int64_t)c.L2.nrows + count;
         if (k > 16384 || k * n > (int64_t)1 << 28) return RSILU_EINVAL;
     }
     const bool scale = c.prm.colscale != 0;
@@ -869,8 +869,216 @@ rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const i
     c.plAT = plan_spmv(c.AhatT);
     c.plL2 = plan_spmv(c.L2);
     c.plL2T = plan_spmv(c.L2T);
-    if (c.smode == RSILU_S_DENSE) return build_dense_S(c);
+    if (c.smode == RSILU_S_DENSE) {
+        const rsilu_status_t rc = build_dense_S(c);
+        if (rc != RSILU_OK) return rc;
+    }
+    // with removed A1 rows, W depends on the operator the new rows changed
+    if (c.R.nrows > 0) return build_woodbury(c);
     return RSILU_OK;
+}
+
+namespace {
+
+// x = T^{-1} b for a strictly triangular CSR T with an optional diagonal, rows
+// ascending (lower) or descending (upper); products summed in entry order.
+void host_trsv(const Csr &T, const double *diag, bool lower, const double *b, double *x)
+{
+    const int32_t n = T.nrows;
+    for (int32_t q = 0; q < n; ++q) {
+        const int32_t i = lower ? q : n - 1 - q;
+        double s = 0.0;
+        for (int32_t e = T.ptr[i]; e < T.ptr[(size_t)i + 1]; ++e) {
+            const double prod = T.val[e] * x[T.col[e]];
+            s = s + prod;
+        }
+        const double r = b[i] - s;
+        x[i] = diag ? r / diag[i] : r;
+    }
+}
+
+void host_spmv(const Csr &A, const double *x, double *y)
+{
+    for (int32_t i = 0; i < A.nrows; ++i) {
+        double s = 0.0;
+        for (int32_t e = A.ptr[i]; e < A.ptr[(size_t)i + 1]; ++e) s += A.val[e] * x[A.col[e]];
+        y[i] = s;
+    }
+}
+
+// w = (F F^T)^{-1} w for F packed lower by rows (k x k)
+void host_chol_solve(const std::vector<double> &F, int64_t k, double *w)
+{
+    auto at = [](int64_t i, int64_t j) { return (size_t)(i * (i + 1) / 2 + j); };
+    for (int64_t i = 0; i < k; ++i) {
+        double s = w[i];
+        for (int64_t j = 0; j < i; ++j) s -= F[at(i, j)] * w[j];
+        w[i] = s / F[at(i, i)];
+    }
+    for (int64_t i = k - 1; i >= 0; --i) {
+        double s = w[i];
+        for (int64_t j = i + 1; j < k; ++j) s -= F[at(j, i)] * w[j];
+        w[i] = s / F[at(i, i)];
+    }
+}
+
+// h = M^{-1} z of Algorithm 2 (k = n) with the dense S~ (or none when m = n), in the
+// factored form of the device path: g = L1^{-T} U^{-T} z, u = S~^{-1} L2 L1^{-1} g,
+// h = U^{-1} L1^{-1} (g - L1^{-T} L2^T u).
+void host_apply_alg2(const Ctx &c, const double *z, double *h)
+{
+    const int32_t n = (int32_t)c.n;
+    const int64_t k = c.L2.nrows;
+    std::vector<double> t((size_t)n), g((size_t)n), v((size_t)n);
+    host_trsv(c.UT, c.Udiag.data(), true, z, t.data());
+    host_trsv(c.L1T, nullptr, false, t.data(), g.data());
+    if (k > 0 && !c.sfac.empty()) {
+        host_trsv(c.L1, nullptr, true, g.data(), v.data());
+        std::vector<double> u((size_t)k), gq((size_t)n), c2((size_t)n);
+        host_spmv(c.L2, v.data(), u.data());
+        host_chol_solve(c.sfac, k, u.data());
+        host_spmv(c.L2T, u.data(), gq.data());
+        host_trsv(c.L1T, nullptr, false, gq.data(), c2.data());
+        for (int32_t i = 0; i < n; ++i) g[i] = g[i] - c2[i];
+    }
+    host_trsv(c.L1, nullptr, true, g.data(), v.data());
+    host_trsv(c.U, c.Udiag.data(), false, v.data(), h);
+}
+
+Csr rows_of(const Csr &A, const std::vector<int32_t> &keep)
+{
+    Csr o;
+    o.nrows = (int32_t)keep.size();
+    o.ncols = A.ncols;
+    o.ptr.assign(1, 0);
+    for (int32_t i : keep) {
+        for (int32_t e = A.ptr[i]; e < A.ptr[(size_t)i + 1]; ++e) {
+            o.col.push_back(A.col[e]);
+            o.val.push_back(A.val[e]);
+        }
+        o.ptr.push_back((int32_t)o.col.size());
+    }
+    return o;
+}
+
+}  // namespace
+
+// W = I - R M^{-1} R^T for the removed A1 rows R, with the current Algorithm 2
+// operator M^{-1} (host, FP64), and its packed lower Cholesky factor; also R^T
+// and the products' plans. BREAKDOWN if W is not positive definite.
+rsilu_status_t build_woodbury(Ctx &c)
+{
+    const int64_t n = c.n;
+    const int64_t r = c.R.nrows;
+    c.RT = transpose(c.R);
+    c.plR = plan_spmv(c.R);
+    c.plRT = plan_spmv(c.RT);
+    c.wfac.assign((size_t)(r * (r + 1) / 2), 0.0);
+    auto at = [](int64_t i, int64_t j) { return (size_t)(i * (i + 1) / 2 + j); };
+    {
+        std::vector<double> e((size_t)n), h((size_t)n), col((size_t)r);
+        std::vector<double> Wd((size_t)(r * r));
+        for (int64_t i = 0; i < r; ++i) {
+            std::fill(e.begin(), e.end(), 0.0);
+            for (int32_t q = c.R.ptr[i]; q < c.R.ptr[(size_t)i + 1]; ++q) e[c.R.col[q]] = c.R.val[q];
+            host_apply_alg2(c, e.data(), h.data());
+            host_spmv(c.R, h.data(), col.data());
+            for (int64_t j = 0; j < r; ++j) Wd[(size_t)(j * r + i)] = (i == j ? 1.0 : 0.0) - col[j];
+        }
+        for (int64_t i = 0; i < r; ++i)
+            for (int64_t j = 0; j <= i; ++j)
+                c.wfac[at(i, j)] = 0.5 * (Wd[(size_t)(i * r + j)] + Wd[(size_t)(j * r + i)]);
+    }
+    for (int64_t j = 0; j < r; ++j) {
+        double d = c.wfac[at(j, j)];
+        for (int64_t t = 0; t < j; ++t) d -= c.wfac[at(j, t)] * c.wfac[at(j, t)];
+        if (!(d > 0.0) || !std::isfinite(d)) return RSILU_BREAKDOWN;
+        d = std::sqrt(d);
+        c.wfac[at(j, j)] = d;
+        for (int64_t i = j + 1; i < r; ++i) {
+            double sum = c.wfac[at(i, j)];
+            for (int64_t t = 0; t < j; ++t) sum -= c.wfac[at(i, t)] * c.wfac[at(j, t)];
+            c.wfac[at(i, j)] = sum / d;
+        }
+    }
+    return RSILU_OK;
+}
+
+// Section 3.4, removing rows (original indices, renumbered afterwards in their
+// order): the factorization is kept. Removed rows of A2 leave L2 and S~ is
+// refactored; removed rows of A1 leave A_hat and join R, and the preconditioner
+// becomes M^{-1} + M^{-1} R^T W^{-1} R M^{-1}, W = I - R M^{-1} R^T, for every A1 row
+// removed so far (C1 = C - R^T R, Woodbury). Needs Algorithm 2, FP64 and the dense
+// S~ (the mode in which M approximates A^T A, not only its A1 part).
+rsilu_status_t remove_rows(Ctx &c, int64_t count, const int64_t *rows)
+{
+    const int64_t m = c.m, n = c.n;
+    if (c.prm.form != RSILU_FORM_ALG2 || c.prm.precision != RSILU_PREC_FP64 || c.smode != RSILU_S_DENSE ||
+        c.prm.trsv == RSILU_TRSV_SYNCFREE)
+        return RSILU_EINVAL;
+    if (count < 1 || !rows || m - count < n) return RSILU_EINVAL;
+    std::vector<int32_t> pos((size_t)m);
+    for (int64_t p = 0; p < m; ++p) pos[c.perm[p]] = (int32_t)p;
+    std::vector<char> gone_row((size_t)m, 0), gone_pos((size_t)m, 0);
+    for (int64_t i = 0; i < count; ++i) {
+        if (rows[i] < 0 || rows[i] >= m || gone_row[rows[i]]) return RSILU_EINVAL;
+        gone_row[rows[i]] = 1;
+        gone_pos[pos[rows[i]]] = 1;
+    }
+    const int64_t r_old = c.R.nrows;
+    int64_t r_new = r_old;
+    for (int64_t p = 0; p < n; ++p) r_new += gone_pos[p];
+    if (r_new > 4096) return RSILU_EINVAL;
+    // new numbering of the kept original rows
+    std::vector<int32_t> renum((size_t)m, -1);
+    std::vector<int32_t> kept_rows;
+    for (int64_t i = 0; i < m; ++i)
+        if (!gone_row[i]) {
+            renum[i] = (int32_t)kept_rows.size();
+            kept_rows.push_back((int32_t)i);
+        }
+    std::vector<int32_t> kept_pos, kept_l2, a1_gone;
+    for (int64_t p = 0; p < m; ++p) {
+        if (!gone_pos[p]) kept_pos.push_back((int32_t)p);
+        else if (p < n) a1_gone.push_back((int32_t)p);
+        if (p >= n && !gone_pos[p]) kept_l2.push_back((int32_t)(p - n));
+    }
+    // R grows by the removed A1 rows of A_hat (in position order)
+    {
+        Csr add = rows_of(c.Ahat, a1_gone);
+        if (c.R.nrows == 0) {
+            c.R = add;
+        } else {
+            for (int32_t i = 0; i < add.nrows; ++i) {
+                for (int32_t e = add.ptr[i]; e < add.ptr[(size_t)i + 1]; ++e) {
+                    c.R.col.push_back(add.col[e]);
+                    c.R.val.push_back(add.val[e]);
+                }
+                c.R.ptr.push_back((int32_t)c.R.col.size());
+                c.R.nrows++;
+            }
+        }
+    }
+    std::vector<int32_t> perm;
+    for (int32_t p : kept_pos) perm.push_back(renum[c.perm[p]]);
+    c.perm = perm;
+    c.A = rows_of(c.A, kept_rows);
+    c.Ahat = rows_of(c.Ahat, kept_pos);
+    c.L2 = rows_of(c.L2, kept_l2);
+    c.m = m - count;
+    c.nnz_a = c.A.nnz();
+    c.AhatT = transpose(c.Ahat);
+    c.L2T = transpose(c.L2);
+    c.plA = plan_spmv(c.Ahat);
+    c.plAT = plan_spmv(c.AhatT);
+    c.plL2 = plan_spmv(c.L2);
+    c.plL2T = plan_spmv(c.L2T);
+    c.sfac.clear();
+    if (c.L2.nrows > 0) {
+        const rsilu_status_t rc = build_dense_S(c);
+        if (rc != RSILU_OK) return rc;
+    }
+    return c.R.nrows > 0 ? build_woodbury(c) : RSILU_OK;
 }
 
 // ---------------------------------------------------------------- device layout
@@ -939,7 +1147,7 @@ void plan_layout(Ctx &c)
 {
     Bump b;
     Layout &L = c.lay;
-    const size_t m = (size_t)c.m, n = (size_t)c.n, k = (size_t)(c.m - c.n);
+    const size_t m = (size_t)c.m, n = (size_t)c.n, k = (size_t)c.L2.nrows;
     L.state = b.take(4096);
     L.A = place_csr(b, c.Ahat);
     L.AT = place_csr(b, c.AhatT);
@@ -957,6 +1165,16 @@ void plan_layout(Ctx &c)
     L.perm = b.take(sizeof(int32_t) * m);
     L.colnorm = b.take(sizeof(double) * n);
     L.sfac = b.take(sizeof(double) * c.sfac.size());
+    if (c.R.nrows > 0) {
+        L.R = place_csr(b, c.R);
+        L.RT = place_csr(b, c.RT);
+        L.pR = place_plan(b, c.plR);
+        L.pRT = place_plan(b, c.plRT);
+        L.wfac = b.take(sizeof(double) * c.wfac.size());
+        L.wr = b.take(sizeof(double) * (size_t)c.R.nrows);
+        L.wz = b.take(sizeof(double) * n);
+        L.wh = b.take(sizeof(double) * n);
+    }
     for (size_t *o : {&L.xh, &L.p, &L.z, &L.h, &L.t, &L.y, &L.v, &L.g, &L.gp, &L.s2, &L.c2})
         *o = b.take(sizeof(double) * n);
     L.r = b.take(sizeof(double) * m);
@@ -982,11 +1200,13 @@ void plan_layout(Ctx &c)
                                               blocks(c.AhatT.nrows, c.plAT.lanes), blocks(c.L2.nrows, c.plL2.lanes),
                                               blocks(c.L2T.nrows, c.plL2T.lanes)});
     const int64_t nlong = std::max<int64_t>({(int64_t)c.plA.long_rows.size(), (int64_t)c.plAT.long_rows.size(),
-                                             (int64_t)c.plL2.long_rows.size(), (int64_t)c.plL2T.long_rows.size()});
+                                             (int64_t)c.plL2.long_rows.size(), (int64_t)c.plL2T.long_rows.size(),
+                                             (int64_t)c.plR.long_rows.size(), (int64_t)c.plRT.long_rows.size()});
     L.npartials = (int32_t)(nparts + nlong + 64);
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);
     int32_t nseg = std::max({(int32_t)c.plA.seg_beg.size(), (int32_t)c.plAT.seg_beg.size(),
-                             (int32_t)c.plL2.seg_beg.size(), (int32_t)c.plL2T.seg_beg.size(), 1});
+                             (int32_t)c.plL2.seg_beg.size(), (int32_t)c.plL2T.seg_beg.size(),
+                             (int32_t)c.plR.seg_beg.size(), (int32_t)c.plRT.seg_beg.size(), 1});
     L.nsegpart = nseg;
     L.segpart = b.take(sizeof(double) * (size_t)nseg);
     L.total = (b.off + 255) & ~(size_t)255;

@@ -28,7 +28,8 @@ LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
 T_L1, T_L1T, T_U, T_UT = 0, 1, 2, 3
 
 EXPORTS = [
-    "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_add_rows", "rsilu_get_stats",
+    "rsilu_params_default", "rsilu_factor", "rsilu_device_bytes", "rsilu_upload", "rsilu_add_rows", "rsilu_remove_rows",
+    "rsilu_get_stats",
     "rsilu_get_perm", "rsilu_get_colnorm", "rsilu_factor_nnz", "rsilu_get_factor", "rsilu_get_levels",
     "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_apply_z", "rsilu_set_profiling",
     "rsilu_get_profile",
@@ -133,6 +134,8 @@ def lib():
         L.rsilu_upload.restype = ctypes.c_int
         L.rsilu_add_rows.argtypes = [P, I64, P, P, P]
         L.rsilu_add_rows.restype = ctypes.c_int
+        L.rsilu_remove_rows.argtypes = [P, I64, P]
+        L.rsilu_remove_rows.restype = ctypes.c_int
         L.rsilu_get_stats.argtypes = [P, ctypes.POINTER(rsilu_stats_t)]
         L.rsilu_get_stats.restype = ctypes.c_int
         L.rsilu_get_perm.argtypes = [P, P]
@@ -268,6 +271,12 @@ def rsilu_add_rows(h, rowptr, colind, val):
     ci, pci = _host(colind, np.int32)
     vv, pvv = _host(val, np.float64)
     return lib().rsilu_add_rows(h, len(rp) - 1, prp, pci, pvv)
+
+
+def rsilu_remove_rows(h, rows):
+    """Remove rows (current numbering) from the handle's A; the handle must be uploaded again."""
+    rr, prr = _host(rows, np.int64)
+    return lib().rsilu_remove_rows(h, len(rr), prr)
 
 
 def rsilu_get_stats(h):
@@ -406,6 +415,13 @@ class Solver:
         """Append rows (Section 3.4) and upload the grown layout to a new buffer."""
         _check(rsilu_add_rows(self.h, rowptr, colind, val), "rsilu_add_rows")
         self.m += len(rowptr) - 1
+        self.stats = rsilu_get_stats(self.h)
+        return self.upload(stream)
+
+    def remove_rows(self, rows, stream=None):
+        """Remove rows (Section 3.4) and upload the changed layout to a new buffer."""
+        _check(rsilu_remove_rows(self.h, rows), "rsilu_remove_rows")
+        self.m -= len(rows)
         self.stats = rsilu_get_stats(self.h)
         return self.upload(stream)
 

@@ -1,8 +1,10 @@
-"""Appending rows (Section 3.4) on the GPU: after rsilu_add_rows and a new upload, the
+"""Row updates (Section 3.4) on the GPU. Appending rows: after rsilu_add_rows and a new upload, the
 solve of the augmented problem follows the oracle's LSQR on the oracle's updated factors
 (four steps: x to 1e-8; whole solves: iterations within 2%, the true ||A^T r|| at 2 tol and
 the oracle's stop-test ball), in both preconditioner precisions and in the batched kernel;
-a solve between the update and the upload is refused."""
+a solve between the update and the upload is refused. Removing rows (the Woodbury update
+of the preconditioner, dense S~): four steps against the oracle's updated operator, whole
+solves like it, with LSQR and Algorithm 1; removal followed by appending."""
 
 import numpy as np
 import pytest
@@ -93,4 +95,72 @@ def test_solve_before_upload_is_refused(gpu_lib):
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     code, it, atr, rel = R.rsilu_solve(S.h, to_dev(b), 1e-8, x)
     assert code == R.ESTATE
+    S.close()
+
+
+def removal_case(seed=5, count=30):
+    p = gen.tiny_c1()
+    rows = np.sort(np.random.default_rng(seed).choice(p.m, count, replace=False))
+    keep = np.setdiff1d(np.arange(p.m), rows)
+    return p, rows, keep
+
+
+DENSE = dict(mu=1.0, form=1, smode=1)  # Algorithm 2 form with the dense S~
+
+
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_removal_four_steps_and_convergence(gpu_lib, krylov):
+    """Rows removed (Section 3.4, Woodbury update for the A1 rows): the reduced solve follows
+    the oracle on its updated operator for four steps and converges like it."""
+    R = gpu_lib
+    p, rows, keep = removal_case()
+    b = p.b[keep]
+    G = oracle.remove_rows(oracle.factor_problem(p, mu=1.0, smode="dense"), rows)
+    assert G.R is not None and G.R.nrows > 0
+    S = R.Solver.from_problem(p, maxit=4, krylov=krylov, **DENSE).upload()
+    S.remove_rows(rows)
+    x, code, it, atr, rel = S.solve(to_dev(b), tol=1e-14)
+    o = oracle.lsqr_m(G, b, tol=1e-14, maxit=4) if krylov else oracle.pcgls(G, b, tol=1e-14, maxit=4, form="alg2")
+    got = x.cpu().numpy()
+    assert it == o.iters == 4 and np.linalg.norm(got - o.x) <= 1e-8 * np.linalg.norm(o.x)
+    S.close()
+    A = p.scipy()[keep]
+    atb = np.linalg.norm(A.T @ b)
+    S = R.Solver.from_problem(p, maxit=2000, krylov=krylov, **DENSE).upload()
+    S.remove_rows(rows)
+    x, code, it, atr, rel = S.solve(to_dev(b), tol=1e-8)
+    got = x.cpu().numpy()
+    o = oracle.lsqr_m(G, b, tol=1e-8, maxit=2000) if krylov else oracle.pcgls(G, b, tol=1e-8, maxit=2000,
+                                                                               form="alg2")
+    assert code == R.OK and o.status == "ok"
+    assert abs(it - o.iters) <= max(1, int(0.02 * o.iters)), (it, o.iters)
+    assert np.linalg.norm(A.T @ (b - A @ got)) <= 2e-8 * atb
+    assert np.linalg.norm(A.T @ (A @ (got - o.x))) <= 4e-8 * atb
+    print("tiny - 30 rows (%d from A1), krylov %d: its %d (oracle %d)" % (G.R.nrows, krylov, it, o.iters))
+    # the batched kernel does not take the updated handle
+    bt = R.Batch(1)
+    import torch
+
+    xb = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    assert bt.solve_raw([S.h], [to_dev(b)], [1e-8], [xb])[0] == R.EINVAL
+    bt.close()
+    S.close()
+
+
+def test_removal_then_addition(gpu_lib):
+    """Rows removed, then rows appended: W is rebuilt for the new operator; the solve
+    follows the oracle's updated factors."""
+    R = gpu_lib
+    p, rows, keep = removal_case(seed=6, count=20)
+    q = gen.random_sparse(15, p.n, k=5, seed=82, transversal=False)
+    b = np.concatenate([p.b[keep], np.random.default_rng(83).standard_normal(15)])
+    G = oracle.remove_rows(oracle.factor_problem(p, mu=1.0, smode="dense"), rows)
+    G = oracle.add_rows(G, q.rowptr, q.col, q.val, tau=1e-2)
+    S = R.Solver.from_problem(p, maxit=4, krylov=1, **DENSE).upload()
+    S.remove_rows(rows)
+    S.add_rows(q.rowptr, q.col, q.val)
+    x, code, it, atr, rel = S.solve(to_dev(b), tol=1e-14)
+    o = oracle.lsqr_m(G, b, tol=1e-14, maxit=4)
+    assert it == o.iters == 4
+    assert np.linalg.norm(x.cpu().numpy() - o.x) <= 1e-8 * np.linalg.norm(o.x)
     S.close()

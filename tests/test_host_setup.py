@@ -349,3 +349,36 @@ def test_add_rows_rejects_bad_rows():
     assert st.m == st0.m and st.nnz_a == st0.nnz_a and R.rsilu_device_bytes(h) == st0.device_bytes
     assert R.lib().rsilu_add_rows(None, 1, None, None, None) == R.EINVAL
     R.rsilu_destroy(h)
+
+
+def test_remove_rows_bit_exact():
+    """rsilu_remove_rows against the oracle's remove_rows: row order, A_hat and every L2
+    entry bit-identical, R the removed A1 rows; other configurations are refused with the
+    handle unchanged."""
+    p = gen.tiny_c1()
+    rows = np.sort(np.random.default_rng(5).choice(p.m, 30, replace=False))
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_DENSE, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    assert R.rsilu_remove_rows(h, rows) == R.OK
+    F = oracle.remove_rows(oracle.factor_problem(p, mu=1.0, smode="dense"), rows)
+    st = R.rsilu_get_stats(h)
+    assert st.m == p.m - 30
+    assert np.array_equal(R.rsilu_get_perm(h, st.m), F.perm)
+    for which, C in [(R.L1, F.L1), (R.L2, F.L2), (R.U, F.U), (R.AHAT, F.Ahat)]:
+        rp, cc, vv = R.rsilu_get_factor(h, which, C.nrows)
+        assert np.array_equal(rp, C.rowptr) and np.array_equal(cc, C.col), which
+        assert np.array_equal(bits(vv), bits(C.val)), which
+    R.rsilu_destroy(h)
+    # refused: S^ none, bad indices (handle unchanged)
+    prm2 = R.rsilu_params_default(mu=1.0, smode=R.S_NONE, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR)
+    code, h2 = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm2)
+    assert R.rsilu_remove_rows(h2, np.array([1])) == R.EINVAL
+    R.rsilu_destroy(h2)
+    code, h3 = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    b0 = R.rsilu_device_bytes(h3)
+    for bad in ([3, 3], [-1], [p.m], list(range(p.m - p.n + 1))):
+        assert R.rsilu_remove_rows(h3, np.array(bad, dtype=np.int64)) == R.EINVAL, bad
+    assert R.rsilu_get_stats(h3).m == p.m and R.rsilu_device_bytes(h3) == b0
+    assert R.lib().rsilu_remove_rows(h3, 0, None) == R.EINVAL
+    R.rsilu_destroy(h3)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's row-append update (Section 3.4, adding rows).
+"""Pins of the oracle's row updates (Section 3.4, adding and removing rows).
 
 * With no dropping, every new L2 row l satisfies l U = a_hat (the definition: the kept
   factorization P A_hat ~ [L1; L2] U extended by the new rows).
@@ -9,6 +9,7 @@
 """
 
 import numpy as np
+import pytest
 
 import gen
 import oracle
@@ -62,3 +63,54 @@ def test_complete_factors_give_augmented_least_squares():
     x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
     assert res.status == "ok" and res.iters <= 2
     assert np.linalg.norm(res.x - x_ls) <= 1e-8 * np.linalg.norm(x_ls)
+
+
+# ---------------------------------------------------------------- removing rows
+
+
+def test_removal_complete_factors_gives_reduced_normal_matrix():
+    """Complete factors, dense S~: removing rows of A1 and A2 leaves the Woodbury-updated
+    operator equal to the inverse normal matrix of the reduced A_hat, and LSQR reaches the
+    reduced least-squares solution in one or two steps."""
+    p = gen.random_sparse(70, 45, k=4, seed=67, rhs="uniform")
+    F = oracle.factor_problem(p, p=INF, tau=0.0, mu=1.0, smode="dense")
+    pos = np.empty(p.m, dtype=np.int64)
+    pos[F.perm] = np.arange(p.m)
+    rows = np.array([2, 9, 17, 30, 44, 51, 63])
+    assert np.any(pos[rows] < p.n) and np.any(pos[rows] >= p.n)  # both blocks
+    G = oracle.remove_rows(F, rows)
+    keep = np.setdiff1d(np.arange(p.m), rows)
+    Ah = p.dense()[keep] / F.colnorm[None, :]
+    z = np.random.default_rng(3).standard_normal(45)
+    want = np.linalg.solve(Ah.T @ Ah, z)
+    assert np.allclose(oracle.apply_alg2(G, z), want, rtol=1e-8, atol=1e-8 * np.abs(want).max())
+    assert G.R is not None and G.R.nrows == int(np.sum(pos[rows] < p.n))
+    res = oracle.lsqr_m(G, p.b[keep], tol=1e-10, maxit=10)
+    x_ls = np.linalg.lstsq(p.dense()[keep], p.b[keep], rcond=None)[0]
+    assert res.status == "ok" and res.iters <= 2
+    assert np.linalg.norm(res.x - x_ls) <= 1e-8 * np.linalg.norm(x_ls)
+
+
+def test_removal_renumbers_and_keeps_factors():
+    p = gen.random_sparse(90, 50, k=4, seed=68)
+    F = oracle.factor_problem(p, mu=1.0, smode="dense")
+    rows = np.array([0, 5, 33, 89])
+    G = oracle.remove_rows(F, rows)
+    keep = np.setdiff1d(np.arange(p.m), rows)
+    assert G.m == p.m - 4 and sorted(G.perm.tolist()) == list(range(G.m))
+    # position order of the kept rows is unchanged; numbers are compacted
+    old = F.perm[np.isin(F.perm, keep)]
+    assert np.array_equal(keep[G.perm], old)
+    assert np.array_equal(G.L1.val, F.L1.val) and np.array_equal(G.U.val, F.U.val)
+    assert np.array_equal(G.A.dense(), p.dense()[keep])
+
+
+def test_removal_rejects():
+    p = gen.random_sparse(60, 40, k=4, seed=69)
+    F = oracle.factor_problem(p, mu=1.0, smode="none")
+    with pytest.raises(ValueError):
+        oracle.remove_rows(F, [1])  # needs the dense S~
+    Fd = oracle.factor_problem(p, mu=1.0, smode="dense")
+    for bad in ([], [3, 3], [-1], [60], list(range(21))):
+        with pytest.raises(ValueError):
+            oracle.remove_rows(Fd, bad)
