@@ -32,6 +32,7 @@ namespace {
 constexpr unsigned long long kSentinel = 0x7FF4DEADBEEF0001ull;
 constexpr unsigned long long kQuietNaN = 0x7FF8000000000000ull;
 constexpr int kSpinLimit = 1 << 20;
+constexpr int kSpmvRows = 2;  // rows per lane group of k_spmv_mr
 
 __device__ __forceinline__ bool stop_now(const int32_t *done) { return done != nullptr && *done != 0; }
 
@@ -247,6 +248,76 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh
     if constexpr (EPI == EPI_SQ || EPI == EPI_WSQ) {
         const double s = block_sum256(contrib, lds4);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// Two or more rows per lane group (RPT) for rows of up to 2G entries: the
+// row pointers of all of a thread's rows, then their first two entries per
+// lane (at clamped in-bounds positions, masked values), then the gathers are
+// all in flight before any is used, so a block spends one memory latency per
+// dependent step for RPT rows instead of one. Rows are interleaved across the
+// block so one load instruction covers consecutive rows; entries past 2G go
+// through a loop. The stop flag is read beside the first loads and masks the
+// stores (every load is in bounds either way). Rows longer than long_thresh
+// are left to the segment kernel, as in k_spmv. Needs nnz >= 1.
+template <int G, int RPT, int EPI, class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_mr(DCsrT<T> a, int32_t long_thresh, const T *__restrict__ x,
+                                                     T *__restrict__ y, const T *__restrict__ aux,
+                                                     double *__restrict__ partials, const int32_t *done)
+{
+    __shared__ double lds4[4];
+    const bool live = !stop_now(done);
+    constexpr int RPB = kBlock / G;
+    const int gl = threadIdx.x % G;
+    const int base = blockIdx.x * RPB * RPT + threadIdx.x / G;
+    int b[RPT], e[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rc = min(base + j * RPB, a.nrows - 1);
+        b[j] = a.ptr[rc];
+        e[j] = a.ptr[rc + 1];
+    }
+    int c[RPT][2];
+    T v[RPT][2];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = b[j] + gl + u * G;
+            const int kc = max(min(k, e[j] - 1), 0);
+            c[j][u] = a.col[kc];
+            const T vv = a.val[kc];
+            v[j][u] = k < e[j] ? vv : (T)0;
+        }
+    T xv[RPT][2];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) xv[j][u] = x[c[j][u]];
+    double contrib = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        T sum = v[j][0] * xv[j][0];
+        sum += v[j][1] * xv[j][1];
+        for (int k = b[j] + gl + 2 * G; k < e[j]; k += G) sum += a.val[k] * x[a.col[k]];
+        sum = group_sum<G>(sum);
+        const int row = base + j * RPB;
+        if (live && row < a.nrows && e[j] - b[j] <= long_thresh && gl == 0) {
+            T out = sum;
+            if (EPI == EPI_SUB) out = aux[row] - sum;
+            if (EPI == EPI_NEG) out = -sum;
+            if (EPI == EPI_ADD) out = aux[row] + sum;
+            y[row] = out;
+            if (EPI == EPI_SQ) contrib += out * out;
+            if (EPI == EPI_WSQ) {
+                const double t = aux[row] * out;
+                contrib += t * t;
+            }
+        }
+    }
+    if constexpr (EPI == EPI_SQ || EPI == EPI_WSQ) {
+        const double s = block_sum256(contrib, lds4);
+        if (threadIdx.x == 0 && live) partials[blockIdx.x] = s;
     }
 }
 
@@ -965,9 +1036,15 @@ void spmv_dispatch(hipStream_t s, int lanes, int blocks, const DCsrT<T> &a, int3
         hipLaunchKernelGGL((k_spmv<G, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done); \
         break;
     switch (lanes) {
+    case 4:
+        hipLaunchKernelGGL((k_spmv_mr<4, kSpmvRows, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux,
+                           partials, done);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_spmv_mr<8, kSpmvRows, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux,
+                           partials, done);
+        break;
         RSILU_SPMV_CASE(2)
-        RSILU_SPMV_CASE(4)
-        RSILU_SPMV_CASE(8)
         RSILU_SPMV_CASE(16)
         RSILU_SPMV_CASE(32)
         RSILU_SPMV_CASE(64)
@@ -993,7 +1070,9 @@ void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, 
 {
     if (a.nrows <= 0) return;
     const int lanes = pl.lanes;
-    const int blocks = (int)((a.nrows + (kBlock / lanes) - 1) / (kBlock / lanes));
+    // rows per block: 4 and 8 lanes per row take kSpmvRows rows per lane group
+    const int rpb = (kBlock / lanes) * (lanes == 4 || lanes == 8 ? kSpmvRows : 1);
+    const int blocks = (int)((a.nrows + rpb - 1) / rpb);
     constexpr bool fp64 = std::is_same<T, double>::value;
     switch (epi) {
     case EPI_PLAIN: spmv_dispatch<EPI_PLAIN, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;

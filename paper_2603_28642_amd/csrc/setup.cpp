@@ -415,11 +415,21 @@ int32_t lanes_for(double avg)
     return g;
 }
 
+// Lanes per row of a CSR product: 4 up to 8 entries per row on average and 8
+// up to 16 (two rows per lane group, both entries of a lane loaded at once),
+// else the power of two at or above the mean.
+int32_t spmv_lanes(double avg)
+{
+    if (avg <= 8.0) return 4;
+    if (avg <= 16.0) return 8;
+    return lanes_for(avg);
+}
+
 SpmvPlan plan_spmv(const Csr &a)
 {
     SpmvPlan pl;
     double avg = a.nrows ? (double)a.nnz() / (double)a.nrows : 1.0;
-    pl.lanes = lanes_for(avg);
+    pl.lanes = a.nnz() > 0 ? spmv_lanes(avg) : 2;  // the paired-row kernel needs an entry to clamp to
     pl.long_thresh = std::max<int32_t>(32 * pl.lanes, 2048);
     const int32_t seg = 4096;
     pl.seg_ptr.push_back(0);
