@@ -125,10 +125,11 @@ def iteration_bytes(st, form, smode, vb=8):
     return it
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, args):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE counter
     runs (profiles/traffic_<kernel>_<workload>.json, calibrated by a copy of known size),
-    or None when there is no record or the kernel's sources changed since it was taken."""
+    or None when there is no record, the record was taken with another solver
+    configuration than this run's, or the kernel's sources changed since it was taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
@@ -136,6 +137,9 @@ def measured_traffic(kernel, workload):
         return None
     with open(path) as f:
         rec = json.load(f)
+    cfg = rec.get("config")
+    if cfg is None or any(getattr(args, k) != v for k, v in cfg.items()):
+        return None
     h = hashlib.sha256()
     for fn in rec["sources"]:
         with open(os.path.join(ROOT, fn), "rb") as src:
@@ -304,7 +308,7 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK,
-            "traffic": measured_traffic(dom, args.workload),
+            "traffic": measured_traffic(dom, args.workload, args),
             "bytes_per_launch": kb,
             "avg_launch_us": avg_s * 1e6,
             "launches": launches,

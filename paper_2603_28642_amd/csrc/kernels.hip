@@ -735,7 +735,7 @@ __device__ __forceinline__ void load_chunk<float>(const unsigned char *vb, int c
     d = p.w;
 }
 
-template <class T>
+template <class T, int NR>
 __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned char *__restrict__ blob, int64_t off,
                                                                int32_t size, int32_t npos_first, int32_t p0,
                                                                int32_t nb, const T *__restrict__ rhs_lo, T *x,
@@ -844,6 +844,74 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             RSILU_LOAD_BATCH(noff, size_next >> 4, np0, npos_next)
             RSILU_LOAD_EXT(next_ext, nnext)
         }
+        if constexpr (NR > 0) {
+            // One phase per level: one row per thread. A thread loads its row's
+            // chunks NR at a time (all slot words, then all values, then all
+            // gathers, so each gather waits only for its own slot word), forms
+            // the chunk sums and adds them to the row sum in chunk order (the
+            // order of the two-phase scheme); one barrier per level publishes
+            // the results.
+            (void)lc_v;
+            (void)nent;
+            const uint32_t zz = (uint32_t)kSweepZeroSlot | ((uint32_t)kSweepZeroSlot << 16);
+            const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+            for (int L = 0; L < nlev; ++L) {
+                const int pa = __builtin_amdgcn_readlane(lo_v, L), pb = __builtin_amdgcn_readlane(lo_v, L + 1);
+                if (pa + wbase < pb) {  // the wavefront holds rows of this level
+                    const int p = pa + tid;
+                    const int pp = min(p, pb - 1);  // lanes past the level repeat its last row
+                    const int r0 = rchunk[pp], r1 = rchunk[pp + 1];
+                    const T rhs = rl[pp];
+                    const T dgv = hd ? dg[pp] : (T)1;
+                    const T add = al[pp];
+                    const int row = rowid[pp];
+                    T s = 0;
+                    for (int q = r0; q < r1; q += NR) {
+                        uint2 sl[NR];
+                        T v[NR][4];
+                        bool ok[NR];
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) {
+                            ok[j] = q + j < r1;
+                            sl[j] = eslot4[min(q + j, r1 - 1)];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int j = 0; j < NR; ++j)
+                            load_chunk<T>(evals, min(q + j, r1 - 1), v[j][0], v[j][1], v[j][2], v[j][3]);
+                        __builtin_amdgcn_sched_barrier(0);
+                        T g[NR][4];
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) {
+                            const uint2 t = ok[j] ? sl[j] : make_uint2(zz, zz);
+                            g[j][0] = xw[t.x & 0xffffu];
+                            g[j][1] = xw[t.x >> 16];
+                            g[j][2] = xw[t.y & 0xffffu];
+                            g[j][3] = xw[t.y >> 16];
+                        }
+                        T cs[NR];
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) {
+                            T t = v[j][0] * g[j][0];
+                            t += v[j][1] * g[j][1];
+                            t += v[j][2] * g[j][2];
+                            t += v[j][3] * g[j][3];
+                            cs[j] = ok[j] ? t : (T)0;
+                        }
+#pragma unroll
+                        for (int j = 0; j < NR; ++j) s += cs[j];
+                    }
+                    T r = rhs - s;
+                    if (hd) r = r * dgv;  // reciprocal of the diagonal, stored by the setup
+                    if (p < pb) {
+                        xw[cur + p] = r;
+                        x[row] = r;
+                        if (y2) y2[row] = add + r;
+                    }
+                }
+                __syncthreads();
+            }
+        } else {
         // Level loop: one chunk and one row per thread. Phase 1 forms the
         // chunk sums (four entries each, padded with the zero slot so the
         // loads are branch-free); phase 2 adds each row's chunk sums, solves
@@ -912,6 +980,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                 if (y2) y2[m.row] = m.add + r;
             }
             __syncthreads();
+        }
         }
         if (more) {
             RSILU_STORE_BATCH(size_next >> 4, npos_next)
@@ -1234,16 +1303,28 @@ template void launch_trsv_level<float>(hipStream_t, const DTriT<float> &, int32_
 
 template <class T>
 void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
-                       int32_t p0, int32_t nb, const T *rhs_lo, T *x, const T *add_lo, T *y2, const int32_t *done)
+                       int32_t p0, int32_t nb, int32_t rounds, const T *rhs_lo, T *x, const T *add_lo, T *y2,
+                       const int32_t *done)
 {
     if (nb <= 0) return;
-    hipLaunchKernelGGL(k_trsv_sweep<T>, dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0, nb,
-                       rhs_lo, x, add_lo, y2, done);
+    switch (rounds) {
+    case 2:
+        hipLaunchKernelGGL((k_trsv_sweep<T, 2>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
+                           nb, rhs_lo, x, add_lo, y2, done);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_trsv_sweep<T, 3>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
+                           nb, rhs_lo, x, add_lo, y2, done);
+        break;
+    default:
+        hipLaunchKernelGGL((k_trsv_sweep<T, 0>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
+                           nb, rhs_lo, x, add_lo, y2, done);
+    }
 }
 template void launch_trsv_sweep<double>(hipStream_t, const unsigned char *, int64_t, int32_t, int32_t, int32_t, int32_t,
-                                        const double *, double *, const double *, double *, const int32_t *);
+                                        int32_t, const double *, double *, const double *, double *, const int32_t *);
 template void launch_trsv_sweep<float>(hipStream_t, const unsigned char *, int64_t, int32_t, int32_t, int32_t, int32_t,
-                                       const float *, float *, const float *, float *, const int32_t *);
+                                       int32_t, const float *, float *, const float *, float *, const int32_t *);
 
 template <class T>
 void launch_gather_lo(hipStream_t s, int32_t n, const int32_t *rows, const T *src, T *dst, const T *src2, T *dst2,

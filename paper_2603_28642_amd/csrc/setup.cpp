@@ -215,6 +215,8 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     int64_t bpos = 0, bent = 0, bchk = 0;
     int32_t stamp = 0;
     std::vector<int64_t> batch_rows, batch_nnz;  // per serialized batch
+    // levels of the open run, and those whose longest row has at most 2 or 3 chunks
+    int64_t run_lev = 0, run_le2 = 0, run_le3 = 0;
 
     // older inputs of level l that a batch starting at position p0 would gather
     auto new_ext = [&](int32_t l, int32_t p0) {
@@ -328,6 +330,13 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             lev_chunk[lvl - l0] = ch;
         }
         rchunk[npos] = (uint16_t)ch;
+        for (int32_t l = l0; l < l1; ++l) {
+            int64_t mx = 0;
+            for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) mx = std::max(mx, chunks_of(rowlen(lv.rows[p])));
+            ++run_lev;
+            run_le2 += mx <= 2 ? 1 : 0;
+            run_le3 += mx <= 3 ? 1 : 0;
+        }
         // the previous batch of the run learns this batch's size and older inputs,
         // so they are gathered while the previous batch is being solved
         if (bi > 0) {
@@ -357,10 +366,15 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
                 rows += batch_rows[(size_t)bb];
                 nnz += batch_nnz[(size_t)bb];
             }
-            sw.segs.push_back({-1, run_b0, nbatches(), rows, nnz});
+            // one phase per level when nearly every level's rows fit one load round
+            // (measured on gfx950: it wins there and loses where long rows need
+            // several dependent rounds)
+            const int32_t rounds = run_le2 >= 0.95 * (double)run_lev ? 2 : run_le3 >= 0.95 * (double)run_lev ? 3 : 0;
+            sw.segs.push_back({-1, run_b0, nbatches(), rows, nnz, rounds});
         }
         run_b0 = -1;
         prev_p0 = prev_p1 = -1;
+        run_lev = run_le2 = run_le3 = 0;
     };
     auto fits = [&](int64_t nlev, int64_t npos, int64_t nent, int64_t next, int64_t nchk) {
         (void)nent;
@@ -372,7 +386,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         const int64_t ne = entries(l), nc = chunks(l);
         if (w > kSweepRows || nc > kSweepLevEnt) {
             close_run();
-            sw.segs.push_back({l, -1, -1, w, ne});
+            sw.segs.push_back({l, -1, -1, w, ne, 0});
             continue;
         }
         if (bl0 >= 0) {
@@ -394,7 +408,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         const int64_t e1 = new_ext(l, lv.ptr[l]);
         if (!fits(1, w, ne, e1, nc)) {
             close_run();
-            sw.segs.push_back({l, -1, -1, w, ne});
+            sw.segs.push_back({l, -1, -1, w, ne, 0});
             continue;
         }
         if (run_b0 < 0) run_b0 = nbatches();
