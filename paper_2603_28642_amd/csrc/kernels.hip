@@ -708,7 +708,9 @@ __global__ __launch_bounds__(kBlock) void k_trsv_level(DTriT<T> t, int32_t beg, 
 // lev_off[nlev+1], lev_chunk[nlev+1], rowid[npos], ext_idx[next],
 // next_ext[kSweepExt], uint16 rchunk[npos+1], cstart[nchunk+1], eslot[nent],
 // then (16-aligned) T eval[nent], rdiag[npos] (reciprocal diagonal; T = double, or float for the
-// FP32 preconditioner). A row's entries are cut into chunks of at most
+// FP32 preconditioner), and for the segmented scheme uint16 crow[nchunk] (the
+// position of the chunk's row in the batch, bit 15 set on the row's last chunk;
+// 0x7fff on padding chunks). A row's entries are cut into chunks of at most
 // kSweepChunk; eslot indexes the LDS window xw = [even batches' results | odd
 // batches' results | older inputs].
 template <class T>
@@ -733,6 +735,48 @@ __device__ __forceinline__ void load_chunk<float>(const unsigned char *vb, int c
     b = p.y;
     cc = p.z;
     d = p.w;
+}
+
+// Segmented inclusive sum over the 16-lane groups of a wavefront: lanes with
+// equal key form contiguous segments inside one group; after shifts of 1, 2, 4
+// and 8 lanes each lane holds the sum of its segment up to itself, so a
+// segment's last lane holds the segment's sum. Every lane must be active.
+template <int D>
+__device__ __forceinline__ double shr_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x110 + D, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + D, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int D>
+__device__ __forceinline__ float shr_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xf, 0xf, false));
+}
+template <int D>
+__device__ __forceinline__ int shr_key(int k)
+{
+    return __builtin_amdgcn_update_dpp(-1, k, 0x110 + D, 0xf, 0xf, false);
+}
+template <class T, int D>
+__device__ __forceinline__ T seg_step(T v, int key)
+{
+    T o;
+    if constexpr (std::is_same<T, double>::value)
+        o = shr_f64<D>(v);
+    else
+        o = shr_f32<D>(v);
+    return shr_key<D>(key) == key ? v + o : v;
+}
+template <class T>
+__device__ __forceinline__ T seg_scan16(T v, int key)
+{
+    v = seg_step<T, 1>(v, key);
+    v = seg_step<T, 2>(v, key);
+    v = seg_step<T, 4>(v, key);
+    v = seg_step<T, 8>(v, key);
+    return v;
 }
 
 template <class T, int NR>
@@ -844,7 +888,52 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             RSILU_LOAD_BATCH(noff, size_next >> 4, np0, npos_next)
             RSILU_LOAD_EXT(next_ext, nnext)
         }
-        if constexpr (NR > 0) {
+        if constexpr (NR == kSweepSegmented) {
+            // One phase per level, one chunk per thread: a row's chunks sit on
+            // consecutive lanes of one 16-lane group (the setup pads the level so),
+            // the chunk sums are combined by a segmented inclusive scan over DPP
+            // row shifts (1, 2, 4, 8), and the row's last lane solves the row.
+            (void)nent;
+            const uint32_t zzs = (uint32_t)kSweepZeroSlot | ((uint32_t)kSweepZeroSlot << 16);
+            const uint16_t *crow = reinterpret_cast<const uint16_t *>(sb + o_val + 4 * (int)sizeof(T) * nchunk +
+                                                                      (hd ? (int)sizeof(T) * npos : 0));
+            const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+            for (int L = 0; L < nlev; ++L) {
+                const int ca = __builtin_amdgcn_readlane(lc_v, L), cb = __builtin_amdgcn_readlane(lc_v, L + 1);
+                if (ca + wbase < cb) {  // the wavefront holds chunks of this level
+                    const int c = ca + tid;
+                    const bool has = c < cb;
+                    const int cc = min(c, cb - 1);
+                    const uint2 sl0 = eslot4[cc];
+                    T v0, v1, v2, v3;
+                    load_chunk<T>(evals, cc, v0, v1, v2, v3);
+                    const int cr = crow[cc];
+                    const int key = has ? (cr & 0x7fff) : 0xffff;
+                    const bool last = has && (cr & 0x8000) != 0;
+                    const int pp = min(cr & 0x7fff, npos - 1);
+                    const T rhs = rl[pp];
+                    const T dgv = hd ? dg[pp] : (T)1;
+                    const T add = al[pp];
+                    const int row = rowid[pp];
+                    const uint2 sl = has ? sl0 : make_uint2(zzs, zzs);
+                    T t = v0 * xw[sl.x & 0xffffu];
+                    t += v1 * xw[sl.x >> 16];
+                    t += v2 * xw[sl.y & 0xffffu];
+                    t += v3 * xw[sl.y >> 16];
+                    T v = has ? t : (T)0;
+                    v = seg_scan16<T>(v, key);
+                    if (last) {
+                        const int p = cr & 0x7fff;
+                        T r = rhs - v;
+                        if (hd) r = r * dgv;  // reciprocal of the diagonal, stored by the setup
+                        xw[cur + p] = r;
+                        x[row] = r;
+                        if (y2) y2[row] = add + r;
+                    }
+                }
+                __syncthreads();
+            }
+        } else if constexpr (NR > 0) {
             // One phase per level: one row per thread. A thread loads its row's
             // chunks NR at a time (all slot words, then all values, then all
             // gathers, so each gather waits only for its own slot word), forms
@@ -1308,12 +1397,12 @@ void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, in
 {
     if (nb <= 0) return;
     switch (rounds) {
+    case kSweepSegmented:
+        hipLaunchKernelGGL((k_trsv_sweep<T, kSweepSegmented>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size,
+                           npos_first, p0, nb, rhs_lo, x, add_lo, y2, done);
+        break;
     case 2:
         hipLaunchKernelGGL((k_trsv_sweep<T, 2>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
-                           nb, rhs_lo, x, add_lo, y2, done);
-        break;
-    case 3:
-        hipLaunchKernelGGL((k_trsv_sweep<T, 3>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
                            nb, rhs_lo, x, add_lo, y2, done);
         break;
     default:

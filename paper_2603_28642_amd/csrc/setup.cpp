@@ -117,9 +117,9 @@ Chunks make_chunks(const Levels &lv, int32_t cap)
 
 // Byte offsets inside a sweep batch blob (layout in kernels.hip, k_trsv_sweep).
 struct BlobLayout {
-    int64_t lev, lch, row, ext, next_ext, rch, slot, val, diag, size;
+    int64_t lev, lch, row, ext, next_ext, rch, slot, val, diag, crow, size;
 };
-BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag, int64_t vb)
+BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag, int64_t vb, bool seg)
 {
     BlobLayout o;
     o.lev = 4 * kSweepHdr;
@@ -131,12 +131,13 @@ BlobLayout blob_layout(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk,
     o.slot = (o.rch + 2 * (npos + 1) + 7) & ~(int64_t)7;
     o.val = (o.slot + 8 * nchunk + 15) & ~(int64_t)15;
     o.diag = o.val + 4 * vb * nchunk;
-    o.size = (o.diag + (diag ? vb * npos : 0) + 15) & ~(int64_t)15;
+    o.crow = o.diag + (diag ? vb * npos : 0);
+    o.size = (o.crow + (seg ? 2 * nchunk : 0) + 15) & ~(int64_t)15;
     return o;
 }
-int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag, int64_t vb)
+int64_t blob_bytes(int64_t nlev, int64_t npos, int64_t next, int64_t nchunk, bool diag, int64_t vb, bool seg)
 {
-    return blob_layout(nlev, npos, next, nchunk, diag, vb).size;
+    return blob_layout(nlev, npos, next, nchunk, diag, vb, seg).size;
 }
 
 template <class V>
@@ -182,7 +183,9 @@ int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
 // Runs of levels of at most kSweepRows rows are cut into batches; an input of a
 // row is read from LDS: from the results of the same batch, of the previous
 // batch of the run, or from the batch's gathered older inputs ("ext"). Rows
-// are cut into chunks of at most kSweepChunk entries (one thread each).
+// are cut into chunks of at most kSweepChunk entries. In the segmented scheme a
+// level's chunks are padded so no row's chunks cross a 16-chunk group, and a row
+// without entries gets one chunk of padding (its lane solves it).
 // V is the value type stored in the blob: double, or float for the FP32
 // preconditioner (values rounded to nearest).
 template <class V>
@@ -203,9 +206,41 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) ne += rowlen(lv.rows[p]);
         return ne;
     };
+    auto maxchunks = [&](int32_t l) {
+        int64_t mx = 0;
+        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) mx = std::max(mx, chunks_of(rowlen(lv.rows[p])));
+        return mx;
+    };
+    // Level scheme of the whole factor, from its narrow levels' longest rows (measured
+    // on gfx950): one phase with a row's chunks loaded two at a time when nearly every
+    // level's rows have at most 2 chunks; else, when nearly every level's rows have at
+    // most 16, a row's chunks on consecutive lanes of one 16-lane DPP row, summed by a
+    // segmented scan (kSweepSegmented; a level with a longer row becomes a wide level);
+    // else two phases per level (chunk sums, then row sums).
+    int32_t scheme;
+    {
+        int64_t nl = 0, le2 = 0, le16 = 0;
+        for (int32_t l = 0; l < lv.nlev(); ++l) {
+            if (lv.ptr[(size_t)l + 1] - lv.ptr[l] > kSweepRows) continue;
+            const int64_t mx = maxchunks(l);
+            ++nl;
+            le2 += mx <= 2 ? 1 : 0;
+            le16 += mx <= 16 ? 1 : 0;
+        }
+        scheme = le2 >= 0.95 * (double)nl ? 2 : le16 >= 0.95 * (double)nl ? kSweepSegmented : 0;
+    }
+    const bool seg = scheme == kSweepSegmented;
+    // chunks of a row in the blob: in the segmented scheme a row without entries still
+    // gets one (its lane solves it)
+    auto rchunks = [&](int32_t row) { return seg ? std::max<int64_t>(1, chunks_of(rowlen(row))) : chunks_of(rowlen(row)); };
+    // chunk count of level l, with the padding that keeps a row inside one 16-lane group
     auto chunks = [&](int32_t l) {
         int64_t nc = 0;
-        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) nc += chunks_of(rowlen(lv.rows[p]));
+        for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) {
+            const int64_t k = rchunks(lv.rows[p]);
+            if (seg && (nc % 16) + k > 16) nc += 16 - nc % 16;
+            nc += k;
+        }
         return nc;
     };
 
@@ -215,8 +250,6 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     int64_t bpos = 0, bent = 0, bchk = 0;
     int32_t stamp = 0;
     std::vector<int64_t> batch_rows, batch_nnz;  // per serialized batch
-    // levels of the open run, and those whose longest row has at most 2 or 3 chunks
-    int64_t run_lev = 0, run_le2 = 0, run_le3 = 0;
 
     // older inputs of level l that a batch starting at position p0 would gather
     auto new_ext = [&](int32_t l, int32_t p0) {
@@ -242,9 +275,9 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         ++stamp;
         std::vector<int32_t> ext;
         int64_t nent = 0, nchunk = 0;
+        for (int32_t l = l0; l < l1; ++l) nchunk += chunks(l);
         for (int32_t p = p0; p < p1; ++p) {
             const int32_t row = lv.rows[p];
-            nchunk += chunks_of(rowlen(row));
             for (int32_t e = T.ptr[row]; e < T.ptr[(size_t)row + 1]; ++e, ++nent) {
                 const int32_t c = T.col[e], pc = posof[c];
                 if (pc >= p0 || (pc >= prev_p0 && pc < prev_p1)) continue;
@@ -256,7 +289,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             }
         }
         const int64_t next = (int64_t)ext.size();
-        const BlobLayout lay = blob_layout(nlev, npos, next, nchunk, hd, vb);
+        const BlobLayout lay = blob_layout(nlev, npos, next, nchunk, hd, vb, seg);
         const int64_t size = lay.size;
         if (npos > kSweepPos || next > kSweepExt || size > kSweepBlob || nchunk > 65535 || nlev > kSweepLevels)
             throw std::length_error("sweep batch exceeds the LDS limits");
@@ -284,19 +317,42 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         uint16_t *eslot = reinterpret_cast<uint16_t *>(b + lay.slot);
         V *eval = reinterpret_cast<V *>(b + lay.val);
         V *dg = reinterpret_cast<V *>(b + lay.diag);
+        uint16_t *crow = reinterpret_cast<uint16_t *>(b + lay.crow);  // segmented scheme only
         for (int64_t j = 0; j < next; ++j) ext_idx[j] = ext[(size_t)j];
         int32_t ch = 0;
         int32_t lvl = l0;
         lev_off[0] = 0;
         lev_chunk[0] = 0;
+        auto pad_chunk = [&](uint16_t who) {
+            for (int32_t q = 0; q < kSweepChunk; ++q) {
+                eslot[(int64_t)kSweepChunk * ch + q] = (uint16_t)kSweepZeroSlot;
+                eval[(int64_t)kSweepChunk * ch + q] = (V)0;
+            }
+            crow[ch] = who;
+            ++ch;
+        };
+        int32_t lch0 = 0;  // first chunk of the current level
         for (int32_t p = p0; p < p1; ++p) {
             while (p >= lv.ptr[(size_t)lvl + 1]) {
                 ++lvl;
                 lev_off[lvl - l0] = p - p0;
                 lev_chunk[lvl - l0] = ch;
+                lch0 = ch;
             }
             const int32_t row = lv.rows[p];
             rowid[p - p0] = row;
+            if (seg) {
+                // keep the row's chunks inside one 16-lane group of the level
+                const int64_t k = rchunks(row), t = ch - lch0;
+                if ((t % 16) + k > 16)
+                    for (int64_t q = t % 16; q < 16; ++q) pad_chunk(0x7fff);
+                if (rowlen(row) == 0) {
+                    rchunk[p - p0] = (uint16_t)ch;
+                    pad_chunk((uint16_t)(0x8000 | (p - p0)));
+                    if (hd) dg[p - p0] = (V)(1.0 / (*diag)[row]);
+                    continue;
+                }
+            }
             rchunk[p - p0] = (uint16_t)ch;
             int32_t k = T.ptr[row];
             while (k < T.ptr[(size_t)row + 1]) {
@@ -320,6 +376,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
                         eval[e] = (V)0;
                     }
                 }
+                if (seg) crow[ch] = (uint16_t)((k == T.ptr[(size_t)row + 1] ? 0x8000 : 0) | (p - p0));
                 ++ch;
             }
             if (hd) dg[p - p0] = (V)(1.0 / (*diag)[row]);  // the sweep multiplies by the reciprocal
@@ -330,13 +387,6 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             lev_chunk[lvl - l0] = ch;
         }
         rchunk[npos] = (uint16_t)ch;
-        for (int32_t l = l0; l < l1; ++l) {
-            int64_t mx = 0;
-            for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) mx = std::max(mx, chunks_of(rowlen(lv.rows[p])));
-            ++run_lev;
-            run_le2 += mx <= 2 ? 1 : 0;
-            run_le3 += mx <= 3 ? 1 : 0;
-        }
         // the previous batch of the run learns this batch's size and older inputs,
         // so they are gathered while the previous batch is being solved
         if (bi > 0) {
@@ -366,25 +416,20 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
                 rows += batch_rows[(size_t)bb];
                 nnz += batch_nnz[(size_t)bb];
             }
-            // one phase per level when nearly every level's rows fit one load round
-            // (measured on gfx950: it wins there and loses where long rows need
-            // several dependent rounds)
-            const int32_t rounds = run_le2 >= 0.95 * (double)run_lev ? 2 : run_le3 >= 0.95 * (double)run_lev ? 3 : 0;
-            sw.segs.push_back({-1, run_b0, nbatches(), rows, nnz, rounds});
+            sw.segs.push_back({-1, run_b0, nbatches(), rows, nnz, scheme});
         }
         run_b0 = -1;
         prev_p0 = prev_p1 = -1;
-        run_lev = run_le2 = run_le3 = 0;
     };
     auto fits = [&](int64_t nlev, int64_t npos, int64_t nent, int64_t next, int64_t nchk) {
         (void)nent;
         return nlev <= kSweepLevels && npos <= kSweepPos && next <= kSweepExt &&
-               blob_bytes(nlev, npos, next, nchk, hd, vb) <= kSweepBlob;
+               blob_bytes(nlev, npos, next, nchk, hd, vb, seg) <= kSweepBlob;
     };
     for (int32_t l = 0; l < lv.nlev(); ++l) {
         const int64_t w = lv.ptr[(size_t)l + 1] - lv.ptr[l];
         const int64_t ne = entries(l), nc = chunks(l);
-        if (w > kSweepRows || nc > kSweepLevEnt) {
+        if (w > kSweepRows || nc > kSweepLevEnt || (seg && maxchunks(l) > 16)) {
             close_run();
             sw.segs.push_back({l, -1, -1, w, ne, 0});
             continue;

@@ -18,5 +18,6 @@ constexpr int kSweepZeroSlot = 2 * kSweepPos + kSweepExt;  // LDS slot that alwa
 constexpr int kSweepBlobRoom = 163840 - 1024 - (2 * kSweepPos + kSweepExt + 8 + 2 * kSweepPos + kSweepLevEnt) * 8;
 constexpr int kSweepBlob = kSweepBlobRoom < 5 * 16 * kSweepThreads ? (kSweepBlobRoom & ~15) : 5 * 16 * kSweepThreads;
 constexpr int kSweepHdr = 12;        // int32 header words of a batch blob
+constexpr int kSweepSegmented = 1;   // level scheme: a row's chunks on one 16-lane group, segmented sum
 
 }  // namespace rsilu
