@@ -769,13 +769,14 @@ __device__ __forceinline__ T seg_step(T v, int key)
         o = shr_f32<D>(v);
     return shr_key<D>(key) == key ? v + o : v;
 }
+// span: the longest segment in lanes (uniform); shifts at or beyond it add nothing
 template <class T>
-__device__ __forceinline__ T seg_scan16(T v, int key)
+__device__ __forceinline__ T seg_scan16(T v, int key, int span)
 {
-    v = seg_step<T, 1>(v, key);
-    v = seg_step<T, 2>(v, key);
-    v = seg_step<T, 4>(v, key);
-    v = seg_step<T, 8>(v, key);
+    if (span > 1) v = seg_step<T, 1>(v, key);
+    if (span > 2) v = seg_step<T, 2>(v, key);
+    if (span > 4) v = seg_step<T, 4>(v, key);
+    if (span > 8) v = seg_step<T, 8>(v, key);
     return v;
 }
 
@@ -899,7 +900,9 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                                                                       (hd ? (int)sizeof(T) * npos : 0));
             const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
             for (int L = 0; L < nlev; ++L) {
-                const int ca = __builtin_amdgcn_readlane(lc_v, L), cb = __builtin_amdgcn_readlane(lc_v, L + 1);
+                const int lc = __builtin_amdgcn_readlane(lc_v, L);
+                const int ca = lc & 0xffff, cb = __builtin_amdgcn_readlane(lc_v, L + 1) & 0xffff;
+                const int span = lc >> 16;  // the level's longest row in chunks (lanes)
                 if (ca + wbase < cb) {  // the wavefront holds chunks of this level
                     const int c = ca + tid;
                     const bool has = c < cb;
@@ -921,7 +924,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                     t += v2 * xw[sl.y & 0xffffu];
                     t += v3 * xw[sl.y >> 16];
                     T v = has ? t : (T)0;
-                    v = seg_scan16<T>(v, key);
+                    v = seg_scan16<T>(v, key, span);
                     if (last) {
                         const int p = cr & 0x7fff;
                         T r = rhs - v;

@@ -387,6 +387,10 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             lev_chunk[lvl - l0] = ch;
         }
         rchunk[npos] = (uint16_t)ch;
+        // segmented scheme: bits 16..23 of a level's chunk offset hold its longest row in
+        // chunks, which bounds the scan shifts the level needs
+        if (seg)
+            for (int32_t l = l0; l < l1; ++l) lev_chunk[l - l0] |= (int32_t)(std::min<int64_t>(maxchunks(l), 255) << 16);
         // the previous batch of the run learns this batch's size and older inputs,
         // so they are gathered while the previous batch is being solved
         if (bi > 0) {
