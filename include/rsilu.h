@@ -116,6 +116,22 @@ enum {
                                 swept by a single workgroup through LDS (default) */
 };
 
+/* Level scheme of the single-workgroup sweeps of the hybrid schedule. Every
+ * scheme solves each row as rhs minus the sum of its products, times the
+ * reciprocal diagonal; they differ in how the threads share the work and in
+ * the order of the row sums (chunk order, or a tree over lanes). */
+enum {
+    RSILU_SWEEP_AUTO = 0,      /* per factor, from its rows' lengths (default) */
+    RSILU_SWEEP_TWO_PHASE = 1, /* one 4-entry chunk and one row per thread; chunk sums
+                                  through LDS, two barriers per level */
+    RSILU_SWEEP_SEGMENTED = 2, /* one chunk per thread, a row's chunks on one 16-lane
+                                  group summed by a segmented scan, one barrier per
+                                  level (levels with a row of more than 16 chunks are
+                                  solved as wide levels) */
+    RSILU_SWEEP_ROWS = 3       /* one row per thread, its chunks loaded two at a time,
+                                  one barrier per level */
+};
+
 typedef struct {
     int32_t p;        /* ILUP: at most p entries kept per column of L~ and of U~
                          above the diagonal (Algorithm 4); default 10 */
@@ -135,6 +151,7 @@ typedef struct {
                           into a HIP graph (per upload) and replayed, one launch instead
                           of some 30 kernel launches per iteration; 0: launched one by
                           one. Profiling runs always launch one by one. Default 1. */
+    int32_t sweep;     /* RSILU_SWEEP_*; default RSILU_SWEEP_AUTO */
 } rsilu_params_t;
 
 typedef struct {
@@ -159,7 +176,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
- * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1. */
+ * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1, sweep = AUTO. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

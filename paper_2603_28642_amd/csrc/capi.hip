@@ -557,6 +557,7 @@ void rsilu_params_default(rsilu_params_t *p)
     p->cg_steps = 2;
     p->krylov = RSILU_KRYLOV_PCGLS;
     p->graph = 1;
+    p->sweep = RSILU_SWEEP_AUTO;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)

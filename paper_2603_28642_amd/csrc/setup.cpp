@@ -189,7 +189,7 @@ int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
 // V is the value type stored in the blob: double, or float for the FP32
 // preconditioner (values rounded to nearest).
 template <class V>
-Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv)
+Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv, int32_t force)
 {
     constexpr int64_t vb = (int64_t)sizeof(V);
     Sweep sw;
@@ -228,6 +228,9 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             le16 += mx <= 16 ? 1 : 0;
         }
         scheme = le2 >= 0.95 * (double)nl ? 2 : le16 >= 0.95 * (double)nl ? kSweepSegmented : 0;
+        if (force == RSILU_SWEEP_TWO_PHASE) scheme = 0;
+        if (force == RSILU_SWEEP_SEGMENTED) scheme = kSweepSegmented;
+        if (force == RSILU_SWEEP_ROWS) scheme = 2;
     }
     const bool seg = scheme == kSweepSegmented;
     // chunks of a row in the blob: in the segmented scheme a row without entries still
@@ -599,6 +602,7 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
          P.smode != RSILU_S_NONE && P.smode != RSILU_S_CG) ||
         (P.krylov != RSILU_KRYLOV_PCGLS && P.krylov != RSILU_KRYLOV_LSQR) || (P.graph != 0 && P.graph != 1) ||
+        P.sweep < RSILU_SWEEP_AUTO || P.sweep > RSILU_SWEEP_ROWS ||
         (P.krylov == RSILU_KRYLOV_LSQR &&
          (P.form != RSILU_FORM_ALG2 || P.trsv == RSILU_TRSV_SYNCFREE ||
           (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_NONE && P.smode != RSILU_S_DENSE))) ||
@@ -839,12 +843,13 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.chL1T = make_chunks(c.lvL1T, 64 / tri_lanes(c.L1T));
     c.chU = make_chunks(c.lvU, 64 / tri_lanes(c.U));
     const bool f32 = P.precision == RSILU_PREC_FP32;
-    c.swL1 = f32 ? make_sweep<float>(c.L1, nullptr, c.lvL1) : make_sweep<double>(c.L1, nullptr, c.lvL1);
-    c.swL1T = f32 ? make_sweep<float>(c.L1T, nullptr, c.lvL1T) : make_sweep<double>(c.L1T, nullptr, c.lvL1T);
-    c.swU = f32 ? make_sweep<float>(c.U, &c.Udiag, c.lvU) : make_sweep<double>(c.U, &c.Udiag, c.lvU);
+    const int32_t sw = P.sweep;
+    c.swL1 = f32 ? make_sweep<float>(c.L1, nullptr, c.lvL1, sw) : make_sweep<double>(c.L1, nullptr, c.lvL1, sw);
+    c.swL1T = f32 ? make_sweep<float>(c.L1T, nullptr, c.lvL1T, sw) : make_sweep<double>(c.L1T, nullptr, c.lvL1T, sw);
+    c.swU = f32 ? make_sweep<float>(c.U, &c.Udiag, c.lvU, sw) : make_sweep<double>(c.U, &c.Udiag, c.lvU, sw);
     // U^T (forward, Udiag on the diagonal) for Algorithm 2's M_a = (L1 U)^T (L1 U)
     c.chUT = make_chunks(c.lvUT, 64 / tri_lanes(c.UT));
-    c.swUT = f32 ? make_sweep<float>(c.UT, &c.Udiag, c.lvUT) : make_sweep<double>(c.UT, &c.Udiag, c.lvUT);
+    c.swUT = f32 ? make_sweep<float>(c.UT, &c.Udiag, c.lvUT, sw) : make_sweep<double>(c.UT, &c.Udiag, c.lvUT, sw);
 
     auto lo = [&](const Csr &T, const std::vector<double> *diag, const Levels &lv) {
         return f32 ? level_ordered<float>(T, diag, lv) : level_ordered<double>(T, diag, lv);

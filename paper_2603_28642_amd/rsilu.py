@@ -21,6 +21,7 @@ FORM_ALG3, FORM_ALG2 = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 KRYLOV_PCGLS, KRYLOV_LSQR = 0, 1
 TRSV_SYNCFREE, TRSV_LEVELS, TRSV_HYBRID = 0, 1, 2
+SWEEP_AUTO, SWEEP_TWO_PHASE, SWEEP_SEGMENTED, SWEEP_ROWS = 0, 1, 2, 3
 # factor / level selectors
 L1, L2, U, AHAT, UDIAG = 0, 1, 2, 3, 4
 LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
@@ -50,7 +51,7 @@ class rsilu_params_t(ctypes.Structure):
                 ("small", ctypes.c_double), ("colscale", ctypes.c_int32), ("smode", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
-                ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32), ("sweep", ctypes.c_int32)]
 
 
 class rsilu_stats_t(ctypes.Structure):

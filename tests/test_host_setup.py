@@ -110,7 +110,8 @@ def test_explicit_zeros_are_stripped():
 @pytest.mark.parametrize("case", ["m<n", "bad col", "unsorted", "duplicate", "nan", "inf", "bad ptr", "bad mu",
                                   "bad tau", "bad small", "bad form", "bad smode", "bad precision",
                                   "fp32 syncfree", "fp32 dense", "cg fp32", "cg syncfree", "cg steps",
-                                  "lsqr alg3", "lsqr identity", "lsqr syncfree", "bad krylov"])
+                                  "lsqr alg3", "lsqr identity", "lsqr syncfree", "bad krylov", "bad sweep",
+                                  "negative sweep"])
 def test_invalid_input(case):
     m, n, rp, c, v = dense_problem(np.array([[1.0, 2.0], [3.0, 0.0], [0.0, 4.0]]))
     prm = R.rsilu_params_default()
@@ -173,6 +174,10 @@ def test_invalid_input(case):
             prm.trsv = R.TRSV_SYNCFREE
         elif case == "bad krylov":
             prm.krylov = 2
+        elif case == "bad sweep":
+            prm.sweep = 4
+        elif case == "negative sweep":
+            prm.sweep = -1
         code, h = R.rsilu_factor(m, n, rp, c, v, prm)
     assert code == R.EINVAL and h is None
 
@@ -382,3 +387,25 @@ def test_remove_rows_bit_exact():
     assert R.rsilu_get_stats(h3).m == p.m and R.rsilu_device_bytes(h3) == b0
     assert R.lib().rsilu_remove_rows(h3, 0, None) == R.EINVAL
     R.rsilu_destroy(h3)
+
+
+@pytest.mark.parametrize("sweep", [0, 1, 2, 3])
+def test_every_sweep_scheme_sets_up(sweep):
+    """Every level scheme of the sweeps builds, and leaves the factors and level
+    schedules as they are (the scheme only changes the sweep blobs)."""
+    import gen
+
+    p = gen.random_sparse(900, 600, k=40, seed=5)
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_IDENTITY, p=60, tau=0.0, sweep=sweep)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    ref_prm = R.rsilu_params_default(mu=1.0, smode=R.S_IDENTITY, p=60, tau=0.0)
+    code, h0 = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, ref_prm)
+    assert code == R.OK
+    for which in (R.L1, R.U):
+        a, b = R.rsilu_get_factor(h, which, p.n), R.rsilu_get_factor(h0, which, p.n)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    st, st0 = R.rsilu_get_stats(h), R.rsilu_get_stats(h0)
+    assert (st.levels_l1, st.levels_u) == (st0.levels_l1, st0.levels_u)
+    R.rsilu_destroy(h)
+    R.rsilu_destroy(h0)
