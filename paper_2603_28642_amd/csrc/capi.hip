@@ -237,7 +237,7 @@ void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const DTriT<T> 
                 const int32_t size = (int32_t)(sw.batch_off[(size_t)g.b0 + 1] - off);
                 const int32_t *h0 = reinterpret_cast<const int32_t *>(sw.blob.data() + off);
                 ProfScope pk(c, s, RSILU_PROF_K_SWEEP, bytes(g.rows, g.nnz));
-                launch_trsv_sweep<T>(s, blob, off, size, h0[1], h0[6], g.b1 - g.b0, g.rounds, W.lo_rhs, x, W.lo_add, y2,
+                launch_trsv_sweep<T>(s, blob, off, size, h0[1], h0[6], g.b1 - g.b0, g.scheme, W.lo_rhs, x, W.lo_add, y2,
                                      done);
             }
         }

@@ -44,10 +44,7 @@ struct Sweep {
         int32_t wide_level;  // >= 0: one multi-CU launch for this level
         int32_t b0, b1;      // otherwise: batches [b0, b1) in one single-workgroup launch
         int64_t rows, nnz;   // rows solved and stored entries read by the launch
-        int32_t rounds;      // single-workgroup launch, level scheme: 0 = two phases per level
-                             // (chunk sums, then row sums); kSweepSegmented = one phase, a
-                             // row's chunks on one 16-lane group summed by a segmented scan;
-                             // 2 = one phase, a row's chunks loaded two at a time
+        int32_t scheme;      // single-workgroup launch: its level scheme (kScheme*)
     };
     std::vector<Seg> segs;
     std::vector<int64_t> batch_off;  // nbatches + 1 byte offsets into blob

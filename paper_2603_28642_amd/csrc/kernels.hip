@@ -780,7 +780,7 @@ __device__ __forceinline__ T seg_scan16(T v, int key, int span)
     return v;
 }
 
-template <class T, int NR>
+template <class T, int SCHEME>
 __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned char *__restrict__ blob, int64_t off,
                                                                int32_t size, int32_t npos_first, int32_t p0,
                                                                int32_t nb, const T *__restrict__ rhs_lo, T *x,
@@ -889,7 +889,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             RSILU_LOAD_BATCH(noff, size_next >> 4, np0, npos_next)
             RSILU_LOAD_EXT(next_ext, nnext)
         }
-        if constexpr (NR == kSweepSegmented) {
+        if constexpr (SCHEME == kSchemeSegmented) {
             // One phase per level, one chunk per thread: a row's chunks sit on
             // consecutive lanes of one 16-lane group (the setup pads the level so),
             // the chunk sums are combined by a segmented inclusive scan over DPP
@@ -936,7 +936,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                 }
                 __syncthreads();
             }
-        } else if constexpr (NR > 0) {
+        } else if constexpr (SCHEME == kSchemeRows) {
+            constexpr int NR = kRowsRound;
             // One phase per level: one row per thread. A thread loads its row's
             // chunks NR at a time (all slot words, then all values, then all
             // gathers, so each gather waits only for its own slot word), forms
@@ -1395,21 +1396,21 @@ template void launch_trsv_level<float>(hipStream_t, const DTriT<float> &, int32_
 
 template <class T>
 void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
-                       int32_t p0, int32_t nb, int32_t rounds, const T *rhs_lo, T *x, const T *add_lo, T *y2,
+                       int32_t p0, int32_t nb, int32_t scheme, const T *rhs_lo, T *x, const T *add_lo, T *y2,
                        const int32_t *done)
 {
     if (nb <= 0) return;
-    switch (rounds) {
-    case kSweepSegmented:
-        hipLaunchKernelGGL((k_trsv_sweep<T, kSweepSegmented>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size,
+    switch (scheme) {
+    case kSchemeSegmented:
+        hipLaunchKernelGGL((k_trsv_sweep<T, kSchemeSegmented>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size,
                            npos_first, p0, nb, rhs_lo, x, add_lo, y2, done);
         break;
-    case 2:
-        hipLaunchKernelGGL((k_trsv_sweep<T, 2>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
+    case kSchemeRows:
+        hipLaunchKernelGGL((k_trsv_sweep<T, kSchemeRows>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
                            nb, rhs_lo, x, add_lo, y2, done);
         break;
     default:
-        hipLaunchKernelGGL((k_trsv_sweep<T, 0>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
+        hipLaunchKernelGGL((k_trsv_sweep<T, kSchemeTwoPhase>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size, npos_first, p0,
                            nb, rhs_lo, x, add_lo, y2, done);
     }
 }

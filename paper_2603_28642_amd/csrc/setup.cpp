@@ -215,7 +215,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     // on gfx950): one phase with a row's chunks loaded two at a time when nearly every
     // level's rows have at most 2 chunks; else, when nearly every level's rows have at
     // most 16, a row's chunks on consecutive lanes of one 16-lane DPP row, summed by a
-    // segmented scan (kSweepSegmented; a level with a longer row becomes a wide level);
+    // segmented scan (kSchemeSegmented; a level with a longer row becomes a wide level);
     // else two phases per level (chunk sums, then row sums).
     int32_t scheme;
     {
@@ -227,12 +227,12 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             le2 += mx <= 2 ? 1 : 0;
             le16 += mx <= 16 ? 1 : 0;
         }
-        scheme = le2 >= 0.95 * (double)nl ? 2 : le16 >= 0.95 * (double)nl ? kSweepSegmented : 0;
-        if (force == RSILU_SWEEP_TWO_PHASE) scheme = 0;
-        if (force == RSILU_SWEEP_SEGMENTED) scheme = kSweepSegmented;
-        if (force == RSILU_SWEEP_ROWS) scheme = 2;
+        scheme = le2 >= 0.95 * (double)nl ? kSchemeRows : le16 >= 0.95 * (double)nl ? kSchemeSegmented : kSchemeTwoPhase;
+        if (force == RSILU_SWEEP_TWO_PHASE) scheme = kSchemeTwoPhase;
+        if (force == RSILU_SWEEP_SEGMENTED) scheme = kSchemeSegmented;
+        if (force == RSILU_SWEEP_ROWS) scheme = kSchemeRows;
     }
-    const bool seg = scheme == kSweepSegmented;
+    const bool seg = scheme == kSchemeSegmented;
     // chunks of a row in the blob: in the segmented scheme a row without entries still
     // gets one (its lane solves it)
     auto rchunks = [&](int32_t row) { return seg ? std::max<int64_t>(1, chunks_of(rowlen(row))) : chunks_of(rowlen(row)); };

@@ -18,6 +18,10 @@ constexpr int kSweepZeroSlot = 2 * kSweepPos + kSweepExt;  // LDS slot that alwa
 constexpr int kSweepBlobRoom = 163840 - 1024 - (2 * kSweepPos + kSweepExt + 8 + 2 * kSweepPos + kSweepLevEnt) * 8;
 constexpr int kSweepBlob = kSweepBlobRoom < 5 * 16 * kSweepThreads ? (kSweepBlobRoom & ~15) : 5 * 16 * kSweepThreads;
 constexpr int kSweepHdr = 12;        // int32 header words of a batch blob
-constexpr int kSweepSegmented = 1;   // level scheme: a row's chunks on one 16-lane group, segmented sum
+// Level schemes of the single-workgroup sweep (one kernel instantiation each).
+constexpr int kSchemeTwoPhase = 0;   // one chunk and one row per thread; chunk sums through LDS, two barriers
+constexpr int kSchemeSegmented = 1;  // one chunk per thread, a row on one 16-lane group, segmented scan
+constexpr int kSchemeRows = 2;       // one row per thread, its chunks loaded kRowsRound at a time
+constexpr int kRowsRound = 2;
 
 }  // namespace rsilu
