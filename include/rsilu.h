@@ -121,7 +121,9 @@ enum {
  * reciprocal diagonal; they differ in how the threads share the work and in
  * the order of the row sums (chunk order, or a tree over lanes). */
 enum {
-    RSILU_SWEEP_AUTO = 0,      /* per factor, from its rows' lengths (default) */
+    RSILU_SWEEP_AUTO = 0,      /* per factor, from its rows' lengths: SEGMENTED when
+                                  nearly every level's rows have at most 16 chunks,
+                                  else TWO_PHASE (default) */
     RSILU_SWEEP_TWO_PHASE = 1, /* one 4-entry chunk and one row per thread; chunk sums
                                   through LDS, two barriers per level */
     RSILU_SWEEP_SEGMENTED = 2, /* one chunk per thread, a row's chunks on one 16-lane

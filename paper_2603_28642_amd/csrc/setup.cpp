@@ -212,22 +212,20 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         return mx;
     };
     // Level scheme of the whole factor, from its narrow levels' longest rows (measured
-    // on gfx950): one phase with a row's chunks loaded two at a time when nearly every
-    // level's rows have at most 2 chunks; else, when nearly every level's rows have at
-    // most 16, a row's chunks on consecutive lanes of one 16-lane DPP row, summed by a
-    // segmented scan (kSchemeSegmented; a level with a longer row becomes a wide level);
-    // else two phases per level (chunk sums, then row sums).
+    // on gfx950): when nearly every level's rows have at most 16 chunks, a row's chunks
+    // on consecutive lanes of one 16-lane DPP row, summed by a segmented scan
+    // (kSchemeSegmented; a level with a longer row becomes a wide level); else two
+    // phases per level (chunk sums, then row sums). The one-row-per-thread scheme is
+    // selected only on request.
     int32_t scheme;
     {
-        int64_t nl = 0, le2 = 0, le16 = 0;
+        int64_t nl = 0, le16 = 0;
         for (int32_t l = 0; l < lv.nlev(); ++l) {
             if (lv.ptr[(size_t)l + 1] - lv.ptr[l] > kSweepRows) continue;
-            const int64_t mx = maxchunks(l);
             ++nl;
-            le2 += mx <= 2 ? 1 : 0;
-            le16 += mx <= 16 ? 1 : 0;
+            le16 += maxchunks(l) <= 16 ? 1 : 0;
         }
-        scheme = le2 >= 0.95 * (double)nl ? kSchemeRows : le16 >= 0.95 * (double)nl ? kSchemeSegmented : kSchemeTwoPhase;
+        scheme = le16 >= 0.95 * (double)nl ? kSchemeSegmented : kSchemeTwoPhase;
         if (force == RSILU_SWEEP_TWO_PHASE) scheme = kSchemeTwoPhase;
         if (force == RSILU_SWEEP_SEGMENTED) scheme = kSchemeSegmented;
         if (force == RSILU_SWEEP_ROWS) scheme = kSchemeRows;
