@@ -122,14 +122,15 @@ enum {
  * the order of the row sums (chunk order, or a tree over lanes). */
 enum {
     RSILU_SWEEP_AUTO = 0,      /* per factor, from its rows' lengths: SEGMENTED when
-                                  nearly every level's rows have at most 16 chunks,
+                                  nearly every level's rows have at most 64 chunks,
                                   else TWO_PHASE (default) */
     RSILU_SWEEP_TWO_PHASE = 1, /* one 4-entry chunk and one row per thread; chunk sums
                                   through LDS, two barriers per level */
-    RSILU_SWEEP_SEGMENTED = 2, /* one chunk per thread, a row's chunks on one 16-lane
-                                  group summed by a segmented scan, one barrier per
-                                  level (levels with a row of more than 16 chunks are
-                                  solved as wide levels) */
+    RSILU_SWEEP_SEGMENTED = 2, /* one chunk per thread, a row's chunks on consecutive
+                                  lanes of one 16-lane group (of one wavefront for
+                                  rows of 17 to 64 chunks) summed by a segmented scan,
+                                  one barrier per level (levels with a row of more
+                                  than 64 chunks are solved as wide levels) */
     RSILU_SWEEP_ROWS = 3       /* one row per thread, its chunks loaded two at a time,
                                   one barrier per level */
 };

@@ -769,14 +769,48 @@ __device__ __forceinline__ T seg_step(T v, int key)
         o = shr_f32<D>(v);
     return shr_key<D>(key) == key ? v + o : v;
 }
-// span: the longest segment in lanes (uniform); shifts at or beyond it add nothing
-template <class T>
-__device__ __forceinline__ T seg_scan16(T v, int key, int span)
+// Segments longer than 16 lanes (they never cross the wavefront) continue over
+// the 16-lane groups with the broadcast of lane 15 of each group to the next
+// (groups 1 and 3) and of lane 31 to groups 2 and 3.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double bcast_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float bcast_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <class T, int CTRL, int ROWS>
+__device__ __forceinline__ T seg_bcast(T v, int key)
+{
+    T o;
+    if constexpr (std::is_same<T, double>::value)
+        o = bcast_f64<CTRL, ROWS>(v);
+    else
+        o = bcast_f32<CTRL, ROWS>(v);
+    return __builtin_amdgcn_update_dpp(-1, key, CTRL, ROWS, 0xf, false) == key ? v + o : v;
+}
+
+// span: the longest segment in lanes (uniform); shifts at or beyond it add nothing.
+// WIDE: segments may span the wavefront's four 16-lane groups.
+template <class T, bool WIDE>
+__device__ __forceinline__ T seg_scan(T v, int key, int span)
 {
     if (span > 1) v = seg_step<T, 1>(v, key);
     if (span > 2) v = seg_step<T, 2>(v, key);
     if (span > 4) v = seg_step<T, 4>(v, key);
     if (span > 8) v = seg_step<T, 8>(v, key);
+    if constexpr (WIDE) {
+        if (span > 16) {
+            v = seg_bcast<T, 0x142, 0xa>(v, key);  // row_bcast:15 into groups 1 and 3
+            v = seg_bcast<T, 0x143, 0xc>(v, key);  // row_bcast:31 into groups 2 and 3
+        }
+    }
     return v;
 }
 
@@ -889,11 +923,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
             RSILU_LOAD_BATCH(noff, size_next >> 4, np0, npos_next)
             RSILU_LOAD_EXT(next_ext, nnext)
         }
-        if constexpr (SCHEME == kSchemeSegmented) {
+        if constexpr (SCHEME == kSchemeSegmented || SCHEME == kSchemeSegmentedWide) {
             // One phase per level, one chunk per thread: a row's chunks sit on
-            // consecutive lanes of one 16-lane group (the setup pads the level so),
-            // the chunk sums are combined by a segmented inclusive scan over DPP
-            // row shifts (1, 2, 4, 8), and the row's last lane solves the row.
+            // consecutive lanes of one 16-lane group (the setup pads the level so;
+            // in the wide variant a row of 17 to 64 chunks stays inside the
+            // wavefront instead), the chunk sums are combined by a segmented
+            // inclusive scan over DPP row shifts (1, 2, 4, 8; then the lane 15 and
+            // lane 31 broadcasts in the wide variant), and the row's last lane
+            // solves the row.
             (void)nent;
             const uint32_t zzs = (uint32_t)kSweepZeroSlot | ((uint32_t)kSweepZeroSlot << 16);
             const uint16_t *crow = reinterpret_cast<const uint16_t *>(sb + o_val + 4 * (int)sizeof(T) * nchunk +
@@ -924,7 +961,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                     t += v2 * xw[sl.y & 0xffffu];
                     t += v3 * xw[sl.y >> 16];
                     T v = has ? t : (T)0;
-                    v = seg_scan16<T>(v, key, span);
+                    v = seg_scan<T, SCHEME == kSchemeSegmentedWide>(v, key, span);
                     if (last) {
                         const int p = cr & 0x7fff;
                         T r = rhs - v;
@@ -1401,6 +1438,10 @@ void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, in
 {
     if (nb <= 0) return;
     switch (scheme) {
+    case kSchemeSegmentedWide:
+        hipLaunchKernelGGL((k_trsv_sweep<T, kSchemeSegmentedWide>), dim3(1), dim3(kSweepThreads), 0, s, blob, off,
+                           size, npos_first, p0, nb, rhs_lo, x, add_lo, y2, done);
+        break;
     case kSchemeSegmented:
         hipLaunchKernelGGL((k_trsv_sweep<T, kSchemeSegmented>), dim3(1), dim3(kSweepThreads), 0, s, blob, off, size,
                            npos_first, p0, nb, rhs_lo, x, add_lo, y2, done);

@@ -125,8 +125,8 @@ void launch_trsv_level(hipStream_t s, const DTriT<T> &t, int32_t beg, int32_t en
 // nb consecutive batches of a hybrid sweep by one workgroup, starting with the
 // batch at byte `off` of `blob` (its size and row count given); rhs_lo and
 // add_lo are the right-hand side and addend in level order. scheme: the level
-// scheme the blob was built for (kSchemeTwoPhase, kSchemeSegmented or
-// kSchemeRows; other values: two phases).
+// scheme the blob was built for (kSchemeTwoPhase, kSchemeSegmented,
+// kSchemeSegmentedWide or kSchemeRows; other values: two phases).
 template <class T>
 void launch_trsv_sweep(hipStream_t s, const unsigned char *blob, int64_t off, int32_t size, int32_t npos_first,
                        int32_t p0, int32_t nb, int32_t scheme, const T *rhs_lo, T *x, const T *add_lo, T *y2,

@@ -184,8 +184,9 @@ int64_t chunks_of(int64_t len) { return (len + kSweepChunk - 1) / kSweepChunk; }
 // row is read from LDS: from the results of the same batch, of the previous
 // batch of the run, or from the batch's gathered older inputs ("ext"). Rows
 // are cut into chunks of at most kSweepChunk entries. In the segmented scheme a
-// level's chunks are padded so no row's chunks cross a 16-chunk group, and a row
-// without entries gets one chunk of padding (its lane solves it).
+// level's chunks are padded so no row of up to 16 chunks crosses a 16-chunk group
+// and no longer row crosses a 64-chunk group, and a row without entries gets one
+// chunk of padding (its lane solves it).
 // V is the value type stored in the blob: double, or float for the FP32
 // preconditioner (values rounded to nearest).
 template <class V>
@@ -212,34 +213,44 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
         return mx;
     };
     // Level scheme of the whole factor, from its narrow levels' longest rows (measured
-    // on gfx950): when nearly every level's rows have at most 16 chunks, a row's chunks
-    // on consecutive lanes of one 16-lane DPP row, summed by a segmented scan
-    // (kSchemeSegmented; a level with a longer row becomes a wide level); else two
-    // phases per level (chunk sums, then row sums). The one-row-per-thread scheme is
-    // selected only on request.
+    // on gfx950): when nearly every level's rows have at most 64 chunks, a row's chunks
+    // on consecutive lanes of one 16-lane DPP row (rows of more than 16 chunks: of one
+    // wavefront), summed by a segmented scan (kSchemeSegmented, or kSchemeSegmentedWide
+    // when some row has more than 16 chunks; a level with a row of more than 64 becomes
+    // a wide level); else two phases per level (chunk sums, then row sums). The
+    // one-row-per-thread scheme is selected only on request.
     int32_t scheme;
+    bool over16 = false;  // a narrow level holds a row of 17..64 chunks
     {
-        int64_t nl = 0, le16 = 0;
+        int64_t nl = 0, le64 = 0;
         for (int32_t l = 0; l < lv.nlev(); ++l) {
             if (lv.ptr[(size_t)l + 1] - lv.ptr[l] > kSweepRows) continue;
+            const int64_t mx = maxchunks(l);
             ++nl;
-            le16 += maxchunks(l) <= 16 ? 1 : 0;
+            le64 += mx <= 64 ? 1 : 0;
+            over16 = over16 || (mx > 16 && mx <= 64);
         }
-        scheme = le16 >= 0.95 * (double)nl ? kSchemeSegmented : kSchemeTwoPhase;
+        scheme = le64 >= 0.95 * (double)nl ? kSchemeSegmented : kSchemeTwoPhase;
         if (force == RSILU_SWEEP_TWO_PHASE) scheme = kSchemeTwoPhase;
         if (force == RSILU_SWEEP_SEGMENTED) scheme = kSchemeSegmented;
         if (force == RSILU_SWEEP_ROWS) scheme = kSchemeRows;
     }
-    const bool seg = scheme == kSchemeSegmented;
+    // rows of more than 16 chunks need the wavefront-wide scan (its own instantiation,
+    // so factors without such rows run the 16-lane one)
+    if (scheme == kSchemeSegmented && over16) scheme = kSchemeSegmentedWide;
+    const bool seg = scheme == kSchemeSegmented || scheme == kSchemeSegmentedWide;
     // chunks of a row in the blob: in the segmented scheme a row without entries still
     // gets one (its lane solves it)
     auto rchunks = [&](int32_t row) { return seg ? std::max<int64_t>(1, chunks_of(rowlen(row))) : chunks_of(rowlen(row)); };
-    // chunk count of level l, with the padding that keeps a row inside one 16-lane group
+    // lanes a row of k chunks must not cross in the segmented scheme: one 16-lane group,
+    // or the wavefront for rows of more than 16 chunks
+    auto group_of = [](int64_t k) -> int64_t { return k <= 16 ? 16 : 64; };
+    // chunk count of level l, with the padding that keeps each row inside its group
     auto chunks = [&](int32_t l) {
         int64_t nc = 0;
         for (int32_t p = lv.ptr[l]; p < lv.ptr[(size_t)l + 1]; ++p) {
-            const int64_t k = rchunks(lv.rows[p]);
-            if (seg && (nc % 16) + k > 16) nc += 16 - nc % 16;
+            const int64_t k = rchunks(lv.rows[p]), g = group_of(k);
+            if (seg && (nc % g) + k > g) nc += g - nc % g;
             nc += k;
         }
         return nc;
@@ -343,10 +354,10 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
             const int32_t row = lv.rows[p];
             rowid[p - p0] = row;
             if (seg) {
-                // keep the row's chunks inside one 16-lane group of the level
-                const int64_t k = rchunks(row), t = ch - lch0;
-                if ((t % 16) + k > 16)
-                    for (int64_t q = t % 16; q < 16; ++q) pad_chunk(0x7fff);
+                // keep the row's chunks inside its group of the level's lanes
+                const int64_t k = rchunks(row), t = ch - lch0, g = group_of(k);
+                if ((t % g) + k > g)
+                    for (int64_t q = t % g; q < g; ++q) pad_chunk(0x7fff);
                 if (rowlen(row) == 0) {
                     rchunk[p - p0] = (uint16_t)ch;
                     pad_chunk((uint16_t)(0x8000 | (p - p0)));
@@ -434,7 +445,7 @@ Sweep make_sweep(const Csr &T, const std::vector<double> *diag, const Levels &lv
     for (int32_t l = 0; l < lv.nlev(); ++l) {
         const int64_t w = lv.ptr[(size_t)l + 1] - lv.ptr[l];
         const int64_t ne = entries(l), nc = chunks(l);
-        if (w > kSweepRows || nc > kSweepLevEnt || (seg && maxchunks(l) > 16)) {
+        if (w > kSweepRows || nc > kSweepLevEnt || (seg && maxchunks(l) > 64)) {
             close_run();
             sw.segs.push_back({l, -1, -1, w, ne, 0});
             continue;

@@ -22,6 +22,7 @@ constexpr int kSweepHdr = 12;        // int32 header words of a batch blob
 constexpr int kSchemeTwoPhase = 0;   // one chunk and one row per thread; chunk sums through LDS, two barriers
 constexpr int kSchemeSegmented = 1;  // one chunk per thread, a row on one 16-lane group, segmented scan
 constexpr int kSchemeRows = 2;       // one row per thread, its chunks loaded kRowsRound at a time
+constexpr int kSchemeSegmentedWide = 3;  // segmented, rows of up to 64 chunks (one wavefront)
 constexpr int kRowsRound = 2;
 
 }  // namespace rsilu

@@ -12,8 +12,8 @@ test_gpu_parity.py (unit roundoff eps = 2^-53):
   * the two-phase and rows-per-thread schemes add a row's chunk sums in chunk order,
     so they must agree bit for bit; the segmented scheme sums over lanes in a tree.
 The long-factor problem (ILUP(60, 0) on 40 entries per row) has factor rows of up
-to 204 entries: its levels with rows of more than 16 chunks are solved as wide
-levels under the segmented scheme, and the automatic choice takes two phases.
+to 204 entries (51 chunks): under the segmented scheme those rows span several
+16-lane groups of a wavefront and are summed with the wavefront-wide scan.
 """
 
 import numpy as np
