@@ -20,6 +20,10 @@
  *   orc_upper_solve    back substitution with an upper-triangular CSR.
  *   orc_levels         depth of every row in the dependency DAG of a
  *                      triangular factor (longest path from a source).
+ *   orc_explicit_y     Section 3.2: the rows of Y~ = L2 L1^{-1} as a sparse
+ *                      matrix, by back substitution with L1^T on each sparse
+ *                      row of L2, small entries dropped.
+ *   orc_dot            sum_i a_i b_i, sequential in index order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -416,4 +420,124 @@ void orc_levels(int64_t n, const int64_t *rowptr, const int32_t *col, int forwar
         }
         level[i] = lv;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3.2 offers to compute Y~ = L2 L1^{-1} and store it as a sparse
+ * matrix by solving L1^T Y~^T = L2^T with a back substitution that handles a
+ * sparse right-hand side. Row i of Y~ is the y with y L1 = l (l = row i of
+ * L2; L1 unit lower triangular, strictly lower part given by rows). Taking the
+ * positions k in descending order, y_k is final once every row k' > k has been
+ * processed; a final y_k is then pushed into the lower positions of row k of
+ * L1: y_j = y_j - (y_k * l_kj). Positions are reached only from l's pattern
+ * and from kept entries, so a max-heap of reached positions gives the order.
+ * A final value is dropped (and not pushed further) when it is zero or
+ * |y_k| < tauY, the rule the ILUP applies to the entries of L.
+ *
+ * Rows row_begin.. are written into yptr/ycol/yval (yptr[row_begin] must hold
+ * the running count) until the capacity `cap` would be exceeded. Returns the
+ * number of rows completed; the caller grows the arrays and calls again from
+ * there. Within a row the kept entries are stored in ascending column order. */
+static void orc_heap_push(int64_t *h, int64_t *cnt, int64_t v)
+{
+    int64_t i = (*cnt)++;
+    h[i] = v;
+    while (i > 0) {
+        int64_t parent = (i - 1) / 2;
+        if (h[parent] >= h[i]) break;
+        int64_t t = h[parent];
+        h[parent] = h[i];
+        h[i] = t;
+        i = parent;
+    }
+}
+
+static int64_t orc_heap_pop(int64_t *h, int64_t *cnt)
+{
+    int64_t top = h[0];
+    int64_t last = h[--(*cnt)];
+    int64_t i = 0;
+    if (*cnt == 0) return top;
+    h[0] = last;
+    for (;;) {
+        int64_t a = 2 * i + 1, b = 2 * i + 2, big = i;
+        if (a < *cnt && h[a] > h[big]) big = a;
+        if (b < *cnt && h[b] > h[big]) big = b;
+        if (big == i) break;
+        int64_t t = h[big];
+        h[big] = h[i];
+        h[i] = t;
+        i = big;
+    }
+    return top;
+}
+
+int64_t orc_explicit_y(int64_t row_begin, int64_t nrows, int64_t n, const int64_t *l2ptr, const int32_t *l2col,
+                       const double *l2val, const int64_t *l1ptr, const int32_t *l1col, const double *l1val,
+                       double tauY, int64_t cap, int64_t *yptr, int32_t *ycol, double *yval)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *x = (double *)calloc(nn, sizeof(double));
+    char *reached = (char *)calloc(nn, 1);
+    int64_t *heap = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t *kcol = (int64_t *)malloc(nn * sizeof(int64_t));
+    double *kval = (double *)malloc(nn * sizeof(double));
+    if (!x || !reached || !heap || !kcol || !kval) {
+        free(x); free(reached); free(heap); free(kcol); free(kval);
+        return -1;
+    }
+    int64_t row = row_begin;
+    for (; row < nrows; ++row) {
+        int64_t hc = 0, nk = 0;
+        for (int64_t e = l2ptr[row]; e < l2ptr[row + 1]; ++e) {
+            int32_t j = l2col[e];
+            x[j] = l2val[e];
+            reached[j] = 1;
+            orc_heap_push(heap, &hc, j);
+        }
+        while (hc > 0) {
+            int64_t k = orc_heap_pop(heap, &hc);
+            double yk = x[k];
+            reached[k] = 0;
+            x[k] = 0.0;
+            if (yk == 0.0 || fabs(yk) < tauY) continue;
+            kcol[nk] = k;
+            kval[nk] = yk;
+            nk++;
+            for (int64_t e = l1ptr[k]; e < l1ptr[k + 1]; ++e) {
+                int32_t j = l1col[e];
+                double prod = yk * l1val[e];
+                if (!reached[j]) {
+                    reached[j] = 1;
+                    x[j] = 0.0;
+                    orc_heap_push(heap, &hc, j);
+                }
+                x[j] = x[j] - prod;
+            }
+        }
+        if (yptr[row] + nk > cap) break;
+        /* found in descending position order: store ascending */
+        for (int64_t t = 0; t < nk; ++t) {
+            ycol[yptr[row] + t] = (int32_t)kcol[nk - 1 - t];
+            yval[yptr[row] + t] = kval[nk - 1 - t];
+        }
+        yptr[row + 1] = yptr[row] + nk;
+    }
+    free(x);
+    free(reached);
+    free(heap);
+    free(kcol);
+    free(kval);
+    return row;
+}
+
+/* sum_i a_i b_i, accumulated sequentially in index order. */
+double orc_dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double prod = a[i] * b[i];
+        s = s + prod;
+    }
+    return s;
 }

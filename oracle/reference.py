@@ -13,6 +13,9 @@ It follows the paper step by step:
   * levels              dependency depths of the triangular factors
   * dense_S             S~ = I + Y~ Y~^T with Y~ = L2 L1^{-1}, (3.9), factored
                         once by Cholesky (Section 3.2)
+  * explicit_Y          Y~ stored as a sparse matrix (Section 3.2), by back
+                        substitution with L1^T on each row of L2, entries
+                        below a drop tolerance dropped
   * cg_S                S~ w = u by a fixed number of CG steps, S~ applied
                         implicitly (Section 3.2, Table 3(a))
   * apply_alg3          Algorithm 3 on the residual components (r1, r2)
@@ -66,6 +69,10 @@ def _load():
         lib.orc_upper_solve.restype = I64
         lib.orc_levels.argtypes = [I64, P, P, ctypes.c_int, P]
         lib.orc_levels.restype = None
+        lib.orc_explicit_y.argtypes = [I64, I64, I64, P, P, P, P, P, P, D, I64, P, P, P]
+        lib.orc_explicit_y.restype = I64
+        lib.orc_dot.argtypes = [I64, P, P]
+        lib.orc_dot.restype = D
         _lib = lib
     return _lib
 
@@ -142,6 +149,41 @@ def upper_solve(U, b, diag=None):
     if bad:
         raise ValueError("matrix is not strictly upper triangular at row %d" % (bad - 1))
     return x
+
+
+def dot(a, b):
+    """(a, b): the correctly rounded sum (math.fsum) of the rounded products a_i b_i. It does
+    not depend on the order of the terms, and its error is below that of any summation
+    order a GPU reduction may take."""
+    a = _c(a, np.float64)
+    b = _c(b, np.float64)
+    assert a.shape == b.shape
+    return math.fsum(a * b)
+
+
+def explicit_Y(L1, L2, tauY):
+    """Section 3.2: Y~ = L2 L1^{-1} as a sparse matrix. Row i solves y L1 = (row i of L2)
+    by back substitution with a sparse right-hand side (oracle_core.c, orc_explicit_y); a
+    final entry that is zero or below tauY in magnitude is dropped and not propagated
+    (tauY = 0 keeps every nonzero: the exact Y~ up to rounding)."""
+    k, n = L2.nrows, L1.nrows
+    yptr = np.zeros(k + 1, dtype=np.int64)
+    cap = max(16, 4 * L2.nnz)
+    ycol = np.empty(cap, dtype=np.int32)
+    yval = np.empty(cap)
+    row = 0
+    while row < k:
+        done = _load().orc_explicit_y(row, k, n, _p(L2.rowptr), _p(L2.col), _p(L2.val), _p(L1.rowptr),
+                                      _p(L1.col), _p(L1.val), float(tauY), cap, _p(yptr), _p(ycol), _p(yval))
+        if done < 0:
+            raise MemoryError("orc_explicit_y")
+        row = int(done)
+        if row < k:
+            cap *= 2
+            ycol = np.resize(ycol, cap)
+            yval = np.resize(yval, cap)
+    nnz = int(yptr[-1])
+    return CSR(k, n, yptr, ycol[:nnz].copy(), yval[:nnz].copy())
 
 
 # ----------------------------------------------------------------------------
@@ -262,6 +304,9 @@ class Factors:
     W_chol: np.ndarray = field(default=None)  # lower Cholesky factor of I - R M^{-1} R^T
     cg_steps: int = 2  # CG steps on S~ (cg mode)
     lev: dict = field(default_factory=dict)
+    Y: "CSR" = None  # explicit Y~ = L2 L1^{-1} (Section 3.2), or None: applied implicitly
+    YT: "CSR" = None
+    ytau: float = 0.0  # drop tolerance of the explicit Y~
 
     @property
     def psize(self):
@@ -303,8 +348,9 @@ def dense_S(L1, L2):
 
 
 def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=True, smode="identity",
-           cg_steps=2):
-    """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~."""
+           cg_steps=2, ystore=False, ytau=0.0):
+    """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~, and with
+    ystore the explicit Y~ (drop tolerance ytau)."""
     rowptr, col, val = validate(m, n, rowptr, col, val)
     A = CSR(m, n, rowptr, col, val)
     colptr, rowind, cval = to_csc(m, n, rowptr, col, val)
@@ -327,9 +373,15 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
         "UT": level_sets(levels(F.UT, True)),
     }
     if smode == "dense":
+        if ystore:
+            raise ValueError("the explicit Y~ is used with S^ = I, CG or none")
         _, F.S_chol = dense_S(L1, L2)
     elif smode not in ("identity", "none", "cg"):
         raise ValueError(smode)
+    if ystore:
+        F.ytau = float(ytau)
+        F.Y = explicit_Y(L1, L2, F.ytau)
+        F.YT = F.Y.transpose()
     return F
 
 
@@ -342,7 +394,8 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
     A1) and each new row a, prescaled with the setup's column norms (a_hat = a D), becomes
     a row of A2 at the end of the row order with the L2 row l that solves (U)^T l^T =
     a_hat^T by forward substitution; entries with |l_j| < tau (or zero) are dropped, as in
-    the ILUP's dropping of L. Dense S~ is recomputed, and so is W after earlier removals.
+    the ILUP's dropping of L. Dense S~ is recomputed, the explicit Y~ too, and so is W after
+    earlier removals.
     Returns new Factors."""
     import dataclasses
 
@@ -371,6 +424,9 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
                             L2T=L2.transpose())
     if F.smode == "dense":
         _, G.S_chol = dense_S(F.L1, L2)
+    if F.Y is not None:
+        G.Y = explicit_Y(F.L1, L2, F.ytau)
+        G.YT = G.Y.transpose()
     if F.R is not None:
         G.W_chol = _woodbury_chol(G)
     return G
@@ -381,7 +437,10 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
 
 
 def S_product(F, d):
-    """S~ d = d + Y~ Y~^T d with Y~ = L2 L1^{-1} applied implicitly (Section 3.2)."""
+    """S~ d = d + Y~ Y~^T d (Section 3.2): with the explicit Y~ two sparse products,
+    otherwise Y~ = L2 L1^{-1} applied implicitly."""
+    if F.Y is not None:
+        return d + F.Y.matvec(F.YT.matvec(d))
     return d + F.L2.matvec(lower_solve(F.L1, upper_solve(F.L1T, F.L2T.matvec(d))))
 
 
@@ -391,19 +450,19 @@ def cg_S(F, u):
     w = np.zeros_like(u)
     res = u.copy()
     p = u.copy()
-    rr = float(np.dot(res, res))
+    rr = dot(res, res)
     for i in range(F.cg_steps):
         if not rr > 0.0:
             break
         q = S_product(F, p)
-        pq = float(np.dot(p, q))
+        pq = dot(p, q)
         if not (pq > 0.0 and math.isfinite(pq)):
             break
         alpha = rr / pq
         w = w + alpha * p
         res = res - alpha * q
         if i + 1 < F.cg_steps:
-            rr_new = float(np.dot(res, res))
+            rr_new = dot(res, res)
             p = res + (rr_new / rr) * p
             rr = rr_new
     return w
@@ -417,10 +476,16 @@ def apply_alg3(F, r):
     """
     n = F.n
     r1, r2 = r[:n], r[n:]
-    t = lower_solve(F.L1, r1)
     if F.smode == "none" or F.m == n:
         # no correction (w = 0): y = r1
-        return upper_solve(F.U, t, F.Udiag)
+        return upper_solve(F.U, lower_solve(F.L1, r1), F.Udiag)
+    if F.Y is not None:
+        # explicit Y~ (Section 3.2): u = r2 - Y~ r1, S^ w = u, y = r1 + Y~^T w
+        u = r2 - F.Y.matvec(r1)
+        w = cg_S(F, u) if F.smode == "cg" else u
+        y = r1 + F.YT.matvec(w)
+        return upper_solve(F.U, lower_solve(F.L1, y), F.Udiag)
+    t = lower_solve(F.L1, r1)
     u = r2 - F.L2.matvec(t)
     if F.smode == "dense":
         w = sla.cho_solve((F.S_chol, True), u)
@@ -451,14 +516,25 @@ def apply_alg2(F, z):
     needs); step 5 solves M_a h = w_a. Here M_a = (L1 U)^T (L1 U), A2 is
     represented by L2 U (its image under the incomplete factorization, so
     that A2 M_a^{-1} A2^T = Y~ Y~^T), and M_b is S~ (dense mode), I
-    (identity mode) or absent (none mode: v_b = 0, h = u_a).
+    (identity mode) or absent (none mode: v_b = 0, h = u_a). With the explicit Y~
+    (F.Y), A2 = L2 U = Y~ L1 U is applied through Y~ and S~ products are Y~ Y~^T
+    products.
     """
     if F.R is not None:
         return _apply_removed(F, z)
     ua = _ma_solve(F, z)
     if F.smode == "none" or F.m == F.n:
         return ua
-    wb = F.L2.matvec(F.U.matvec(ua) + F.Udiag * ua)
+    Uua = F.U.matvec(ua) + F.Udiag * ua
+    if F.Y is not None:
+        # explicit Y~: A2 = L2 U = Y~ L1 U, so w_b = Y~ (L1 U u_a) and A2^T v_b = U^T L1^T Y~^T v_b
+        wb = F.Y.matvec(F.L1.matvec(Uua) + Uua)
+        vb = cg_S(F, wb) if F.smode == "cg" else wb
+        g = F.YT.matvec(vb)
+        g = F.L1T.matvec(g) + g
+        wa = z - (F.UT.matvec(g) + F.Udiag * g)
+        return _ma_solve(F, wa)
+    wb = F.L2.matvec(Uua)
     if F.smode == "dense":
         vb = sla.cho_solve((F.S_chol, True), wb)
     elif F.smode == "cg":
@@ -560,7 +636,7 @@ def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):
     n = F.n
     r = b[F.perm.astype(np.int64)].copy()
     xh = np.zeros(n)
-    beta1 = math.sqrt(float(np.dot(r, r)))
+    beta1 = math.sqrt(dot(r, r))
     status = "not_converged"
     iters = 0
     hist = []
@@ -569,11 +645,11 @@ def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):
     else:
         u = r / beta1
         s = F.AhatT.matvec(u)
-        s1 = math.sqrt(float(np.dot(F.colnorm * s, F.colnorm * s)))
+        s1 = math.sqrt(dot(F.colnorm * s, F.colnorm * s))
         nb = beta1 * s1
         hist.append(nb)
         vp = apply_alg2(F, s)
-        sv = float(np.dot(s, vp))
+        sv = dot(s, vp)
         if not (sv > 0.0 and math.isfinite(sv)):
             status = "breakdown" if nb > 0.0 else "ok"
         else:
@@ -584,15 +660,15 @@ def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):
             phibar, rhobar = beta1, alpha
             for it in range(1, maxit + 1):
                 t = F.Ahat.matvec(v) - alpha * u
-                beta = math.sqrt(float(np.dot(t, t)))
+                beta = math.sqrt(dot(t, t))
                 if not math.isfinite(beta):
                     status = "breakdown"
                     break
                 u = t / beta if beta > 0.0 else t
                 s = F.AhatT.matvec(u) - beta * Mv
-                sn_ = math.sqrt(float(np.dot(F.colnorm * s, F.colnorm * s)))
+                sn_ = math.sqrt(dot(F.colnorm * s, F.colnorm * s))
                 vp = apply_alg2(F, s)
-                sv = float(np.dot(s, vp))
+                sv = dot(s, vp)
                 alpha = math.sqrt(sv) if sv > 0.0 else 0.0
                 rho = math.sqrt(rhobar * rhobar + beta * beta)
                 c, sn = rhobar / rho, beta / rho
@@ -665,7 +741,7 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False, form="alg3"):
     r = b[F.perm.astype(np.int64)].copy()
     xh = np.zeros(n)
     z = F.AhatT.matvec(r)
-    nb = math.sqrt(float(np.dot(F.colnorm * z, F.colnorm * z)))
+    nb = math.sqrt(dot(F.colnorm * z, F.colnorm * z))
     hist = [nb]
     rn, orth = [float(np.linalg.norm(r))], []
     status = "not_converged"
@@ -674,14 +750,14 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False, form="alg3"):
         status = "ok"
     else:
         h = apply(F, r, z)
-        rho = float(np.dot(z, h))
+        rho = dot(z, h)
         p = h.copy()
         if rho == 0.0 or not math.isfinite(rho):
             status = "breakdown"
         else:
             for it in range(1, maxit + 1):
                 q = F.Ahat.matvec(p)
-                delta = float(np.dot(q, q))
+                delta = dot(q, q)
                 if delta == 0.0 or not math.isfinite(delta):
                     status = "breakdown"
                     break
@@ -689,11 +765,11 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False, form="alg3"):
                 xh += alpha * p
                 r -= alpha * q
                 z = F.AhatT.matvec(r)
-                zn = math.sqrt(float(np.dot(F.colnorm * z, F.colnorm * z)))
+                zn = math.sqrt(dot(F.colnorm * z, F.colnorm * z))
                 hist.append(zn)
                 if trace:
                     rn.append(float(np.linalg.norm(r)))
-                    orth.append(float(np.dot(p, z)) / rho)
+                    orth.append(dot(p, z) / rho)
                 iters = it
                 if zn <= tol * nb:
                     status = "ok"
@@ -701,7 +777,7 @@ def pcgls(F, b, tol=1e-8, maxit=2000, apply=None, trace=False, form="alg3"):
                 if it == maxit:
                     break
                 h = apply(F, r, z)
-                rho_new = float(np.dot(z, h))
+                rho_new = dot(z, h)
                 if rho_new == 0.0 or not math.isfinite(rho_new):
                     status = "breakdown"
                     break
