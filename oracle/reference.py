@@ -307,6 +307,8 @@ class Factors:
     Y: "CSR" = None  # explicit Y~ = L2 L1^{-1} (Section 3.2), or None: applied implicitly
     YT: "CSR" = None
     ytau: float = 0.0  # drop tolerance of the explicit Y~
+    cheb_b: float = 1.0  # Chebyshev M_b: upper end of the interval [1, b] (cheb mode)
+    cheb_degree: int = 0  # its number of steps
 
     @property
     def psize(self):
@@ -348,9 +350,10 @@ def dense_S(L1, L2):
 
 
 def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=True, smode="identity",
-           cg_steps=2, ystore=False, ytau=0.0):
-    """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~, and with
-    ystore the explicit Y~ (drop tolerance ytau)."""
+           cg_steps=2, ystore=False, ytau=0.0, poly_degree=0, poly_delta=0.9):
+    """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~, with ystore
+    the explicit Y~ (drop tolerance ytau), and in cheb mode the Chebyshev interval and
+    degree (poly_degree = 0: chosen by cheb_plan from poly_delta)."""
     rowptr, col, val = validate(m, n, rowptr, col, val)
     A = CSR(m, n, rowptr, col, val)
     colptr, rowind, cval = to_csc(m, n, rowptr, col, val)
@@ -376,12 +379,14 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
         if ystore:
             raise ValueError("the explicit Y~ is used with S^ = I, CG or none")
         _, F.S_chol = dense_S(L1, L2)
-    elif smode not in ("identity", "none", "cg"):
+    elif smode not in ("identity", "none", "cg", "cheb"):
         raise ValueError(smode)
     if ystore:
         F.ytau = float(ytau)
         F.Y = explicit_Y(L1, L2, F.ytau)
         F.YT = F.Y.transpose()
+    if smode == "cheb" and m > n:
+        F.cheb_b, F.cheb_degree = cheb_plan(lambda_max_S(F), poly_delta, poly_degree)
     return F
 
 
@@ -468,6 +473,79 @@ def cg_S(F, u):
     return w
 
 
+def lambda_max_S(F, steps=50):
+    """Estimate of the largest eigenvalue of S~ = I + Y~ Y~^T: `steps` power iterations from
+    the all-ones vector, v <- S~ v / ||S~ v||, returning the last Rayleigh quotient
+    (v, S~ v) with ||v|| = 1 (a lower bound of lambda_max)."""
+    k = F.m - F.n
+    v = np.ones(k) / math.sqrt(k)
+    lam = 1.0
+    for _ in range(steps):
+        w = S_product(F, v)
+        lam = dot(v, w)
+        nw = math.sqrt(dot(w, w))
+        v = w / nw
+    return lam
+
+
+def cheb_plan(lam, delta, degree=0):
+    """Interval and degree of the Chebyshev polynomial that stands for S~^{-1}.
+
+    The spectrum of S~ lies in [1, lambda_max]; the iteration uses [1, b] with
+    b = 1.05 lam. After K steps from w = 0 the residual is r_K(S~) u with
+    r_K(t) = T_K((b + 1 - 2t) / (b - 1)) / T_K((b + 1) / (b - 1)), so |r_K| <= eps_K =
+    1 / T_K((b + 1) / (b - 1)) on [1, b]. The Algorithm 2 operator with this M_b^{-1}
+    has, on an eigenvector of Y~^T Y~ with eigenvalue t - 1, the factor
+    1 + (t - 1) r_K(t) in place of the exact 1 (up to the congruence with L1 U), which
+    is positive for every t in [1, b] when (b - 1) eps_K < 1, and for every t > b when
+    K is even (T_K is then positive left of -1). The default degree is the smallest
+    even K with (b - 1) eps_K <= delta (at most 512). Returns (b, K); K = 0 when
+    S~ = I (lam <= 1), meaning w = u."""
+    if not lam > 1.0:
+        return 1.0, 0
+    b = 1.05 * lam
+    sigma = (b + 1.0) / (b - 1.0)
+    if degree > 0:
+        return b, int(degree)
+    K = 2
+    while K < 512 and (b - 1.0) / math.cosh(K * math.acosh(sigma)) > delta:
+        K += 2
+    return b, K
+
+
+def cheb_S(F, u):
+    """M_b^{-1} u by the Chebyshev iteration on S~ w = u over [1, F.cheb_b] with F.cheb_degree
+    steps from w = 0 (the classical three-term form: theta = (b + 1)/2, delta = (b - 1)/2,
+    sigma = theta/delta, rho_0 = 1/sigma, d_0 = u/theta; each step w += d, r -= S~ d,
+    rho' = 1/(2 sigma - rho), d = rho' rho d + (2 rho'/delta) r). A fixed polynomial in S~:
+    linear in u and symmetric positive definite (cheb_plan). Degree 0: w = u (S~ = I)."""
+    K, b = F.cheb_degree, F.cheb_b
+    if K == 0:
+        return u.copy()
+    theta, half = (b + 1.0) / 2.0, (b - 1.0) / 2.0
+    sigma = theta / half
+    rho = 1.0 / sigma
+    w = np.zeros_like(u)
+    r = u.copy()
+    d = r / theta
+    for _ in range(K):
+        w = w + d
+        r = r - S_product(F, d)
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = (rho_new * rho) * d + (2.0 * rho_new / half) * r
+        rho = rho_new
+    return w
+
+
+def Mb_solve(F, u):
+    """Step 3 of Algorithm 2 / step 2 of Algorithm 3 with S^ = CG or Chebyshev on S~, or I."""
+    if F.smode == "cg":
+        return cg_S(F, u)
+    if F.smode == "cheb":
+        return cheb_S(F, u)
+    return u
+
+
 def apply_alg3(F, r):
     """Algorithm 3 on the residual r (pivot order): h from (r1, r2).
 
@@ -482,17 +560,15 @@ def apply_alg3(F, r):
     if F.Y is not None:
         # explicit Y~ (Section 3.2): u = r2 - Y~ r1, S^ w = u, y = r1 + Y~^T w
         u = r2 - F.Y.matvec(r1)
-        w = cg_S(F, u) if F.smode == "cg" else u
+        w = Mb_solve(F, u)
         y = r1 + F.YT.matvec(w)
         return upper_solve(F.U, lower_solve(F.L1, y), F.Udiag)
     t = lower_solve(F.L1, r1)
     u = r2 - F.L2.matvec(t)
     if F.smode == "dense":
         w = sla.cho_solve((F.S_chol, True), u)
-    elif F.smode == "cg":
-        w = cg_S(F, u)
     else:
-        w = u
+        w = Mb_solve(F, u)
     g = F.L2T.matvec(w)
     y = r1 + upper_solve(F.L1T, g)
     v = lower_solve(F.L1, y)
@@ -529,7 +605,7 @@ def apply_alg2(F, z):
     if F.Y is not None:
         # explicit Y~: A2 = L2 U = Y~ L1 U, so w_b = Y~ (L1 U u_a) and A2^T v_b = U^T L1^T Y~^T v_b
         wb = F.Y.matvec(F.L1.matvec(Uua) + Uua)
-        vb = cg_S(F, wb) if F.smode == "cg" else wb
+        vb = Mb_solve(F, wb)
         g = F.YT.matvec(vb)
         g = F.L1T.matvec(g) + g
         wa = z - (F.UT.matvec(g) + F.Udiag * g)
@@ -537,10 +613,8 @@ def apply_alg2(F, z):
     wb = F.L2.matvec(Uua)
     if F.smode == "dense":
         vb = sla.cho_solve((F.S_chol, True), wb)
-    elif F.smode == "cg":
-        vb = cg_S(F, wb)
     else:
-        vb = wb
+        vb = Mb_solve(F, wb)
     s = F.L2T.matvec(vb)
     wa = z - (F.UT.matvec(s) + F.Udiag * s)
     return _ma_solve(F, wa)
@@ -616,7 +690,7 @@ def remove_rows(F, rows):
 
 def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):
     """LSQR on min || P b - A_hat N y ||, x_hat = N y, with N N^T = M^{-1} the SPD operator
-    of Algorithm 2 (apply_alg2; modes "none" and "dense"), in the M-inner-product form:
+    of Algorithm 2 (apply_alg2; modes "none", "dense" and "cheb"), in the M-inner-product form:
     v = N v_hat, M v = N^{-T} v_hat, so only M^{-1} is ever applied.
 
     Init: beta1 = ||P b||, u = P b / beta1, s = A_hat^T u, v' = M^{-1} s,
@@ -630,7 +704,7 @@ def lsqr_m(F, b, tol=1e-8, maxit=2000, trace=False):
     |phibar c| ||D^{-1} s|| <= tol ||A^T b|| with ||A^T b|| = beta1 ||D^{-1} s_1||.
     Breakdown: s . v' <= 0 or a non-finite scalar.
     """
-    if F.smode not in ("none", "dense") and F.m > F.n:
+    if F.smode not in ("none", "dense", "cheb") and F.m > F.n:
         raise ValueError("LSQR needs a symmetric positive definite M^{-1}")
     b = _c(b, np.float64)
     n = F.n
