@@ -1,18 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: preconditioned least-squares solves per second on one MI355X.
 
-A step is one whole preconditioned solve (LSQR or Algorithm 1, every kernel
-on the GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from
-b resident in HBM to x in HBM with the iteration count and ||A^T r|| on the
-host. Setup (the host ILUP) is done once, outside the timed region.
+A step is one whole preconditioned solve (Algorithm 1 or LSQR, every kernel on
+the GPU) of the grid-shaped workload, m = 600,000, n = 400,000, from b resident
+in HBM to x in HBM with the iteration count and ||A^T r|| on the host. Setup
+(the host ILUP and the explicit Y~) is done once, outside the timed region.
 
-The default Krylov method is LSQR in the M-inner-product form (--krylov pcgls
-runs Algorithm 1; both give the same iterates in exact arithmetic), with the
-preconditioner applied by Algorithm 2 with k = n and M_a = (L1 U)^T (L1 U)
-from the ILUP(10, 1e-2) factors (mu = 1), without the M_b correction: on this
-workload it reaches ||A^T r|| <= 1e-8 ||A^T b||, whereas Algorithm 3 on the
-residual stalls near its starting residual (--form alg3 --krylov pcgls runs
-it; the solve then ends at maxit or on a breakdown).
+The default configuration is the paper's method with the A2 correction in every
+iteration: Algorithm 1 (left-preconditioned CGLS) with the preconditioner
+applied by Algorithm 2 with k = n, M_a = (L1 U)^T (L1 U) from the ILUP(10, 1e-2)
+factors (mu = 1), and M_b given by 32 CG steps on S~ = I + Y~ Y~^T, with Y~ =
+L2 L1^{-1} stored explicitly as a sparse matrix (Section 3.2; entries below
+1e-2 dropped). Beside it the JSON line carries the A1-only preconditioner
+(no M_b correction, LSQR; the Lauchli-type preconditioner of the related work)
+on the same workload, and the tiny workload with the dense S~ (Table 2 form).
 
 Prints one JSON line with the throughput, p50/p99 latency, the roofline of the
 dominant kernel (HIP events recorded by the library on the solve's stream over
@@ -46,10 +47,18 @@ def parse():
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--maxit", type=int, default=2000)
-    ap.add_argument("--smode", default="none", choices=["none", "identity", "dense", "auto"])
+    ap.add_argument("--smode", default="cg", choices=["cg", "none", "identity", "dense", "auto"],
+                    help="S^ / M_b: CG steps on S~ (default), none (A1 only), identity, dense S~")
+    ap.add_argument("--cg-steps", type=int, default=32)
+    ap.add_argument("--ystore", default="explicit", choices=["explicit", "implicit"],
+                    help="Y~ = L2 L1^{-1} stored as a sparse matrix (default) or applied by sweeps")
+    ap.add_argument("--ytau", type=float, default=1e-2, help="drop tolerance of the explicit Y~")
     ap.add_argument("--form", default="alg2", choices=["alg2", "alg3"])
-    ap.add_argument("--krylov", default="lsqr", choices=["pcgls", "lsqr"],
-                    help="Algorithm 1 (PCGLS) or LSQR in the M-inner-product form (needs --form alg2)")
+    ap.add_argument("--krylov", default="pcgls", choices=["pcgls", "lsqr"],
+                    help="Algorithm 1 (PCGLS) or LSQR in the M-inner-product form (needs --form alg2 and an SPD "
+                         "M^{-1}: --smode none or dense)")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the A1-only and dense-S~ (tiny workload) lines")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the preconditioner (factors and Algorithm 2/3); Krylov part is FP64")
     ap.add_argument("--trsv", default="hybrid", choices=["hybrid", "syncfree", "levels"])
@@ -97,6 +106,13 @@ def step_bytes(st, vb=8):
         "spmv_L2_sub": e * l2 + 4 * (k + 1) + vb * (n + 2 * k),
         "spmv_L2T": e * l2 + 4 * (n + 1) + vb * (k + n),
         "dense_S": 8 * k * (k + 1) + 16 * k,
+        # the explicit Y~ (k x n) and Y~^T: entries, row pointers, gathered input, output (+ aux)
+        "spmv_Y": e * st.nnz_y + 4 * (k + 1) + vb * (n + k),
+        "spmv_YT": e * st.nnz_y + 4 * (n + 1) + vb * (k + n),
+        # one CG step on S~ besides its two products: (p, q), w += a p, res -= a q, (res, res),
+        # p = res + b p; and the steps' set-up (res = p = u, w = 0, (res, res)) and result copy
+        "cg_vectors": 8 * (2 * k + 6 * k + k + 3 * k),
+        "cg_setup": 8 * (4 * k + k + 2 * k),
         # x += alpha p, r -= alpha q; rho = (z, h); p = h + beta p
         "vectors": 8 * (3 * n + 3 * m) + 16 * n + 24 * n,
         # FP32 preconditioner: input to FP32 and h back to FP64
@@ -104,7 +120,7 @@ def step_bytes(st, vb=8):
     }
 
 
-def iteration_bytes(st, form, smode, vb=8):
+def iteration_bytes(st, form, smode, vb=8, ystore="implicit", cg_steps=0):
     """Algorithmic bytes of one iteration of Algorithm 1 with the given form."""
     b = step_bytes(st, vb)
     k = st.m - st.n
@@ -112,6 +128,17 @@ def iteration_bytes(st, form, smode, vb=8):
     if vb == 4 and form == "alg3":
         it += 12 * (st.m - st.n)  # the m-vector r is converted, not only n entries
     corr = k > 0 and smode != "none"
+    cg = b["cg_setup"] + cg_steps * (b["spmv_Y"] + b["spmv_YT"] + vb * k + b["cg_vectors"]) if smode == "cg" else 0
+    if ystore == "explicit" and corr:
+        # Y~ x (- or + an addend), S^, Y~^T w with an addend; two or four sweeps
+        it += b["spmv_Y"] + vb * k + b["spmv_YT"] + vb * st.n + cg
+        if form == "alg3":
+            return it + b["trsv_L1"] + b["trsv_U"]
+        return it + b["trsv_UT"] + b["trsv_L1T"] + b["trsv_L1"] + b["trsv_U"]
+    if smode == "cg" and corr:
+        # implicit S~ products: L2^T, L1^T, L1, L2 with an addend
+        it += cg - cg_steps * (b["spmv_Y"] + b["spmv_YT"]) + cg_steps * (
+            b["spmv_L2T"] + b["trsv_L1T"] + b["trsv_L1"] + b["spmv_L2"])
     if form == "alg3":
         it += b["trsv_L1"] + b["trsv_U"]
         if corr:
@@ -159,8 +186,11 @@ def cpu_baseline(prob, args, iters_per_solve):
 
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        smode = args.smode if args.smode != "auto" else ("dense" if 0 < prob.m - prob.n <= 4096 else "identity")
-        F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode)
+        smode = args.smode
+        if smode == "auto":
+            smode = "dense" if 0 < prob.m - prob.n <= 4096 and args.ystore != "explicit" else "identity"
+        F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, cg_steps=args.cg_steps,
+                                  ystore=args.ystore == "explicit", ytau=args.ytau)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         def run(maxit):
@@ -191,11 +221,99 @@ def cpu_baseline(prob, args, iters_per_solve):
         "cores": 1,
         "kind": "oracle",
         "sample": "oracle " + ("LSQR" if args.krylov == "lsqr" else "Algorithm 1") + " + Algorithm " + args.form[-1] +
-                  " (plain C substitutions, numpy vectors, 1 thread) on the same "
+                  (" with %d CG steps on S~ (%s Y~)" % (args.cg_steps, args.ystore) if smode == "cg" else
+                   " (S^ %s)" % smode) +
+                  " (plain C substitutions and products, numpy vectors, 1 thread) on the same "
                   "workload: %d iterations timed (%.1f s, %.1f ms/iteration), scaled to the %d iterations of one "
                   "GPU solve; oracle setup %.1f s not counted; host %s, nproc %d"
                   % (res.iters, t, per_iter * 1e3, iters_per_solve, t_setup, cpu, os.cpu_count() or 0),
     }
+
+
+def make_solver(R, prob, args):
+    smode = {"cg": R.S_CG, "none": R.S_NONE, "identity": R.S_IDENTITY, "dense": R.S_DENSE,
+             "auto": R.S_AUTO}[args.smode]
+    return R.Solver.from_problem(
+        prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit,
+        trsv={"hybrid": R.TRSV_HYBRID, "syncfree": R.TRSV_SYNCFREE, "levels": R.TRSV_LEVELS}[args.trsv],
+        form={"alg2": R.FORM_ALG2, "alg3": R.FORM_ALG3}[args.form],
+        precision={"fp64": R.PREC_FP64, "fp32": R.PREC_FP32}[args.precision],
+        krylov={"pcgls": R.KRYLOV_PCGLS, "lsqr": R.KRYLOV_LSQR}[args.krylov],
+        cg_steps=max(1, args.cg_steps), ystore={"explicit": R.Y_EXPLICIT, "implicit": R.Y_IMPLICIT}[args.ystore],
+        ytau=args.ytau)
+
+
+def timed_solves(prob, args, steps, warmup):
+    """Set up (untimed), upload, `warmup` solves, then `steps` solves timed with the
+    library's HIP-event profile on; returns the measurements."""
+    import numpy as np
+    import torch
+
+    from paper_2603_28642_amd import rsilu as R
+
+    t0 = time.perf_counter()
+    S = make_solver(R, prob, args)
+    t_setup = time.perf_counter() - t0
+    S.upload()
+    st = S.stats
+    b = torch.from_numpy(prob.b).cuda()
+    x = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        S.solve(b, tol=args.tol, x_dev=x)
+    torch.cuda.synchronize()
+    R.rsilu_set_profiling(S.h, 1)
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    result = None
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        result = S.solve(b, tol=args.tol, x_dev=x)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    prof = R.rsilu_get_profile(S.h)
+    R.rsilu_set_profiling(S.h, 0)
+    S.close()
+    _, code, iters, atr, rel = result
+    smode_used = {R.S_NONE: "none", R.S_IDENTITY: "identity", R.S_DENSE: "dense", R.S_CG: "cg"}[st.smode]
+    status = {R.OK: "converged", R.NOT_CONVERGED: "not_converged", R.BREAKDOWN: "breakdown"}.get(code, str(code))
+    b_iter = iteration_bytes(st, args.form, smode_used, 4 if args.precision == "fp32" else 8,
+                             ystore=args.ystore, cg_steps=args.cg_steps if smode_used == "cg" else 0)
+    return dict(st=st, t_setup=t_setup, total=total, lat=lat, prof=prof, code=code, iters=iters, atr=atr, rel=rel,
+                smode=smode_used, status=status, t_solve=total / steps, b_solve=(iters + 1) * b_iter,
+                p50=1e3 * float(np.percentile(lat, 50)), p99=1e3 * float(np.percentile(lat, 99)))
+
+
+def describe(args, r):
+    st = r["st"]
+    krylov = ("LSQR (M-inner-product form)" if args.krylov == "lsqr" else "Algorithm 1 (PCGLS)") + \
+        " + Algorithm %s" % args.form[-1]
+    cfg = {
+        "nnz": int(st.nnz_a),
+        "ilup": {"p": args.p, "tau": args.tau, "mu": args.mu, "small": 1e-10},
+        "S": r["smode"],
+        "krylov": krylov,
+        "trsv": args.trsv,
+        "precond_precision": args.precision,
+        "tol": args.tol,
+        "maxit": args.maxit,
+        "iters": r["iters"],
+        "status": r["status"],
+        "atr_rel": r["rel"],
+        "factors": {"nnz_l1": int(st.nnz_l1), "nnz_l2": int(st.nnz_l2), "nnz_u": int(st.nnz_u),
+                    "levels_l1": int(st.levels_l1), "levels_l1t": int(st.levels_l1t),
+                    "levels_u": int(st.levels_u), "levels_ut": int(st.levels_ut), "nmod": int(st.nmod)},
+        "setup_s": r["t_setup"],
+    }
+    if r["smode"] == "cg":
+        cfg["cg_steps"] = args.cg_steps
+    if r["smode"] != "none" and st.m > st.n:
+        cfg["Y"] = {"store": args.ystore, "ytau": args.ytau if args.ystore == "explicit" else None,
+                    "nnz_y": int(st.nnz_y)}
+    return cfg
 
 
 def main():
@@ -210,7 +328,6 @@ def main():
         copy_probe(args.copy_probe)
         return
 
-    import numpy as np
     import torch
 
     import gen
@@ -218,40 +335,8 @@ def main():
 
     torch.cuda.set_device(0)
     prob = gen.by_name(args.workload)
-    smode = {"none": R.S_NONE, "identity": R.S_IDENTITY, "dense": R.S_DENSE, "auto": R.S_AUTO}[args.smode]
-    trsv = {"hybrid": R.TRSV_HYBRID, "syncfree": R.TRSV_SYNCFREE, "levels": R.TRSV_LEVELS}[args.trsv]
-    form = {"alg2": R.FORM_ALG2, "alg3": R.FORM_ALG3}[args.form]
-    t0 = time.perf_counter()
-    precision = {"fp64": R.PREC_FP64, "fp32": R.PREC_FP32}[args.precision]
-    krylov = {"pcgls": R.KRYLOV_PCGLS, "lsqr": R.KRYLOV_LSQR}[args.krylov]
-    S = R.Solver.from_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit, trsv=trsv,
-                              form=form, precision=precision, krylov=krylov)
-    t_setup = time.perf_counter() - t0
-    S.upload()
-    st = S.stats
-    b = torch.from_numpy(prob.b).cuda()
-    x = torch.empty(prob.n, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-
-    for _ in range(args.warmup):
-        S.solve(b, tol=args.tol, x_dev=x)
-    torch.cuda.synchronize()
-
-    R.rsilu_set_profiling(S.h, 1)
-    lat = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    result = None
-    for _ in range(args.steps):
-        t1 = time.perf_counter()
-        result = S.solve(b, tol=args.tol, x_dev=x)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t1)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    prof = R.rsilu_get_profile(S.h)
-    R.rsilu_set_profiling(S.h, 0)
-    _, code, iters, atr, rel = result
+    r = timed_solves(prob, args, args.steps, args.warmup)
+    prof = r["prof"]
 
     # dominant kernel by total time in the timed region (single-kernel classes; the
     # library adds up the algorithmic bytes of every timed launch)
@@ -261,46 +346,26 @@ def main():
     avg_s = (ms / 1e3) / max(launches, 1)
     kb = kbytes / max(launches, 1)
     achieved = kb / avg_s if avg_s > 0 else 0.0
-    t_solve = total / args.steps
-    smode_used = {R.S_NONE: "none", R.S_IDENTITY: "identity", R.S_DENSE: "dense"}[st.smode]
-    b_solve = (iters + 1) * iteration_bytes(st, args.form, smode_used, 4 if args.precision == "fp32" else 8)
-    status = {R.OK: "converged", R.NOT_CONVERGED: "not_converged", R.BREAKDOWN: "breakdown"}.get(code, str(code))
+    cfg = {"workload": prob.name + " (%s)" % args.workload}
+    cfg.update(describe(args, r))
 
     out = {
         "metric": METRIC,
-        "value": args.steps / total,
+        "value": args.steps / r["total"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * t_solve,
+        "ms_per_step": 1e3 * r["t_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64 (preconditioner f32)",
         "data": "synthetic",
-        "config": {
-            "workload": prob.name + " (%s)" % args.workload,
-            "nnz": int(st.nnz_a),
-            "ilup": {"p": args.p, "tau": args.tau, "mu": args.mu, "small": 1e-10},
-            "S": smode_used,
-            "krylov": ("LSQR (M-inner-product form)" if args.krylov == "lsqr" else "Algorithm 1 (PCGLS)") +
-                      " + Algorithm %s" % args.form[-1],
-            "trsv": args.trsv,
-            "precond_precision": args.precision,
-            "tol": args.tol,
-            "maxit": args.maxit,
-            "iters": iters,
-            "status": status,
-            "atr_rel": rel,
-            "factors": {"nnz_l1": int(st.nnz_l1), "nnz_l2": int(st.nnz_l2), "nnz_u": int(st.nnz_u),
-                        "levels_l1": int(st.levels_l1), "levels_l1t": int(st.levels_l1t),
-                        "levels_u": int(st.levels_u), "levels_ut": int(st.levels_ut), "nmod": int(st.nmod)},
-            "setup_s": t_setup,
-        },
-        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-        "hbm_frac_solve": b_solve / t_solve / HBM_PEAK,
+        "config": cfg,
+        "p50_ms": r["p50"],
+        "p99_ms": r["p99"],
+        "hbm_frac_solve": r["b_solve"] / r["t_solve"] / HBM_PEAK,
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -317,9 +382,26 @@ def main():
             "kernel_avg_us": {k: round(1e3 * prof[k][1] / prof[k][0], 2) for k in kernels if prof[k][0]},
         },
     }
+    if not args.no_baselines:
+        # the A1-only preconditioner (no M_b correction) on the same workload, LSQR
+        a1 = argparse.Namespace(**vars(args))
+        a1.smode, a1.krylov, a1.form = "none", "lsqr", "alg2"
+        ra = timed_solves(prob, a1, 2, 1)
+        out["a1_only_baseline"] = {
+            "what": "A1-only preconditioner M^{-1} = (L1 U)^{-1} (L1 U)^{-T} (no A2 correction), LSQR, same workload",
+            "value": 2 / ra["total"], "unit": "solves/s", "ms_per_solve": 1e3 * ra["t_solve"], "iters": ra["iters"],
+            "status": ra["status"], "atr_rel": ra["rel"]}
+        if args.workload != "c1":
+            # the tiny workload with the dense S~ (Table 2 form), Algorithm 1 + Algorithm 2
+            c1 = argparse.Namespace(**vars(args))
+            c1.smode, c1.krylov, c1.form, c1.ystore = "dense", "pcgls", "alg2", "implicit"
+            rc = timed_solves(gen.by_name("c1"), c1, 20, 3)
+            out["c1_dense_S"] = {
+                "what": "tiny workload m=2000 n=1000, dense S~ (Cholesky), Algorithm 1 + Algorithm 2",
+                "value": 20 / rc["total"], "unit": "solves/s", "ms_per_solve": 1e3 * rc["t_solve"],
+                "p99_ms": rc["p99"], "iters": rc["iters"], "status": rc["status"], "atr_rel": rc["rel"]}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, args, iters)
-    S.close()
+        out["cpu_baseline"] = cpu_baseline(prob, args, r["iters"])
     print(json.dumps(out), flush=True)
 
 

@@ -71,8 +71,25 @@ enum {
                              h = M_a^{-1} z */
     RSILU_S_CG = 3        /* cg_steps steps of conjugate gradients on S~ w = u from
                              w = 0 (Section 3.2; Table 3(a) uses two), S~ applied
-                             implicitly as d + L2 L1^{-1} L1^{-T} L2^T d; FP64 with the
-                             hybrid or level schedule only */
+                             implicitly as d + L2 L1^{-1} L1^{-T} L2^T d, or as
+                             d + Y~ (Y~^T d) with the explicit Y~ (RSILU_Y_EXPLICIT);
+                             FP64 with the hybrid or level schedule only */
+};
+
+/* How Y~ = L2 L1^{-1} is applied (Section 3.2; rsilu_params_t.ystore).
+ *   IMPLICIT: Y~ r = L2 (L1^{-1} r) and Y~^T w = L1^{-T} (L2^T w), one triangular
+ *             sweep and one product each, so a product with S~ = I + Y~ Y~^T costs
+ *             two sweeps.
+ *   EXPLICIT: Y~ is computed at setup and stored as a sparse matrix: row i of Y~
+ *             solves y L1 = (row i of L2) by back substitution with L1^T on a sparse
+ *             right-hand side, positions finalised in descending order; a finished
+ *             entry that is zero or smaller than ytau in magnitude is dropped before it
+ *             propagates. Products with Y~, Y~^T and S~ are then sparse products, with no
+ *             triangular sweep. Used with S^ = I, CG or none (EINVAL with the dense S~),
+ *             FP64 or FP32, hybrid or level schedule. */
+enum {
+    RSILU_Y_IMPLICIT = 0,
+    RSILU_Y_EXPLICIT = 1
 };
 
 /* Form of the preconditioning step of Algorithm 1 (see the top of this file). */
@@ -148,13 +165,18 @@ typedef struct {
     int32_t poll;     /* iterations enqueued between host polls of the stop flag; 8 */
     int32_t form;     /* RSILU_FORM_*; default RSILU_FORM_ALG3 */
     int32_t precision; /* RSILU_PREC_*; default RSILU_PREC_FP64 */
-    int32_t cg_steps;  /* CG steps of RSILU_S_CG, 1..64; default 2 */
+    int32_t cg_steps;  /* CG steps of RSILU_S_CG, 1..256; default 2 */
     int32_t krylov;    /* RSILU_KRYLOV_*; default RSILU_KRYLOV_PCGLS */
     int32_t graph;     /* 1: the `poll` iterations between two polls are captured once
                           into a HIP graph (per upload) and replayed, one launch instead
                           of some 30 kernel launches per iteration; 0: launched one by
                           one. Profiling runs always launch one by one. Default 1. */
     int32_t sweep;     /* RSILU_SWEEP_*; default RSILU_SWEEP_AUTO */
+    int32_t ystore;    /* RSILU_Y_*; default RSILU_Y_IMPLICIT */
+    double ytau;       /* drop tolerance of the explicit Y~ (RSILU_Y_EXPLICIT): an entry of
+                          Y~ that is zero or below ytau in magnitude when its substitution
+                          step finishes is dropped and not propagated; 0 keeps every
+                          nonzero (Y~ exact up to rounding); default 1e-2 */
 } rsilu_params_t;
 
 typedef struct {
@@ -172,6 +194,7 @@ typedef struct {
     int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY, _DENSE, _NONE or _CG) */
     int32_t reserved;
     size_t device_bytes;   /* what rsilu_upload needs */
+    int64_t nnz_y;         /* entries of the explicit Y~ (0 when applied implicitly) */
 } rsilu_stats_t;
 
 typedef struct rsilu_ctx *rsilu_handle_t;
@@ -179,7 +202,8 @@ typedef struct rsilu_ctx *rsilu_handle_t;
 /* Defaults of rsilu_params_t: p = 10, tau = 1e-2, mu = 0.1, small = 1e-10
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
- * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1, sweep = AUTO. */
+ * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1, sweep = AUTO,
+ * ystore = IMPLICIT, ytau = 1e-2. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting
@@ -259,7 +283,8 @@ rsilu_status_t rsilu_get_colnorm(rsilu_handle_t h, double *colnorm);
 /* Factor and operator export, for inspection and tests (host arrays).
  * which: 0 = L1 (n x n, strictly lower), 1 = L2 ((m-n) x n),
  *        2 = U (n x n, strictly upper), 3 = A_hat (m x n, pivot order),
- *        4 = diagonal of U (val[n] only; rowptr and col may be NULL).
+ *        4 = diagonal of U (val[n] only; rowptr and col may be NULL),
+ *        5 = the explicit Y~ ((m-n) x n; RSILU_Y_EXPLICIT only, else EINVAL / -1).
  * rsilu_factor_nnz returns the entry count of `which` (or -1 if invalid).
  * rowptr has nrows+1 entries; columns are sorted within each row. */
 int64_t rsilu_factor_nnz(rsilu_handle_t h, int32_t which);
@@ -293,6 +318,8 @@ rsilu_status_t rsilu_solve(rsilu_handle_t h, const double *b_dev, double tol, do
  *                 1  y[n] = A_hat^T x[m]      (Algorithm 1, z = A^T r)
  *                 2  y[m-n] = L2 x[n]         (Algorithm 3, Y r1 = L2 L1^{-1} r1)
  *                 3  y[n] = L2^T x[m-n]       (Algorithm 3, Y^T w = L1^{-T} L2^T w)
+ *                 4  y[m-n] = Y~ x[n]         (the explicit Y~, RSILU_Y_EXPLICIT only)
+ *                 5  y[n] = Y~^T x[m-n]       (its transpose)
  * rsilu_trsv, which: 0  L1 x = rhs   1  L1^T x = rhs   2  U x = rhs
  *                   3  U^T x = rhs (Algorithm 2, M_a = (L1 U)^T (L1 U))  (n-vectors)
  * rsilu_apply:   h[n] from the residual r[m] by Algorithm 3.
@@ -320,14 +347,16 @@ enum {
     RSILU_PROF_TRSV_L1 = 2,   /* L1 forward solves */
     RSILU_PROF_TRSV_L1T = 3,  /* L1^T backward solves */
     RSILU_PROF_TRSV_U = 4,    /* U backward solves */
-    RSILU_PROF_SPMV_L2 = 5,   /* products with L2 */
-    RSILU_PROF_SPMV_L2T = 6,  /* products with L2^T */
+    RSILU_PROF_SPMV_L2 = 5,   /* products with L2 (or with the explicit Y~) */
+    RSILU_PROF_SPMV_L2T = 6,  /* products with L2^T (or with the explicit Y~^T) */
     RSILU_PROF_DENSE_S = 7,   /* dense S~ solves, or the CG steps on S~ (whole) */
     RSILU_PROF_TRSV_UT = 8,   /* U^T forward solves (Algorithm 2 form) */
     RSILU_PROF_K_SWEEP = 9,   /* launches of the single-workgroup sweep kernel */
     RSILU_PROF_K_LEVEL = 10,  /* launches of the one-level kernel (hybrid schedule) */
     RSILU_PROF_K_GATHER = 11, /* level-order gathers ahead of the sweeps */
-    RSILU_PROF_COUNT = 12
+    RSILU_PROF_K_SPMV_Y = 12, /* launches of the products with the explicit Y~ and Y~^T
+                                 (inside and outside the CG steps on S~) */
+    RSILU_PROF_COUNT = 13
 };
 
 typedef struct {

@@ -106,7 +106,7 @@ struct Ptrs {
     const int32_t *done;
     double *partials, *segpart;
     DCsr A, AT, L2, L2T;
-    DPlan pA, pAT, pL2, pL2T;
+    DPlan pA, pAT, pL2, pL2T, pY, pYT;
     DTri L1f, L1b, Ub, UTf;
     const int32_t *perm;
     const double *colnorm, *sfac;
@@ -130,6 +130,8 @@ Ptrs ptrs(const Ctx &c)
     P.pAT = dplan(c, L.pAT);
     P.pL2 = dplan(c, L.pL2);
     P.pL2T = dplan(c, L.pL2T);
+    P.pY = dplan(c, L.pY);
+    P.pYT = dplan(c, L.pYT);
     P.L1f = dtri(c, L.L1f);
     P.L1b = dtri(c, L.L1b);
     P.Ub = dtri(c, L.Ub);
@@ -161,7 +163,7 @@ Ptrs ptrs(const Ctx &c)
 // hold FP32 values and the work vectors are read as float arrays).
 template <class T>
 struct Pre {
-    DCsrT<T> L2, L2T;
+    DCsrT<T> L2, L2T, Y, YT;  // Y, YT: the explicit Y~ (RSILU_Y_EXPLICIT)
     DTriT<T> L1f, L1b, Ub, UTf;
     T *t, *gp, *v, *g, *y, *s2, *c2, *u, *lo_rhs, *lo_add, *segpart;
 };
@@ -186,6 +188,8 @@ Pre<T> pre(const Ctx &c)
     Pre<T> W;
     W.L2 = dcsr_t<T>(c, L.L2);
     W.L2T = dcsr_t<T>(c, L.L2T);
+    W.Y = dcsr_t<T>(c, L.Y);
+    W.YT = dcsr_t<T>(c, L.YT);
     W.L1f = dtri_t<T>(c, L.L1f);
     W.L1b = dtri_t<T>(c, L.L1b);
     W.Ub = dtri_t<T>(c, L.Ub);
@@ -249,9 +253,26 @@ void trsv(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const DTriT<T> 
     }
 }
 
+// Product with the explicit Y~ (yt = false: y = epi(Y~ x), rows m - n) or with
+// Y~^T (yt = true: rows n), timed as one launch of its kernel class.
+template <class T>
+void spmv_y(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, bool yt, const T *x, T *y, const T *aux,
+            Epi epi, const int32_t *done)
+{
+    const DCsrT<T> &a = yt ? W.YT : W.Y;
+    const DevCsrOff &o = yt ? c.lay.YT : c.lay.Y;
+    // values and column indices once, the row pointers, the gathered input and the output (plus aux)
+    const double vb = (double)sizeof(T);
+    const double bytes = (4.0 + vb) * (double)o.nnz + 4.0 * (o.nrows + 1) + vb * (double)o.ncols +
+                         vb * (double)o.nrows * (aux ? 2.0 : 1.0);
+    ProfScope pk(c, s, RSILU_PROF_K_SPMV_Y, bytes);
+    launch_spmv<T>(s, a, yt ? P.pYT : P.pY, x, y, aux, epi, FIN_NONE, P.partials, W.segpart, P.st, done);
+}
+
 // Step 2 of Algorithm 3 / step 3 of Algorithm 2 with S^ by CG: u <- w after
 // cg_steps steps of unpreconditioned CG on S~ w = u from w = 0, with
-// S~ d = d + L2 (L1^{-1} (L1^{-T} (L2^T d))) (Section 3.2). The scalars stay on
+// S~ d = d + L2 (L1^{-1} (L1^{-T} (L2^T d))), or d + Y~ (Y~^T d) with the explicit
+// Y~ (Section 3.2). The scalars stay on
 // the device; a zero residual makes the remaining steps leave w unchanged.
 // Temporaries: g, c2 and s2 (free at this point in both forms).
 void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, const int32_t *done)
@@ -263,12 +284,19 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
     launch_cg_init(s, k, W.u, w, res, p, done);
     launch_dot(s, k, res, res, FIN_CG_RR0, P.partials, P.st, done);
     for (int32_t i = 0; i < c.prm.cg_steps; ++i) {
-        launch_spmv<double>(s, W.L2T, P.pL2T, p, W.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, done);
-        trsv<double>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.g, W.c2, nullptr, nullptr, 1, done,
-                     RSILU_PROF_TRSV_L1T);
-        trsv<double>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.c2, W.s2, nullptr, nullptr, 2, done,
-                     RSILU_PROF_TRSV_L1);
-        launch_spmv<double>(s, W.L2, P.pL2, W.s2, q, p, EPI_ADD, FIN_NONE, P.partials, W.segpart, P.st, done);
+        if (yexplicit(c)) {
+            // q = p + Y~ (Y~^T p)
+            spmv_y<double>(c, s, P, W, true, p, W.g, nullptr, EPI_PLAIN, done);
+            spmv_y<double>(c, s, P, W, false, W.g, q, p, EPI_ADD, done);
+        } else {
+            launch_spmv<double>(s, W.L2T, P.pL2T, p, W.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st,
+                                done);
+            trsv<double>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.g, W.c2, nullptr, nullptr, 1, done,
+                         RSILU_PROF_TRSV_L1T);
+            trsv<double>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.c2, W.s2, nullptr, nullptr, 2, done,
+                         RSILU_PROF_TRSV_L1);
+            launch_spmv<double>(s, W.L2, P.pL2, W.s2, q, p, EPI_ADD, FIN_NONE, P.partials, W.segpart, P.st, done);
+        }
         launch_dot(s, k, p, q, FIN_CG_ALPHA, P.partials, P.st, done);
         launch_cg_update(s, k, p, q, w, res, P.st, done);
         if (i + 1 < c.prm.cg_steps) {
@@ -287,6 +315,17 @@ template <class T>
 void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *r, T *hout, const int32_t *done)
 {
     const int32_t n = (int32_t)c.n, k = c.L2.nrows;
+    if (yexplicit(c) && k > 0 && c.smode != RSILU_S_NONE) {
+        // explicit Y~: u = r2 - Y~ r1, S^ w = u, y = r1 + Y~^T w, L1 v = y, U h = v
+        spmv_y<T>(c, s, P, W, false, r, W.u, r + n, EPI_SUB, done);
+        if constexpr (std::is_same<T, double>::value) {
+            if (c.smode == RSILU_S_CG) cg_solve_S(c, s, P, W, done);
+        }
+        spmv_y<T>(c, s, P, W, true, W.u, W.y, r, EPI_ADD, done);
+        trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.y, W.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
+        trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+        return;
+    }
     // step 1: u = r2 - Y r1 with Y r1 = L2 (L1^{-1} r1)
     trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, r, W.t, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
     if (k == 0 || c.smode == RSILU_S_NONE) {
@@ -348,6 +387,18 @@ void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
     if (!alg2_correction(c)) {
         trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.gp, W.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
         trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
+        return;
+    }
+    if (yexplicit(c)) {
+        // explicit Y~ (A2 M_a^{-1} = Y~ L1^{-T} U^{-T}): w_b = Y~ g, v_b = M_b^{-1} w_b,
+        // h = U^{-1} L1^{-1} (g - Y~^T v_b)
+        spmv_y<T>(c, s, P, W, false, W.gp, W.u, nullptr, EPI_PLAIN, done);
+        if constexpr (std::is_same<T, double>::value) {
+            if (c.smode == RSILU_S_CG) cg_solve_S(c, s, P, W, done);
+        }
+        spmv_y<T>(c, s, P, W, true, W.u, W.y, W.gp, EPI_SUB, done);
+        trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.y, W.s2, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
+        trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.s2, hout, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_U);
         return;
     }
     // step 2: w_b = L2 (L1^{-1} g) into u
@@ -558,6 +609,8 @@ void rsilu_params_default(rsilu_params_t *p)
     p->krylov = RSILU_KRYLOV_PCGLS;
     p->graph = 1;
     p->sweep = RSILU_SWEEP_AUTO;
+    p->ystore = RSILU_Y_IMPLICIT;
+    p->ytau = 1e-2;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)
@@ -625,6 +678,7 @@ rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *s)
     s->levels_ut = h->lvUT.nlev();
     s->smode = h->smode;
     s->device_bytes = h->lay.total;
+    s->nnz_y = yexplicit(*h) ? h->Y.nnz() : 0;
     return RSILU_OK;
 }
 
@@ -649,6 +703,7 @@ static const Csr *factor_of(rsilu_handle_t h, int32_t which)
     case 1: return &h->L2;
     case 2: return &h->U;
     case 3: return &h->Ahat;
+    case 5: return yexplicit(*h) ? &h->Y : nullptr;
     default: return nullptr;
     }
 }
@@ -751,6 +806,12 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put_plan(L.pAT, c.plAT));
     RSILU_HIP(put_plan(L.pL2, c.plL2));
     RSILU_HIP(put_plan(L.pL2T, c.plL2T));
+    if (yexplicit(c)) {
+        RSILU_HIP(put_csr(L.Y, c.Y));
+        RSILU_HIP(put_csr(L.YT, c.YT));
+        RSILU_HIP(put_plan(L.pY, c.plY));
+        RSILU_HIP(put_plan(L.pYT, c.plYT));
+    }
     RSILU_HIP(put_tri(L.L1f, c.L1, nullptr, c.lvL1, c.chL1, c.loL1));
     RSILU_HIP(put_tri(L.L1b, c.L1T, nullptr, c.lvL1T, c.chL1T, c.loL1T));
     RSILU_HIP(put_tri(L.Ub, c.U, &c.Udiag, c.lvU, c.chU, c.loU));
@@ -919,21 +980,25 @@ rsilu_status_t rsilu_spmv(rsilu_handle_t h, int32_t op, const double *xin, doubl
     case 0: launch_spmv<double>(s, P.A, P.pA, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
     case 1: launch_spmv<double>(s, P.AT, P.pAT, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, P.segpart, P.st, nullptr); break;
     case 2:
-    case 3: {
-        // products with L2 and L2^T in the preconditioner's precision
-        const bool l2 = op == 2;
-        const int32_t nin = l2 ? n : k, nout = l2 ? k : n;
+    case 3:
+    case 4:
+    case 5: {
+        // products with L2, L2^T, Y~ and Y~^T in the preconditioner's precision
+        if (op >= 4 && !yexplicit(c)) return RSILU_EINVAL;
+        const bool fwd = op == 2 || op == 4;  // (m-n) x n operator
+        const int32_t nin = fwd ? n : k, nout = fwd ? k : n;
+        const DPlan &pl = op == 2 ? P.pL2 : op == 3 ? P.pL2T : op == 4 ? P.pY : P.pYT;
         if (fp32(c)) {
             const Pre<float> W = pre<float>(c);
+            const DCsrT<float> &a = op == 2 ? W.L2 : op == 3 ? W.L2T : op == 4 ? W.Y : W.YT;
             float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
             launch_cvt(s, nin, xin, in, nullptr);
-            launch_spmv<float>(s, l2 ? W.L2 : W.L2T, l2 ? P.pL2 : P.pL2T, in, out, nullptr, EPI_PLAIN, FIN_NONE,
-                               P.partials, W.segpart, P.st, nullptr);
+            launch_spmv<float>(s, a, pl, in, out, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, nullptr);
             launch_cvt(s, nout, out, y, nullptr);
         } else {
             const Pre<double> W = pre<double>(c);
-            launch_spmv<double>(s, l2 ? W.L2 : W.L2T, l2 ? P.pL2 : P.pL2T, xin, y, nullptr, EPI_PLAIN, FIN_NONE,
-                                P.partials, W.segpart, P.st, nullptr);
+            const DCsrT<double> &a = op == 2 ? W.L2 : op == 3 ? W.L2T : op == 4 ? W.Y : W.YT;
+            launch_spmv<double>(s, a, pl, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, nullptr);
         }
         break;
     }

@@ -105,6 +105,8 @@ struct Layout {
     size_t total = 0;
     DevCsrOff A, AT, L2, L2T;
     DevPlanOff pA, pAT, pL2, pL2T;
+    DevCsrOff Y, YT;     // explicit Y~ and its transpose (RSILU_Y_EXPLICIT)
+    DevPlanOff pY, pYT;
     DevTriOff L1f, L1b, Ub, UTf;  // L1 forward, L1^T backward, U backward, U^T forward
     size_t perm = 0, colnorm = 0, sfac = 0;
     // removed rows (present when R has rows): R, R^T, W's factor, and work vectors
@@ -144,6 +146,8 @@ struct Ctx {
     LoTri loL1, loL1T, loU, loUT;
     SpmvPlan plA, plAT, plL2, plL2T;
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
+    Csr Y, YT;                     // explicit Y~ = L2 L1^{-1} (Section 3.2) and its transpose
+    SpmvPlan plY, plYT;
     // Section 3.4, removed rows: R = the removed rows of A_hat that were in A1, and the packed
     // lower Cholesky factor of W = I - R M^{-1} R^T (Woodbury update of the preconditioner)
     Csr R, RT;
@@ -183,6 +187,8 @@ void plan_layout(Ctx &c);
 rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const int32_t *colind, const double *val);
 rsilu_status_t remove_rows(Ctx &c, int64_t count, const int64_t *rows);
 rsilu_status_t build_woodbury(Ctx &c);
+void build_explicit_Y(Ctx &c);
+inline bool yexplicit(const Ctx &c) { return c.prm.ystore == RSILU_Y_EXPLICIT; }
 // device driver (capi.hip): drop a captured iteration graph
 void release_graph(Ctx &c);
 

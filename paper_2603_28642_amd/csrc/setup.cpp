@@ -7,6 +7,8 @@
 //   split        P A D ~ [L1; L2] U, transposes                     (3.8)
 //   levels       dependency levels of the triangular solves
 //   dense S~     S~ = I + Y Y^T, Y = L2 L1^{-1}, Cholesky           Section 3.2
+//   explicit Y~  Y~ = L2 L1^{-1} as a sparse matrix, small entries
+//                dropped                                            Section 3.2
 //
 // Floating-point decisions of the factorization (pivot choice, dropping) are
 // taken on values computed in a fixed order with separately rounded products
@@ -19,6 +21,7 @@
 #include <new>
 #include <queue>
 #include <stdexcept>
+#include <thread>
 #include <utility>
 
 #include "internal.hpp"
@@ -555,6 +558,99 @@ double modified_pivot(int64_t j1, int64_t n, double colmax, double small)
 
 }  // namespace
 
+// Section 3.2: Y~ = L2 L1^{-1} computed once and stored as a sparse matrix. Row i
+// of Y~ is the y with y L1 = l, l = row i of L2, i.e. the back substitution
+// L1^T y^T = l^T with a sparse right-hand side: y_j = l_j - sum_{k>j} y_k L1(k,j).
+// The positions are finalised from the highest down (a max-priority queue holds
+// the positions reached so far; a position enters it once, from l's pattern or
+// from the first kept y_k whose row of L1 has an entry in its column), so each
+// y_j is complete when it leaves the queue. A finished y_k that is zero or below
+// ytau in magnitude is dropped before it reaches any lower position, as the ILUP
+// drops entries of L; a kept one is pushed down: y_j = y_j - (y_k * L1(k,j)),
+// separately rounded, in the order the y_k finish. Rows are independent, so
+// blocks of rows run on host threads and are concatenated in row order.
+void build_explicit_Y(Ctx &c)
+{
+    const Csr &L1 = c.L1, &L2 = c.L2;
+    const int32_t n = (int32_t)c.n, k = L2.nrows;
+    const double ytau = c.prm.ytau;
+    struct Part {
+        std::vector<int32_t> len, col;
+        std::vector<double> val;
+    };
+    const int32_t nthreads =
+        (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16,
+                                                         ((int64_t)k + 1023) / 1024}));
+    std::vector<Part> parts((size_t)nthreads);
+    auto work = [&](int32_t t) {
+        const int32_t r0 = (int32_t)((int64_t)k * t / nthreads), r1 = (int32_t)((int64_t)k * (t + 1) / nthreads);
+        Part &out = parts[(size_t)t];
+        std::vector<double> x((size_t)n, 0.0);
+        std::vector<int32_t> stamp((size_t)n, -1);  // row index that queued the position
+        std::priority_queue<int32_t> queue;
+        std::vector<std::pair<int32_t, double>> row;
+        for (int32_t i = r0; i < r1; ++i) {
+            for (int32_t e = L2.ptr[i]; e < L2.ptr[(size_t)i + 1]; ++e) {
+                x[(size_t)L2.col[e]] = L2.val[e];
+                stamp[(size_t)L2.col[e]] = i;
+                queue.push(L2.col[e]);
+            }
+            row.clear();
+            while (!queue.empty()) {
+                const int32_t kk = queue.top();
+                queue.pop();
+                const double yk = x[(size_t)kk];
+                if (yk == 0.0 || std::fabs(yk) < ytau) continue;
+                row.emplace_back(kk, yk);
+                for (int32_t e = L1.ptr[kk]; e < L1.ptr[(size_t)kk + 1]; ++e) {
+                    const int32_t j = L1.col[e];
+                    if (stamp[(size_t)j] != i) {
+                        stamp[(size_t)j] = i;
+                        x[(size_t)j] = 0.0;
+                        queue.push(j);
+                    }
+                    const double prod = yk * L1.val[e];
+                    x[(size_t)j] = x[(size_t)j] - prod;
+                }
+            }
+            out.len.push_back((int32_t)row.size());
+            for (auto it = row.rbegin(); it != row.rend(); ++it) {
+                out.col.push_back(it->first);
+                out.val.push_back(it->second);
+            }
+        }
+    };
+    if (nthreads == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int32_t t = 0; t < nthreads; ++t) pool.emplace_back(work, t);
+        for (std::thread &th : pool) th.join();
+    }
+    Csr &Y = c.Y;
+    Y = Csr{};
+    Y.nrows = k;
+    Y.ncols = n;
+    Y.ptr.assign((size_t)k + 1, 0);
+    int64_t total = 0;
+    for (const Part &pt : parts) total += (int64_t)pt.col.size();
+    if (total > kMaxIdx) throw std::bad_alloc();
+    Y.col.reserve((size_t)total);
+    Y.val.reserve((size_t)total);
+    int32_t i = 0;
+    for (const Part &pt : parts) {
+        for (int32_t len : pt.len) {
+            Y.ptr[(size_t)i + 1] = Y.ptr[(size_t)i] + len;
+            ++i;
+        }
+        Y.col.insert(Y.col.end(), pt.col.begin(), pt.col.end());
+        Y.val.insert(Y.val.end(), pt.val.begin(), pt.val.end());
+    }
+    c.YT = transpose(Y);
+    c.plY = plan_spmv(c.Y);
+    c.plYT = plan_spmv(c.YT);
+}
+
 // S~ = I + Y~ Y~^T with Y~^T = L1^{-T} L2^T, factored by Cholesky (Section 3.2),
 // packed lower factor by rows.
 rsilu_status_t build_dense_S(Ctx &c)
@@ -616,7 +712,9 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
          (P.form != RSILU_FORM_ALG2 || P.trsv == RSILU_TRSV_SYNCFREE ||
           (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_NONE && P.smode != RSILU_S_DENSE))) ||
         (P.smode == RSILU_S_CG &&
-         (P.precision != RSILU_PREC_FP64 || P.trsv == RSILU_TRSV_SYNCFREE || P.cg_steps < 1 || P.cg_steps > 64)) ||
+         (P.precision != RSILU_PREC_FP64 || P.trsv == RSILU_TRSV_SYNCFREE || P.cg_steps < 1 || P.cg_steps > 256)) ||
+        (P.ystore != RSILU_Y_IMPLICIT && P.ystore != RSILU_Y_EXPLICIT) || !(P.ytau >= 0.0) || !std::isfinite(P.ytau) ||
+        (P.ystore == RSILU_Y_EXPLICIT && (P.smode == RSILU_S_DENSE || P.trsv == RSILU_TRSV_SYNCFREE)) ||
         (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
         (P.precision != RSILU_PREC_FP64 && P.precision != RSILU_PREC_FP32) ||
         (P.precision == RSILU_PREC_FP32 && (P.trsv == RSILU_TRSV_SYNCFREE || P.smode == RSILU_S_DENSE)) ||
@@ -869,11 +967,13 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     c.loUT = lo(c.UT, &c.Udiag, c.lvUT);
 
     // ---- S^ (Section 3.2)
+    const bool yexp = P.ystore == RSILU_Y_EXPLICIT;
     c.smode = P.smode;
     if (c.smode == RSILU_S_AUTO)
-        c.smode = (m - n > 0 && m - n <= 4096 && !f32)
+        c.smode = (m - n > 0 && m - n <= 4096 && !f32 && !yexp)
                       ? RSILU_S_DENSE
                       : (P.krylov == RSILU_KRYLOV_LSQR ? RSILU_S_NONE : RSILU_S_IDENTITY);
+    if (yexp) build_explicit_Y(c);
     if (c.smode == RSILU_S_DENSE && m > n) {
         const rsilu_status_t rc = build_dense_S(c);
         if (rc != RSILU_OK) return rc;
@@ -960,6 +1060,7 @@ rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const i
         const rsilu_status_t rc = build_dense_S(c);
         if (rc != RSILU_OK) return rc;
     }
+    if (yexplicit(c)) build_explicit_Y(c);
     // with removed A1 rows, W depends on the operator the new rows changed
     if (c.R.nrows > 0) return build_woodbury(c);
     return RSILU_OK;
@@ -1245,6 +1346,12 @@ void plan_layout(Ctx &c)
     L.pAT = place_plan(b, c.plAT);
     L.pL2 = place_plan(b, c.plL2);
     L.pL2T = place_plan(b, c.plL2T);
+    if (yexplicit(c)) {
+        L.Y = place_csr(b, c.Y, vb);
+        L.YT = place_csr(b, c.YT, vb);
+        L.pY = place_plan(b, c.plY);
+        L.pYT = place_plan(b, c.plYT);
+    }
     L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, c.loL1, n, vb);
     L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, c.loL1T, n, vb);
     L.Ub = place_tri(b, c.U, true, c.lvU, c.chU, c.swU, c.loU, n, vb);
@@ -1285,15 +1392,18 @@ void plan_layout(Ctx &c)
     };
     const int64_t nparts = std::max<int64_t>({(int64_t)2048, blocks(c.Ahat.nrows, c.plA.lanes),
                                               blocks(c.AhatT.nrows, c.plAT.lanes), blocks(c.L2.nrows, c.plL2.lanes),
-                                              blocks(c.L2T.nrows, c.plL2T.lanes)});
+                                              blocks(c.L2T.nrows, c.plL2T.lanes), blocks(c.Y.nrows, c.plY.lanes),
+                                              blocks(c.YT.nrows, c.plYT.lanes)});
     const int64_t nlong = std::max<int64_t>({(int64_t)c.plA.long_rows.size(), (int64_t)c.plAT.long_rows.size(),
                                              (int64_t)c.plL2.long_rows.size(), (int64_t)c.plL2T.long_rows.size(),
-                                             (int64_t)c.plR.long_rows.size(), (int64_t)c.plRT.long_rows.size()});
+                                             (int64_t)c.plR.long_rows.size(), (int64_t)c.plRT.long_rows.size(),
+                                             (int64_t)c.plY.long_rows.size(), (int64_t)c.plYT.long_rows.size()});
     L.npartials = (int32_t)(nparts + nlong + 64);
     L.partials = b.take(sizeof(double) * (size_t)L.npartials);
     int32_t nseg = std::max({(int32_t)c.plA.seg_beg.size(), (int32_t)c.plAT.seg_beg.size(),
                              (int32_t)c.plL2.seg_beg.size(), (int32_t)c.plL2T.seg_beg.size(),
-                             (int32_t)c.plR.seg_beg.size(), (int32_t)c.plRT.seg_beg.size(), 1});
+                             (int32_t)c.plR.seg_beg.size(), (int32_t)c.plRT.seg_beg.size(),
+                             (int32_t)c.plY.seg_beg.size(), (int32_t)c.plYT.seg_beg.size(), 1});
     L.nsegpart = nseg;
     L.segpart = b.take(sizeof(double) * (size_t)nseg);
     L.total = (b.off + 255) & ~(size_t)255;

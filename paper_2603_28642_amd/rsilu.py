@@ -22,8 +22,9 @@ PREC_FP64, PREC_FP32 = 0, 1
 KRYLOV_PCGLS, KRYLOV_LSQR = 0, 1
 TRSV_SYNCFREE, TRSV_LEVELS, TRSV_HYBRID = 0, 1, 2
 SWEEP_AUTO, SWEEP_TWO_PHASE, SWEEP_SEGMENTED, SWEEP_ROWS = 0, 1, 2, 3
+Y_IMPLICIT, Y_EXPLICIT = 0, 1
 # factor / level selectors
-L1, L2, U, AHAT, UDIAG = 0, 1, 2, 3, 4
+L1, L2, U, AHAT, UDIAG, YEXP = 0, 1, 2, 3, 4, 5
 LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
 # triangular-solve selectors of rsilu_trsv
 T_L1, T_L1T, T_U, T_UT = 0, 1, 2, 3
@@ -41,7 +42,7 @@ EXPORTS = [
     "rsilu_tune", "rsilu_tuner_size", "rsilu_tuner_destroy",
 ]
 PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S", "trsv_UT",
-              "k_trsv_sweep", "k_trsv_level", "k_gather_lo"]
+              "k_trsv_sweep", "k_trsv_level", "k_gather_lo", "k_spmv_y"]
 # classes that time whole steps (the rest time single kernels)
 PROF_STEPS = PROF_NAMES[:9]
 
@@ -51,7 +52,8 @@ class rsilu_params_t(ctypes.Structure):
                 ("small", ctypes.c_double), ("colscale", ctypes.c_int32), ("smode", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
-                ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32), ("sweep", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32), ("sweep", ctypes.c_int32),
+                ("ystore", ctypes.c_int32), ("ytau", ctypes.c_double)]
 
 
 class rsilu_stats_t(ctypes.Structure):
@@ -59,14 +61,15 @@ class rsilu_stats_t(ctypes.Structure):
                 ("nnz_l1", ctypes.c_int64), ("nnz_l2", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
                 ("psize", ctypes.c_int64), ("nmod", ctypes.c_int64), ("levels_l1", ctypes.c_int32),
                 ("levels_l1t", ctypes.c_int32), ("levels_u", ctypes.c_int32), ("levels_ut", ctypes.c_int32),
-                ("smode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+                ("smode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
+                ("nnz_y", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class rsilu_profile_t(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 12), ("ms", ctypes.c_double * 12), ("bytes", ctypes.c_double * 12)]
+    _fields_ = [("launches", ctypes.c_int64 * 13), ("ms", ctypes.c_double * 13), ("bytes", ctypes.c_double * 13)]
 
 
 class rsilu_tile_t(ctypes.Structure):

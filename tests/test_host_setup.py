@@ -409,3 +409,78 @@ def test_every_sweep_scheme_sets_up(sweep):
     assert (st.levels_l1, st.levels_u) == (st0.levels_l1, st0.levels_u)
     R.rsilu_destroy(h)
     R.rsilu_destroy(h0)
+
+
+def compare_Y(prob, ytau, mu=1.0, precision=0):
+    prm = R.rsilu_params_default(mu=mu, smode=R.S_CG, form=R.FORM_ALG2, ystore=R.Y_EXPLICIT, ytau=ytau,
+                                 cg_steps=8, precision=precision)
+    if precision == 1:
+        prm.smode = R.S_IDENTITY
+    code, h = R.rsilu_factor(prob.m, prob.n, prob.rowptr, prob.col, prob.val, prm)
+    assert code == R.OK, R.status_string(code)
+    try:
+        F = oracle.factor_problem(prob, mu=mu, smode="cg", ystore=True, ytau=ytau)
+        st = R.rsilu_get_stats(h)
+        assert st.nnz_y == F.Y.nnz
+        rp, cc, vv = R.rsilu_get_factor(h, R.YEXP, F.Y.nrows)
+        assert np.array_equal(rp, F.Y.rowptr) and np.array_equal(cc, F.Y.col)
+        assert np.array_equal(bits(vv), bits(F.Y.val))
+        return st
+    finally:
+        R.rsilu_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small", "c3-mini"])
+@pytest.mark.parametrize("ytau", [0.0, 1e-3, 1e-2])
+def test_explicit_Y_bit_exact(name, ytau):
+    """The explicit Y~ = L2 L1^{-1} with dropping (Section 3.2): every entry bit-identical to
+    the oracle's substitution (same finishing order, same separately rounded updates)."""
+    compare_Y(gen.by_name(name), ytau)
+
+
+def test_explicit_Y_fp32_handle_and_stats():
+    st = compare_Y(gen.by_name("c2-small"), 1e-2, precision=1)
+    assert st.nnz_y > 0
+
+
+def test_explicit_Y_full_size_bit_exact():
+    """The explicit Y~ of the 600000 x 400000 grid workload (ytau = 1e-2): bit-identical."""
+    st = compare_Y(gen.by_name("c2"), 1e-2)
+    assert st.nnz_y > 10_000_000
+
+
+def test_explicit_Y_rejected_configurations():
+    p = gen.tiny_c1()
+    bad = [dict(ystore=R.Y_EXPLICIT, smode=R.S_DENSE), dict(ystore=R.Y_EXPLICIT, trsv=R.TRSV_SYNCFREE),
+           dict(ystore=R.Y_EXPLICIT, ytau=-1.0), dict(ystore=R.Y_EXPLICIT, ytau=float("nan")), dict(ystore=2),
+           dict(smode=R.S_CG, cg_steps=257), dict(smode=R.S_CG, cg_steps=0)]
+    for kw in bad:
+        prm = R.rsilu_params_default(mu=1.0, **kw)
+        code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+        assert code == R.EINVAL and h is None, kw
+    # AUTO with the explicit Y~ never picks the dense S~
+    prm = R.rsilu_params_default(mu=1.0, ystore=R.Y_EXPLICIT)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK and R.rsilu_get_stats(h).smode == R.S_IDENTITY
+    assert R.rsilu_factor_nnz(h, R.YEXP) == R.rsilu_get_stats(h).nnz_y > 0
+    R.rsilu_destroy(h)
+    # without it, Y~ cannot be exported
+    prm = R.rsilu_params_default(mu=1.0)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert R.rsilu_factor_nnz(h, R.YEXP) == -1 and R.rsilu_get_stats(h).nnz_y == 0
+    R.rsilu_destroy(h)
+
+
+def test_add_rows_rebuilds_explicit_Y():
+    p = gen.by_name("c2-small")
+    q = gen.random_sparse(300, p.n, k=5, seed=71, transversal=False)
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_CG, cg_steps=8, form=R.FORM_ALG2, ystore=R.Y_EXPLICIT, ytau=1e-2)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    assert R.rsilu_add_rows(h, q.rowptr, q.col, q.val) == R.OK
+    F = oracle.add_rows(oracle.factor_problem(p, mu=1.0, smode="cg", ystore=True, ytau=1e-2), q.rowptr, q.col,
+                        q.val, tau=1e-2)
+    rp, cc, vv = R.rsilu_get_factor(h, R.YEXP, F.Y.nrows)
+    assert F.Y.nrows == p.m - p.n + 300
+    assert np.array_equal(rp, F.Y.rowptr) and np.array_equal(cc, F.Y.col) and np.array_equal(bits(vv), bits(F.Y.val))
+    R.rsilu_destroy(h)
