@@ -47,9 +47,12 @@ def parse():
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--maxit", type=int, default=2000)
-    ap.add_argument("--smode", default="cg", choices=["cg", "none", "identity", "dense", "auto"],
-                    help="S^ / M_b: CG steps on S~ (default), none (A1 only), identity, dense S~")
+    ap.add_argument("--smode", default="cg", choices=["cg", "cheb", "none", "identity", "dense", "auto"],
+                    help="S^ / M_b: CG steps on S~ (default), a Chebyshev polynomial in S~, none (A1 only), "
+                         "identity, dense S~")
     ap.add_argument("--cg-steps", type=int, default=32)
+    ap.add_argument("--poly-degree", type=int, default=0, help="Chebyshev degree (0: automatic)")
+    ap.add_argument("--poly-delta", type=float, default=0.9, help="spectral spread the automatic degree meets")
     ap.add_argument("--ystore", default="explicit", choices=["explicit", "implicit"],
                     help="Y~ = L2 L1^{-1} stored as a sparse matrix (default) or applied by sweeps")
     ap.add_argument("--ytau", type=float, default=1e-2, help="drop tolerance of the explicit Y~")
@@ -113,6 +116,9 @@ def step_bytes(st, vb=8):
         # p = res + b p; and the steps' set-up (res = p = u, w = 0, (res, res)) and result copy
         "cg_vectors": 8 * (2 * k + 6 * k + k + 3 * k),
         "cg_setup": 8 * (4 * k + k + 2 * k),
+        # one Chebyshev step besides its two products: q, r, d, w read, r, d, w written
+        "cheb_vectors": vb * 7 * k,
+        "cheb_setup": vb * 4 * k,
         # x += alpha p, r -= alpha q; rho = (z, h); p = h + beta p
         "vectors": 8 * (3 * n + 3 * m) + 16 * n + 24 * n,
         # FP32 preconditioner: input to FP32 and h back to FP64
@@ -121,21 +127,26 @@ def step_bytes(st, vb=8):
 
 
 def iteration_bytes(st, form, smode, vb=8, ystore="implicit", cg_steps=0):
-    """Algorithmic bytes of one iteration of Algorithm 1 with the given form."""
+    """Algorithmic bytes of one iteration of Algorithm 1 with the given form (cg_steps: the CG
+    steps, or the Chebyshev degree)."""
     b = step_bytes(st, vb)
     k = st.m - st.n
     it = b["spmv_A"] + b["spmv_AT"] + b["vectors"] + b["convert"]
     if vb == 4 and form == "alg3":
         it += 12 * (st.m - st.n)  # the m-vector r is converted, not only n entries
     corr = k > 0 and smode != "none"
-    cg = b["cg_setup"] + cg_steps * (b["spmv_Y"] + b["spmv_YT"] + vb * k + b["cg_vectors"]) if smode == "cg" else 0
+    cg = 0
+    if smode == "cg":
+        cg = b["cg_setup"] + cg_steps * (b["spmv_Y"] + b["spmv_YT"] + vb * k + b["cg_vectors"])
+    elif smode == "cheb":
+        cg = b["cheb_setup"] + cg_steps * (b["spmv_Y"] + b["spmv_YT"] + b["cheb_vectors"])
     if ystore == "explicit" and corr:
         # Y~ x (- or + an addend), S^, Y~^T w with an addend; two or four sweeps
         it += b["spmv_Y"] + vb * k + b["spmv_YT"] + vb * st.n + cg
         if form == "alg3":
             return it + b["trsv_L1"] + b["trsv_U"]
         return it + b["trsv_UT"] + b["trsv_L1T"] + b["trsv_L1"] + b["trsv_U"]
-    if smode == "cg" and corr:
+    if smode in ("cg", "cheb") and corr:
         # implicit S~ products: L2^T, L1^T, L1, L2 with an addend
         it += cg - cg_steps * (b["spmv_Y"] + b["spmv_YT"]) + cg_steps * (
             b["spmv_L2T"] + b["trsv_L1T"] + b["trsv_L1"] + b["spmv_L2"])
@@ -190,7 +201,8 @@ def cpu_baseline(prob, args, iters_per_solve):
         if smode == "auto":
             smode = "dense" if 0 < prob.m - prob.n <= 4096 and args.ystore != "explicit" else "identity"
         F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, cg_steps=args.cg_steps,
-                                  ystore=args.ystore == "explicit", ytau=args.ytau)
+                                  ystore=args.ystore == "explicit", ytau=args.ytau, poly_degree=args.poly_degree,
+                                  poly_delta=args.poly_delta)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         def run(maxit):
@@ -222,6 +234,7 @@ def cpu_baseline(prob, args, iters_per_solve):
         "kind": "oracle",
         "sample": "oracle " + ("LSQR" if args.krylov == "lsqr" else "Algorithm 1") + " + Algorithm " + args.form[-1] +
                   (" with %d CG steps on S~ (%s Y~)" % (args.cg_steps, args.ystore) if smode == "cg" else
+                   " with a degree-%d Chebyshev M_b (%s Y~)" % (F.cheb_degree, args.ystore) if smode == "cheb" else
                    " (S^ %s)" % smode) +
                   " (plain C substitutions and products, numpy vectors, 1 thread) on the same "
                   "workload: %d iterations timed (%.1f s, %.1f ms/iteration), scaled to the %d iterations of one "
@@ -231,7 +244,7 @@ def cpu_baseline(prob, args, iters_per_solve):
 
 
 def make_solver(R, prob, args):
-    smode = {"cg": R.S_CG, "none": R.S_NONE, "identity": R.S_IDENTITY, "dense": R.S_DENSE,
+    smode = {"cg": R.S_CG, "cheb": R.S_CHEB, "none": R.S_NONE, "identity": R.S_IDENTITY, "dense": R.S_DENSE,
              "auto": R.S_AUTO}[args.smode]
     return R.Solver.from_problem(
         prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, maxit=args.maxit,
@@ -240,7 +253,7 @@ def make_solver(R, prob, args):
         precision={"fp64": R.PREC_FP64, "fp32": R.PREC_FP32}[args.precision],
         krylov={"pcgls": R.KRYLOV_PCGLS, "lsqr": R.KRYLOV_LSQR}[args.krylov],
         cg_steps=max(1, args.cg_steps), ystore={"explicit": R.Y_EXPLICIT, "implicit": R.Y_IMPLICIT}[args.ystore],
-        ytau=args.ytau)
+        ytau=args.ytau, poly_degree=args.poly_degree, poly_delta=args.poly_delta)
 
 
 def timed_solves(prob, args, steps, warmup):
@@ -278,10 +291,12 @@ def timed_solves(prob, args, steps, warmup):
     R.rsilu_set_profiling(S.h, 0)
     S.close()
     _, code, iters, atr, rel = result
-    smode_used = {R.S_NONE: "none", R.S_IDENTITY: "identity", R.S_DENSE: "dense", R.S_CG: "cg"}[st.smode]
+    smode_used = {R.S_NONE: "none", R.S_IDENTITY: "identity", R.S_DENSE: "dense", R.S_CG: "cg",
+                  R.S_CHEB: "cheb"}[st.smode]
     status = {R.OK: "converged", R.NOT_CONVERGED: "not_converged", R.BREAKDOWN: "breakdown"}.get(code, str(code))
     b_iter = iteration_bytes(st, args.form, smode_used, 4 if args.precision == "fp32" else 8,
-                             ystore=args.ystore, cg_steps=args.cg_steps if smode_used == "cg" else 0)
+                             ystore=args.ystore, cg_steps=args.cg_steps if smode_used == "cg" else
+                             (st.cheb_degree if smode_used == "cheb" else 0))
     return dict(st=st, t_setup=t_setup, total=total, lat=lat, prof=prof, code=code, iters=iters, atr=atr, rel=rel,
                 smode=smode_used, status=status, t_solve=total / steps, b_solve=(iters + 1) * b_iter,
                 p50=1e3 * float(np.percentile(lat, 50)), p99=1e3 * float(np.percentile(lat, 99)))
@@ -310,6 +325,8 @@ def describe(args, r):
     }
     if r["smode"] == "cg":
         cfg["cg_steps"] = args.cg_steps
+    if r["smode"] == "cheb":
+        cfg["chebyshev"] = {"degree": int(st.cheb_degree), "b": st.cheb_b, "delta": args.poly_delta}
     if r["smode"] != "none" and st.m > st.n:
         cfg["Y"] = {"store": args.ystore, "ytau": args.ytau if args.ystore == "explicit" else None,
                     "nnz_y": int(st.nnz_y)}

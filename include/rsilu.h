@@ -69,6 +69,18 @@ enum {
     RSILU_S_NONE = 2,     /* no A2 correction: w = 0, so that Algorithm 3 gives
                              h = U^{-1} L1^{-1} r1 and Algorithm 2 gives
                              h = M_a^{-1} z */
+    RSILU_S_CHEB = 4,     /* M_b^{-1} = a fixed Chebyshev polynomial in S~ (an approximation
+                             S^ of S~, Section 3.2): poly_degree steps of the Chebyshev
+                             iteration on S~ w = u from w = 0 over [1, b], b = 1.05 times a
+                             50-step power-iteration estimate of lambda_max(S~) taken at
+                             setup. Linear in u and symmetric positive definite: the default
+                             degree is the smallest even K with (b - 1) / T_K((b+1)/(b-1)) <=
+                             poly_delta, so the Algorithm 2 operator times A~^T A~ has its
+                             eigenvalues in [1 - poly_delta, 1 + poly_delta] (A~ = [L1; Y~ L1] U
+                             with the explicit Y~, [L1; L2] U otherwise), and an even degree
+                             keeps it positive definite beyond b. LSQR may use it. S~ products
+                             as for RSILU_S_CG. FP64 or FP32 (with the explicit Y~); hybrid or
+                             level schedule */
     RSILU_S_CG = 3        /* cg_steps steps of conjugate gradients on S~ w = u from
                              w = 0 (Section 3.2; Table 3(a) uses two), S~ applied
                              implicitly as d + L2 L1^{-1} L1^{-T} L2^T d, or as
@@ -105,8 +117,9 @@ enum {
  *          that M in exact arithmetic (Section 1 notes the equivalence of CGLS
  *          and LSQR), usually better behaved in floating point. It needs a
  *          symmetric positive definite M^{-1}: the Algorithm 2 form with S^
- *          none or dense (AUTO resolves to dense when m - n <= 4096 in FP64,
- *          else to none), and the hybrid or level schedule. Its stop test uses
+ *          none, dense or Chebyshev (AUTO resolves to dense when m - n <= 4096
+ *          in FP64 with Y~ implicit, else to none), and the hybrid or level
+ *          schedule. Its stop test uses
  *          the recurrence ||A^T r|| = |phibar c| ||D^{-1} s||. */
 enum {
     RSILU_KRYLOV_PCGLS = 0,
@@ -118,8 +131,8 @@ enum {
  * Algorithm 3 or Algorithm 2 runs in FP32 (its input converted from and its
  * output back to FP64); the products with A, the Krylov vectors, the
  * recurrence scalars, the norms and the exit residual stay FP64. FP32 needs
- * the hybrid or level schedule and S^ = I or none (EINVAL otherwise; AUTO
- * resolves to I). */
+ * the hybrid or level schedule and S^ = I, none, or Chebyshev with the explicit
+ * Y~ (EINVAL otherwise; AUTO resolves to I or none). */
 enum {
     RSILU_PREC_FP64 = 0,
     RSILU_PREC_FP32 = 1
@@ -177,6 +190,11 @@ typedef struct {
                           Y~ that is zero or below ytau in magnitude when its substitution
                           step finishes is dropped and not propagated; 0 keeps every
                           nonzero (Y~ exact up to rounding); default 1e-2 */
+    int32_t poly_degree; /* RSILU_S_CHEB: steps of the Chebyshev iteration, 1..512, or 0 to
+                            choose the smallest even degree that meets poly_delta; default 0 */
+    double poly_delta;   /* RSILU_S_CHEB: bound on the spread of the preconditioned spectrum
+                            around 1 that the automatic degree meets, 0 < poly_delta < 1;
+                            default 0.9 */
 } rsilu_params_t;
 
 typedef struct {
@@ -195,6 +213,9 @@ typedef struct {
     int32_t reserved;
     size_t device_bytes;   /* what rsilu_upload needs */
     int64_t nnz_y;         /* entries of the explicit Y~ (0 when applied implicitly) */
+    double cheb_b;         /* RSILU_S_CHEB: upper end b of the Chebyshev interval [1, b] */
+    int32_t cheb_degree;   /* RSILU_S_CHEB: steps of the Chebyshev iteration (0: S~ = I) */
+    int32_t reserved2;
 } rsilu_stats_t;
 
 typedef struct rsilu_ctx *rsilu_handle_t;
@@ -203,7 +224,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
  * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1, sweep = AUTO,
- * ystore = IMPLICIT, ytau = 1e-2. */
+ * ystore = IMPLICIT, ytau = 1e-2, poly_degree = 0, poly_delta = 0.9. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

@@ -40,7 +40,7 @@ DCsr dcsr(const Ctx &c, const DevCsrOff &o)
 DPlan dplan(const Ctx &c, const DevPlanOff &o)
 {
     return DPlan{at<int32_t>(c, o.long_rows), at<int32_t>(c, o.seg_ptr), at<int32_t>(c, o.seg_beg),
-                 at<int32_t>(c, o.seg_end), o.nlong, o.nseg, o.lanes, o.long_thresh};
+                 at<int32_t>(c, o.seg_end), o.nlong, o.nseg, o.lanes, o.long_thresh, o.unroll};
 }
 
 DTri dtri(const Ctx &c, const DevTriOff &o)
@@ -308,6 +308,37 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
     (void)n;
 }
 
+// Step 2 of Algorithm 3 / step 3 of Algorithm 2 with S^ by Chebyshev (RSILU_S_CHEB):
+// u <- w after cheb_K steps of the Chebyshev iteration on S~ w = u over [1, cheb_b]
+// from w = 0, each step one product with S~ (two with the explicit Y~; L2^T, two
+// sweeps and L2 otherwise) and one fused vector update; the coefficients are fixed
+// at setup, so no scalar is computed on the device. Temporaries: g, c2, s2 and the
+// four (m - n)-vectors of the CG steps.
+template <class T>
+void cheb_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const int32_t *done)
+{
+    const int32_t k = c.L2.nrows;
+    if (c.cheb_K == 0 || k == 0) return;  // S~ = I: w = u
+    T *w = at<T>(c, c.lay.cg_w), *r = at<T>(c, c.lay.cg_r), *d = at<T>(c, c.lay.cg_p), *q = at<T>(c, c.lay.cg_q);
+    ProfScope ps(c, s, RSILU_PROF_DENSE_S);
+    launch_cheb_init<T>(s, k, W.u, r, d, w, c.cheb_theta, done);
+    for (int32_t j = 0; j < c.cheb_K; ++j) {
+        if (yexplicit(c)) {
+            spmv_y<T>(c, s, P, W, true, d, W.g, nullptr, EPI_PLAIN, done);
+            spmv_y<T>(c, s, P, W, false, W.g, q, nullptr, EPI_PLAIN, done);
+        } else {
+            launch_spmv<T>(s, W.L2T, P.pL2T, d, W.g, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, done);
+            trsv<T>(c, s, P, W, W.L1b, c.lvL1T, c.swL1T, c.lay.L1b, W.g, W.c2, nullptr, nullptr, 1, done,
+                    RSILU_PROF_TRSV_L1T);
+            trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.c2, W.s2, nullptr, nullptr, 2, done,
+                    RSILU_PROF_TRSV_L1);
+            launch_spmv<T>(s, W.L2, P.pL2, W.s2, q, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, done);
+        }
+        launch_cheb_update<T>(s, k, q, r, d, w, j + 1 == c.cheb_K ? W.u : nullptr, c.cheb_c1[(size_t)j],
+                              c.cheb_c2[(size_t)j], done);
+    }
+}
+
 // Algorithm 3 on the residual r (pivot order) -> hout, in precision T. For
 // sync-free solves the outputs t, gp, v and hout must have been
 // sentinel-filled, tickets cleared.
@@ -321,6 +352,7 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
         if constexpr (std::is_same<T, double>::value) {
             if (c.smode == RSILU_S_CG) cg_solve_S(c, s, P, W, done);
         }
+        if (c.smode == RSILU_S_CHEB) cheb_solve_S<T>(c, s, P, W, done);
         spmv_y<T>(c, s, P, W, true, W.u, W.y, r, EPI_ADD, done);
         trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.y, W.v, nullptr, nullptr, 2, done, RSILU_PROF_TRSV_L1);
         trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.v, hout, nullptr, nullptr, 3, done, RSILU_PROF_TRSV_U);
@@ -346,6 +378,7 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
             cg_solve_S(c, s, P, W, done);
         }
     }
+    if (c.smode == RSILU_S_CHEB) cheb_solve_S<T>(c, s, P, W, done);
     // step 3: y = r1 + Y^T w with Y^T w = L1^{-T} (L2^T w)
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
@@ -396,6 +429,7 @@ void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
         if constexpr (std::is_same<T, double>::value) {
             if (c.smode == RSILU_S_CG) cg_solve_S(c, s, P, W, done);
         }
+        if (c.smode == RSILU_S_CHEB) cheb_solve_S<T>(c, s, P, W, done);
         spmv_y<T>(c, s, P, W, true, W.u, W.y, W.gp, EPI_SUB, done);
         trsv<T>(c, s, P, W, W.L1f, c.lvL1, c.swL1, c.lay.L1f, W.y, W.s2, nullptr, nullptr, 0, done, RSILU_PROF_TRSV_L1);
         trsv<T>(c, s, P, W, W.Ub, c.lvU, c.swU, c.lay.Ub, W.s2, hout, nullptr, nullptr, 1, done, RSILU_PROF_TRSV_U);
@@ -416,6 +450,7 @@ void apply_alg2(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
             cg_solve_S(c, s, P, W, done);
         }
     }
+    if (c.smode == RSILU_S_CHEB) cheb_solve_S<T>(c, s, P, W, done);
     // steps 4-5: y = g + L1^{-T} (-L2^T v_b), then L1 s2 = y, U h = s2
     {
         ProfScope ps(c, s, RSILU_PROF_SPMV_L2T);
@@ -611,6 +646,8 @@ void rsilu_params_default(rsilu_params_t *p)
     p->sweep = RSILU_SWEEP_AUTO;
     p->ystore = RSILU_Y_IMPLICIT;
     p->ytau = 1e-2;
+    p->poly_degree = 0;
+    p->poly_delta = 0.9;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)
@@ -679,6 +716,8 @@ rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *s)
     s->smode = h->smode;
     s->device_bytes = h->lay.total;
     s->nnz_y = yexplicit(*h) ? h->Y.nnz() : 0;
+    s->cheb_b = h->cheb_b;
+    s->cheb_degree = h->cheb_K;
     return RSILU_OK;
 }
 

@@ -66,6 +66,7 @@ struct LoTri {
 // split into segments of at most `seg` entries, reduced in a fixed order.
 struct SpmvPlan {
     int32_t lanes = 8;           // lanes per row for ordinary rows
+    int32_t unroll = 2;          // entries per lane loaded at once (paired-row kernel)
     int32_t long_thresh = 0;     // rows longer than this are "long"
     std::vector<int32_t> long_rows;
     std::vector<int32_t> seg_ptr;   // long row i owns segments seg_ptr[i]..seg_ptr[i+1]
@@ -82,7 +83,7 @@ struct DevCsrOff {
 };
 struct DevPlanOff {
     size_t long_rows = 0, seg_ptr = 0, seg_beg = 0, seg_end = 0;
-    int32_t nlong = 0, nseg = 0, lanes = 8, long_thresh = 0;
+    int32_t nlong = 0, nseg = 0, lanes = 8, long_thresh = 0, unroll = 2;
 };
 struct DevTriOff {
     DevCsrOff a;
@@ -119,7 +120,7 @@ struct Layout {
     size_t u = 0;                                                              // m - n
     size_t lo_rhs = 0, lo_add = 0;  // level-ordered right-hand side and addend of a sweep (n)
     size_t f32a = 0, f32b = 0;      // FP32 preconditioner: converted input and output (m floats each)
-    size_t cg_w = 0, cg_r = 0, cg_p = 0, cg_q = 0;  // CG on S~ (m - n each)
+    size_t cg_w = 0, cg_r = 0, cg_p = 0, cg_q = 0;  // CG or Chebyshev steps on S~ (m - n each)
     size_t l_v = 0, l_mv = 0, l_w = 0;              // LSQR: v, M v, w (n each)
     size_t partials = 0;  // reduction partials
     int32_t npartials = 0;
@@ -148,6 +149,11 @@ struct Ctx {
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
     Csr Y, YT;                     // explicit Y~ = L2 L1^{-1} (Section 3.2) and its transpose
     SpmvPlan plY, plYT;
+    // Chebyshev M_b (RSILU_S_CHEB): interval [1, cheb_b], cheb_K steps with coefficients
+    // d <- c1[j] d + c2[j] r, starting from d = u / theta
+    double cheb_b = 1.0, cheb_theta = 1.0;
+    int32_t cheb_K = 0;
+    std::vector<double> cheb_c1, cheb_c2;
     // Section 3.4, removed rows: R = the removed rows of A_hat that were in A1, and the packed
     // lower Cholesky factor of W = I - R M^{-1} R^T (Woodbury update of the preconditioner)
     Csr R, RT;
@@ -188,6 +194,7 @@ rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const i
 rsilu_status_t remove_rows(Ctx &c, int64_t count, const int64_t *rows);
 rsilu_status_t build_woodbury(Ctx &c);
 void build_explicit_Y(Ctx &c);
+void build_chebyshev(Ctx &c);
 inline bool yexplicit(const Ctx &c) { return c.prm.ystore == RSILU_Y_EXPLICIT; }
 // device driver (capi.hip): drop a captured iteration graph
 void release_graph(Ctx &c);

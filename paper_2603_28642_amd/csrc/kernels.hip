@@ -251,16 +251,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh
     }
 }
 
-// Two or more rows per lane group (RPT) for rows of up to 2G entries: the
-// row pointers of all of a thread's rows, then their first two entries per
+// Two or more rows per lane group (RPT) for rows of up to U*G entries: the
+// row pointers of all of a thread's rows, then their first U entries per
 // lane (at clamped in-bounds positions, masked values), then the gathers are
 // all in flight before any is used, so a block spends one memory latency per
 // dependent step for RPT rows instead of one. Rows are interleaved across the
-// block so one load instruction covers consecutive rows; entries past 2G go
+// block so one load instruction covers consecutive rows; entries past U*G go
 // through a loop. The stop flag is read beside the first loads and masks the
 // stores (every load is in bounds either way). Rows longer than long_thresh
 // are left to the segment kernel, as in k_spmv. Needs nnz >= 1.
-template <int G, int RPT, int EPI, class T>
+template <int G, int RPT, int U, int EPI, class T>
 __global__ __launch_bounds__(kBlock) void k_spmv_mr(DCsrT<T> a, int32_t long_thresh, const T *__restrict__ x,
                                                      T *__restrict__ y, const T *__restrict__ aux,
                                                      double *__restrict__ partials, const int32_t *done)
@@ -277,29 +277,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mr(DCsrT<T> a, int32_t long_thr
         b[j] = a.ptr[rc];
         e[j] = a.ptr[rc + 1];
     }
-    int c[RPT][2];
-    T v[RPT][2];
+    int c[RPT][U];
+    T v[RPT][U];
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int k = b[j] + gl + u * G;
             const int kc = max(min(k, e[j] - 1), 0);
             c[j][u] = a.col[kc];
             const T vv = a.val[kc];
             v[j][u] = k < e[j] ? vv : (T)0;
         }
-    T xv[RPT][2];
+    T xv[RPT][U];
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
 #pragma unroll
-        for (int u = 0; u < 2; ++u) xv[j][u] = x[c[j][u]];
+        for (int u = 0; u < U; ++u) xv[j][u] = x[c[j][u]];
     double contrib = 0.0;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         T sum = v[j][0] * xv[j][0];
-        sum += v[j][1] * xv[j][1];
-        for (int k = b[j] + gl + 2 * G; k < e[j]; k += G) sum += a.val[k] * x[a.col[k]];
+#pragma unroll
+        for (int u = 1; u < U; ++u) sum += v[j][u] * xv[j][u];
+        for (int k = b[j] + gl + U * G; k < e[j]; k += G) sum += a.val[k] * x[a.col[k]];
         sum = group_sum<G>(sum);
         const int row = base + j * RPB;
         if (live && row < a.nrows && e[j] - b[j] <= long_thresh && gl == 0) {
@@ -601,6 +602,40 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(int32_t k, const double *__re
     if (stop_now(done)) return;
     const double bt = st->cg_beta;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) p[i] = res[i] + bt * p[i];
+}
+
+// Chebyshev steps on S~ w = u (RSILU_S_CHEB): the set-up r = u, d = u / theta, w = 0,
+// and one step's update once q = Y~ (Y~^T d) is formed: w += d, r -= d + q,
+// d = c1 d + c2 r; the last step also writes w to out.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cheb_init(int32_t k, const T *__restrict__ u, T *__restrict__ r,
+                                                      T *__restrict__ d, T *__restrict__ w, T theta,
+                                                      const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        const T ui = u[i];
+        r[i] = ui;
+        d[i] = ui / theta;
+        w[i] = (T)0;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cheb_update(int32_t k, const T *__restrict__ q, T *__restrict__ r,
+                                                        T *__restrict__ d, T *__restrict__ w, T *__restrict__ out,
+                                                        T c1, T c2, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        const T di = d[i];
+        const T wi = w[i] + di;
+        const T ri = r[i] - (di + q[i]);
+        w[i] = wi;
+        r[i] = ri;
+        d[i] = c1 * di + c2 * ri;
+        if (out) out[i] = wi;
+    }
 }
 
 template <class A, class B>
@@ -1226,31 +1261,32 @@ int grid_for(long long n, int cap = 8192)
     return (int)g;
 }
 
+// Kernel of a product: the paired-row kernel with U entries per lane in flight for
+// G = lanes <= 32 (U from the plan), one row per group of 64 lanes beyond.
 template <int EPI, class T>
-void spmv_dispatch(hipStream_t s, int lanes, int blocks, const DCsrT<T> &a, int32_t lt, const T *x, T *y,
+void spmv_dispatch(hipStream_t s, int lanes, int unroll, int blocks, const DCsrT<T> &a, int32_t lt, const T *x, T *y,
                    const T *aux, double *partials, const int32_t *done)
 {
-#define RSILU_SPMV_CASE(G)                                                                                        \
-    case G:                                                                                                       \
-        hipLaunchKernelGGL((k_spmv<G, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done); \
-        break;
-    switch (lanes) {
-    case 4:
-        hipLaunchKernelGGL((k_spmv_mr<4, kSpmvRows, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux,
-                           partials, done);
-        break;
-    case 8:
-        hipLaunchKernelGGL((k_spmv_mr<8, kSpmvRows, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux,
-                           partials, done);
-        break;
-        RSILU_SPMV_CASE(2)
-        RSILU_SPMV_CASE(16)
-        RSILU_SPMV_CASE(32)
-        RSILU_SPMV_CASE(64)
-    default:
+#define RSILU_SPMV_MR(G, U)                                                                                    \
+    hipLaunchKernelGGL((k_spmv_mr<G, kSpmvRows, U, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, \
+                       partials, done)
+    if (lanes == 4 && unroll == 2) RSILU_SPMV_MR(4, 2);
+    else if (lanes == 8 && unroll == 2) RSILU_SPMV_MR(8, 2);
+    else if (lanes == 8) RSILU_SPMV_MR(8, 4);
+    else if (lanes == 16) RSILU_SPMV_MR(16, 4);
+    else if (lanes == 32) RSILU_SPMV_MR(32, 4);
+    else if (lanes == 2)
+        hipLaunchKernelGGL((k_spmv<2, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done);
+    else
         hipLaunchKernelGGL((k_spmv<64, EPI, T>), dim3(blocks), dim3(kBlock), 0, s, a, lt, x, y, aux, partials, done);
-    }
-#undef RSILU_SPMV_CASE
+#undef RSILU_SPMV_MR
+}
+
+// Rows per block of the kernel spmv_dispatch picks.
+int spmv_rows_per_block(int lanes)
+{
+    if (lanes >= 4 && lanes <= 32) return (kBlock / lanes) * kSpmvRows;
+    return kBlock / (lanes == 2 ? 2 : 64);
 }
 
 }  // namespace
@@ -1268,21 +1304,20 @@ void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, 
                  Fin fin, double *partials, T *segpart, DevState *st, const int32_t *done)
 {
     if (a.nrows <= 0) return;
-    const int lanes = pl.lanes;
-    // rows per block: 4 and 8 lanes per row take kSpmvRows rows per lane group
-    const int rpb = (kBlock / lanes) * (lanes == 4 || lanes == 8 ? kSpmvRows : 1);
+    const int lanes = pl.lanes, unroll = pl.unroll;
+    const int rpb = spmv_rows_per_block(lanes);
     const int blocks = (int)((a.nrows + rpb - 1) / rpb);
     constexpr bool fp64 = std::is_same<T, double>::value;
     switch (epi) {
-    case EPI_PLAIN: spmv_dispatch<EPI_PLAIN, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_SUB: spmv_dispatch<EPI_SUB, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_NEG: spmv_dispatch<EPI_NEG, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
-    case EPI_ADD: spmv_dispatch<EPI_ADD, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_PLAIN: spmv_dispatch<EPI_PLAIN, T>(s, lanes, unroll, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_SUB: spmv_dispatch<EPI_SUB, T>(s, lanes, unroll, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_NEG: spmv_dispatch<EPI_NEG, T>(s, lanes, unroll, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
+    case EPI_ADD: spmv_dispatch<EPI_ADD, T>(s, lanes, unroll, blocks, a, pl.long_thresh, x, y, aux, partials, done); break;
     case EPI_SQ:
-        if constexpr (fp64) spmv_dispatch<EPI_SQ, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done);
+        if constexpr (fp64) spmv_dispatch<EPI_SQ, T>(s, lanes, unroll, blocks, a, pl.long_thresh, x, y, aux, partials, done);
         break;
     case EPI_WSQ:
-        if constexpr (fp64) spmv_dispatch<EPI_WSQ, T>(s, lanes, blocks, a, pl.long_thresh, x, y, aux, partials, done);
+        if constexpr (fp64) spmv_dispatch<EPI_WSQ, T>(s, lanes, unroll, blocks, a, pl.long_thresh, x, y, aux, partials, done);
         break;
     }
     if (pl.nseg > 0)
@@ -1520,6 +1555,28 @@ void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const
 {
     hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(k)), dim3(kBlock), 0, s, k, res, p, st, done);
 }
+
+template <class T>
+void launch_cheb_init(hipStream_t s, int32_t k, const T *u, T *r, T *d, T *w, double theta, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_cheb_init<T>, dim3(grid_for(k)), dim3(kBlock), 0, s, k, u, r, d, w, (T)theta, done);
+}
+template void launch_cheb_init<double>(hipStream_t, int32_t, const double *, double *, double *, double *, double,
+                                       const int32_t *);
+template void launch_cheb_init<float>(hipStream_t, int32_t, const float *, float *, float *, float *, double,
+                                      const int32_t *);
+
+template <class T>
+void launch_cheb_update(hipStream_t s, int32_t k, const T *q, T *r, T *d, T *w, T *out, double c1, double c2,
+                        const int32_t *done)
+{
+    hipLaunchKernelGGL(k_cheb_update<T>, dim3(grid_for(k)), dim3(kBlock), 0, s, k, q, r, d, w, out, (T)c1, (T)c2,
+                       done);
+}
+template void launch_cheb_update<double>(hipStream_t, int32_t, const double *, double *, double *, double *, double *,
+                                         double, double, const int32_t *);
+template void launch_cheb_update<float>(hipStream_t, int32_t, const float *, float *, float *, float *, float *,
+                                        double, double, const int32_t *);
 
 void launch_cvt(hipStream_t s, int32_t n, const double *in, float *out, const int32_t *done)
 {

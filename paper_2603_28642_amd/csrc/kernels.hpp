@@ -48,6 +48,7 @@ struct DPlan {
     const int32_t *seg_beg;
     const int32_t *seg_end;
     int32_t nlong, nseg, lanes, long_thresh;
+    int32_t unroll;  // entries per lane loaded at once by the paired-row kernel (2 or 4)
 };
 
 // Triangular operator: strictly triangular CSR, optional diagonal, level-ordered rows,
@@ -163,5 +164,12 @@ void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double
 void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
                       const DevState *st, const int32_t *done);
 void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done);
+// Chebyshev steps on S~: r = u, d = u / theta, w = 0; then per step, with q = Y~ (Y~^T d):
+// w += d, r -= d + q, d = c1 d + c2 r, and out = w when out is given (the last step)
+template <class T>
+void launch_cheb_init(hipStream_t s, int32_t k, const T *u, T *r, T *d, T *w, double theta, const int32_t *done);
+template <class T>
+void launch_cheb_update(hipStream_t s, int32_t k, const T *q, T *r, T *d, T *w, T *out, double c1, double c2,
+                        const int32_t *done);
 
 }  // namespace rsilu

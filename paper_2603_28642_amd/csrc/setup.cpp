@@ -493,21 +493,27 @@ int32_t lanes_for(double avg)
     return g;
 }
 
-// Lanes per row of a CSR product: 4 up to 8 entries per row on average and 8
-// up to 16 (two rows per lane group, both entries of a lane loaded at once),
-// else the power of two at or above the mean.
+// Lanes per row of a CSR product and entries per lane loaded at once: two rows
+// per lane group with 4 lanes up to 8 entries per row on average, 8 lanes up to
+// 16 (2 entries per lane) and up to 32 (4), 16 lanes up to 64 and 32 lanes up to
+// 128 (4 entries per lane); one row per 64-lane group beyond.
 int32_t spmv_lanes(double avg)
 {
     if (avg <= 8.0) return 4;
-    if (avg <= 16.0) return 8;
-    return lanes_for(avg);
+    if (avg <= 32.0) return 8;
+    if (avg <= 64.0) return 16;
+    if (avg <= 128.0) return 32;
+    return 64;
 }
+
+int32_t spmv_unroll(double avg) { return avg <= 16.0 ? 2 : 4; }
 
 SpmvPlan plan_spmv(const Csr &a)
 {
     SpmvPlan pl;
     double avg = a.nrows ? (double)a.nnz() / (double)a.nrows : 1.0;
     pl.lanes = a.nnz() > 0 ? spmv_lanes(avg) : 2;  // the paired-row kernel needs an entry to clamp to
+    pl.unroll = spmv_unroll(avg);
     pl.long_thresh = std::max<int32_t>(32 * pl.lanes, 2048);
     const int32_t seg = 4096;
     pl.seg_ptr.push_back(0);
@@ -651,6 +657,89 @@ void build_explicit_Y(Ctx &c)
     c.plYT = plan_spmv(c.YT);
 }
 
+// Section 3.2 lets an approximation S^ of S~ stand in for it when that is cheaper to
+// solve with; RSILU_S_CHEB takes M_b^{-1} = the polynomial in S~ of K Chebyshev steps
+// over [1, b]. S~ = I + Y~ Y~^T has its spectrum in [1, lambda_max]; b is 1.05 times a
+// power-iteration estimate of lambda_max (50 products from the all-ones vector, the
+// last Rayleigh quotient). K is the smallest even degree with (b - 1) / T_K(sigma) <=
+// poly_delta, sigma = (b + 1)/(b - 1) (then 1 + (t - 1) r_K(t) stays within
+// poly_delta of 1 on [1, b], and positive beyond b for even K), unless poly_degree
+// fixes it. The step coefficients of the three-term recurrence are formed here once:
+// theta = (b + 1)/2, delta = (b - 1)/2, rho_0 = delta/theta, rho_{j+1} = 1/(2 theta/delta
+// - rho_j), c1_j = rho_{j+1} rho_j, c2_j = 2 rho_{j+1}/delta.
+void build_chebyshev(Ctx &c)
+{
+    const int64_t k = c.L2.nrows, n = c.n;
+    c.cheb_c1.clear();
+    c.cheb_c2.clear();
+    c.cheb_b = 1.0;
+    c.cheb_K = 0;
+    if (k == 0) return;
+    // S~ d = d + Y~ (Y~^T d): explicit, or L2 L1^{-1} L1^{-T} L2^T d
+    std::vector<double> g((size_t)n), t((size_t)n), q((size_t)k);
+    auto spmv = [](const Csr &a, const double *x, double *y) {
+        for (int32_t i = 0; i < a.nrows; ++i) {
+            double sum = 0.0;
+            for (int32_t e = a.ptr[i]; e < a.ptr[(size_t)i + 1]; ++e) sum += a.val[e] * x[a.col[e]];
+            y[i] = sum;
+        }
+    };
+    auto S = [&](const std::vector<double> &d, std::vector<double> &out) {
+        if (yexplicit(c)) {
+            spmv(c.YT, d.data(), g.data());
+            spmv(c.Y, g.data(), q.data());
+        } else {
+            spmv(c.L2T, d.data(), g.data());
+            for (int64_t r = n - 1; r >= 0; --r) {  // L1^T t = g (unit upper, by rows of L1^T)
+                double sum = g[(size_t)r];
+                for (int32_t e = c.L1T.ptr[r]; e < c.L1T.ptr[(size_t)r + 1]; ++e) sum -= c.L1T.val[e] * t[c.L1T.col[e]];
+                t[(size_t)r] = sum;
+            }
+            for (int64_t r = 0; r < n; ++r) {  // L1 g = t
+                double sum = t[(size_t)r];
+                for (int32_t e = c.L1.ptr[r]; e < c.L1.ptr[(size_t)r + 1]; ++e) sum -= c.L1.val[e] * g[c.L1.col[e]];
+                g[(size_t)r] = sum;
+            }
+            spmv(c.L2, g.data(), q.data());
+        }
+        for (int64_t i = 0; i < k; ++i) out[(size_t)i] = d[(size_t)i] + q[(size_t)i];
+    };
+    std::vector<double> v((size_t)k, 1.0 / std::sqrt((double)k)), w((size_t)k);
+    double lam = 1.0;
+    for (int it = 0; it < 50; ++it) {
+        S(v, w);
+        double vw = 0.0, ww = 0.0;
+        for (int64_t i = 0; i < k; ++i) {
+            vw += v[(size_t)i] * w[(size_t)i];
+            ww += w[(size_t)i] * w[(size_t)i];
+        }
+        lam = vw;
+        const double nw = std::sqrt(ww);
+        if (!(nw > 0.0) || !std::isfinite(nw)) break;
+        for (int64_t i = 0; i < k; ++i) v[(size_t)i] = w[(size_t)i] / nw;
+    }
+    if (!(lam > 1.0) || !std::isfinite(lam)) return;  // S~ = I: M_b^{-1} = I
+    const double b = 1.05 * lam;
+    const double sigma = (b + 1.0) / (b - 1.0);
+    int32_t K = c.prm.poly_degree;
+    if (K == 0) {
+        K = 2;
+        while (K < 512 && (b - 1.0) / std::cosh(K * std::acosh(sigma)) > c.prm.poly_delta) K += 2;
+    }
+    c.cheb_b = b;
+    c.cheb_K = K;
+    const double theta = (b + 1.0) / 2.0, half = (b - 1.0) / 2.0;
+    const double sig = theta / half;
+    double rho = 1.0 / sig;
+    for (int32_t j = 0; j < K; ++j) {
+        const double rho_new = 1.0 / (2.0 * sig - rho);
+        c.cheb_c1.push_back(rho_new * rho);
+        c.cheb_c2.push_back(2.0 * rho_new / half);
+        rho = rho_new;
+    }
+    c.cheb_theta = theta;
+}
+
 // S~ = I + Y~ Y~^T with Y~^T = L1^{-T} L2^T, factored by Cholesky (Section 3.2),
 // packed lower factor by rows.
 rsilu_status_t build_dense_S(Ctx &c)
@@ -705,12 +794,16 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     if (P.p < 0 || !(P.tau >= 0.0) || !(P.mu > 0.0 && P.mu <= 1.0) || !(P.small > 0.0) ||
         !std::isfinite(P.tau) || P.maxit < 0 || P.poll < 1 ||
         (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_IDENTITY && P.smode != RSILU_S_DENSE &&
-         P.smode != RSILU_S_NONE && P.smode != RSILU_S_CG) ||
+         P.smode != RSILU_S_NONE && P.smode != RSILU_S_CG && P.smode != RSILU_S_CHEB) ||
         (P.krylov != RSILU_KRYLOV_PCGLS && P.krylov != RSILU_KRYLOV_LSQR) || (P.graph != 0 && P.graph != 1) ||
         P.sweep < RSILU_SWEEP_AUTO || P.sweep > RSILU_SWEEP_ROWS ||
         (P.krylov == RSILU_KRYLOV_LSQR &&
          (P.form != RSILU_FORM_ALG2 || P.trsv == RSILU_TRSV_SYNCFREE ||
-          (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_NONE && P.smode != RSILU_S_DENSE))) ||
+          (P.smode != RSILU_S_AUTO && P.smode != RSILU_S_NONE && P.smode != RSILU_S_DENSE &&
+           P.smode != RSILU_S_CHEB))) ||
+        (P.smode == RSILU_S_CHEB &&
+         (P.trsv == RSILU_TRSV_SYNCFREE || P.poly_degree < 0 || P.poly_degree > 512 || !(P.poly_delta > 0.0) ||
+          !(P.poly_delta < 1.0) || (P.precision == RSILU_PREC_FP32 && P.ystore != RSILU_Y_EXPLICIT))) ||
         (P.smode == RSILU_S_CG &&
          (P.precision != RSILU_PREC_FP64 || P.trsv == RSILU_TRSV_SYNCFREE || P.cg_steps < 1 || P.cg_steps > 256)) ||
         (P.ystore != RSILU_Y_IMPLICIT && P.ystore != RSILU_Y_EXPLICIT) || !(P.ytau >= 0.0) || !std::isfinite(P.ytau) ||
@@ -718,6 +811,7 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
         (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
         (P.precision != RSILU_PREC_FP64 && P.precision != RSILU_PREC_FP32) ||
         (P.precision == RSILU_PREC_FP32 && (P.trsv == RSILU_TRSV_SYNCFREE || P.smode == RSILU_S_DENSE)) ||
+        (P.smode != RSILU_S_AUTO && (P.smode < RSILU_S_IDENTITY || P.smode > RSILU_S_CHEB)) ||
         (P.trsv != RSILU_TRSV_SYNCFREE && P.trsv != RSILU_TRSV_LEVELS && P.trsv != RSILU_TRSV_HYBRID))
         return RSILU_EINVAL;
     if (rowptr[0] != 0 || rowptr[m] > kMaxIdx) return RSILU_EINVAL;
@@ -977,9 +1071,10 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
     if (c.smode == RSILU_S_DENSE && m > n) {
         const rsilu_status_t rc = build_dense_S(c);
         if (rc != RSILU_OK) return rc;
-    } else if (c.smode != RSILU_S_NONE && c.smode != RSILU_S_CG) {
+    } else if (c.smode != RSILU_S_NONE && c.smode != RSILU_S_CG && c.smode != RSILU_S_CHEB) {
         c.smode = RSILU_S_IDENTITY;
     }
+    if (c.smode == RSILU_S_CHEB) build_chebyshev(c);
     return RSILU_OK;
 }
 
@@ -1061,6 +1156,7 @@ rsilu_status_t append_rows(Ctx &c, int64_t count, const int64_t *rowptr, const i
         if (rc != RSILU_OK) return rc;
     }
     if (yexplicit(c)) build_explicit_Y(c);
+    if (c.smode == RSILU_S_CHEB) build_chebyshev(c);
     // with removed A1 rows, W depends on the operator the new rows changed
     if (c.R.nrows > 0) return build_woodbury(c);
     return RSILU_OK;
@@ -1302,6 +1398,7 @@ DevPlanOff place_plan(Bump &b, const SpmvPlan &pl)
     o.nlong = (int32_t)pl.long_rows.size();
     o.nseg = (int32_t)pl.seg_beg.size();
     o.lanes = pl.lanes;
+    o.unroll = pl.unroll;
     o.long_thresh = pl.long_thresh;
     o.long_rows = b.take(sizeof(int32_t) * pl.long_rows.size());
     o.seg_ptr = b.take(sizeof(int32_t) * pl.seg_ptr.size());
@@ -1380,7 +1477,7 @@ void plan_layout(Ctx &c)
         L.f32a = b.take(sizeof(float) * m);
         L.f32b = b.take(sizeof(float) * m);
     }
-    if (c.smode == RSILU_S_CG)
+    if (c.smode == RSILU_S_CG || c.smode == RSILU_S_CHEB)
         for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
     if (c.prm.krylov == RSILU_KRYLOV_LSQR)
         for (size_t *o : {&L.l_v, &L.l_mv, &L.l_w}) *o = b.take(sizeof(double) * n);

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "librsilu.so")
 # status codes
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ESTATE, EINTERNAL = -1, -2, -3, -4, -5
-S_AUTO, S_IDENTITY, S_DENSE, S_NONE, S_CG = -1, 0, 1, 2, 3
+S_AUTO, S_IDENTITY, S_DENSE, S_NONE, S_CG, S_CHEB = -1, 0, 1, 2, 3, 4
 FORM_ALG3, FORM_ALG2 = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 KRYLOV_PCGLS, KRYLOV_LSQR = 0, 1
@@ -53,7 +53,8 @@ class rsilu_params_t(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("trsv", ctypes.c_int32), ("poll", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32), ("sweep", ctypes.c_int32),
-                ("ystore", ctypes.c_int32), ("ytau", ctypes.c_double)]
+                ("ystore", ctypes.c_int32), ("ytau", ctypes.c_double), ("poly_degree", ctypes.c_int32),
+                ("poly_delta", ctypes.c_double)]
 
 
 class rsilu_stats_t(ctypes.Structure):
@@ -62,10 +63,11 @@ class rsilu_stats_t(ctypes.Structure):
                 ("psize", ctypes.c_int64), ("nmod", ctypes.c_int64), ("levels_l1", ctypes.c_int32),
                 ("levels_l1t", ctypes.c_int32), ("levels_u", ctypes.c_int32), ("levels_ut", ctypes.c_int32),
                 ("smode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
-                ("nnz_y", ctypes.c_int64)]
+                ("nnz_y", ctypes.c_int64), ("cheb_b", ctypes.c_double), ("cheb_degree", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("reserved")}
 
 
 class rsilu_profile_t(ctypes.Structure):

@@ -484,3 +484,33 @@ def test_add_rows_rebuilds_explicit_Y():
     assert F.Y.nrows == p.m - p.n + 300
     assert np.array_equal(rp, F.Y.rowptr) and np.array_equal(cc, F.Y.col) and np.array_equal(bits(vv), bits(F.Y.val))
     R.rsilu_destroy(h)
+
+
+@pytest.mark.parametrize("name,ystore", [("c1", 1), ("c2-small", 1), ("c2-small", 0), ("c3-mini", 1)])
+def test_chebyshev_plan_matches_oracle(name, ystore):
+    """The Chebyshev interval (b = 1.05 x a 50-step power-iteration estimate of lambda_max(S~))
+    and its degree agree with the oracle's; the two sums are ordered differently, so b to
+    1e-12 relative and the degree exactly."""
+    p = gen.by_name(name)
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_CHEB, form=R.FORM_ALG2, ystore=ystore, ytau=1e-2)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK
+    st = R.rsilu_get_stats(h)
+    F = oracle.factor_problem(p, mu=1.0, smode="cheb", ystore=bool(ystore), ytau=1e-2)
+    assert st.smode == R.S_CHEB
+    assert abs(st.cheb_b - F.cheb_b) <= 1e-12 * F.cheb_b and st.cheb_degree == F.cheb_degree
+    assert st.cheb_degree % 2 == 0 and st.cheb_degree > 0
+    R.rsilu_destroy(h)
+    # a fixed degree is taken as given; LSQR accepts the Chebyshev M_b; bad settings are rejected
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_CHEB, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR, ystore=ystore,
+                                 poly_degree=7)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    assert code == R.OK and R.rsilu_get_stats(h).cheb_degree == 7
+    R.rsilu_destroy(h)
+    for kw in (dict(poly_degree=-1), dict(poly_degree=513), dict(poly_delta=0.0), dict(poly_delta=1.0),
+               dict(trsv=R.TRSV_SYNCFREE), dict(precision=R.PREC_FP32, ystore=0)):
+        prm = R.rsilu_params_default(mu=1.0, smode=R.S_CHEB, form=R.FORM_ALG2, ystore=ystore)
+        for k_, v_ in kw.items():
+            setattr(prm, k_, v_)
+        code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+        assert code == R.EINVAL and h is None, kw
