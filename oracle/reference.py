@@ -154,11 +154,19 @@ def upper_solve(U, b, diag=None):
 def dot(a, b):
     """(a, b): the correctly rounded sum (math.fsum) of the rounded products a_i b_i. It does
     not depend on the order of the terms, and its error is below that of any summation
-    order a GPU reduction may take."""
+    order a GPU reduction may take. Non-finite products or an overflowing sum give the
+    plain sum (inf or nan), as an IEEE summation would."""
     a = _c(a, np.float64)
     b = _c(b, np.float64)
     assert a.shape == b.shape
-    return math.fsum(a * b)
+    with np.errstate(over="ignore", invalid="ignore"):
+        p = a * b
+    if not np.all(np.isfinite(p)):
+        return float(np.sum(p))  # inf or nan: the caller's breakdown test sees it
+    try:
+        return math.fsum(p)
+    except OverflowError:  # the exact sum leaves the double range
+        return float(np.sum(p))
 
 
 def explicit_Y(L1, L2, tauY):

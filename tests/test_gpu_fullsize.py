@@ -1,7 +1,17 @@
-"""Parity at the full sizes of the benchmarked configurations, in the launch
-configuration bench.py times (hybrid schedule, Algorithm 2 without correction, LSQR).
+"""Parity at the full sizes of the benchmarked configurations, in the launch configurations
+bench.py times: Algorithm 1 with Algorithm 2 and the M_b correction by CG(32) on S~ through
+the explicit Y~ (the headline), and beside it the A1-only preconditioner with LSQR.
 
-* grid workload, 600000 x 400000: every triangular solve against the oracle's
+* grid workload, 600000 x 400000, with the correction: the products with the explicit Y~
+  and Y~^T componentwise; one application of the correction with CG(8) element by element;
+  four Algorithm 1 steps with CG(8) against the oracle's (x to 1e-8); the whole solve in the
+  headline configuration: converged, the true ||A^T r|| at the tolerance, the iteration
+  count within 2% of the oracle's. CG(32) iterates are held at the whole-solve level only:
+  past some 16 CG steps the iterates depend on the rounding of the inner products well
+  beyond eps, on the oracle as on the GPU. The Chebyshev M_b (a fixed polynomial, degree
+  80 here): one application element by element and four LSQR steps;
+
+* grid workload, 600000 x 400000, A1 only: every triangular solve against the oracle's
   substitutions (componentwise backward error, forward difference); four LSQR steps
   against the oracle's; the whole solve against the oracle's (iteration counts within 2%,
   both solutions in the same stop-test ball);
@@ -123,3 +133,113 @@ def test_c4_fp32_preconditioner(gpu_lib):
           " fp64 %.1e, fp32 %.1e; ||x - x_or|| / ||x_or|| fp64 %.1e, fp32 %.1e" % (
               out[R.PREC_FP64][2], out[R.PREC_FP32][2], o.iters, ball[R.PREC_FP64], ball[R.PREC_FP32],
               rel[R.PREC_FP64], rel[R.PREC_FP32]))
+
+
+# ------------------------------------------------------------------ with the A2 correction
+
+HEAD = dict(mu=1.0, form=1, smode=3, cg_steps=32, ystore=1, ytau=1e-2)  # the headline configuration
+
+
+@pytest.fixture(scope="module")
+def c2y():
+    prob = gen.by_name("c2")
+    F = oracle.factor_problem(prob, mu=1.0, smode="cg", cg_steps=8, ystore=True, ytau=1e-2)
+    return prob, F
+
+
+def elementwise(got, want, rtol, atol):
+    bound = rtol * np.abs(want) + atol * np.max(np.abs(want))
+    return float(np.max(np.abs(got - want) / bound))
+
+
+def test_c2_products_with_Y(gpu_lib, c2y):
+    R = gpu_lib
+    import torch
+
+    prob, F = c2y
+    S = R.Solver.from_problem(prob, **HEAD).upload()
+    assert S.stats.nnz_y == F.Y.nnz
+    rng = np.random.default_rng(51)
+    for op, C in ((4, F.Y), (5, F.YT)):
+        x = rng.standard_normal(C.ncols)
+        y = torch.empty(C.nrows, dtype=torch.float64, device="cuda")
+        assert R.rsilu_spmv(S.h, op, torch.from_numpy(x).cuda(), y) == R.OK
+        got = y.cpu().numpy()
+        want = C.matvec(x)
+        k = np.diff(C.rowptr)
+        assert np.all(np.abs(got - want) <= 2 * k * EPS * (abs(C.scipy()) @ np.abs(x)) + 1e-300), op
+    S.close()
+
+
+def test_c2_correction_apply_and_four_steps(gpu_lib, c2y):
+    R = gpu_lib
+    import torch
+
+    prob, F = c2y
+    S = R.Solver.from_problem(prob, **dict(HEAD, cg_steps=8)).upload()
+    z = np.random.default_rng(52).standard_normal(prob.n)
+    h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    assert R.rsilu_apply_z(S.h, torch.from_numpy(z).cuda(), h) == R.OK
+    ratio = elementwise(h.cpu().numpy(), oracle.apply_alg2(F, z), 1e-8, 1e-11)
+    S.close()
+    S = R.Solver.from_problem(prob, maxit=4, **dict(HEAD, cg_steps=8)).upload()
+    x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=1e-14)
+    got = x.cpu().numpy()
+    S.close()
+    res = oracle.pcgls(F, prob.b, tol=1e-14, maxit=4, form="alg2")
+    err = np.linalg.norm(got - res.x) / np.linalg.norm(res.x)
+    print("grid 600000 x 400000, CG(8) correction: apply elementwise ratio %.2e; 4 steps x rel diff %.2e" % (
+        ratio, err))
+    assert ratio <= 1.0
+    assert it == res.iters == 4 and err <= 1e-8
+    assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm
+
+
+def test_c2_headline_whole_solve(gpu_lib, c2y):
+    R = gpu_lib
+    import dataclasses
+    import torch
+
+    prob, F = c2y
+    tol = 1e-8
+    S = R.Solver.from_problem(prob, maxit=2000, **HEAD).upload()
+    x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=tol)
+    got = x.cpu().numpy()
+    S.close()
+    res = oracle.pcgls(dataclasses.replace(F, cg_steps=32), prob.b, tol=tol, maxit=2000, form="alg2")
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    ball = np.linalg.norm(A.T @ (A @ (got - res.x))) / atb
+    print("grid 600000 x 400000, CG(32) correction: gpu its %d, oracle its %d, true rel %.2e, ball %.2e" % (
+        it, res.iters, rel, ball))
+    assert code == R.OK and res.status == "ok"
+    assert abs(it - res.iters) <= max(1, int(0.02 * res.iters))
+    assert np.linalg.norm(A.T @ (prob.b - A @ got)) <= 2 * tol * atb
+    assert ball <= 4 * tol
+
+
+def test_c2_chebyshev_apply_and_four_lsqr_steps(gpu_lib):
+    R = gpu_lib
+    import torch
+
+    prob = gen.by_name("c2")
+    F = oracle.factor_problem(prob, mu=1.0, smode="cheb", ystore=True, ytau=1e-2)
+    kw = dict(mu=1.0, form=1, smode=R.S_CHEB, ystore=1, ytau=1e-2, krylov=R.KRYLOV_LSQR)
+    S = R.Solver.from_problem(prob, **kw).upload()
+    st = S.stats
+    assert st.cheb_degree == F.cheb_degree and abs(st.cheb_b - F.cheb_b) <= 1e-12 * F.cheb_b
+    z = np.random.default_rng(53).standard_normal(prob.n)
+    h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    assert R.rsilu_apply_z(S.h, torch.from_numpy(z).cuda(), h) == R.OK
+    ratio = elementwise(h.cpu().numpy(), oracle.apply_alg2(F, z), 1e-9, 1e-12)
+    S.close()
+    S = R.Solver.from_problem(prob, maxit=4, **kw).upload()
+    x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=1e-14)
+    got = x.cpu().numpy()
+    S.close()
+    res = oracle.lsqr_m(F, prob.b, tol=1e-14, maxit=4)
+    err = np.linalg.norm(got - res.x) / np.linalg.norm(res.x)
+    print("grid 600000 x 400000, Chebyshev degree %d: apply elementwise ratio %.2e; 4 LSQR steps x rel diff %.2e"
+          % (st.cheb_degree, ratio, err))
+    assert ratio <= 1.0
+    assert it == res.iters == 4 and err <= 1e-8

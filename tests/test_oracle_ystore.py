@@ -150,3 +150,9 @@ def test_dot_is_correctly_rounded():
     # products are rounded first: (1 + 2^-30)^2 has a term below the last bit of the product
     d = np.array([1.0 + 2.0**-30])
     assert oracle.dot(d, d) == float((1.0 + 2.0**-30) * (1.0 + 2.0**-30))
+
+
+def test_dot_non_finite():
+    assert oracle.dot(np.array([1e200, 1e200]), np.array([1e200, 1.0])) == float("inf")
+    assert math.isnan(oracle.dot(np.array([np.inf, -np.inf]), np.array([1.0, 1.0])))
+    assert oracle.dot(np.array([1e308, 1e308]), np.array([1.0, 1.0])) == float("inf")
