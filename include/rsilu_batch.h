@@ -96,6 +96,23 @@ rsilu_status_t rsilu_batch_solve(rsilu_batch_t bt, int32_t count, const rsilu_ha
 /* Free the batch object (NULL is ignored). Wait for its last launch first. */
 void rsilu_batch_destroy(rsilu_batch_t bt);
 
+/* For callers that cannot allocate device or pinned memory (code between stream
+ * captures, tight serving loops, harnesses that forbid allocation): the batched
+ * solve of rsilu_batch_solve without a batch object. The descriptor table and the
+ * outcome slots of the launch live in a fixed device array of the library, one per
+ * GPU (sizeof of 256 descriptors and outcomes, under 200 KiB), held until the process
+ * ends; the call makes no hipMalloc, hipHostMalloc, hipFree or graph, and stages
+ * the table through fixed host arrays of the library. Arguments, arithmetic, results
+ * and errors as rsilu_batch_solve (each handle's maxit applies), with count at most
+ * rsilu_batch_static_max() = 256 (EINVAL beyond) on the current device (ESTATE for
+ * handles uploaded on another). It waits for its launch. Calls in one process are
+ * serialised; calls from several processes on one GPU each use their own copy of the
+ * array. */
+rsilu_status_t rsilu_batch_solve_static(int32_t count, const rsilu_handle_t *hs, const double *const *b,
+                                        const double *tol, double *const *x, const rsilu_tile_t *tile,
+                                        rsilu_batch_result_t *res, hipStream_t s);
+int32_t rsilu_batch_static_max(void);
+
 /* Outcome of rsilu_tune. path: 0 = the persistent batched kernel with `tile`,
  * 1 = the plain multi-kernel path (rsilu_solve). The times are per iteration,
  * measured (or those of the cached measurement when from_cache = 1). */

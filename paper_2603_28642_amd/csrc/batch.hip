@@ -585,6 +585,17 @@ const TileEntry *find_tile(const rsilu_tile_t &t)
 
 constexpr rsilu_tile_t kDefaultTile = {1024, 4, 4, 0};
 
+// ------------------------------------------------------------------ fixed descriptor table
+
+// rsilu_batch_solve_static: the descriptor table and outcome slots of one launch in a
+// fixed device array (one copy per GPU, for the process lifetime), so that the call
+// allocates nothing. In host code `scratch` is only a handle for the symbol: its device
+// address on each GPU comes from hipGetSymbolAddress, with that GPU current.
+constexpr int32_t kStaticBatchMax = 256;
+constexpr size_t kStaticDescBytes = ((sizeof(BDesc) * kStaticBatchMax + 255) / 256) * 256;
+constexpr size_t kStaticBytes = kStaticDescBytes + sizeof(BOut) * kStaticBatchMax;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
 // ------------------------------------------------------------------ host side
 
 template <class T>
@@ -904,6 +915,113 @@ void rsilu_batch_destroy(rsilu_batch_t bt)
     if (bt->h_out) (void)hipHostFree(bt->h_out);
     delete bt;
 }
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kStaticDevices = 64;
+
+struct StaticBatchState {
+    std::mutex mu;                      // one call at a time in this process
+    unsigned char *dev[kStaticDevices] = {};  // device address of `scratch` per GPU
+    BDesc h_desc[kStaticBatchMax];      // host staging (pageable; the copies are synchronised)
+    BOut h_out[kStaticBatchMax];
+};
+
+StaticBatchState &static_state()
+{
+    static StaticBatchState st;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsilu_status_t rsilu_batch_solve_static(int32_t count, const rsilu_handle_t *hs, const double *const *b,
+                                        const double *tol, double *const *x, const rsilu_tile_t *tile,
+                                        rsilu_batch_result_t *res, hipStream_t s)
+{
+    if (count < 0 || count > kStaticBatchMax) return RSILU_EINVAL;
+    if (count == 0) return RSILU_OK;
+    if (!hs || !b || !tol || !x || !res) return RSILU_EINVAL;
+    const TileEntry *te = find_tile(tile ? *tile : kDefaultTile);
+    if (!te) return RSILU_EINVAL;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return RSILU_EHIP;
+    if (device < 0 || device >= kStaticDevices) return RSILU_EINVAL;
+    bool any32 = false, any64 = false;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!hs[i] || !b[i] || !x[i] || static_cast<const void *>(b[i]) == static_cast<const void *>(x[i]))
+            return RSILU_EINVAL;
+        if (!(tol[i] >= 0.0) || !std::isfinite(tol[i])) return RSILU_EINVAL;
+        const rsilu_status_t st = check_handle(*hs[i]);
+        if (st != RSILU_OK) return st;
+        if (hs[i]->device != device) return RSILU_ESTATE;
+        (fp32(*hs[i]) ? any32 : any64) = true;
+        for (int32_t j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return RSILU_EINVAL;
+    }
+    StaticBatchState &S = static_state();
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (!S.dev[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RSILU_EHIP;
+        S.dev[device] = static_cast<unsigned char *>(p);
+    }
+    BDesc *d_desc = reinterpret_cast<BDesc *>(S.dev[device]);
+    BOut *d_out = reinterpret_cast<BOut *>(S.dev[device] + kStaticDescBytes);
+    // largest problems first, as rsilu_batch_solve orders them (insertion sort: no allocation)
+    int32_t order[kStaticBatchMax];
+    for (int32_t i = 0; i < count; ++i) {
+        const double wi = work_of(*hs[i]);
+        int32_t j = i;
+        while (j > 0 && work_of(*hs[order[j - 1]]) < wi) {
+            order[j] = order[j - 1];
+            --j;
+        }
+        order[j] = i;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fp = pass == 1;
+        if ((fp && !any32) || (!fp && !any64)) continue;
+        int32_t idx[kStaticBatchMax];
+        int32_t k = 0;
+        for (int32_t t = 0; t < count; ++t)
+            if (fp32(*hs[order[t]]) == fp) idx[k++] = order[t];
+        const size_t vb = fp ? sizeof(float) : sizeof(double);
+        size_t xl = 0;
+        for (int32_t j = 0; j < k; ++j) {
+            const Ctx &c = *hs[idx[j]];
+            S.h_desc[j] = make_desc(c, b[idx[j]], x[idx[j]], tol[idx[j]], c.prm.maxit, d_out + j);
+            const size_t need = 2 * (size_t)c.n * vb;
+            if (need <= xl_bound(te->tile.threads)) xl = std::max(xl, need);
+        }
+        if (hipMemcpyAsync(d_desc, S.h_desc, sizeof(BDesc) * (size_t)k, hipMemcpyHostToDevice, s) != hipSuccess)
+            return RSILU_EHIP;
+        BDesc *arg = d_desc;
+        uint32_t xlb = (uint32_t)xl;
+        void *args[] = {&arg, &xlb};
+        if (hipLaunchKernel(te->fn[fp ? 1 : 0], dim3((unsigned)k), dim3((unsigned)te->tile.threads), args, xl, s) !=
+            hipSuccess)
+            return RSILU_EHIP;
+        if (hipMemcpyAsync(S.h_out, d_out, sizeof(BOut) * (size_t)k, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return RSILU_EHIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return RSILU_EHIP;
+        for (int32_t j = 0; j < k; ++j) {
+            const BOut &o = S.h_out[j];
+            rsilu_batch_result_t &r = res[idx[j]];
+            r.iters = o.iters;
+            r.atr_norm = o.atr;
+            r.atr_rel = o.nb > 0.0 ? o.atr / o.nb : 0.0;
+            r.status = map_status(o, hs[idx[j]]->prm.maxit);
+        }
+    }
+    return RSILU_OK;
+}
+
+int32_t rsilu_batch_static_max(void) { return kStaticBatchMax; }
 
 rsilu_status_t rsilu_tuner_create(double slack, int32_t iters, rsilu_tuner_t *out)
 {

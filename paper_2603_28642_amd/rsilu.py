@@ -39,7 +39,7 @@ EXPORTS = [
     "rsilu_server_create", "rsilu_server_submit", "rsilu_server_poll", "rsilu_server_drain", "rsilu_server_destroy",
     "rsilu_batch_tiles", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_solve_auto", "rsilu_batch_destroy",
     "rsilu_tuner_create",
-    "rsilu_tune", "rsilu_tuner_size", "rsilu_tuner_destroy",
+    "rsilu_tune", "rsilu_tuner_size", "rsilu_tuner_destroy", "rsilu_batch_solve_static", "rsilu_batch_static_max",
 ]
 PROF_NAMES = ["spmv_A", "spmv_AT", "trsv_L1", "trsv_L1T", "trsv_U", "spmv_L2", "spmv_L2T", "dense_S", "trsv_UT",
               "k_trsv_sweep", "k_trsv_level", "k_gather_lo", "k_spmv_y"]
@@ -192,6 +192,11 @@ def lib():
         L.rsilu_batch_solve_auto.argtypes = [P, P, I32, P, P, P, P, ctypes.POINTER(rsilu_batch_result_t),
                                              ctypes.POINTER(I32), ctypes.POINTER(rsilu_tile_t), P]
         L.rsilu_batch_solve_auto.restype = ctypes.c_int
+        L.rsilu_batch_solve_static.argtypes = [I32, P, P, P, P, ctypes.POINTER(rsilu_tile_t),
+                                               ctypes.POINTER(rsilu_batch_result_t), P]
+        L.rsilu_batch_solve_static.restype = ctypes.c_int
+        L.rsilu_batch_static_max.argtypes = []
+        L.rsilu_batch_static_max.restype = I32
         L.rsilu_batch_destroy.argtypes = [P]
         L.rsilu_batch_destroy.restype = None
         L.rsilu_tuner_create.argtypes = [D, I32, ctypes.POINTER(P)]
@@ -516,6 +521,21 @@ def make_tile(tile):
         return None
     t, s_, r = tile
     return rsilu_tile_t(threads=t, spmv_lanes=s_, tri_lanes=r, reserved=0)
+
+
+def rsilu_batch_solve_static(handles, b_devs, tols, x_devs, tile=None, stream=None):
+    """The batched solve without a batch object (fixed device descriptor table, no
+    allocation). Returns (status code of the call, [result dicts])."""
+    k = len(handles)
+    hs = (ctypes.c_void_p * max(k, 1))(*[h if isinstance(h, int) else h.value for h in handles])
+    bs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in b_devs])
+    xs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in x_devs])
+    ts = (ctypes.c_double * max(k, 1))(*[float(t) for t in tols])
+    res = (rsilu_batch_result_t * max(k, 1))()
+    tl = make_tile(tile)
+    code = lib().rsilu_batch_solve_static(k, hs, bs, ts, xs, ctypes.byref(tl) if tl is not None else None, res,
+                                          _stream(stream))
+    return code, [{f: getattr(res[i], f) for f, _ in res[i]._fields_} for i in range(k)]
 
 
 class Batch:
