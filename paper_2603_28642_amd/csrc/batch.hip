@@ -696,6 +696,8 @@ struct rsilu_batch {
     BOut *h_out = nullptr;    // pinned
     hipStream_t cap_stream = nullptr;
     hipStream_t aux_stream = nullptr;  // plain-path solves of rsilu_batch_solve_auto
+    hipEvent_t ev_in = nullptr;        // the caller's stream up to the call (aux_stream waits on it)
+    hipEvent_t ev_out = nullptr;       // aux_stream's plain solves (the caller's stream waits on it)
     std::map<std::tuple<int32_t, const void *, size_t>, hipGraphExec_t> graphs;  // (count, kernel, LDS)
     std::mutex mu;  // one launch at a time per batch object
 };
@@ -909,6 +911,8 @@ void rsilu_batch_destroy(rsilu_batch_t bt)
     for (auto &kv : bt->graphs) (void)hipGraphExecDestroy(kv.second);
     if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
     if (bt->aux_stream) (void)hipStreamDestroy(bt->aux_stream);
+    if (bt->ev_in) (void)hipEventDestroy(bt->ev_in);
+    if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
     if (bt->d_desc) (void)hipFree(bt->d_desc);
     if (bt->d_out) (void)hipFree(bt->d_out);
     if (bt->h_desc) (void)hipHostFree(bt->h_desc);
@@ -1167,9 +1171,18 @@ rsilu_status_t rsilu_batch_solve_auto(rsilu_batch_t bt, rsilu_tuner_t t, int32_t
             run_plain(s);
             return plain_rc;
         }
-        if (!plain.empty() && !bt->aux_stream &&
-            hipStreamCreateWithFlags(&bt->aux_stream, hipStreamNonBlocking) != hipSuccess)
-            return RSILU_EHIP;
+        if (!plain.empty()) {
+            if (!bt->aux_stream && hipStreamCreateWithFlags(&bt->aux_stream, hipStreamNonBlocking) != hipSuccess)
+                return RSILU_EHIP;
+            if (!bt->ev_in && hipEventCreateWithFlags(&bt->ev_in, hipEventDisableTiming) != hipSuccess)
+                return RSILU_EHIP;
+            if (!bt->ev_out && hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming) != hipSuccess)
+                return RSILU_EHIP;
+            // the plain solves on aux_stream start after the work the caller queued on s
+            // (copies of b, for instance), and s resumes only after them
+            if (hipEventRecord(bt->ev_in, s) != hipSuccess || hipStreamWaitEvent(bt->aux_stream, bt->ev_in, 0) != hipSuccess)
+                return RSILU_EHIP;
+        }
         std::vector<rsilu_handle_t> bh;
         std::vector<const double *> bb;
         std::vector<double> bt_tol;
@@ -1185,6 +1198,9 @@ rsilu_status_t rsilu_batch_solve_auto(rsilu_batch_t bt, rsilu_tuner_t t, int32_t
         const rsilu_status_t rc =
             batch_solve(*bt, (int32_t)batched.size(), bh.data(), bb.data(), bt_tol.data(), bx.data(), &tile, br.data(),
                         s, -1, plain.empty() ? std::function<void()>() : std::function<void()>([&] { run_plain(bt->aux_stream); }));
+        if (!plain.empty() &&
+            (hipEventRecord(bt->ev_out, bt->aux_stream) != hipSuccess || hipStreamWaitEvent(s, bt->ev_out, 0) != hipSuccess))
+            return RSILU_EHIP;
         if (rc != RSILU_OK) return rc;
         for (size_t q = 0; q < batched.size(); ++q) res[batched[q]] = br[q];
         return plain_rc;

@@ -44,6 +44,46 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// Sum over aligned groups of G lanes (G a power of two up to 64) left in the LAST lane of
+// each group, by DPP moves (register to register, no LDS): row shifts right by 1, 2, 4
+// and 8 within the 16-lane rows (a lane's sum of itself and the lanes below it in the
+// row), then for G >= 32 lane 15 of each row added into rows 1 and 3 and for G = 64
+// lane 31 into rows 2 and 3. Lanes shifted in from outside a row read 0. Every lane
+// must be active. Only the group's last lane holds the group's sum.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS, class T>
+__device__ __forceinline__ T dpp_add(T v)
+{
+    if constexpr (std::is_same<T, double>::value)
+        return v + dpp_f64<CTRL, ROWS>(v);
+    else
+        return v + dpp_f32<CTRL, ROWS>(v);
+}
+template <int G, class T>
+__device__ __forceinline__ T group_sum_last(T v)
+{
+    static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "group of 2..64 lanes");
+    v = dpp_add<0x111, 0xf>(v);                       // row_shr:1
+    if constexpr (G >= 4) v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    if constexpr (G >= 8) v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    if constexpr (G >= 16) v = dpp_add<0x118, 0xf>(v); // row_shr:8
+    if constexpr (G >= 32) v = dpp_add<0x142, 0xa>(v); // row_bcast:15 into rows 1, 3
+    if constexpr (G >= 64) v = dpp_add<0x143, 0xc>(v); // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // Fixed-order sum of one value per thread of a 256-thread block; thread 0 gets it.
 __device__ __forceinline__ double block_sum256(double v, double *lds4)
 {
@@ -257,7 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh
 // all in flight before any is used, so a block spends one memory latency per
 // dependent step for RPT rows instead of one. Rows are interleaved across the
 // block so one load instruction covers consecutive rows; entries past U*G go
-// through a loop. The stop flag is read beside the first loads and masks the
+// through a loop. A row's sum is formed by DPP moves in its group's last lane,
+// which stores it. The stop flag is read beside the first loads and masks the
 // stores (every load is in bounds either way). Rows longer than long_thresh
 // are left to the segment kernel, as in k_spmv. Needs nnz >= 1.
 template <int G, int RPT, int U, int EPI, class T>
@@ -301,9 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mr(DCsrT<T> a, int32_t long_thr
 #pragma unroll
         for (int u = 1; u < U; ++u) sum += v[j][u] * xv[j][u];
         for (int k = b[j] + gl + U * G; k < e[j]; k += G) sum += a.val[k] * x[a.col[k]];
-        sum = group_sum<G>(sum);
+        sum = group_sum_last<G>(sum);
         const int row = base + j * RPB;
-        if (live && row < a.nrows && e[j] - b[j] <= long_thresh && gl == 0) {
+        if (live && row < a.nrows && e[j] - b[j] <= long_thresh && gl == G - 1) {
             T out = sum;
             if (EPI == EPI_SUB) out = aux[row] - sum;
             if (EPI == EPI_NEG) out = -sum;

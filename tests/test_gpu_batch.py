@@ -276,3 +276,46 @@ def test_solve_auto_split(gpu_lib):
     tu.close()
     for s in S:
         s.close()
+
+
+def test_solve_auto_waits_for_the_callers_stream(gpu_lib):
+    """With the tuner warm (every signature cached, so nothing synchronises the caller's
+    stream before the plain solves start on the batch object's second stream), the
+    right-hand sides are copied on the caller's stream just before the call; every result
+    must still equal a lone solve of the final b, bit for bit."""
+    import torch
+
+    R = gpu_lib
+    probs = [gen.served_request(2000, 2600, 70), gen.served_request(2600, 3200, 71), PROBLEMS["c1"]()]
+    S = [R.Solver.from_problem(p, maxit=2000, **LSQR).upload() for p in probs[:-1]]
+    S.append(R.Solver.from_problem(probs[-1], mu=1.0, smode=R.S_NONE, form=1, krylov=0, maxit=2000).upload())
+    bt = R.Batch(4)
+    tu = R.Tuner(slack=1.0, iters=4)
+    warm = [to_dev(p.b) for p in probs]
+    bt.solve_auto(tu, S, warm, 1e-8)  # fills the tuner's cache
+    side = torch.cuda.Stream()
+    bs = [torch.zeros(p.m, dtype=torch.float64, device="cuda") for p in probs]
+    host = [torch.from_numpy(p.b).pin_memory() for p in probs]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for d, h in zip(bs, host):
+            d.copy_(h, non_blocking=True)
+        xs, res, paths, tile = bt.solve_auto(tu, S, bs, 1e-8, stream=side)
+    side.synchronize()
+    assert paths[-1] == 1
+    one = R.Batch(1)
+    for i, (x, r) in enumerate(zip(xs, res)):
+        got = x.cpu().numpy()
+        if paths[i] == 0:
+            x1, r1 = one.solve([S[i]], [warm[i]], 1e-8, tile=tile)
+            lone, it = x1[0].cpu().numpy(), r1[0]["iters"]
+        else:
+            xl, code, it, atr, rel = S[i].solve(warm[i], tol=1e-8)
+            lone = xl.cpu().numpy()
+        assert r["status"] == R.OK and it == r["iters"], (i, r)
+        assert np.array_equal(lone.view(np.int64), got.view(np.int64)), i
+    one.close()
+    bt.close()
+    tu.close()
+    for s in S:
+        s.close()
