@@ -70,7 +70,73 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (three of them) and exit: the known-size "
                          "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--traffic-record", nargs=5, metavar=("KERNEL", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                          "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_<KERNEL>_<workload>.json from rocprofv3 --pmc FETCH_SIZE and "
+                         "WRITE_SIZE counter files of this configuration and of --copy-probe, then exit")
+    ap.add_argument("--copy-mib", type=int, default=256, help="size of the --copy-probe run the record used")
     return ap.parse_args()
+
+
+TRAFFIC_CONFIG_KEYS = ("precision", "form", "krylov", "trsv", "smode", "mu", "tau", "p", "cg_steps", "ystore", "ytau",
+                       "poly_degree", "poly_delta")
+TRAFFIC_SOURCES = ("paper_2603_28642_amd/csrc/kernels.hip", "paper_2603_28642_amd/csrc/sweep_limits.hpp",
+                   "paper_2603_28642_amd/csrc/setup.cpp")
+
+
+def _sources_sha256(files):
+    import hashlib
+
+    h = hashlib.sha256()
+    for fn in files:
+        with open(os.path.join(ROOT, fn), "rb") as src:
+            h.update(src.read())
+    return h.hexdigest()
+
+
+def _counter_kib_per_dispatch(path, counter, match):
+    """Mean of `counter` over the dispatches whose kernel name contains `match`, from a
+    rocprofv3 counter_collection CSV (values in KiB as rocprofv3 reports FETCH_SIZE and
+    WRITE_SIZE)."""
+    import csv
+
+    vals = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter or match not in row.get("Kernel_Name", ""):
+                continue
+            key = row.get("Dispatch_Id") or row.get("Correlation_Id") or len(vals)
+            vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+    if not vals:
+        raise SystemExit("no %s dispatches of %s in %s" % (counter, match, path))
+    return sum(vals.values()) / len(vals), len(vals)
+
+
+def traffic_record(args):
+    kernel, fetch, write, cfetch, cwrite = args.traffic_record
+    copy_bytes = args.copy_mib * (1 << 20)
+    f_kib, nf = _counter_kib_per_dispatch(fetch, "FETCH_SIZE", kernel)
+    w_kib, nw = _counter_kib_per_dispatch(write, "WRITE_SIZE", kernel)
+    cf_kib, _ = _counter_kib_per_dispatch(cfetch, "FETCH_SIZE", "copyBuffer")
+    cw_kib, _ = _counter_kib_per_dispatch(cwrite, "WRITE_SIZE", "copyBuffer")
+    fs, ws = copy_bytes / (cf_kib * 1024.0), copy_bytes / (cw_kib * 1024.0)
+    rec = {
+        "kernel": kernel,
+        "workload": args.workload,
+        "dispatches": [nf, nw],
+        "fetch_kib_per_launch": f_kib,
+        "write_kib_per_launch": w_kib,
+        "fetch_scale": fs,
+        "write_scale": ws,
+        "traffic_bytes_per_launch": f_kib * 1024.0 * fs + w_kib * 1024.0 * ws,
+        "sources": list(TRAFFIC_SOURCES),
+        "sources_sha256": _sources_sha256(TRAFFIC_SOURCES),
+        "config": {k: getattr(args, k) for k in TRAFFIC_CONFIG_KEYS},
+    }
+    out = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, args.workload))
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def copy_probe(mib):
@@ -168,21 +234,15 @@ def measured_traffic(kernel, workload, args):
     runs (profiles/traffic_<kernel>_<workload>.json, calibrated by a copy of known size),
     or None when there is no record, the record was taken with another solver
     configuration than this run's, or the kernel's sources changed since it was taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     cfg = rec.get("config")
-    if cfg is None or any(getattr(args, k) != v for k, v in cfg.items()):
+    if cfg is None or any(getattr(args, k, None) != v for k, v in cfg.items()):
         return None
-    h = hashlib.sha256()
-    for fn in rec["sources"]:
-        with open(os.path.join(ROOT, fn), "rb") as src:
-            h.update(src.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    if _sources_sha256(rec["sources"]) != rec["sources_sha256"]:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -343,6 +403,9 @@ def main():
 
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.traffic_record:
+        traffic_record(args)
         return
 
     import torch
