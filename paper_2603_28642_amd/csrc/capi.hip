@@ -347,8 +347,11 @@ void apply_alg3(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const T *
 {
     const int32_t n = (int32_t)c.n, k = c.L2.nrows;
     if (yexplicit(c) && k > 0 && c.smode != RSILU_S_NONE) {
-        // explicit Y~: u = r2 - Y~ r1, S^ w = u, y = r1 + Y~^T w, L1 v = y, U h = v
-        spmv_y<T>(c, s, P, W, false, r, W.u, r + n, EPI_SUB, done);
+        // explicit Y~: u = r2 - Y~ r1, S^ w = u, y = r1 + Y~^T w, L1 v = y, U h = v; u and w
+        // in the device order of Y~'s rows (r2 gathered into it first)
+        T *r2 = at<T>(c, c.lay.yk);
+        launch_gather_lo<T>(s, k, at<int32_t>(c, c.lay.yperm), r + n, r2, nullptr, nullptr, done);
+        spmv_y<T>(c, s, P, W, false, r, W.u, r2, EPI_SUB, done);
         if constexpr (std::is_same<T, double>::value) {
             if (c.smode == RSILU_S_CG) cg_solve_S(c, s, P, W, done);
         }
@@ -846,8 +849,10 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put_plan(L.pL2, c.plL2));
     RSILU_HIP(put_plan(L.pL2T, c.plL2T));
     if (yexplicit(c)) {
-        RSILU_HIP(put_csr(L.Y, c.Y));
-        RSILU_HIP(put_csr(L.YT, c.YT));
+        RSILU_HIP(put_csr(L.Y, c.Yd));
+        RSILU_HIP(put_csr(L.YT, c.YdT));
+        RSILU_HIP(put(L.yperm, c.yperm.data(), c.yperm.size() * sizeof(int32_t)));
+        RSILU_HIP(put(L.yperm_inv, c.yperm_inv.data(), c.yperm_inv.size() * sizeof(int32_t)));
         RSILU_HIP(put_plan(L.pY, c.plY));
         RSILU_HIP(put_plan(L.pYT, c.plYT));
     }
@@ -1027,18 +1032,30 @@ rsilu_status_t rsilu_spmv(rsilu_handle_t h, int32_t op, const double *xin, doubl
         const bool fwd = op == 2 || op == 4;  // (m-n) x n operator
         const int32_t nin = fwd ? n : k, nout = fwd ? k : n;
         const DPlan &pl = op == 2 ? P.pL2 : op == 3 ? P.pL2T : op == 4 ? P.pY : P.pYT;
+        // the device copy of Y~ holds its rows in yperm order: Y~ x is put back into the
+        // user's row order, and Y~^T takes its input in the device order
+        double *yk = op >= 4 ? at<double>(c, c.lay.yk) : nullptr;
+        const int32_t *yp = op >= 4 ? at<int32_t>(c, c.lay.yperm) : nullptr;
+        const int32_t *ypi = op >= 4 ? at<int32_t>(c, c.lay.yperm_inv) : nullptr;
+        const double *src = xin;
+        if (op == 5) {
+            launch_gather_lo<double>(s, k, yp, xin, yk, nullptr, nullptr, nullptr);
+            src = yk;
+        }
+        double *dst = op == 4 ? yk : y;
         if (fp32(c)) {
             const Pre<float> W = pre<float>(c);
             const DCsrT<float> &a = op == 2 ? W.L2 : op == 3 ? W.L2T : op == 4 ? W.Y : W.YT;
             float *in = at<float>(c, c.lay.f32a), *out = at<float>(c, c.lay.f32b);
-            launch_cvt(s, nin, xin, in, nullptr);
+            launch_cvt(s, nin, src, in, nullptr);
             launch_spmv<float>(s, a, pl, in, out, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, nullptr);
-            launch_cvt(s, nout, out, y, nullptr);
+            launch_cvt(s, nout, out, dst, nullptr);
         } else {
             const Pre<double> W = pre<double>(c);
             const DCsrT<double> &a = op == 2 ? W.L2 : op == 3 ? W.L2T : op == 4 ? W.Y : W.YT;
-            launch_spmv<double>(s, a, pl, xin, y, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, nullptr);
+            launch_spmv<double>(s, a, pl, src, dst, nullptr, EPI_PLAIN, FIN_NONE, P.partials, W.segpart, P.st, nullptr);
         }
+        if (op == 4) launch_gather_lo<double>(s, k, ypi, yk, y, nullptr, nullptr, nullptr);
         break;
     }
     default: return RSILU_EINVAL;

@@ -106,8 +106,9 @@ struct Layout {
     size_t total = 0;
     DevCsrOff A, AT, L2, L2T;
     DevPlanOff pA, pAT, pL2, pL2T;
-    DevCsrOff Y, YT;     // explicit Y~ and its transpose (RSILU_Y_EXPLICIT)
+    DevCsrOff Y, YT;     // explicit Y~ (rows in yperm order) and its transpose (RSILU_Y_EXPLICIT)
     DevPlanOff pY, pYT;
+    size_t yperm = 0, yperm_inv = 0, yk = 0;  // the row order, its inverse, an (m-n)-vector
     DevTriOff L1f, L1b, Ub, UTf;  // L1 forward, L1^T backward, U backward, U^T forward
     size_t perm = 0, colnorm = 0, sfac = 0;
     // removed rows (present when R has rows): R, R^T, W's factor, and work vectors
@@ -148,7 +149,9 @@ struct Ctx {
     SpmvPlan plA, plAT, plL2, plL2T;
     std::vector<double> sfac;      // packed lower Cholesky factor of S~ (dense mode)
     Csr Y, YT;                     // explicit Y~ = L2 L1^{-1} (Section 3.2) and its transpose
-    SpmvPlan plY, plYT;
+    Csr Yd, YdT;                   // the device copy: Y~'s rows in yperm order, and its transpose
+    std::vector<int32_t> yperm, yperm_inv;  // device row i of Y~ is row yperm[i]
+    SpmvPlan plY, plYT;            // plans of Yd and YdT
     // Chebyshev M_b (RSILU_S_CHEB): interval [1, cheb_b], cheb_K steps with coefficients
     // d <- c1[j] d + c2[j] r, starting from d = u / theta
     double cheb_b = 1.0, cheb_theta = 1.0;

@@ -84,6 +84,18 @@ __device__ __forceinline__ T group_sum_last(T v)
     return v;
 }
 
+// The chip deals a launch's blocks to its 8 XCDs round robin (block b to XCD b % 8),
+// and each XCD has its own L2. Renumbering the blocks so that each XCD takes one
+// contiguous range of them keeps the rows an XCD processes, and the input entries
+// they gather, together in its L2. A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    constexpr int kXcd = 8;
+    const int q = nb / kXcd, r = nb % kXcd;
+    const int x = b % kXcd, i = b / kXcd;
+    return x * q + min(x, r) + i;
+}
+
 // Fixed-order sum of one value per thread of a 256-thread block; thread 0 gets it.
 __device__ __forceinline__ double block_sum256(double v, double *lds4)
 {
@@ -260,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh
     __shared__ double lds4[4];
     if (stop_now(done)) return;
     constexpr int RPB = kBlock / G;
-    const int row = blockIdx.x * RPB + threadIdx.x / G;
+    const int row = xcd_block(blockIdx.x, gridDim.x) * RPB + threadIdx.x / G;
     const int gl = threadIdx.x % G;
     T sum = 0;
     bool own = false;
@@ -287,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(DCsrT<T> a, int32_t long_thresh
     }
     if constexpr (EPI == EPI_SQ || EPI == EPI_WSQ) {
         const double s = block_sum256(contrib, lds4);
-        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+        if (threadIdx.x == 0) partials[xcd_block(blockIdx.x, gridDim.x)] = s;
     }
 }
 
@@ -310,7 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mr(DCsrT<T> a, int32_t long_thr
     const bool live = !stop_now(done);
     constexpr int RPB = kBlock / G;
     const int gl = threadIdx.x % G;
-    const int base = blockIdx.x * RPB * RPT + threadIdx.x / G;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int base = bid * RPB * RPT + threadIdx.x / G;
     int b[RPT], e[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -359,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_mr(DCsrT<T> a, int32_t long_thr
     }
     if constexpr (EPI == EPI_SQ || EPI == EPI_WSQ) {
         const double s = block_sum256(contrib, lds4);
-        if (threadIdx.x == 0 && live) partials[blockIdx.x] = s;
+        if (threadIdx.x == 0 && live) partials[bid] = s;
     }
 }
 

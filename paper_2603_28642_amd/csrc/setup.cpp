@@ -653,8 +653,34 @@ void build_explicit_Y(Ctx &c)
         Y.val.insert(Y.val.end(), pt.val.begin(), pt.val.end());
     }
     c.YT = transpose(Y);
-    c.plY = plan_spmv(c.Y);
-    c.plYT = plan_spmv(c.YT);
+    // The device copy takes Y~'s rows in the order of their first column (rows without
+    // entries last, ties by row), so that rows near each other in the launch gather nearby
+    // entries of their input, and the columns of its transpose follow that order: the
+    // (m-n)-vectors of the S~ steps live in this order on the device. The products'
+    // row sums are unchanged; only the order of the entries of those vectors differs.
+    std::vector<int32_t> order((size_t)k);
+    for (int32_t r = 0; r < k; ++r) order[(size_t)r] = r;
+    auto first_col = [&](int32_t r) { return Y.ptr[(size_t)r + 1] > Y.ptr[r] ? Y.col[Y.ptr[r]] : n; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return first_col(a) < first_col(b); });
+    c.yperm = order;
+    c.yperm_inv.assign((size_t)k, 0);
+    for (int32_t r = 0; r < k; ++r) c.yperm_inv[(size_t)order[(size_t)r]] = r;
+    Csr &D = c.Yd;
+    D = Csr{};
+    D.nrows = k;
+    D.ncols = n;
+    D.ptr.assign((size_t)k + 1, 0);
+    D.col.reserve(Y.col.size());
+    D.val.reserve(Y.val.size());
+    for (int32_t r = 0; r < k; ++r) {
+        const int32_t src = order[(size_t)r];
+        D.col.insert(D.col.end(), Y.col.begin() + Y.ptr[src], Y.col.begin() + Y.ptr[(size_t)src + 1]);
+        D.val.insert(D.val.end(), Y.val.begin() + Y.ptr[src], Y.val.begin() + Y.ptr[(size_t)src + 1]);
+        D.ptr[(size_t)r + 1] = (int32_t)D.col.size();
+    }
+    c.YdT = transpose(D);
+    c.plY = plan_spmv(c.Yd);
+    c.plYT = plan_spmv(c.YdT);
 }
 
 // Section 3.2 lets an approximation S^ of S~ stand in for it when that is cheaper to
@@ -1444,10 +1470,13 @@ void plan_layout(Ctx &c)
     L.pL2 = place_plan(b, c.plL2);
     L.pL2T = place_plan(b, c.plL2T);
     if (yexplicit(c)) {
-        L.Y = place_csr(b, c.Y, vb);
-        L.YT = place_csr(b, c.YT, vb);
+        L.Y = place_csr(b, c.Yd, vb);
+        L.YT = place_csr(b, c.YdT, vb);
         L.pY = place_plan(b, c.plY);
         L.pYT = place_plan(b, c.plYT);
+        L.yperm = b.take(sizeof(int32_t) * std::max<size_t>(k, 1));
+        L.yperm_inv = b.take(sizeof(int32_t) * std::max<size_t>(k, 1));
+        L.yk = b.take(sizeof(double) * std::max<size_t>(k, 1));
     }
     L.L1f = place_tri(b, c.L1, false, c.lvL1, c.chL1, c.swL1, c.loL1, n, vb);
     L.L1b = place_tri(b, c.L1T, false, c.lvL1T, c.chL1T, c.swL1T, c.loL1T, n, vb);
@@ -1489,8 +1518,8 @@ void plan_layout(Ctx &c)
     };
     const int64_t nparts = std::max<int64_t>({(int64_t)2048, blocks(c.Ahat.nrows, c.plA.lanes),
                                               blocks(c.AhatT.nrows, c.plAT.lanes), blocks(c.L2.nrows, c.plL2.lanes),
-                                              blocks(c.L2T.nrows, c.plL2T.lanes), blocks(c.Y.nrows, c.plY.lanes),
-                                              blocks(c.YT.nrows, c.plYT.lanes)});
+                                              blocks(c.L2T.nrows, c.plL2T.lanes), blocks(c.Yd.nrows, c.plY.lanes),
+                                              blocks(c.YdT.nrows, c.plYT.lanes)});
     const int64_t nlong = std::max<int64_t>({(int64_t)c.plA.long_rows.size(), (int64_t)c.plAT.long_rows.size(),
                                              (int64_t)c.plL2.long_rows.size(), (int64_t)c.plL2T.long_rows.size(),
                                              (int64_t)c.plR.long_rows.size(), (int64_t)c.plRT.long_rows.size(),

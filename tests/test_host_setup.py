@@ -144,7 +144,7 @@ def test_invalid_input(case):
         elif case == "bad form":
             prm.form = 2
         elif case == "bad smode":
-            prm.smode = 4
+            prm.smode = 5
         elif case == "bad precision":
             prm.precision = 2
         elif case == "fp32 syncfree":
