@@ -10,8 +10,12 @@ Tolerances (FP64 everywhere, unit roundoff eps = 2^-53 ~ 1.1e-16):
     the sync-free and level-scheduled schedules use identical per-row
     arithmetic and must agree bit for bit (the hybrid schedule sums a narrow
     row sequentially, so it is held to the oracle bounds only);
-  * Algorithm 3 and Algorithm 1: 1e-10 (a few iterations, mu = 1 factors) and
-    the 1e-8 relative bound on x for converged solves.
+  * one preconditioner application (Algorithm 3 or Algorithm 2), element by element:
+    |h - h_or| <= rtol |h_or| + atol ||h_or||_inf (apply_tol below);
+  * Algorithm 1 and LSQR: four steps with x within 1e-8 (the sparse-dense mini case in
+    ||b - A x||, see test_solve_alg2_fixed_iterations); whole solves to 1e-8 with iteration
+    counts within 2%, the true ||A^T r|| at the tolerance and x in the oracle's stop-test
+    ball, and again at tol 1e-12 with x within 1e-6 (grid workload).
 """
 
 import numpy as np
@@ -62,6 +66,21 @@ PROBLEMS = {
 
 def oracle_for(prob, **kw):
     return oracle.factor_problem(prob, **kw)
+
+
+def elementwise(got, want, rtol, atol):
+    """Largest ratio of |got - want| to rtol |want| + atol ||want||_inf (<= 1 passes)."""
+    bound = rtol * np.abs(want) + atol * np.max(np.abs(want))
+    return float(np.max(np.abs(got - want) / bound))
+
+
+def apply_tol(name, cg=False):
+    """Element-by-element bound of one preconditioner application: (1e-10, 1e-13) when only
+    triangular solves and products separate the two sides, (1e-8, 1e-11) with CG steps on S~
+    (exact line searches pass rounding differences on), 100x wider on the sparse-dense mini
+    case, whose factors have kappa(L1 U) = 2.6e9 (against 4.3 on c1)."""
+    rtol, atol = (1e-8, 1e-11) if cg else (1e-10, 1e-13)
+    return (100 * rtol, 100 * atol) if name == "c3-mini" else (rtol, atol)
 
 
 # --------------------------------------------------------------- products
@@ -146,7 +165,9 @@ def test_apply_alg3(gpu_lib, name, smode):
     assert R.rsilu_apply(S.h, to_dev(r), h) == R.OK
     got = to_host(h)
     want = oracle.apply_alg3(F, r)
-    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+    ratio = elementwise(got, want, *apply_tol(name))
+    print(f"{name} alg3 {smode}: elementwise ratio {ratio:.2e}")
+    assert ratio <= 1.0
     S.close()
 
 
@@ -268,7 +289,9 @@ def test_apply_alg2(gpu_lib, name, smode, mode):
     assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
     got = to_host(h)
     want = oracle.apply_alg2(F, z)
-    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+    ratio = elementwise(got, want, *apply_tol(name))
+    print(f"{name} alg2 {smode} {mode}: elementwise ratio {ratio:.2e}")
+    assert ratio <= 1.0
     S.close()
 
 
@@ -283,7 +306,7 @@ def test_apply_alg3_none(gpu_lib, name):
     h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
     assert R.rsilu_apply(S.h, to_dev(r), h) == R.OK
     want = oracle.apply_alg3(F, r)
-    assert np.linalg.norm(to_host(h) - want) <= 1e-10 * np.linalg.norm(want)
+    assert elementwise(to_host(h), want, *apply_tol(name)) <= 1.0
     S.close()
 
 
@@ -301,15 +324,18 @@ def test_solve_alg2_fixed_iterations(gpu_lib, name, smode, mode):
     F = oracle.factor_problem(prob, mu=1.0, smode=smode)
     res = oracle.pcgls(F, prob.b, tol=1e-14, maxit=maxit, form="alg2")
     assert it == res.iters
-    # The bound is 1e-8, unless the iteration itself amplifies rounding beyond it: then
-    # the oracle's own response to a rounding-level change of b (relative 1e-15) sets
-    # the scale (the sparse-dense mini workload with its dense rows in A1 amplifies
-    # such changes by about 1e11 within four steps).
-    b2 = prob.b * (1.0 + 1e-15 * np.random.default_rng(9).standard_normal(prob.m))
-    res2 = oracle.pcgls(F, b2, tol=1e-14, maxit=maxit, form="alg2")
-    sens = np.linalg.norm(res2.x - res.x)
-    assert np.linalg.norm(x - res.x) <= max(1e-8 * np.linalg.norm(res.x), 100.0 * sens)
-    assert abs(atr - res.atr_norm) <= max(1e-6 * res.atr_norm, 100.0 * abs(res2.atr_norm - res.atr_norm))
+    if name == "c3-mini":
+        # Its factors (dense rows pivoted into A1 at mu = 1, kappa(L1 U) = 2.6e9) make x after
+        # four steps move by 2.4e-4 relative, and ||A^T r|| by 2.9e-6, when the oracle merely
+        # sums its inner products in another order; ||b - A x|| moves by 6.9e-10. It is held
+        # to ||b - A x|| at 1e-7 and ||A^T r|| at 1e-4 (a wrong kernel is off by far more).
+        A = prob.scipy()
+        rn, rn_or = np.linalg.norm(prob.b - A @ x), np.linalg.norm(prob.b - A @ res.x)
+        assert abs(rn - rn_or) <= 1e-7 * rn_or
+        assert abs(atr - res.atr_norm) <= 1e-4 * res.atr_norm
+    else:
+        assert np.linalg.norm(x - res.x) <= 1e-8 * np.linalg.norm(res.x)
+        assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm
 
 
 @pytest.mark.parametrize("name", ["c1", "c2-small"])
@@ -338,6 +364,14 @@ def test_solve_alg2_converges_like_oracle(gpu_lib, name):
         name, it, res.iters, np.linalg.norm(e) / np.linalg.norm(res.x)))
     if name == "c1":
         assert np.linalg.norm(e) <= 1e-8 * np.linalg.norm(res.x)
+    # both sides again at tol 1e-12, where x is determined far better: x to 1e-6
+    x2, code2, it2, _, _ = run_solve(R, prob, 1e-12, mu=1.0, smode=R.S_NONE, maxit=2000, form=R.FORM_ALG2)
+    res2 = oracle.pcgls(F, prob.b, tol=1e-12, maxit=2000, form="alg2")
+    e2 = np.linalg.norm(x2 - res2.x) / np.linalg.norm(res2.x)
+    print("%s at tol 1e-12: gpu its %d oracle its %d, |x - x_or|/|x_or| = %.3e" % (name, it2, res2.iters, e2))
+    assert code2 == R.OK and res2.status == "ok"
+    assert abs(it2 - res2.iters) <= max(1, int(0.02 * res2.iters))
+    assert e2 <= 1e-6
 
 
 # --------------------------------------------------------------- FP32 preconditioner
@@ -451,7 +485,9 @@ def test_apply_cg(gpu_lib, name, form, steps, mode):
         z = rng.standard_normal(prob.n)
         assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
         want = oracle.apply_alg2(F, z)
-    assert np.linalg.norm(to_host(h) - want) <= 1e-10 * np.linalg.norm(want)
+    ratio = elementwise(to_host(h), want, *apply_tol(name, cg=True))
+    print(f"{name} {form} CG({steps}) {mode}: elementwise ratio {ratio:.2e}")
+    assert ratio <= 1.0
     S.close()
 
 
@@ -510,6 +546,16 @@ def test_lsqr_converges_like_oracle(gpu_lib, name, precision):
     e = x - res.x
     assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
     print("%s precision %d: LSQR its %d, oracle its %d" % (name, precision, it, res.iters))
+    if precision == 0:
+        # both sides again at tol 1e-12: x to 1e-6
+        x2, code2, it2, _, _ = run_solve(R, prob, 1e-12, mu=1.0, smode=R.S_NONE, maxit=2000, form=R.FORM_ALG2,
+                                         krylov=R.KRYLOV_LSQR)
+        res2 = oracle.lsqr_m(F, prob.b, tol=1e-12, maxit=2000)
+        e2 = np.linalg.norm(x2 - res2.x) / np.linalg.norm(res2.x)
+        print("%s at tol 1e-12: LSQR its %d, oracle its %d, |x - x_or|/|x_or| = %.3e" % (name, it2, res2.iters, e2))
+        assert code2 == R.OK and res2.status == "ok"
+        assert abs(it2 - res2.iters) <= max(1, int(0.02 * res2.iters))
+        assert e2 <= 1e-6
 
 
 # --------------------------------------------------------------- captured iteration graphs
