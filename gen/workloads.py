@@ -361,6 +361,10 @@ def by_name(name):
         return grid_c2(n=1_000_000, m=1_500_000, gw=1000, seed=4)
     if name == "c2-small":
         return grid_c2(n=20_000, m=30_000, gw=142, seed=12)
+    if name == "c3-40k":
+        # the sparse-dense recipe at the largest size whose host setup stays near a minute
+        # (the elimination's reach grows with the column index on this recipe)
+        return sparse_dense_c3(n=40_000, m_sparse=45_000, n_dense=64, dense_frac=0.3, k=6, seed=3)
     if name == "c3-mini":
         return sparse_dense_c3(n=2000, m_sparse=2250, n_dense=8, dense_frac=0.3, k=6, seed=13)
     raise KeyError(name)
