@@ -10,10 +10,13 @@
  * norms are separated by workgroup barriers only; no problem ever waits for
  * another, so every workgroup exits after at most maxit iterations.
  *
- * The arithmetic is that of rsilu_solve with krylov = RSILU_KRYLOV_LSQR, form =
- * RSILU_FORM_ALG2 and S^ none (Algorithm 2 with k = n and no M_b correction,
- * so M^{-1} = (L1 U)^{-1} (L1 U)^{-T}, Section 3.1; LSQR in the M-inner-product
- * form, rsilu.h), in the handle's preconditioner precision (FP64 or FP32; the
+ * The arithmetic is that of rsilu_solve with krylov = RSILU_KRYLOV_LSQR and form =
+ * RSILU_FORM_ALG2 (Algorithm 2 with k = n; LSQR in the M-inner-product form,
+ * rsilu.h), with S^ none (no M_b correction, M^{-1} = (L1 U)^{-1} (L1 U)^{-T},
+ * Section 3.1) or, with the explicit Y~ (ystore = RSILU_Y_EXPLICIT), the M_b
+ * correction of Section 3.2 with M_b = I (RSILU_S_IDENTITY) or the Chebyshev
+ * polynomial in S~ (RSILU_S_CHEB), whose steps the workgroup runs between the
+ * L1^T and L1 solves; in the handle's preconditioner precision (FP64 or FP32; the
  * LSQR vectors, recurrences, norms and the exit residual stay FP64). Only the
  * order of the floating-point sums differs from rsilu_solve. A problem's result
  * depends only on its own data and on the tile, never on the other problems of
@@ -26,7 +29,8 @@
  * The autotuner (rsilu_tune) times every compiled tile, and the plain
  * multi-kernel path (rsilu_solve), on a few iterations of a given problem and
  * keeps its choice per problem signature (precision, size and density
- * classes, level-count class), so later problems of the same class are not
+ * classes, level-count class, long rows, the correction's cost class), so
+ * later problems of the same class are not
  * timed again.
  *
  * All calls return rsilu_status_t; none throws.
@@ -86,7 +90,9 @@ rsilu_status_t rsilu_batch_create(int32_t capacity, rsilu_batch_t *out);
  * Each handle's maxit bounds its iterations. A handle's work vectors are used, so
  * a handle may not be solved elsewhere while the call runs.
  * EINVAL: count outside [0, capacity], a NULL pointer, a handle not uploaded or
- * configured otherwise, a repeated handle, a tile that is not compiled, a
+ * configured otherwise (another Krylov method or form, removed rows, or a
+ * correction other than those above: dense S~, CG steps, or Y~ applied by
+ * sweeps), a repeated handle, a tile that is not compiled, a
  * negative or non-finite tol; ESTATE: handles on another device than the
  * batch object; EHIP on runtime errors. count = 0 returns OK at once. */
 rsilu_status_t rsilu_batch_solve(rsilu_batch_t bt, int32_t count, const rsilu_handle_t *hs,

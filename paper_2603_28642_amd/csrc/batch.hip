@@ -27,7 +27,7 @@ namespace {
 // summed by the whole workgroup.
 struct BOp {
     const int32_t *ptr, *col;
-    const double *val;
+    const void *val;  // FP64 (A_hat, A_hat^T), or the preconditioner's precision (Y~, Y~^T)
     const int32_t *long_rows;
     int32_t nrows, nlong, long_thresh, pad;
 };
@@ -59,6 +59,13 @@ struct BDesc {
     double *x;
     double *xh, *z, *h, *r, *q, *v, *Mv, *w;
     void *pin, *pt0, *pt1, *pt2, *pout;  // preconditioner input, temporaries, output (its precision)
+    // M_b correction of Algorithm 2 through the explicit Y~ (rows in its device order):
+    // corr = 0 none, 1 cheb_K Chebyshev steps on S~ (coefficients c1 then c2; K = 0: M_b = I)
+    BOp Y, YT;
+    const double *cheb;
+    double cheb_theta;
+    int32_t corr, cheb_K, k, pad2;
+    void *cg, *cy, *ct, *cu, *cr, *cd, *cw, *cq;  // n: g copy, y, Y~^T product; m - n: u, r, d, w, q
     double tol;
     int32_t maxit, m, n, pad;
     BOut *out;
@@ -131,14 +138,14 @@ __device__ __forceinline__ double wg_sum(double v, double *red)
 // thread; rows longer than long_thresh are then summed by the whole workgroup.
 // The caller separates it from the producers of x and the readers of y with
 // workgroup barriers.
-template <int NT, int G>
-__device__ __forceinline__ void wg_spmv(const BOp &a, const double *xp, double *yp, double *red)
+template <int NT, int G, class T = double>
+__device__ __forceinline__ void wg_spmv(const BOp &a, const T *xp, T *yp, double *red)
 {
     constexpr int RPP = NT / G;
     constexpr int U = 2;
     const auto ptr = gm(a.ptr);
     const auto col = gm(a.col);
-    const auto val = gm(a.val);
+    const auto val = gm(static_cast<const T *>(a.val));
     const auto x = gm(xp);
     const auto y = gm(yp);
     const int gl = threadIdx.x % G, slot = threadIdx.x / G;
@@ -160,10 +167,10 @@ __device__ __forceinline__ void wg_spmv(const BOp &a, const double *xp, double *
                     own[u] = true;
             }
         }
-        double s[U];
+        T s[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            s[u] = 0.0;
+            s[u] = (T)0;
             for (int k = rb[u] + gl; k < re[u]; k += G) s[u] += val[k] * x[col[k]];
         }
 #pragma unroll
@@ -176,10 +183,10 @@ __device__ __forceinline__ void wg_spmv(const BOp &a, const double *xp, double *
     for (int i = 0; i < a.nlong; ++i) {
         const int row = longr[i];
         const int b = ptr[row], e = ptr[row + 1];
-        double s = 0.0;
+        T s = (T)0;
         for (int k = b + (int)threadIdx.x; k < e; k += NT) s += val[k] * x[col[k]];
-        s = wg_sum<NT>(s, red);
-        if (threadIdx.x == 0) y[row] = s;
+        const double tot = wg_sum<NT>((double)s, red);
+        if (threadIdx.x == 0) y[row] = (T)tot;
     }
 }
 
@@ -309,13 +316,69 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
     }
 }
 
-// h = M^{-1} z with M^{-1} = (L1 U)^{-1} (L1 U)^{-T} (Algorithm 2, k = n, no M_b
-// correction): U^T t0 = z, L1^T t1 = t0, L1 t2 = t1, U h = t2. In FP32 the input
+// Steps 2-4 of Algorithm 2 with the explicit Y~ (Section 3.2), from g = L1^{-T} U^{-T} z
+// (global, n values) to y = g - Y~^T v_b: w_b = Y~ g, v_b = M_b^{-1} w_b by cheb_K
+// Chebyshev steps on S~ = I + Y~ Y~^T (none: v_b = w_b; per step q = Y~ (Y~^T d), w += d,
+// r -= d + q, d = c1 d + c2 r, from r = w_b, d = w_b / theta, w = 0; v_b = w), then
+// y = g - Y~^T v_b. The (m - n)-vectors are in the device order of Y~'s rows. The caller
+// separates g's producers and y's readers from it with barriers.
+template <class T, int NT, int G>
+__device__ __forceinline__ void wg_correction(const BDesc &d, const T *gp, T *yp, double *red)
+{
+    const int n = d.n, k = d.k;
+    const auto g = gm(gp);
+    const auto y = gm(yp);
+    T *u = static_cast<T *>(d.cu);
+    T *t = static_cast<T *>(d.ct);
+    wg_spmv<NT, G, T>(d.Y, gp, u, red);
+    __syncthreads();
+    if (d.cheb_K > 0) {
+        const auto uu = gm(u);
+        const auto r = gm(static_cast<T *>(d.cr)), dd = gm(static_cast<T *>(d.cd)), w = gm(static_cast<T *>(d.cw));
+        const auto q = gm(static_cast<const T *>(d.cq));
+        const T theta = (T)d.cheb_theta;
+        for (int i = threadIdx.x; i < k; i += NT) {
+            const T ui = uu[i];
+            r[i] = ui;
+            dd[i] = ui / theta;
+            w[i] = (T)0;
+        }
+        const auto cf = gm(d.cheb);
+        for (int j = 0; j < d.cheb_K; ++j) {
+            __syncthreads();
+            wg_spmv<NT, G, T>(d.YT, static_cast<const T *>(d.cd), t, red);
+            __syncthreads();
+            wg_spmv<NT, G, T>(d.Y, t, static_cast<T *>(d.cq), red);
+            __syncthreads();
+            const T c1 = (T)cf[j], c2 = (T)cf[d.cheb_K + j];
+            const bool last = j + 1 == d.cheb_K;
+            for (int i = threadIdx.x; i < k; i += NT) {
+                const T di = dd[i];
+                const T wi = w[i] + di;
+                const T ri = r[i] - (di + q[i]);
+                w[i] = wi;
+                r[i] = ri;
+                dd[i] = c1 * di + c2 * ri;
+                if (last) uu[i] = wi;
+            }
+        }
+        __syncthreads();
+    }
+    wg_spmv<NT, G, T>(d.YT, u, t, red);
+    __syncthreads();
+    const auto tt = gm(static_cast<const T *>(t));
+    for (int i = threadIdx.x; i < n; i += NT) y[i] = g[i] - tt[i];
+    __syncthreads();
+}
+
+// h = M^{-1} z with M^{-1} = (L1 U)^{-1} (L1 U)^{-T} (Algorithm 2, k = n, without the M_b
+// correction): U^T t0 = z, L1^T t1 = t0, L1 t2 = t1, U h = t2; with it, t1 is replaced
+// by t1 - Y~^T v_b before the L1 solve (wg_correction). In FP32 the input
 // is rounded to FP32 first and h converted back. With XL the four solution
 // vectors live in LDS (two arrays of n values, used alternately; xl holds 2n
 // values), so a level reads its inputs from LDS instead of through the caches.
-template <class T, int NT, int G, bool XL>
-__device__ __forceinline__ void wg_precond_in(const BDesc &d, T *xl)
+template <class T, int NT, int G, int GS, bool XL>
+__device__ __forceinline__ void wg_precond_in(const BDesc &d, T *xl, double *red)
 {
     const int n = d.n;
     const auto z = gm(d.z);
@@ -330,7 +393,16 @@ __device__ __forceinline__ void wg_precond_in(const BDesc &d, T *xl)
         T *xa = xl, *xb = xl + n;
         wg_trsv<T, NT, G>(d.tri[0], in, xa);
         wg_trsv<T, NT, G>(d.tri[1], xa, xb);
-        wg_trsv<T, NT, G>(d.tri[2], xb, xa);
+        if (d.corr) {
+            __syncthreads();
+            const auto gc = gm(static_cast<T *>(d.cg));
+            for (int i = threadIdx.x; i < n; i += NT) gc[i] = xb[i];
+            __syncthreads();
+            wg_correction<T, NT, GS>(d, static_cast<const T *>(d.cg), static_cast<T *>(d.cy), red);
+            wg_trsv<T, NT, G>(d.tri[2], gm(static_cast<const T *>(d.cy)), xa);
+        } else {
+            wg_trsv<T, NT, G>(d.tri[2], xb, xa);
+        }
         wg_trsv<T, NT, G>(d.tri[3], xa, xb);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += NT) h[i] = (double)xb[i];
@@ -342,7 +414,13 @@ __device__ __forceinline__ void wg_precond_in(const BDesc &d, T *xl)
         const auto out = gm(std::is_same<T, float>::value ? static_cast<T *>(d.pout) : reinterpret_cast<T *>(d.h));
         wg_trsv<T, NT, G>(d.tri[0], in, t0);
         wg_trsv<T, NT, G>(d.tri[1], t0, t1);
-        wg_trsv<T, NT, G>(d.tri[2], t1, t2);
+        if (d.corr) {
+            __syncthreads();
+            wg_correction<T, NT, GS>(d, static_cast<const T *>(d.pt1), static_cast<T *>(d.cy), red);
+            wg_trsv<T, NT, G>(d.tri[2], gm(static_cast<const T *>(d.cy)), t2);
+        } else {
+            wg_trsv<T, NT, G>(d.tri[2], t1, t2);
+        }
         wg_trsv<T, NT, G>(d.tri[3], t2, out);
         __syncthreads();
         if constexpr (std::is_same<T, float>::value)
@@ -352,13 +430,13 @@ __device__ __forceinline__ void wg_precond_in(const BDesc &d, T *xl)
 
 // The preconditioner of one problem: its solution vectors in LDS when 2 n values
 // fit in the launch's dynamic LDS (xl_bytes), else in global memory.
-template <class T, int NT, int G>
-__device__ __forceinline__ void wg_precond(const BDesc &d, T *xl, uint32_t xl_bytes)
+template <class T, int NT, int G, int GS>
+__device__ __forceinline__ void wg_precond(const BDesc &d, T *xl, uint32_t xl_bytes, double *red)
 {
     if (2 * (uint64_t)d.n * sizeof(T) <= xl_bytes)
-        wg_precond_in<T, NT, G, true>(d, xl);
+        wg_precond_in<T, NT, G, GS, true>(d, xl, red);
     else
-        wg_precond_in<T, NT, G, false>(d, xl);
+        wg_precond_in<T, NT, G, GS, false>(d, xl, red);
 }
 
 // The whole LSQR solve of problem blockIdx.x (M-inner-product form): init,
@@ -418,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
     }
     // h = M^{-1} s, alpha = sqrt(s . h), v = h / alpha, M v = s / alpha, w = v
     if (!done) {
-        wg_precond<T, NT, GT>(d, xl, xl_bytes);
+        wg_precond<T, NT, GT, GS>(d, xl, xl_bytes, red);
         sq = 0.0;
         for (int i = tid; i < n; i += NT) sq += z[i] * h[i];
         const double tot = wg_sum<NT>(sq, red);
@@ -472,7 +550,7 @@ __global__ __launch_bounds__(NT) void k_batch_lsqr(const BDesc *__restrict__ des
         }
         snorm = sqrt(wg_sum<NT>(sq, red));
         // h = M^{-1} s, alpha = sqrt(s . h)
-        wg_precond<T, NT, GT>(d, xl, xl_bytes);
+        wg_precond<T, NT, GT, GS>(d, xl, xl_bytes, red);
         sq = 0.0;
         for (int i = tid; i < n; i += NT) sq += z[i] * h[i];
         const double tot = wg_sum<NT>(sq, red);
@@ -606,8 +684,16 @@ T *at(const Ctx &c, size_t off)
 
 BOp bop(const Ctx &c, const DevCsrOff &o, const DevPlanOff &p)
 {
-    return BOp{at<int32_t>(c, o.ptr), at<int32_t>(c, o.col), at<double>(c, o.val), at<int32_t>(c, p.long_rows),
+    return BOp{at<int32_t>(c, o.ptr), at<int32_t>(c, o.col), at<void>(c, o.val), at<int32_t>(c, p.long_rows),
                o.nrows, p.nlong, p.long_thresh, 0};
+}
+
+// The M_b correction the batched kernel applies: 0 none (no A2 rows, or S^ absent),
+// 1 Chebyshev steps through the explicit Y~; -1 a correction it does not implement.
+int32_t correction_of(const Ctx &c)
+{
+    if (c.L2.nrows == 0 || c.smode == RSILU_S_NONE) return 0;
+    return c.smode == RSILU_S_CHEB && yexplicit(c) ? 1 : -1;
 }
 
 BTri btri(const Ctx &c, const DevTriOff &o)
@@ -621,7 +707,7 @@ rsilu_status_t check_handle(const Ctx &c)
 {
     if (!c.dev) return RSILU_EINVAL;
     if (c.prm.krylov != RSILU_KRYLOV_LSQR || c.prm.form != RSILU_FORM_ALG2) return RSILU_EINVAL;
-    if (c.m > c.n && c.smode != RSILU_S_NONE) return RSILU_EINVAL;
+    if (correction_of(c) < 0) return RSILU_EINVAL;
     if (c.R.nrows > 0) return RSILU_EINVAL;  // removed rows change the preconditioner
     return RSILU_OK;
 }
@@ -657,6 +743,23 @@ BDesc make_desc(const Ctx &c, const double *b, double *x, double tol, int32_t ma
         d.pin = at<void>(c, L.f32a);
         d.pout = at<void>(c, L.f32b);
     }
+    d.corr = correction_of(c);
+    d.k = (int32_t)c.L2.nrows;
+    if (d.corr > 0) {
+        d.Y = bop(c, L.Y, L.pY);
+        d.YT = bop(c, L.YT, L.pYT);
+        d.cg = at<void>(c, L.s2);
+        d.cy = at<void>(c, L.y);
+        d.ct = at<void>(c, L.c2);
+        d.cu = at<void>(c, L.u);
+        d.cheb = at<double>(c, L.cheb);
+        d.cheb_theta = c.cheb_theta;
+        d.cheb_K = c.cheb_K;
+        d.cr = at<void>(c, L.cg_r);
+        d.cd = at<void>(c, L.cg_p);
+        d.cw = at<void>(c, L.cg_w);
+        d.cq = at<void>(c, L.cg_q);
+    }
     d.tol = tol;
     d.maxit = maxit;
     d.m = (int32_t)c.m;
@@ -670,7 +773,9 @@ BDesc make_desc(const Ctx &c, const double *b, double *x, double tol, int32_t ma
 // longest workgroups start first.
 double work_of(const Ctx &c)
 {
-    return 2.0 * (double)c.nnz_a + (double)(c.L1.nnz() * 2 + c.U.nnz() * 2) +
+    const int32_t corr = correction_of(c);
+    const double ny = corr > 0 ? (double)c.Yd.nnz() * (2.0 + 2.0 * c.cheb_K) : 0.0;
+    return 2.0 * (double)c.nnz_a + (double)(c.L1.nnz() * 2 + c.U.nnz() * 2) + ny +
            2000.0 * (double)(c.lvL1.nlev() * 2 + c.lvU.nlev() + c.lvUT.nlev());
 }
 
@@ -828,7 +933,7 @@ struct rsilu_tuner {
     double slack = 1.0;
     int32_t iters = 8;
     rsilu_batch_t bt = nullptr;  // single-problem batch object for timing
-    std::map<std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t>, rsilu_tune_result_t> cache;
+    std::map<std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>, rsilu_tune_result_t> cache;
     std::mutex mu;
 };
 
@@ -837,14 +942,19 @@ namespace {
 
 int32_t log2_class(double v) { return v <= 1.0 ? 0 : (int32_t)std::floor(std::log2(v)); }
 
-// Signature of a problem: precision, size class, density class, level class
-// and whether long rows are present.
-std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> signature(const Ctx &c)
+// Signature of a problem: precision, size class, density class, level class,
+// whether long rows are present, and the correction's class (none, or the
+// products with Y~ per application relative to those with A_hat).
+std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t> signature(const Ctx &c)
 {
     const double nnz_per_row = c.m ? (double)c.nnz_a / (double)c.m : 0.0;
     const int32_t levels = c.lvL1.nlev() + c.lvL1T.nlev() + c.lvU.nlev() + c.lvUT.nlev();
+    const int32_t corr = correction_of(c);
+    const double yrel =
+        corr > 0 ? (double)c.Yd.nnz() * (2.0 + 2.0 * c.cheb_K) / std::max(1.0, 2.0 * (double)c.nnz_a) : 0.0;
     return std::make_tuple((int32_t)fp32(c), log2_class((double)c.n), log2_class(4.0 * nnz_per_row),
-                           log2_class((double)levels), (int32_t)(c.plA.long_rows.size() > 0));
+                           log2_class((double)levels), (int32_t)(c.plA.long_rows.size() > 0),
+                           corr > 0 ? 1 + log2_class(2.0 * yrel) : 0);
 }
 
 double elapsed_ms(std::chrono::steady_clock::time_point a)

@@ -867,6 +867,10 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put(L.perm, c.perm.data(), c.perm.size() * sizeof(int32_t)));
     RSILU_HIP(put(L.colnorm, c.colnorm.data(), c.colnorm.size() * sizeof(double)));
     RSILU_HIP(put(L.sfac, c.sfac.data(), c.sfac.size() * sizeof(double)));
+    if (c.smode == RSILU_S_CHEB) {
+        RSILU_HIP(put(L.cheb, c.cheb_c1.data(), c.cheb_c1.size() * sizeof(double)));
+        RSILU_HIP(put(L.cheb + sizeof(double) * c.cheb_c1.size(), c.cheb_c2.data(), c.cheb_c2.size() * sizeof(double)));
+    }
     if (c.R.nrows > 0) {
         RSILU_HIP(put_csr(L.R, c.R));
         RSILU_HIP(put_csr(L.RT, c.RT));

@@ -122,6 +122,7 @@ struct Layout {
     size_t lo_rhs = 0, lo_add = 0;  // level-ordered right-hand side and addend of a sweep (n)
     size_t f32a = 0, f32b = 0;      // FP32 preconditioner: converted input and output (m floats each)
     size_t cg_w = 0, cg_r = 0, cg_p = 0, cg_q = 0;  // CG or Chebyshev steps on S~ (m - n each)
+    size_t cheb = 0;  // Chebyshev step coefficients c1[K] then c2[K] (read by the batched kernel)
     size_t l_v = 0, l_mv = 0, l_w = 0;              // LSQR: v, M v, w (n each)
     size_t partials = 0;  // reduction partials
     int32_t npartials = 0;

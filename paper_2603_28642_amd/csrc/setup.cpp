@@ -1508,6 +1508,7 @@ void plan_layout(Ctx &c)
     }
     if (c.smode == RSILU_S_CG || c.smode == RSILU_S_CHEB)
         for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
+    if (c.smode == RSILU_S_CHEB) L.cheb = b.take(sizeof(double) * std::max<size_t>(2 * (size_t)c.cheb_K, 1));
     if (c.prm.krylov == RSILU_KRYLOV_LSQR)
         for (size_t *o : {&L.l_v, &L.l_mv, &L.l_w}) *o = b.take(sizeof(double) * n);
     // one partial per block of the largest reduction (a product's blocks hold

@@ -5,6 +5,9 @@
   converge like it (iteration counts within 2%, the true ||A^T r|| at 2 tol, the
   solution in the oracle's stop-test ball ||A^T A (x - x_or)|| <= 4 tol ||A^T b||);
 * every compiled tile, FP64 and FP32 preconditioners;
+* the M_b correction (Chebyshev steps on S~ through the explicit Y~) inside the kernel:
+  four steps against the oracle's LSQR with the same preconditioner on every tile,
+  whole solves like the oracle's, a corrected and an uncorrected problem in one launch;
 * a problem's result in a mixed launch equals its result alone, bit for bit;
 * graph replays of the same batch equal the first call;
 * invalid calls are rejected;
@@ -44,6 +47,14 @@ PROBLEMS = {
 def solvers(R, names, **kw):
     probs = [PROBLEMS[n]() for n in names]
     return probs, [R.Solver.from_problem(p, **dict(LSQR, **kw)).upload() for p in probs]
+
+
+# LSQR with Algorithm 2 and M_b by the Chebyshev polynomial in S~, Y~ stored explicitly
+CHEB = dict(mu=1.0, form=1, krylov=1, smode=4, ystore=1, ytau=1e-2)
+
+
+def cheb_factors(p):
+    return oracle.factor_problem(p, mu=1.0, smode="cheb", ystore=True, ytau=1e-2)
 
 
 def test_batch_four_steps_follow_oracle(gpu_lib):
@@ -182,12 +193,15 @@ def test_batch_rejects_invalid(gpu_lib):
     pcgls = R.Solver.from_problem(p, mu=1.0, smode=R.S_IDENTITY).upload()
     ident = R.Solver.from_problem(p, mu=1.0, smode=R.S_DENSE, form=1, krylov=1).upload()
     not_up = R.Solver.from_problem(p, **LSQR)
+    # the Chebyshev M_b with Y~ applied by sweeps: only the plain path takes it
+    sweeps = R.Solver.from_problem(p, **dict(CHEB, ystore=0)).upload()
     b = to_dev(p.b)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     bt = R.Batch(2)
     assert bt.solve_raw([pcgls.h], [b], [1e-8], [x])[0] == R.EINVAL
     assert bt.solve_raw([ident.h], [b], [1e-8], [x])[0] == R.EINVAL
     assert bt.solve_raw([not_up.h], [b], [1e-8], [x])[0] == R.EINVAL
+    assert bt.solve_raw([sweeps.h], [b], [1e-8], [x])[0] == R.EINVAL
     assert bt.solve_raw([good.h, good.h], [b, b], [1e-8, 1e-8], [x, x])[0] == R.EINVAL
     assert bt.solve_raw([good.h] * 3, [b] * 3, [1e-8] * 3, [x] * 3)[0] == R.EINVAL  # over capacity
     assert bt.solve_raw([good.h], [b], [-1.0], [x])[0] == R.EINVAL
@@ -198,7 +212,7 @@ def test_batch_rejects_invalid(gpu_lib):
     code, res = bt.solve_raw([good.h], [b], [1e-8], [x])
     assert code == R.OK and res[0]["status"] == R.OK
     bt.close()
-    for s in (good, pcgls, ident, not_up):
+    for s in (good, pcgls, ident, not_up, sweeps):
         s.close()
 
 
@@ -319,3 +333,96 @@ def test_solve_auto_waits_for_the_callers_stream(gpu_lib):
     tu.close()
     for s in S:
         s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_correction_every_tile(gpu_lib, precision):
+    """The Chebyshev M_b correction inside the batched kernel, on every compiled tile:
+    FP64, four steps against the oracle's LSQR with the same preconditioner (x to 1e-8,
+    ||A^T r|| to 1e-6; degrees 2 to 104, Y~ rows up to a few thousand entries); FP32, whole
+    solves to 1e-8 (true residual at 2 tol, in the FP64 oracle's stop-test ball)."""
+    R = gpu_lib
+    names = ["c1", "c2-small", "long-rows", "served-dense"] if precision == 0 else ["c1", "served-dense", "served"]
+    maxit = 4 if precision == 0 else 2000
+    tol = 1e-14 if precision == 0 else 1e-8
+    probs = [PROBLEMS[n]() for n in names]
+    S = [R.Solver.from_problem(p, maxit=maxit, precision=precision, **CHEB).upload() for p in probs]
+    Fs = [cheb_factors(p) for p in probs]
+    for s_, F in zip(S, Fs):
+        assert s_.stats.cheb_degree == F.cheb_degree
+    want = [oracle.lsqr_m(F, p.b, tol=tol, maxit=maxit) for F, p in zip(Fs, probs)]
+    bt = R.Batch(len(probs))
+    for tile in R.rsilu_batch_tiles():
+        xs, res = bt.solve(S, [to_dev(p.b) for p in probs], tol, tile=tile)
+        for name, p, x, r, o, F in zip(names, probs, xs, res, want, Fs):
+            got = x.cpu().numpy()
+            if precision == 0:
+                err = np.linalg.norm(got - o.x) / np.linalg.norm(o.x)
+                assert r["iters"] == o.iters == 4, (tile, name)
+                assert err <= 1e-8, (tile, name, err)
+                assert abs(r["atr_norm"] - o.atr_norm) <= 1e-6 * o.atr_norm, (tile, name)
+            else:
+                A = p.scipy()
+                atb = np.linalg.norm(A.T @ p.b)
+                assert r["status"] == R.OK and o.status == "ok", (tile, name)
+                assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2 * tol * atb, (tile, name)
+                assert np.linalg.norm(A.T @ (A @ (got - o.x))) <= 4 * tol * atb, (tile, name)
+        print("tile %s: %s" % (tile, ", ".join("%s %d its" % (n, r["iters"]) for n, r in zip(names, res))))
+    bt.close()
+    for s_ in S:
+        s_.close()
+
+
+def test_batch_correction_converges_like_oracle(gpu_lib):
+    """FP64, default tile: iteration counts within 2% of the oracle's, the true ||A^T r||
+    at the tolerance, the solution in the oracle's stop-test ball; then tol 1e-12, where x
+    agrees with the oracle's to 1e-6."""
+    R = gpu_lib
+    names = ["c1", "c2-small", "served-dense", "served"]
+    probs = [PROBLEMS[n]() for n in names]
+    S = [R.Solver.from_problem(p, maxit=2000, **CHEB).upload() for p in probs]
+    Fs = [cheb_factors(p) for p in probs]
+    bt = R.Batch(len(probs))
+    for tol in (1e-8, 1e-12):
+        xs, res = bt.solve(S, [to_dev(p.b) for p in probs], tol)
+        for name, p, x, r, F in zip(names, probs, xs, res, Fs):
+            o = oracle.lsqr_m(F, p.b, tol=tol, maxit=2000)
+            got = x.cpu().numpy()
+            A = p.scipy()
+            atb = np.linalg.norm(A.T @ p.b)
+            xerr = np.linalg.norm(got - o.x) / np.linalg.norm(o.x)
+            print("%s tol %g: batched its %d, oracle its %d, x rel diff %.1e" % (name, tol, r["iters"], o.iters, xerr))
+            assert r["status"] == R.OK and o.status == "ok", name
+            assert abs(r["iters"] - o.iters) <= max(1, int(0.02 * o.iters)), name
+            assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2 * tol * atb, name
+            assert np.linalg.norm(A.T @ (A @ (got - o.x))) <= 4 * tol * atb, name
+            if tol == 1e-12:
+                assert xerr <= 1e-6, name
+    bt.close()
+    for s_ in S:
+        s_.close()
+
+
+def test_batch_correction_mixed_launch(gpu_lib):
+    """A corrected and an uncorrected problem, FP64 and FP32, in one launch: each result
+    equals its lone launch bit for bit."""
+    R = gpu_lib
+    p1, p2 = gen.served_request(3000, 4500, 81, n_dense=10), gen.served_request(4000, 5200, 82)
+    tile = (256, 8, 1)
+    for prec in (0, 1):
+        S = [R.Solver.from_problem(p1, maxit=2000, precision=prec, **CHEB).upload(),
+             R.Solver.from_problem(p2, maxit=2000, precision=prec, **LSQR).upload(),
+             R.Solver.from_problem(p2, maxit=2000, precision=prec, **CHEB).upload()]
+        bs = [to_dev(p1.b), to_dev(p2.b), to_dev(p2.b)]
+        bt = R.Batch(3)
+        xs, res = bt.solve(S, bs, 1e-8, tile=tile)
+        mixed = [x.cpu().numpy() for x in xs]
+        for i in range(3):
+            x1, r1 = bt.solve([S[i]], [bs[i]], 1e-8, tile=tile)
+            assert r1[0]["iters"] == res[i]["iters"] and r1[0]["status"] == res[i]["status"] == R.OK, (prec, i)
+            assert np.array_equal(x1[0].cpu().numpy().view(np.int64), mixed[i].view(np.int64)), (prec, i)
+        print("precision %d: its corrected %d, uncorrected %d, corrected %d" % (
+            prec, res[0]["iters"], res[1]["iters"], res[2]["iters"]))
+        bt.close()
+        for s_ in S:
+            s_.close()

@@ -243,3 +243,46 @@ def test_c2_chebyshev_apply_and_four_lsqr_steps(gpu_lib):
           % (st.cheb_degree, ratio, err))
     assert ratio <= 1.0
     assert it == res.iters == 4 and err <= 1e-8
+
+
+def test_c4_fp32_preconditioner_with_correction(gpu_lib):
+    """1500000 x 1000000 with the A2 correction stored and applied in FP32: L1, U, the
+    explicit Y~ and the Chebyshev M_b steps in FP32, the LSQR recurrences, norms and the
+    final residual in FP64. One application against the FP64 oracle's (its error stated),
+    then the whole solve beside the FP64 preconditioner on the same GPU."""
+    R = gpu_lib
+    import torch
+
+    prob = gen.by_name("c4")
+    F = oracle.factor_problem(prob, mu=1.0, smode="cheb", ystore=True, ytau=1e-2)
+    kw = dict(mu=1.0, form=1, smode=R.S_CHEB, ystore=1, ytau=1e-2, krylov=R.KRYLOV_LSQR, maxit=2000)
+    z = np.random.default_rng(55).standard_normal(prob.n)
+    want = oracle.apply_alg2(F, z)
+    tol = 1e-8
+    b = torch.from_numpy(prob.b).cuda()
+    out, err = {}, {}
+    for prec in (R.PREC_FP64, R.PREC_FP32):
+        S = R.Solver.from_problem(prob, precision=prec, **kw).upload()
+        st = S.stats
+        assert st.cheb_degree == F.cheb_degree and abs(st.cheb_b - F.cheb_b) <= 1e-12 * F.cheb_b
+        h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        assert R.rsilu_apply_z(S.h, torch.from_numpy(z).cuda(), h) == R.OK
+        got = h.cpu().numpy()
+        err[prec] = (np.linalg.norm(got - want) / np.linalg.norm(want), elementwise(got, want, 1e-9, 1e-12))
+        x, code, it, atr, rel = S.solve(b, tol=tol)
+        out[prec] = (x.cpu().numpy(), code, it, rel)
+        S.close()
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    for prec, (x, code, it, rel) in out.items():
+        assert code == R.OK, prec
+        assert np.linalg.norm(A.T @ (prob.b - A @ x)) <= 2 * tol * atb, prec
+    x64, x32 = out[R.PREC_FP64][0], out[R.PREC_FP32][0]
+    ball = np.linalg.norm(A.T @ (A @ (x32 - x64))) / atb
+    print("grid 1500000 x 1000000, Chebyshev degree %d: apply vs FP64 oracle rel err fp64 %.1e (elementwise ratio "
+          "%.2e), fp32 %.1e; its fp64 %d, fp32 %d; fp32 solution: ball %.1e, ||x32 - x64|| / ||x64|| %.1e" % (
+              F.cheb_degree, err[R.PREC_FP64][0], err[R.PREC_FP64][1], err[R.PREC_FP32][0], out[R.PREC_FP64][2],
+              out[R.PREC_FP32][2], ball, np.linalg.norm(x32 - x64) / np.linalg.norm(x64)))
+    assert err[R.PREC_FP64][1] <= 1.0
+    assert err[R.PREC_FP32][0] <= 1e-4
+    assert ball <= 4 * tol
