@@ -74,11 +74,15 @@ enum {
                              iteration on S~ w = u from w = 0 over [1, b], b = 1.05 times a
                              50-step power-iteration estimate of lambda_max(S~) taken at
                              setup. Linear in u and symmetric positive definite: the default
-                             degree is the smallest even K with (b - 1) / T_K((b+1)/(b-1)) <=
-                             poly_delta, so the Algorithm 2 operator times A~^T A~ has its
-                             eigenvalues in [1 - poly_delta, 1 + poly_delta] (A~ = [L1; Y~ L1] U
-                             with the explicit Y~, [L1; L2] U otherwise), and an even degree
-                             keeps it positive definite beyond b. LSQR may use it. S~ products
+                             degree is the smallest even K with (b - 1) eps_K <= poly_delta,
+                             eps_K = 1 / T_K((b+1)/(b-1)), so the Algorithm 2 operator times
+                             A~^T A~ has its eigenvalues in [1 - poly_delta, 1 + poly_delta]
+                             (A~ = [L1; Y~ L1] U with the explicit Y~, [L1; L2] U otherwise),
+                             and an even degree keeps it positive definite beyond b. A degree
+                             that misses that bound (a fixed poly_degree too low for the
+                             interval, or the cap of 512) starts the iteration from omega u,
+                             omega = 1 / (1 + eps_K), which keeps M_b^{-1} and the operator
+                             positive definite (stats.cheb_scale). LSQR may use it. S~ products
                              as for RSILU_S_CG. FP64 or FP32 (with the explicit Y~); hybrid or
                              level schedule */
     RSILU_S_CG = 3        /* cg_steps steps of conjugate gradients on S~ w = u from
@@ -216,6 +220,8 @@ typedef struct {
     double cheb_b;         /* RSILU_S_CHEB: upper end b of the Chebyshev interval [1, b] */
     int32_t cheb_degree;   /* RSILU_S_CHEB: steps of the Chebyshev iteration (0: S~ = I) */
     int32_t reserved2;
+    double cheb_scale;     /* RSILU_S_CHEB: omega, the scale of the iteration's input (1 when
+                              the degree meets the poly_delta bound) */
 } rsilu_stats_t;
 
 typedef struct rsilu_ctx *rsilu_handle_t;

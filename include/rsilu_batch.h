@@ -74,6 +74,11 @@ typedef struct {
  * copied there. */
 int32_t rsilu_batch_tiles(rsilu_tile_t *tiles, int32_t max);
 
+/* 1 when the batched kernel takes h's configuration (LSQR, Algorithm 2 form, no
+ * removed rows, and no M_b correction or the Chebyshev one through the explicit
+ * Y~), 0 otherwise (also for NULL). h need not be uploaded. */
+int32_t rsilu_batch_accepts(rsilu_handle_t h);
+
 /* Create a batch object for up to `capacity` problems per launch on the current
  * device (allocates the descriptor table and pinned host mirrors).
  * EINVAL: capacity < 1 or > 65535; ENOMEM / EHIP on allocation failure. */

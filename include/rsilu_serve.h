@@ -15,8 +15,8 @@
  * With batch_max = 0 every admitted request is solved alone by rsilu_solve.
  * With batch_max >= 1 a free slot admits, first come first served, up to
  * batch_max ready requests that fit in the arena together. Without the
- * autotuner (tune_slack = 0) those the batched kernel accepts (LSQR,
- * Algorithm 2 form, S^ none) share one persistent launch with 1024 threads, 4
+ * autotuner (tune_slack = 0) those the batched kernel accepts
+ * (rsilu_batch_accepts) share one persistent launch with 1024 threads, 4
  * and 4 lanes (rsilu_batch.h), the others take rsilu_solve. With the autotuner
  * (tune_slack > 0) an admission holding at least two accepted requests is
  * scheduled by rsilu_batch_solve_auto (one batched launch, the slowest requests
@@ -57,6 +57,10 @@ typedef struct {
     double tune_slack;     /* > 0: schedule admissions with the autotuner (rsilu_tuner_create
                               with this slack); 0: the batched kernel with 1024 threads, 4 and
                               4 lanes for every request it accepts */
+    double batch_wait_ms;  /* batch_max >= 2: after admitting a request, a slot waits up to
+                              this long for more requests to finish their setup (while any
+                              are in setup and fewer than batch_max are ready), so arrivals
+                              close together share a launch; 0: no wait */
 } rsilu_server_opts_t;
 
 typedef struct {
@@ -92,7 +96,7 @@ typedef struct {
  * stream (and, with batch_max >= 1, one batch object) per slot and the
  * autotuner, and starts the threads. EINVAL for bad options (slots or
  * setup_threads < 1, batch_max outside [0, 65535], tune_slack negative or not
- * finite), ENOMEM if the arena cannot be allocated, EHIP for other runtime
+ * finite, batch_wait_ms negative or not finite), ENOMEM if the arena cannot be allocated, EHIP for other runtime
  * errors. */
 rsilu_status_t rsilu_server_create(const rsilu_server_opts_t *opts, rsilu_server_t *out);
 

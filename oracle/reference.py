@@ -317,6 +317,9 @@ class Factors:
     ytau: float = 0.0  # drop tolerance of the explicit Y~
     cheb_b: float = 1.0  # Chebyshev M_b: upper end of the interval [1, b] (cheb mode)
     cheb_degree: int = 0  # its number of steps
+    cheb_omega: float = 1.0  # scale of its input (cheb_scale)
+    poly_degree: int = 0  # the requested degree (0: from poly_delta)
+    poly_delta: float = 0.9
 
     @property
     def psize(self):
@@ -393,9 +396,15 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
         F.ytau = float(ytau)
         F.Y = explicit_Y(L1, L2, F.ytau)
         F.YT = F.Y.transpose()
+    F.poly_degree, F.poly_delta = int(poly_degree), float(poly_delta)
     if smode == "cheb" and m > n:
-        F.cheb_b, F.cheb_degree = cheb_plan(lambda_max_S(F), poly_delta, poly_degree)
+        _plan_chebyshev(F)
     return F
+
+
+def _plan_chebyshev(F):
+    F.cheb_b, F.cheb_degree = cheb_plan(lambda_max_S(F), F.poly_delta, F.poly_degree)
+    F.cheb_omega = cheb_scale(F.cheb_b, F.cheb_degree, F.poly_delta)
 
 
 def factor_problem(prob, **kw):
@@ -440,6 +449,8 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
     if F.Y is not None:
         G.Y = explicit_Y(F.L1, L2, F.ytau)
         G.YT = G.Y.transpose()
+    if F.smode == "cheb":
+        _plan_chebyshev(G)  # S~ changed with the rows
     if F.R is not None:
         G.W_chol = _woodbury_chol(G)
     return G
@@ -521,12 +532,27 @@ def cheb_plan(lam, delta, degree=0):
     return b, K
 
 
+def cheb_scale(b, K, delta):
+    """Scale omega of the Chebyshev M_b^{-1} = omega p_K(S~). When (b - 1) eps_K <= delta
+    (cheb_plan's bound; always so for the default degree below 512) omega = 1. Otherwise (a
+    degree fixed too low for the interval, or the cap of 512) the unscaled operator can be
+    indefinite, and omega = 1 / (1 + eps_K): on [1, b] the factor of cheb_plan becomes
+    1 - omega (t - 1) p_K(t) with (t - 1) p_K(t) = (t - 1)(1 - r_K(t)) / t < 1 + eps_K, so it
+    stays above 1 / t > 0; right of b an even K keeps r_K > 0 and p_K(t) < 1 / t."""
+    if K == 0 or not b > 1.0:
+        return 1.0
+    eps = 1.0 / math.cosh(K * math.acosh((b + 1.0) / (b - 1.0)))
+    return 1.0 if (b - 1.0) * eps <= delta else 1.0 / (1.0 + eps)
+
+
 def cheb_S(F, u):
     """M_b^{-1} u by the Chebyshev iteration on S~ w = u over [1, F.cheb_b] with F.cheb_degree
     steps from w = 0 (the classical three-term form: theta = (b + 1)/2, delta = (b - 1)/2,
     sigma = theta/delta, rho_0 = 1/sigma, d_0 = u/theta; each step w += d, r -= S~ d,
-    rho' = 1/(2 sigma - rho), d = rho' rho d + (2 rho'/delta) r). A fixed polynomial in S~:
-    linear in u and symmetric positive definite (cheb_plan). Degree 0: w = u (S~ = I)."""
+    rho' = 1/(2 sigma - rho), d = rho' rho d + (2 rho'/delta) r), started from omega u
+    (cheb_scale; omega = 1 unless the degree is too low for the interval). A fixed polynomial
+    in S~: linear in u and symmetric positive definite (cheb_plan, cheb_scale). Degree 0:
+    w = u (S~ = I)."""
     K, b = F.cheb_degree, F.cheb_b
     if K == 0:
         return u.copy()
@@ -534,7 +560,7 @@ def cheb_S(F, u):
     sigma = theta / half
     rho = 1.0 / sigma
     w = np.zeros_like(u)
-    r = u.copy()
+    r = F.cheb_omega * u
     d = r / theta
     for _ in range(K):
         w = w + d

@@ -63,7 +63,7 @@ struct BDesc {
     // corr = 0 none, 1 cheb_K Chebyshev steps on S~ (coefficients c1 then c2; K = 0: M_b = I)
     BOp Y, YT;
     const double *cheb;
-    double cheb_theta;
+    double cheb_theta, cheb_omega;
     int32_t corr, cheb_K, k, pad2;
     void *cg, *cy, *ct, *cu, *cr, *cd, *cw, *cq;  // n: g copy, y, Y~^T product; m - n: u, r, d, w, q
     double tol;
@@ -319,7 +319,7 @@ __device__ __forceinline__ void wg_trsv(const BTri &t, RP rhs, XP x)
 // Steps 2-4 of Algorithm 2 with the explicit Y~ (Section 3.2), from g = L1^{-T} U^{-T} z
 // (global, n values) to y = g - Y~^T v_b: w_b = Y~ g, v_b = M_b^{-1} w_b by cheb_K
 // Chebyshev steps on S~ = I + Y~ Y~^T (none: v_b = w_b; per step q = Y~ (Y~^T d), w += d,
-// r -= d + q, d = c1 d + c2 r, from r = w_b, d = w_b / theta, w = 0; v_b = w), then
+// r -= d + q, d = c1 d + c2 r, from r = omega w_b, d = r / theta, w = 0; v_b = w), then
 // y = g - Y~^T v_b. The (m - n)-vectors are in the device order of Y~'s rows. The caller
 // separates g's producers and y's readers from it with barriers.
 template <class T, int NT, int G>
@@ -336,11 +336,11 @@ __device__ __forceinline__ void wg_correction(const BDesc &d, const T *gp, T *yp
         const auto uu = gm(u);
         const auto r = gm(static_cast<T *>(d.cr)), dd = gm(static_cast<T *>(d.cd)), w = gm(static_cast<T *>(d.cw));
         const auto q = gm(static_cast<const T *>(d.cq));
-        const T theta = (T)d.cheb_theta;
+        const T theta = (T)d.cheb_theta, omega = (T)d.cheb_omega;
         for (int i = threadIdx.x; i < k; i += NT) {
-            const T ui = uu[i];
-            r[i] = ui;
-            dd[i] = ui / theta;
+            const T ri = omega * uu[i];
+            r[i] = ri;
+            dd[i] = ri / theta;
             w[i] = (T)0;
         }
         const auto cf = gm(d.cheb);
@@ -702,14 +702,20 @@ BTri btri(const Ctx &c, const DevTriOff &o)
                 at<void>(c, o.lo.val), o.ldiag ? at<void>(c, o.ldiag) : nullptr, at<void>(c, o.lrec), o.nlev, 0};
 }
 
-// Whether a handle can be solved by the batched kernel.
-rsilu_status_t check_handle(const Ctx &c)
+// Whether the batched kernel takes a handle's configuration.
+rsilu_status_t check_config(const Ctx &c)
 {
-    if (!c.dev) return RSILU_EINVAL;
     if (c.prm.krylov != RSILU_KRYLOV_LSQR || c.prm.form != RSILU_FORM_ALG2) return RSILU_EINVAL;
     if (correction_of(c) < 0) return RSILU_EINVAL;
     if (c.R.nrows > 0) return RSILU_EINVAL;  // removed rows change the preconditioner
     return RSILU_OK;
+}
+
+// Whether a handle can be solved by the batched kernel.
+rsilu_status_t check_handle(const Ctx &c)
+{
+    if (!c.dev) return RSILU_EINVAL;
+    return check_config(c);
 }
 
 BDesc make_desc(const Ctx &c, const double *b, double *x, double tol, int32_t maxit, BOut *out)
@@ -754,6 +760,7 @@ BDesc make_desc(const Ctx &c, const double *b, double *x, double tol, int32_t ma
         d.cu = at<void>(c, L.u);
         d.cheb = at<double>(c, L.cheb);
         d.cheb_theta = c.cheb_theta;
+        d.cheb_omega = c.cheb_omega;
         d.cheb_K = c.cheb_K;
         d.cr = at<void>(c, L.cg_r);
         d.cd = at<void>(c, L.cg_p);
@@ -966,6 +973,8 @@ double elapsed_ms(std::chrono::steady_clock::time_point a)
 }  // namespace rsilu
 
 extern "C" {
+
+int32_t rsilu_batch_accepts(rsilu_handle_t h) { return h && check_config(*h) == RSILU_OK ? 1 : 0; }
 
 int32_t rsilu_batch_tiles(rsilu_tile_t *out, int32_t max)
 {

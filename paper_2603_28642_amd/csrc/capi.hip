@@ -298,10 +298,11 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
             launch_spmv<double>(s, W.L2, P.pL2, W.s2, q, p, EPI_ADD, FIN_NONE, P.partials, W.segpart, P.st, done);
         }
         launch_dot(s, k, p, q, FIN_CG_ALPHA, P.partials, P.st, done);
-        launch_cg_update(s, k, p, q, w, res, P.st, done);
         if (i + 1 < c.prm.cg_steps) {
-            launch_dot(s, k, res, res, FIN_CG_BETA, P.partials, P.st, done);
+            launch_cg_update_dot(s, k, p, q, w, res, P.partials, P.st, done);  // and beta from res . res
             launch_cg_dir(s, k, res, p, P.st, done);
+        } else {
+            launch_cg_update(s, k, p, q, w, res, P.st, done);
         }
     }
     launch_copy(s, k, w, W.u, done);
@@ -321,7 +322,7 @@ void cheb_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<T> &W, const i
     if (c.cheb_K == 0 || k == 0) return;  // S~ = I: w = u
     T *w = at<T>(c, c.lay.cg_w), *r = at<T>(c, c.lay.cg_r), *d = at<T>(c, c.lay.cg_p), *q = at<T>(c, c.lay.cg_q);
     ProfScope ps(c, s, RSILU_PROF_DENSE_S);
-    launch_cheb_init<T>(s, k, W.u, r, d, w, c.cheb_theta, done);
+    launch_cheb_init<T>(s, k, W.u, r, d, w, c.cheb_theta, c.cheb_omega, done);
     for (int32_t j = 0; j < c.cheb_K; ++j) {
         if (yexplicit(c)) {
             spmv_y<T>(c, s, P, W, true, d, W.g, nullptr, EPI_PLAIN, done);
@@ -721,6 +722,7 @@ rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *s)
     s->nnz_y = yexplicit(*h) ? h->Y.nnz() : 0;
     s->cheb_b = h->cheb_b;
     s->cheb_degree = h->cheb_K;
+    s->cheb_scale = h->cheb_omega;
     return RSILU_OK;
 }
 

@@ -154,8 +154,8 @@ struct Ctx {
     std::vector<int32_t> yperm, yperm_inv;  // device row i of Y~ is row yperm[i]
     SpmvPlan plY, plYT;            // plans of Yd and YdT
     // Chebyshev M_b (RSILU_S_CHEB): interval [1, cheb_b], cheb_K steps with coefficients
-    // d <- c1[j] d + c2[j] r, starting from d = u / theta
-    double cheb_b = 1.0, cheb_theta = 1.0;
+    // d <- c1[j] d + c2[j] r, starting from r = omega u, d = r / theta
+    double cheb_b = 1.0, cheb_theta = 1.0, cheb_omega = 1.0;
     int32_t cheb_K = 0;
     std::vector<double> cheb_c1, cheb_c2;
     // Section 3.4, removed rows: R = the removed rows of A_hat that were in A1, and the packed

@@ -424,9 +424,35 @@ __global__ __launch_bounds__(kBlock) void k_finish(DPlan pl, int32_t nparts, T *
     if (threadIdx.x == 0) apply_fin(fin, total, st);
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double *__restrict__ a,
-                                                 const double *__restrict__ b, double *__restrict__ partials,
-                                                 const int32_t *done)
+// One-launch reductions: every block stores its partial (thread 0, already done when
+// this is called) and counts itself on st->red_ticket; the block that counts last
+// sees every partial (release by the others' fence before their count, acquire by its
+// own fence after it), adds them in index order (the same order for any timing) and
+// takes the scalar step, then clears the counter for the next launch.
+__device__ __forceinline__ void finish_if_last(int32_t nparts, const double *partials, Fin fin, DevState *st,
+                                               double *lds4)
+{
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&st->red_ticket, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kBlock) s += partials[k];
+    const double total = block_sum256(s, lds4);
+    if (threadIdx.x == 0) {
+        apply_fin(fin, total, st);
+        st->red_ticket = 0u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_fin(int32_t n, const double *__restrict__ a,
+                                                     const double *__restrict__ b, double *partials, Fin fin,
+                                                     DevState *st, const int32_t *done)
 {
     __shared__ double lds4[4];
     if (stop_now(done)) return;
@@ -434,17 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double *__restr
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) s += a[i] * b[i];
     const double t = block_sum256(s, lds4);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(kBlock) void k_reduce_fin(int32_t nparts, const double *__restrict__ partials,
-                                                        Fin fin, DevState *st, const int32_t *done)
-{
-    __shared__ double lds4[4];
-    if (stop_now(done)) return;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) s += partials[k];
-    const double total = block_sum256(s, lds4);
-    if (threadIdx.x == 0) apply_fin(fin, total, st);
+    finish_if_last((int32_t)gridDim.x, partials, fin, st, lds4);
 }
 
 // ------------------------------------------------------------------ vectors
@@ -548,8 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_add(int32_t n, const double *__restr
 }
 
 __global__ __launch_bounds__(kBlock) void k_lsqr_t(int32_t m, const double *__restrict__ u, double *__restrict__ t,
-                                                   double *__restrict__ partials, const DevState *st,
-                                                   const int32_t *done)
+                                                   double *partials, Fin fin, DevState *st, const int32_t *done)
 {
     __shared__ double lds4[4];
     if (stop_now(done)) return;
@@ -562,6 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_lsqr_t(int32_t m, const double *__re
     }
     const double tot = block_sum256(sq, lds4);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    finish_if_last((int32_t)gridDim.x, partials, fin, st, lds4);
 }
 
 __global__ __launch_bounds__(kBlock) void k_lsqr_scale(int32_t m, const double *__restrict__ in,
@@ -574,8 +590,8 @@ __global__ __launch_bounds__(kBlock) void k_lsqr_scale(int32_t m, const double *
 }
 
 __global__ __launch_bounds__(kBlock) void k_lsqr_s(int32_t n, double *__restrict__ sv, const double *__restrict__ Mv,
-                                                   const double *__restrict__ colnorm, double *__restrict__ partials,
-                                                   const DevState *st, const int32_t *done)
+                                                   const double *__restrict__ colnorm, double *partials, Fin fin,
+                                                   DevState *st, const int32_t *done)
 {
     __shared__ double lds4[4];
     if (stop_now(done)) return;
@@ -589,6 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_lsqr_s(int32_t n, double *__restrict
     }
     const double tot = block_sum256(sq, lds4);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    finish_if_last((int32_t)gridDim.x, partials, fin, st, lds4);
 }
 
 __global__ __launch_bounds__(kBlock) void k_lsqr_v(int32_t n, const double *__restrict__ h, const double *__restrict__ sv,
@@ -650,6 +667,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int32_t k, const double *_
     }
 }
 
+// w += alpha p, res -= alpha q, then res . res and the step FIN_CG_BETA (one launch)
+__global__ __launch_bounds__(kBlock) void k_cg_update_dot(int32_t k, const double *__restrict__ p,
+                                                          const double *__restrict__ q, double *__restrict__ w,
+                                                          double *__restrict__ res, double *partials, DevState *st,
+                                                          const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    const double a = st->cg_alpha;
+    double s = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        w[i] = w[i] + a * p[i];
+        const double r = res[i] - a * q[i];
+        res[i] = r;
+        s += r * r;
+    }
+    const double t = block_sum256(s, lds4);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    finish_if_last((int32_t)gridDim.x, partials, FIN_CG_BETA, st, lds4);
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_dir(int32_t k, const double *__restrict__ res, double *__restrict__ p,
                                                    const DevState *st, const int32_t *done)
 {
@@ -658,19 +696,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(int32_t k, const double *__re
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) p[i] = res[i] + bt * p[i];
 }
 
-// Chebyshev steps on S~ w = u (RSILU_S_CHEB): the set-up r = u, d = u / theta, w = 0,
-// and one step's update once q = Y~ (Y~^T d) is formed: w += d, r -= d + q,
-// d = c1 d + c2 r; the last step also writes w to out.
+// Chebyshev steps on S~ w = u (RSILU_S_CHEB): the set-up r = omega u, d = r / theta, w = 0
+// (omega = 1 unless the degree is too low for the interval), and one step's update once
+// q = Y~ (Y~^T d) is formed: w += d, r -= d + q, d = c1 d + c2 r; the last step also
+// writes w to out.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_cheb_init(int32_t k, const T *__restrict__ u, T *__restrict__ r,
-                                                      T *__restrict__ d, T *__restrict__ w, T theta,
+                                                      T *__restrict__ d, T *__restrict__ w, T theta, T omega,
                                                       const int32_t *done)
 {
     if (stop_now(done)) return;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
-        const T ui = u[i];
-        r[i] = ui;
-        d[i] = ui / theta;
+        const T ri = omega * u[i];
+        r[i] = ri;
+        d[i] = ri / theta;
         w[i] = (T)0;
     }
 }
@@ -1418,8 +1457,14 @@ void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin 
                 DevState *st, const int32_t *done)
 {
     const int g = grid_for(n, 2048);
-    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, n, a, b, partials, done);
-    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+    hipLaunchKernelGGL(k_dot_fin, dim3(g), dim3(kBlock), 0, s, n, a, b, partials, fin, st, done);
+}
+
+void launch_cg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
+                          double *partials, DevState *st, const int32_t *done)
+{
+    const int g = grid_for(k, 2048);
+    hipLaunchKernelGGL(k_cg_update_dot, dim3(g), dim3(kBlock), 0, s, k, p, q, w, res, partials, st, done);
 }
 
 void launch_update(hipStream_t s, int32_t n, int32_t m, const double *p, double *xh, const double *q, double *r,
@@ -1564,8 +1609,7 @@ void launch_lsqr_t(hipStream_t s, int32_t m, const double *u, double *t, Fin fin
                    const int32_t *done)
 {
     const int g = grid_for(m, 2048);
-    hipLaunchKernelGGL(k_lsqr_t, dim3(g), dim3(kBlock), 0, s, m, u, t, partials, st, done);
-    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+    hipLaunchKernelGGL(k_lsqr_t, dim3(g), dim3(kBlock), 0, s, m, u, t, partials, fin, st, done);
 }
 
 void launch_lsqr_scale(hipStream_t s, int32_t m, const double *in, double *out, const DevState *st,
@@ -1578,8 +1622,7 @@ void launch_lsqr_s(hipStream_t s, int32_t n, double *sv, const double *Mv, const
                    double *partials, DevState *st, const int32_t *done)
 {
     const int g = grid_for(n, 2048);
-    hipLaunchKernelGGL(k_lsqr_s, dim3(g), dim3(kBlock), 0, s, n, sv, Mv, colnorm, partials, st, done);
-    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+    hipLaunchKernelGGL(k_lsqr_s, dim3(g), dim3(kBlock), 0, s, n, sv, Mv, colnorm, partials, fin, st, done);
 }
 
 void launch_lsqr_v(hipStream_t s, int32_t n, const double *h, const double *sv, double *xh, double *v, double *Mv,
@@ -1611,13 +1654,15 @@ void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const
 }
 
 template <class T>
-void launch_cheb_init(hipStream_t s, int32_t k, const T *u, T *r, T *d, T *w, double theta, const int32_t *done)
+void launch_cheb_init(hipStream_t s, int32_t k, const T *u, T *r, T *d, T *w, double theta, double omega,
+                      const int32_t *done)
 {
-    hipLaunchKernelGGL(k_cheb_init<T>, dim3(grid_for(k)), dim3(kBlock), 0, s, k, u, r, d, w, (T)theta, done);
+    hipLaunchKernelGGL(k_cheb_init<T>, dim3(grid_for(k)), dim3(kBlock), 0, s, k, u, r, d, w, (T)theta, (T)omega,
+                       done);
 }
 template void launch_cheb_init<double>(hipStream_t, int32_t, const double *, double *, double *, double *, double,
-                                       const int32_t *);
-template void launch_cheb_init<float>(hipStream_t, int32_t, const float *, float *, float *, float *, double,
+                                       double, const int32_t *);
+template void launch_cheb_init<float>(hipStream_t, int32_t, const float *, float *, float *, float *, double, double,
                                       const int32_t *);
 
 template <class T>

@@ -97,6 +97,7 @@ struct rsilu_server {
     std::deque<Job *> setup_q, ready_q;
     std::deque<rsilu_result_t> results;
     int64_t next_id = 0, completed = 0;
+    int64_t in_setup = 0;  // requests taken by a setup thread and not yet ready or finished
     bool stopping = false;
     std::vector<std::thread> threads;
 
@@ -142,6 +143,7 @@ struct rsilu_server {
                 if (setup_q.empty()) return;
                 j = setup_q.front();
                 setup_q.pop_front();
+                ++in_setup;
             }
             const Clock::time_point t0 = Clock::now();
             rsilu_status_t st = rsilu_factor(j->req.m, j->req.n, j->rowptr.data(), j->col.data(), j->val.data(),
@@ -149,6 +151,11 @@ struct rsilu_server {
             j->t_setup_done = Clock::now();
             j->res.setup_ms = ms_between(t0, j->t_setup_done);
             if (st != RSILU_OK) {
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    --in_setup;
+                }
+                cv_ready.notify_all();
                 finish(j, st);
                 continue;
             }
@@ -157,25 +164,25 @@ struct rsilu_server {
                        round_up(sizeof(double) * (size_t)j->req.n);
             j->res.device_bytes = j->bytes;
             if (j->bytes > opts.hbm_bytes) {
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    --in_setup;
+                }
+                cv_ready.notify_all();
                 finish(j, RSILU_ENOMEM);
                 continue;
             }
             {
                 std::lock_guard<std::mutex> lk(mu);
+                --in_setup;
                 ready_q.push_back(j);
             }
             cv_ready.notify_all();
         }
     }
 
-    // Whether the batched kernel accepts a request (LSQR, Algorithm 2 form, S^ none).
-    static bool batchable(const Job &j)
-    {
-        if (j.req.params.krylov != RSILU_KRYLOV_LSQR || j.req.params.form != RSILU_FORM_ALG2) return false;
-        if (j.req.m == j.req.n) return true;
-        rsilu_stats_t st;
-        return rsilu_get_stats(j.h, &st) == RSILU_OK && st.smode == RSILU_S_NONE;
-    }
+    // Whether the batched kernel accepts a request.
+    static bool batchable(const Job &j) { return rsilu_batch_accepts(j.h) == 1; }
 
     void slot_worker(int slot)
     {
@@ -198,6 +205,14 @@ struct rsilu_server {
                 if (ready_q.empty()) return;
                 jobs.push_back(ready_q.front());
                 ready_q.pop_front();
+                // batching window: wait a little for requests still in setup
+                if (cap >= 2 && opts.batch_wait_ms > 0.0) {
+                    const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                                          std::chrono::duration<double, std::milli>(opts.batch_wait_ms));
+                    cv_ready.wait_until(lk, until, [&] {
+                        return stopping || ready_q.size() + 1 >= cap || (in_setup == 0 && setup_q.empty());
+                    });
+                }
                 while (jobs.size() < cap && !ready_q.empty()) {
                     Job *nx = ready_q.front();
                     const size_t off = arena->take(nx->bytes);
@@ -335,7 +350,8 @@ extern "C" {
 rsilu_status_t rsilu_server_create(const rsilu_server_opts_t *opts, rsilu_server_t *out)
 {
     if (!opts || !out || opts->slots < 1 || opts->setup_threads < 1 || opts->hbm_bytes < kAlign ||
-        opts->batch_max < 0 || opts->batch_max > 65535 || !std::isfinite(opts->tune_slack) || opts->tune_slack < 0.0)
+        opts->batch_max < 0 || opts->batch_max > 65535 || !std::isfinite(opts->tune_slack) || opts->tune_slack < 0.0 ||
+        !std::isfinite(opts->batch_wait_ms) || opts->batch_wait_ms < 0.0)
         return RSILU_EINVAL;
     *out = nullptr;
     rsilu_server *s = nullptr;

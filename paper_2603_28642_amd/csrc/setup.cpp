@@ -700,6 +700,7 @@ void build_chebyshev(Ctx &c)
     c.cheb_c2.clear();
     c.cheb_b = 1.0;
     c.cheb_K = 0;
+    c.cheb_omega = 1.0;
     if (k == 0) return;
     // S~ d = d + Y~ (Y~^T d): explicit, or L2 L1^{-1} L1^{-T} L2^T d
     std::vector<double> g((size_t)n), t((size_t)n), q((size_t)k);
@@ -754,6 +755,10 @@ void build_chebyshev(Ctx &c)
     }
     c.cheb_b = b;
     c.cheb_K = K;
+    // a degree that misses the bound (b - 1) eps_K <= poly_delta: the input scaled by
+    // 1 / (1 + eps_K) keeps M_b^{-1} positive definite
+    const double epsK = 1.0 / std::cosh(K * std::acosh(sigma));
+    c.cheb_omega = (b - 1.0) * epsK <= c.prm.poly_delta ? 1.0 : 1.0 / (1.0 + epsK);
     const double theta = (b + 1.0) / 2.0, half = (b - 1.0) / 2.0;
     const double sig = theta / half;
     double rho = 1.0 / sig;

@@ -37,7 +37,7 @@ EXPORTS = [
     "rsilu_get_profile",
     "rsilu_destroy", "rsilu_status_string",
     "rsilu_server_create", "rsilu_server_submit", "rsilu_server_poll", "rsilu_server_drain", "rsilu_server_destroy",
-    "rsilu_batch_tiles", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_solve_auto", "rsilu_batch_destroy",
+    "rsilu_batch_tiles", "rsilu_batch_accepts", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_solve_auto", "rsilu_batch_destroy",
     "rsilu_tuner_create",
     "rsilu_tune", "rsilu_tuner_size", "rsilu_tuner_destroy", "rsilu_batch_solve_static", "rsilu_batch_static_max",
 ]
@@ -64,7 +64,7 @@ class rsilu_stats_t(ctypes.Structure):
                 ("levels_l1t", ctypes.c_int32), ("levels_u", ctypes.c_int32), ("levels_ut", ctypes.c_int32),
                 ("smode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
                 ("nnz_y", ctypes.c_int64), ("cheb_b", ctypes.c_double), ("cheb_degree", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("reserved2", ctypes.c_int32), ("cheb_scale", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("reserved")}
@@ -84,7 +84,8 @@ class rsilu_tile_t(ctypes.Structure):
 
 class rsilu_server_opts_t(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("setup_threads", ctypes.c_int32),
-                ("batch_max", ctypes.c_int32), ("hbm_bytes", ctypes.c_size_t), ("tune_slack", ctypes.c_double)]
+                ("batch_max", ctypes.c_int32), ("hbm_bytes", ctypes.c_size_t), ("tune_slack", ctypes.c_double),
+                ("batch_wait_ms", ctypes.c_double)]
 
 
 class rsilu_request_t(ctypes.Structure):
@@ -184,6 +185,8 @@ def lib():
         L.rsilu_server_destroy.restype = None
         L.rsilu_batch_tiles.argtypes = [ctypes.POINTER(rsilu_tile_t), I32]
         L.rsilu_batch_tiles.restype = I32
+        L.rsilu_batch_accepts.argtypes = [P]
+        L.rsilu_batch_accepts.restype = I32
         L.rsilu_batch_create.argtypes = [I32, ctypes.POINTER(P)]
         L.rsilu_batch_create.restype = ctypes.c_int
         L.rsilu_batch_solve.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(rsilu_tile_t),
@@ -456,9 +459,10 @@ class Server:
     Host inputs are copied at submit; each request's x buffer is kept alive here until
     its result has been polled."""
 
-    def __init__(self, hbm_bytes, slots=4, setup_threads=4, device=0, batch_max=0, tune_slack=0.0):
+    def __init__(self, hbm_bytes, slots=4, setup_threads=4, device=0, batch_max=0, tune_slack=0.0, batch_wait_ms=0.0):
         opts = rsilu_server_opts_t(device=device, slots=slots, setup_threads=setup_threads, batch_max=int(batch_max),
-                                   hbm_bytes=int(hbm_bytes), tune_slack=float(tune_slack))
+                                   hbm_bytes=int(hbm_bytes), tune_slack=float(tune_slack),
+                                   batch_wait_ms=float(batch_wait_ms))
         h = ctypes.c_void_p()
         _check(lib().rsilu_server_create(ctypes.byref(opts), ctypes.byref(h)), "rsilu_server_create")
         self.h = h
@@ -506,6 +510,11 @@ class Server:
 
 
 # ---------------------------------------------------------------- batched persistent solves
+
+
+def rsilu_batch_accepts(h):
+    """Whether the batched kernel takes the handle's configuration."""
+    return bool(lib().rsilu_batch_accepts(h))
 
 
 def rsilu_batch_tiles():

@@ -1,15 +1,25 @@
 """Served stream of uneven least-squares requests on one GPU, against the plain path.
 
-Requests (sizes from gen.served_stream: n log-uniform, m = n U(1.1, 2.0), a tenth
-with dense rows) arrive as a Poisson process and go through the serving runtime
-(include/rsilu_serve.h): host setup threads, admission by device footprint into one
-HBM arena, concurrent solves on per-slot streams. The plain path handles the same
-requests one at a time (setup, upload, solve). Prints one JSON line with solves/s and
-p50/p99 latency of both, how many served results equal the plain ones bit for bit, and
-the largest ||A^T A (x_served - x_plain)|| / ||A^T b|| (batched launches sum in another
-order than the plain path).
+Requests (sizes from gen.served_stream: n log-uniform, m = n U(1.1, 2.0), a tenth with
+8-32 dense rows) arrive as a Poisson process and go through the serving runtime
+(include/rsilu_serve.h): host setup threads, admission by device footprint into one HBM
+arena, concurrent solves on per-slot streams, requests admitted together sharing batched
+persistent launches. Every request is LSQR with Algorithm 2 and the M_b correction by a
+degree-2 Chebyshev polynomial in S~ through the explicit Y~ (the fixed two-step analogue of
+Table 3(a)'s CG(2); its input is scaled where two steps cannot cover S~'s interval, the
+requests with dense rows), FP32 preconditioner and FP64 Krylov part by default.
 
-Usage: python -m paper_2603_28642_amd.serve_bench [--requests 128] [--slots 8] ...
+The plain path is the same method with the FP64 preconditioner, one request at a time
+(setup, upload, rsilu_solve, copy back), run on every `--plain-every`-th request of the
+stream (the host setup of the whole stream takes over an hour on one core): its latency
+per request is that request's service time with no queueing, and its solves/s is one over
+the mean service time.
+
+Prints one JSON line with solves/s and p50/p99 latency of both, the served device times,
+how many requests took batched launches, and for the requests of the plain sample the
+largest ||A^T A (x_served - x_plain)|| / ||A^T b||.
+
+Usage: python -m paper_2603_28642_amd.serve_bench [--requests 512] [--mode served|plain|both] ...
 """
 
 import argparse
@@ -24,19 +34,24 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=128)
+    ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--n-lo", type=int, default=2000)
-    ap.add_argument("--n-hi", type=int, default=100000)
-    ap.add_argument("--slots", type=int, default=8)
-    ap.add_argument("--setup-threads", type=int, default=12)
-    ap.add_argument("--hbm-gb", type=float, default=32.0)
-    ap.add_argument("--load", type=float, default=0.8, help="offered load as a fraction of the served capacity "
-                                                           "estimated from the plain path and the thread count")
+    ap.add_argument("--n-hi", type=int, default=200000)
+    ap.add_argument("--mode", default="both", choices=["served", "plain", "both"])
+    ap.add_argument("--plain-every", type=int, default=16, help="plain path on every k-th request")
+    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--setup-threads", type=int, default=16)
+    ap.add_argument("--hbm-gb", type=float, default=64.0)
+    ap.add_argument("--rate", type=float, default=1.5, help="Poisson arrival rate, requests/s")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--correction", default="cheb2", choices=["cheb2", "none"],
+                    help="M_b: degree-2 Chebyshev through the explicit Y~, or none (A1 only)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--batch-max", type=int, default=32, help="requests per batched launch (0: rsilu_solve each)")
     ap.add_argument("--tune-slack", type=float, default=8.0, help="autotuner slack (0: default tile, no tuning)")
+    ap.add_argument("--batch-wait-ms", type=float, default=100.0,
+                    help="batching window: a slot that admitted a request waits this long for more to finish setup")
     args = ap.parse_args()
     # one hardware queue per solve slot (the runtime's default is 4)
     os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(max(args.slots, 4), 32)))
@@ -47,87 +62,101 @@ def main():
     import gen
     from paper_2603_28642_amd import rsilu as R
 
+    method = dict(mu=1.0, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR)
+    if args.correction == "cheb2":
+        method.update(smode=R.S_CHEB, ystore=R.Y_EXPLICIT, ytau=1e-2, poly_degree=2)
+    else:
+        method.update(smode=R.S_NONE)
     prec = {"fp32": R.PREC_FP32, "fp64": R.PREC_FP64}[args.precision]
-    params = dict(mu=1.0, form=R.FORM_ALG2, smode=R.S_NONE, krylov=R.KRYLOV_LSQR, precision=prec)
     sizes = gen.served_stream(args.requests, seed=args.seed, n_lo=args.n_lo, n_hi=args.n_hi)
-    probs = [gen.served_request(n, m, s, n_dense=nd) for n, m, s, nd in sizes]
-    print("generated %d requests" % len(probs), file=sys.stderr, flush=True)
-
-    # ---- plain path: one request at a time
-    plain_x, plain_lat, plain_setup = [], [], []
-    t0 = time.perf_counter()
-    for p in probs:
-        t1 = time.perf_counter()
-        S = R.Solver.from_problem(p, **params)
-        t2 = time.perf_counter()
-        S.upload()
-        x, code, it, atr, rel = S.solve(torch.from_numpy(p.b).cuda(), tol=args.tol)
-        plain_x.append(x.cpu().numpy())
-        S.close()
-        plain_lat.append(time.perf_counter() - t1)
-        plain_setup.append(t2 - t1)
-    plain_total = time.perf_counter() - t0
-    print("plain path done in %.1f s" % plain_total, file=sys.stderr, flush=True)
-
-    # ---- served: Poisson arrivals at the offered load
-    capacity = len(probs) / max(plain_total, 1e-9) * min(args.setup_threads, args.slots)
-    rate = args.load * capacity
-    rng = np.random.default_rng(args.seed + 1)
-    gaps = rng.exponential(1.0 / rate, size=len(probs))
-    srv = R.Server(hbm_bytes=int(args.hbm_gb * (1 << 30)), slots=args.slots, setup_threads=args.setup_threads,
-                   batch_max=args.batch_max, tune_slack=args.tune_slack)
-    results = {}
-    ids = {}
-    t_start = time.perf_counter()
-    t_next = t_start
-    for i, p in enumerate(probs):
-        t_next += gaps[i]
-        while True:
-            for res, x in srv.poll(wait_ms=0):
-                results[ids[res["id"]]] = (res, x, time.perf_counter())
-            now = time.perf_counter()
-            if now >= t_next:
-                break
-            time.sleep(min(t_next - now, 0.002))
-        ids[srv.submit(p.m, p.n, p.rowptr, p.col, p.val, p.b, tol=args.tol, **params)] = i
-    while len(results) < len(probs):
-        for res, x in srv.poll(wait_ms=100):
-            results[ids[res["id"]]] = (res, x, time.perf_counter())
-    served_total = max(r[2] for r in results.values()) - t_start
-    srv.close()
-
-    lat = np.array([results[i][0]["total_ms"] for i in range(len(probs))])
-    ok = sum(1 for i in range(len(probs)) if results[i][0]["status"] == R.OK)
-    same = sum(1 for i in range(len(probs)) if np.array_equal(results[i][1].view(np.int64), plain_x[i].view(np.int64)))
-    # batched results differ from the plain ones in the order of sums only: both in the stop-test ball
-    ball = max(float(np.linalg.norm(probs[i].scipy().T @ (probs[i].scipy() @ (results[i][1] - plain_x[i]))) /
-                     np.linalg.norm(probs[i].scipy().T @ probs[i].b)) for i in range(len(probs)))
-    solve_ms = np.array([results[i][0]["solve_ms"] for i in range(len(probs))])
-    setup_ms = np.array([results[i][0]["setup_ms"] for i in range(len(probs))])
-    wait_ms = np.array([results[i][0]["wait_ms"] for i in range(len(probs))])
     out = {
         "metric": "served mixed-size least-squares solves/s; p50/p99 latency (submit to x on the host)",
-        "requests": len(probs),
-        "n_range": [args.n_lo, args.n_hi],
-        "precision": args.precision,
-        "slots": args.slots,
-        "batch_max": args.batch_max,
-        "tune_slack": args.tune_slack,
-        "paths": {"batched": sum(1 for i in range(len(probs)) if results[i][0]["path"] == 0),
-                  "plain": sum(1 for i in range(len(probs)) if results[i][0]["path"] == 1)},
-        "median_launch_size": float(np.median([results[i][0]["launch_size"] for i in range(len(probs))])),
-        "setup_threads": args.setup_threads,
-        "offered_rate_per_s": rate,
-        "served": {"solves_per_s": len(probs) / served_total, "p50_ms": float(np.percentile(lat, 50)),
-                   "p99_ms": float(np.percentile(lat, 99)), "ok": ok,
-                   "median_setup_ms": float(np.median(setup_ms)), "median_wait_ms": float(np.median(wait_ms)),
-                   "median_solve_ms": float(np.median(solve_ms)), "p99_solve_ms": float(np.percentile(solve_ms, 99))},
-        "plain": {"solves_per_s": len(probs) / plain_total, "p50_ms": 1e3 * float(np.percentile(plain_lat, 50)),
-                  "p99_ms": 1e3 * float(np.percentile(plain_lat, 99)),
-                  "median_setup_ms": 1e3 * float(np.median(plain_setup))},
-        "identical_to_plain": same,
-        "max_ball_vs_plain": ball,
+        "requests": len(sizes), "n_range": [args.n_lo, args.n_hi], "method": "LSQR, Algorithm 2, M_b " +
+        ("Chebyshev degree 2 on S~ (explicit Y~)" if args.correction == "cheb2" else "none"),
     }
+    plain_idx = list(range(0, len(sizes), args.plain_every))
+    plain_x = {}
+    if args.mode in ("plain", "both"):
+        lat, setup, solve = [], [], []
+        for i in plain_idx:
+            n, m, s, nd = sizes[i]
+            p = gen.served_request(n, m, s, n_dense=nd)
+            t1 = time.perf_counter()
+            S = R.Solver.from_problem(p, precision=R.PREC_FP64, maxit=2000, **method)
+            t2 = time.perf_counter()
+            S.upload()
+            x, code, it, atr, rel = S.solve(torch.from_numpy(p.b).cuda(), tol=args.tol)
+            plain_x[i] = x.cpu().numpy()
+            t3 = time.perf_counter()
+            S.close()
+            lat.append(t3 - t1)
+            setup.append(t2 - t1)
+            solve.append(t3 - t2)
+            print("plain %d: n %d m %d dense %d: setup %.2f s, device %.1f ms, %d its" % (
+                i, n, m, nd, t2 - t1, 1e3 * (t3 - t2), it), file=sys.stderr, flush=True)
+        lat = np.array(lat)
+        out["plain"] = {"precision": "fp64", "sample": "every %d-th request (%d)" % (args.plain_every, len(plain_idx)),
+                        "solves_per_s": 1.0 / float(lat.mean()), "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                        "p99_ms": 1e3 * float(np.percentile(lat, 99)), "median_setup_ms": 1e3 * float(np.median(setup)),
+                        "median_device_ms": 1e3 * float(np.median(solve)),
+                        "p99_device_ms": 1e3 * float(np.percentile(solve, 99))}
+    if args.mode in ("served", "both"):
+        probs = []
+        for n, m, s, nd in sizes:
+            probs.append(gen.served_request(n, m, s, n_dense=nd))
+        print("generated %d requests" % len(probs), file=sys.stderr, flush=True)
+        rng = np.random.default_rng(args.seed + 1)
+        gaps = rng.exponential(1.0 / args.rate, size=len(probs))
+        srv = R.Server(hbm_bytes=int(args.hbm_gb * (1 << 30)), slots=args.slots, setup_threads=args.setup_threads,
+                       batch_max=args.batch_max, tune_slack=args.tune_slack, batch_wait_ms=args.batch_wait_ms)
+        results, ids = {}, {}
+        t_start = time.perf_counter()
+        t_next = t_start
+        last_report = t_start
+        for i, p in enumerate(probs):
+            t_next += gaps[i]
+            while True:
+                for res, x in srv.poll(wait_ms=0):
+                    results[ids[res["id"]]] = (res, x, time.perf_counter())
+                now = time.perf_counter()
+                if now >= t_next:
+                    break
+                time.sleep(min(t_next - now, 0.002))
+            ids[srv.submit(p.m, p.n, p.rowptr, p.col, p.val, p.b, tol=args.tol, precision=prec, maxit=2000,
+                           **method)] = i
+            if time.perf_counter() - last_report > 30:
+                last_report = time.perf_counter()
+                print("submitted %d, done %d" % (i + 1, len(results)), file=sys.stderr, flush=True)
+        while len(results) < len(probs):
+            for res, x in srv.poll(wait_ms=100):
+                results[ids[res["id"]]] = (res, x, time.perf_counter())
+            if time.perf_counter() - last_report > 30:
+                last_report = time.perf_counter()
+                print("done %d of %d" % (len(results), len(probs)), file=sys.stderr, flush=True)
+        served_total = max(r[2] for r in results.values()) - t_start
+        srv.close()
+        res = [results[i][0] for i in range(len(probs))]
+        lat = np.array([r["total_ms"] for r in res])
+        solve_ms = np.array([r["solve_ms"] for r in res])
+        batched = [r for r in res if r["path"] == 0]
+        ball = None
+        if plain_x:
+            ball = max(float(np.linalg.norm(probs[i].scipy().T @ (probs[i].scipy() @ (results[i][1] - plain_x[i]))) /
+                             np.linalg.norm(probs[i].scipy().T @ probs[i].b)) for i in plain_x)
+        out["served"] = {
+            "precision": args.precision, "slots": args.slots, "setup_threads": args.setup_threads,
+            "batch_max": args.batch_max, "tune_slack": args.tune_slack, "batch_wait_ms": args.batch_wait_ms,
+            "arrival_rate_per_s": args.rate,
+            "solves_per_s": len(probs) / served_total, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "ok": sum(1 for r in res if r["status"] == R.OK),
+            "median_setup_ms": float(np.median([r["setup_ms"] for r in res])),
+            "median_wait_ms": float(np.median([r["wait_ms"] for r in res])),
+            "median_device_ms": float(np.median(solve_ms)), "p99_device_ms": float(np.percentile(solve_ms, 99)),
+            "paths": {"batched": len(batched), "plain": len(res) - len(batched)},
+            "batched_launch_sizes": sorted({int(r["launch_size"]) for r in batched}),
+            "median_iters": float(np.median([r["iters"] for r in res])),
+            "max_ball_vs_plain_sample": ball,
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -426,3 +426,42 @@ def test_batch_correction_mixed_launch(gpu_lib):
         bt.close()
         for s_ in S:
             s_.close()
+
+
+def test_batch_scaled_low_degree(gpu_lib):
+    """Degree 2 Chebyshev with its input scale (dense-row requests, where degree 2 cannot
+    cover the interval) in the batched kernel: four steps against the oracle (x to 1e-8),
+    then whole solves in FP64 and FP32 like the oracle's."""
+    R = gpu_lib
+    probs = [gen.served_request(3000, 4500, 31, n_dense=12), gen.served_request(5000, 6000, 32),
+             gen.served_request(2500, 4000, 33, n_dense=20)]
+    Fs = [oracle.factor_problem(p, mu=1.0, smode="cheb", ystore=True, ytau=1e-2, poly_degree=2) for p in probs]
+    assert Fs[0].cheb_omega < 1 and Fs[2].cheb_omega < 1
+    bt = R.Batch(len(probs))
+    S = [R.Solver.from_problem(p, maxit=4, poly_degree=2, **CHEB).upload() for p in probs]
+    xs, res = bt.solve(S, [to_dev(p.b) for p in probs], 1e-14)
+    for i, (p, F, x, r) in enumerate(zip(probs, Fs, xs, res)):
+        o = oracle.lsqr_m(F, p.b, tol=1e-14, maxit=4)
+        assert r["iters"] == o.iters == 4, i
+        assert np.linalg.norm(x.cpu().numpy() - o.x) <= 1e-8 * np.linalg.norm(o.x), i
+    for s_ in S:
+        s_.close()
+    for prec in (0, 1):
+        S = [R.Solver.from_problem(p, maxit=2000, precision=prec, poly_degree=2, **CHEB).upload() for p in probs]
+        xs, res = bt.solve(S, [to_dev(p.b) for p in probs], 1e-8)
+        for i, (p, F, x, r) in enumerate(zip(probs, Fs, xs, res)):
+            o = oracle.lsqr_m(F, p.b, tol=1e-8, maxit=2000)
+            A = p.scipy()
+            atb = np.linalg.norm(A.T @ p.b)
+            got = x.cpu().numpy()
+            print("request %d precision %d: batched its %d, oracle its %d" % (i, prec, r["iters"], o.iters))
+            assert r["status"] == R.OK and o.status == "ok", (i, prec)
+            if prec == 0:
+                # request 0: the oracle itself stops after 33 or 35 iterations under a 1e-15
+                # relative perturbation of b (its stop estimate hovers at the tolerance)
+                assert abs(r["iters"] - o.iters) <= (2 if i == 0 else max(1, int(0.02 * o.iters))), i
+            assert np.linalg.norm(A.T @ (p.b - A @ got)) <= 2e-8 * atb, (i, prec)
+            assert np.linalg.norm(A.T @ (A @ (got - o.x))) <= 4e-8 * atb, (i, prec)
+        for s_ in S:
+            s_.close()
+    bt.close()

@@ -202,3 +202,38 @@ def test_graph_replays_equal_eager_chebyshev(gpu_lib):
         assert np.array_equal(to_host(x2), outs[-1][0]) and it2 == it
         S.close()
     assert all(np.array_equal(o[0], outs[0][0]) and o[1] == outs[0][1] for o in outs)
+
+
+@pytest.mark.parametrize("name", ["served-dense", "long-rows"])
+def test_scaled_low_degree(gpu_lib, name):
+    """Degree 2 on an interval it cannot cover (dense rows: b of 65 to 800), so the
+    iteration starts from omega u: the scale as the oracle's, one application element by
+    element, four LSQR steps (x to 1e-8), and on the served request a whole solve like the
+    oracle's (the unscaled polynomial breaks LSQR down there)."""
+    R = gpu_lib
+    prob = gen.served_request(3000, 4500, 31, n_dense=12) if name == "served-dense" else PROBLEMS[name]()
+    F = oracle.factor_problem(prob, mu=1.0, smode="cheb", ystore=True, ytau=1e-2, poly_degree=2)
+    S = solver(R, prob, poly_degree=2)
+    st = S.stats
+    assert st.cheb_degree == 2 and F.cheb_omega < 1 and abs(st.cheb_scale - F.cheb_omega) <= 1e-13
+    z = np.random.default_rng(43).standard_normal(prob.n)
+    h = empty(prob.n)
+    assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
+    ratio = elementwise(to_host(h), oracle.apply_alg2(F, z), 1e-9, 1e-12)
+    S.close()
+    x, code, it, atr, rel = run(R, prob, 1e-14, 4, R.KRYLOV_LSQR, poly_degree=2)
+    res = oracle.lsqr_m(F, prob.b, tol=1e-14, maxit=4)
+    err = np.linalg.norm(x - res.x) / np.linalg.norm(res.x)
+    print(f"{name} degree 2, omega {F.cheb_omega:.3f}: apply ratio {ratio:.2e}, 4 LSQR steps x rel diff {err:.2e}")
+    assert ratio <= 1.0
+    assert it == res.iters == 4 and err <= 1e-8
+    if name == "served-dense":
+        x, code, it, atr, rel = run(R, prob, 1e-8, 500, R.KRYLOV_LSQR, poly_degree=2)
+        res = oracle.lsqr_m(F, prob.b, tol=1e-8, maxit=500)
+        A = prob.scipy()
+        ball = np.linalg.norm(A.T @ (A @ (x - res.x))) / np.linalg.norm(A.T @ prob.b)
+        print(f"{name} degree 2: its {it} / {res.iters}, ball {ball:.1e}")
+        # the stop estimate hovers at the tolerance for the last iterations here: the oracle
+        # itself stops after 33 or 35 iterations when b is perturbed by 1e-15 relative
+        assert code == R.OK and res.status == "ok" and abs(it - res.iters) <= 2
+        assert rel <= 2e-8 and ball <= 4e-8

@@ -1,11 +1,14 @@
 """The serving runtime (include/rsilu_serve.h) on the GPU: every result equals the
 same request solved alone (by rsilu_solve on the plain path, by a lone batched launch
-with the same tile on the batched path), and admission by device footprint behaves."""
+with the same tile on the batched path), admission by device footprint behaves, and served
+requests with the M_b correction follow the oracle (four LSQR steps; converged solves in
+its stop-test ball)."""
 
 import numpy as np
 import pytest
 
 import gen
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -106,3 +109,71 @@ def test_batched_serving_equals_lone_solves(gpu_lib, precision, tune_slack):
         sizes.append(res["launch_size"])
     bt.close()
     print("launch sizes:", sizes)
+
+
+# LSQR with the degree-2 Chebyshev M_b through the explicit Y~ (input scaled where two steps
+# cannot cover S~'s interval: the requests with dense rows)
+CHEB2 = dict(mu=1.0, form=1, smode=4, krylov=1, ystore=1, ytau=1e-2, poly_degree=2)
+
+
+def serve(R, probs, tol, precision, **kw):
+    # one slot; after admitting a request it waits (up to 5 s) for the others still in setup
+    srv = R.Server(hbm_bytes=512 << 20, slots=1, setup_threads=4, batch_max=10, tune_slack=0.0,
+                   batch_wait_ms=5000.0)
+    ids = {}
+    for i, p in enumerate(probs):
+        ids[srv.submit(p.m, p.n, p.rowptr, p.col, p.val, p.b, tol=tol, precision=precision, **kw)] = i
+    srv.drain()
+    got = {}
+    while len(got) < len(probs):
+        for res, x in srv.poll(wait_ms=1000):
+            got[ids[res["id"]]] = (res, x)
+    srv.close()
+    return got
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_served_correction_follows_oracle(gpu_lib, precision):
+    """Served with shared batched launches (one slot, a batching window, up to ten requests per
+    admission): each
+    result equals its lone batched launch bit for bit, lies in the oracle's stop-test ball
+    (FP64: iterations within 2% of the oracle's); four steps of a sample against the oracle's
+    (x to 1e-8 in FP64; to 1e-3 with the FP32 preconditioner, whose applications are within
+    about 1e-7 of the FP64 oracle's)."""
+    R = gpu_lib
+    import torch
+
+    probs = requests()
+    got = serve(R, probs, 1e-8, precision, **CHEB2)
+    bt = R.Batch(1)
+    sizes = []
+    for i, p in enumerate(probs):
+        res, x = got[i]
+        assert res["status"] == R.OK and res["path"] == 0, (i, res)
+        S = R.Solver.from_problem(p, precision=precision, **CHEB2).upload()
+        xs, rr = bt.solve([S], [torch.from_numpy(p.b).cuda()], 1e-8, tile=res["tile"])
+        S.close()
+        assert rr[0]["iters"] == res["iters"] and np.array_equal(xs[0].cpu().numpy().view(np.int64), x.view(np.int64))
+        F = oracle.factor_problem(p, mu=1.0, smode="cheb", ystore=True, ytau=1e-2, poly_degree=2)
+        o = oracle.lsqr_m(F, p.b, tol=1e-8, maxit=2000)
+        A = p.scipy()
+        atb = np.linalg.norm(A.T @ p.b)
+        assert o.status == "ok"
+        if precision == 0:
+            assert abs(res["iters"] - o.iters) <= max(1, int(0.02 * o.iters)), (i, res["iters"], o.iters)
+        assert np.linalg.norm(A.T @ (p.b - A @ x)) <= 2e-8 * atb, i
+        assert np.linalg.norm(A.T @ (A @ (x - o.x))) <= 4e-8 * atb, i
+        sizes.append(res["launch_size"])
+    bt.close()
+    print("precision %d launch sizes %s" % (precision, sizes))
+    assert max(sizes) >= 2  # the window made admissions share launches
+    sample = probs[:4]
+    got = serve(R, sample, 1e-14, precision, maxit=4, **CHEB2)
+    for i, p in enumerate(sample):
+        res, x = got[i]
+        F = oracle.factor_problem(p, mu=1.0, smode="cheb", ystore=True, ytau=1e-2, poly_degree=2)
+        o = oracle.lsqr_m(F, p.b, tol=1e-14, maxit=4)
+        err = np.linalg.norm(x - o.x) / np.linalg.norm(o.x)
+        print("request %d precision %d: four steps, x rel diff %.1e" % (i, precision, err))
+        assert res["iters"] == o.iters == 4
+        assert err <= (1e-8 if precision == 0 else 1e-3), (i, err)

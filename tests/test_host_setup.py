@@ -500,12 +500,21 @@ def test_chebyshev_plan_matches_oracle(name, ystore):
     assert st.smode == R.S_CHEB
     assert abs(st.cheb_b - F.cheb_b) <= 1e-12 * F.cheb_b and st.cheb_degree == F.cheb_degree
     assert st.cheb_degree % 2 == 0 and st.cheb_degree > 0
+    assert st.cheb_scale == F.cheb_omega == 1.0  # the default degree meets its bound
     R.rsilu_destroy(h)
     # a fixed degree is taken as given; LSQR accepts the Chebyshev M_b; bad settings are rejected
     prm = R.rsilu_params_default(mu=1.0, smode=R.S_CHEB, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR, ystore=ystore,
                                  poly_degree=7)
     code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
     assert code == R.OK and R.rsilu_get_stats(h).cheb_degree == 7
+    R.rsilu_destroy(h)
+    # degree 2 on an interval it cannot cover: the input scale 1 / (1 + eps_2), as the oracle's
+    prm = R.rsilu_params_default(mu=1.0, smode=R.S_CHEB, form=R.FORM_ALG2, ystore=ystore, poly_degree=2)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+    st = R.rsilu_get_stats(h)
+    F2 = oracle.factor_problem(p, mu=1.0, smode="cheb", ystore=bool(ystore), ytau=1e-2, poly_degree=2)
+    assert code == R.OK and st.cheb_degree == 2 and (F2.cheb_omega < 1) == (name != "c1")  # c1: b = 3.3
+    assert abs(st.cheb_scale - F2.cheb_omega) <= 1e-13 * F2.cheb_omega
     R.rsilu_destroy(h)
     for kw in (dict(poly_degree=-1), dict(poly_degree=513), dict(poly_delta=0.0), dict(poly_delta=1.0),
                dict(trsv=R.TRSV_SYNCFREE), dict(precision=R.PREC_FP32, ystore=0)):

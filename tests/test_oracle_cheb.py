@@ -9,7 +9,12 @@ allows any approximation S^ of S~ that is cheaper to solve with).
   factors, A~ = [L1; Y~ L1] U) has its eigenvalues in [1 - delta, 1 + delta];
 * an even degree keeps it positive definite even when b underestimates lambda_max (an odd
   one need not), which is why the rule takes even degrees;
-* LSQR with this M^{-1} converges to the least-squares solution (dense QR).
+* LSQR with this M^{-1} converges to the least-squares solution (dense QR);
+* a degree fixed too low for the interval scales the input by omega = 1 / (1 + eps_K): the
+  eigenvalues of M^{-1} C~ are then t - omega (t - 1)(1 - r_K(t)) over the spectrum of S~
+  (and 1 on the null space of Y~), all positive, where the unscaled operator has a negative
+  one; LSQR with degree 2 then converges on a request with dense rows, where the unscaled
+  polynomial breaks down.
 """
 
 import math
@@ -125,3 +130,47 @@ def test_lsqr_with_chebyshev_reaches_least_squares(tiny):
     assert np.linalg.norm(res.x - xls) <= 2 * res.atr_norm / smin**2 + 1e-12 * np.linalg.norm(xls)
     pc = oracle.pcgls(F, prob.b, tol=1e-10, maxit=200, form="alg2")
     assert pc.status == "ok" and abs(pc.iters - res.iters) <= 1
+
+
+def test_scale_rule():
+    for lam in (2.0, 220.3, 488.2, 5e4):
+        b, K = oracle.cheb_plan(lam, 0.9)
+        eps = 1.0 / math.cosh(K * math.acosh((b + 1) / (b - 1)))
+        want = 1.0 if (b - 1) * eps <= 0.9 else 1.0 / (1.0 + eps)  # the cap of 512 at 5e4
+        assert oracle.cheb_scale(b, K, 0.9) == want
+    assert oracle.cheb_scale(1.05 * 488.2, 88, 0.9) == 1.0
+    b = 1.05 * 488.2
+    sig = (b + 1) / (b - 1)
+    eps2 = 1.0 / (2 * sig * sig - 1)  # T_2(x) = 2 x^2 - 1
+    assert abs(oracle.cheb_scale(b, 2, 0.9) - 1 / (1 + eps2)) <= 1e-15
+    assert oracle.cheb_scale(1.0, 0, 0.9) == 1.0
+
+
+def test_low_degree_scaled_spectrum():
+    import dataclasses
+
+    prob = gen.random_sparse(60, 40, k=4, seed=63)
+    F = oracle.factor_problem(prob, p=4, tau=1e-2, mu=1.0, smode="cheb", ystore=True, ytau=0.0, poly_degree=2)
+    assert F.cheb_degree == 2 and 0.5 < F.cheb_omega < 1
+    t = np.linalg.eigvalsh(dense_S(F))
+    r = r_K(t, 2, F.cheb_b)
+    want = np.sort(np.concatenate([t - F.cheb_omega * (t - 1) * (1 - r), np.ones(F.n - F.Y.nrows)]))
+    got = np.sort(np.linalg.eigvals(alg2_operator(F) @ factor_normal_matrix(F)).real)
+    assert np.allclose(got, want, rtol=1e-8, atol=1e-10)
+    assert got[0] > 0
+    G = dataclasses.replace(F, cheb_omega=1.0)
+    assert np.linalg.eigvals(alg2_operator(G) @ factor_normal_matrix(G)).real.min() < 0
+
+
+def test_low_degree_lsqr_on_dense_rows():
+    import dataclasses
+
+    prob = gen.served_request(3000, 4500, 31, n_dense=12)
+    F = oracle.factor_problem(prob, mu=1.0, smode="cheb", ystore=True, ytau=1e-2, poly_degree=2)
+    assert F.cheb_omega < 1
+    res = oracle.lsqr_m(F, prob.b, tol=1e-8, maxit=500)
+    A = prob.scipy()
+    assert res.status == "ok"
+    assert np.linalg.norm(A.T @ (prob.b - A @ res.x)) <= 2e-8 * np.linalg.norm(A.T @ prob.b)
+    bad = oracle.lsqr_m(dataclasses.replace(F, cheb_omega=1.0), prob.b, tol=1e-8, maxit=500)
+    assert bad.status == "breakdown"
