@@ -138,7 +138,9 @@ typedef struct {
 /* Create an autotuner. A problem goes to the batched kernel when its best tile's
  * time per iteration is at most `slack` times that of the plain path (slack >= 1
  * favours the batched kernel, which leaves every other compute unit to the other
- * problems of its launch). `iters` (>= 2) iterations are timed per candidate.
+ * problems of its launch). `iters` (>= 2) iterations are timed per candidate:
+ * the plain path (after one untimed run), the default tile, and the other tiles
+ * only when the default one is within twice the slack of the plain path.
  * EINVAL: slack not finite or <= 0, iters < 2. */
 rsilu_status_t rsilu_tuner_create(double slack, int32_t iters, rsilu_tuner_t *out);
 

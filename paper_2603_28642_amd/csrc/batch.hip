@@ -1184,23 +1184,8 @@ rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev
     const int32_t K = std::min<int32_t>(t->iters, std::max<int32_t>(h->prm.maxit, 2));
     const double zero = 0.0;
     rsilu_batch_result_t br;
-    // candidates of the batched kernel: one untimed run (first touch of the
-    // problem's data), then one timed run per compiled tile
-    double best = 1e300;
-    rsilu_tile_t best_tile = kDefaultTile;
-    rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &kDefaultTile, &br, s, K);
-    if (rc != RSILU_OK) return rc;
-    for (const TileEntry &e : tiles()) {
-        const auto t0 = std::chrono::steady_clock::now();
-        rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &e.tile, &br, s, K);
-        if (rc != RSILU_OK) return rc;
-        const double ms = elapsed_ms(t0);
-        if (ms < best) {
-            best = ms;
-            best_tile = e.tile;
-        }
-    }
-    // the plain path with the same iteration count
+    // the plain path first: one untimed run (first touch of the problem's data), one
+    // timed run, with the same iteration count
     const int32_t saved = h->prm.maxit;
     h->prm.maxit = K;
     double plain = 1e300;
@@ -1214,6 +1199,26 @@ rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev
     }
     h->prm.maxit = saved;
     if (rc < 0) return rc;
+    // the batched kernel: the default tile, and every other compiled tile only when the
+    // default one is within twice the slack of the plain path (a problem far too large
+    // for one workgroup is not timed twelve times)
+    double best = 1e300;
+    rsilu_tile_t best_tile = kDefaultTile;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (const TileEntry &e : tiles()) {
+            const bool dflt = std::memcmp(&e.tile, &kDefaultTile, sizeof(rsilu_tile_t)) == 0;
+            if (dflt != (pass == 0)) continue;
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = batch_solve(*t->bt, 1, &h, &b_dev, &zero, &x_dev, &e.tile, &br, s, K);
+            if (rc != RSILU_OK) return rc;
+            const double ms = elapsed_ms(t0);
+            if (ms < best) {
+                best = ms;
+                best_tile = e.tile;
+            }
+        }
+        if (best > 2.0 * t->slack * plain) break;
+    }
     rsilu_tune_result_t r{};
     r.tile = best_tile;
     r.batched_ms_per_iter = best / K;

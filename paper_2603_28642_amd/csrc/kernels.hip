@@ -6,9 +6,10 @@
 //    (G chosen from the mean row length) so consecutive rows' entries are read
 //    contiguously; rows far longer than the mean are cut into fixed segments
 //    reduced in a fixed order, so results never depend on scheduling.
-//  - Norms and dot products are reduced per block in a fixed tree and then by
-//    one block in index order (bit-reproducible), and the same single block
-//    advances the scalar recurrence of Algorithm 1 on the device.
+//  - Norms and dot products are reduced per block in a fixed tree and then in
+//    index order (bit-reproducible) by the last block of the same launch (or by
+//    a single-block finish after a product), which also advances the scalar
+//    recurrence of Algorithm 1 on the device.
 //  - Triangular solves run "sync-free": one launch; wavefronts take chunks of
 //    rows (one level each) from an atomic ticket in level order and wait on
 //    their inputs, which are published with a single 64-bit store over a

@@ -4,10 +4,13 @@ Requests (sizes from gen.served_stream: n log-uniform, m = n U(1.1, 2.0), a tent
 8-32 dense rows) arrive as a Poisson process and go through the serving runtime
 (include/rsilu_serve.h): host setup threads, admission by device footprint into one HBM
 arena, concurrent solves on per-slot streams, requests admitted together sharing batched
-persistent launches. Every request is LSQR with Algorithm 2 and the M_b correction by a
-degree-2 Chebyshev polynomial in S~ through the explicit Y~ (the fixed two-step analogue of
-Table 3(a)'s CG(2); its input is scaled where two steps cannot cover S~'s interval, the
-requests with dense rows), FP32 preconditioner and FP64 Krylov part by default.
+persistent launches. Every request is LSQR with Algorithm 2, FP32 preconditioner and FP64
+Krylov part by default; the sparse requests take the M_b correction by a degree-2 Chebyshev
+polynomial in S~ through the explicit Y~ (the fixed two-step analogue of Table 3(a)'s
+CG(2)), the requests with dense rows none by default (there S~'s interval reaches b = 60 to
+20000: the degree that covers it costs hundreds of products with Y~ per application, and
+degree 2, scaled to stay positive definite, weakens the preconditioner to over 1000
+iterations on some of them).
 
 The plain path is the same method with the FP64 preconditioner, one request at a time
 (setup, upload, rsilu_solve, copy back), run on every `--plain-every`-th request of the
@@ -45,11 +48,14 @@ def main():
     ap.add_argument("--rate", type=float, default=1.5, help="Poisson arrival rate, requests/s")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--correction", default="cheb2", choices=["cheb2", "none"],
-                    help="M_b: degree-2 Chebyshev through the explicit Y~, or none (A1 only)")
+                    help="M_b of the sparse requests: degree-2 Chebyshev through the explicit Y~, or none")
+    ap.add_argument("--dense-correction", default="none", choices=["cheb2", "none"],
+                    help="M_b of the requests with dense rows")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--batch-max", type=int, default=32, help="requests per batched launch (0: rsilu_solve each)")
-    ap.add_argument("--tune-slack", type=float, default=8.0, help="autotuner slack (0: default tile, no tuning)")
+    ap.add_argument("--tune-slack", type=float, default=2.0, help="autotuner slack (0: default tile, no tuning)")
+    ap.add_argument("--records", default="", help="write one JSON record per served request to this file")
     ap.add_argument("--batch-wait-ms", type=float, default=100.0,
                     help="batching window: a slot that admitted a request waits this long for more to finish setup")
     args = ap.parse_args()
@@ -62,17 +68,24 @@ def main():
     import gen
     from paper_2603_28642_amd import rsilu as R
 
-    method = dict(mu=1.0, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR)
-    if args.correction == "cheb2":
-        method.update(smode=R.S_CHEB, ystore=R.Y_EXPLICIT, ytau=1e-2, poly_degree=2)
-    else:
-        method.update(smode=R.S_NONE)
+    def method_for(corr):
+        kw = dict(mu=1.0, form=R.FORM_ALG2, krylov=R.KRYLOV_LSQR)
+        if corr == "cheb2":
+            kw.update(smode=R.S_CHEB, ystore=R.Y_EXPLICIT, ytau=1e-2, poly_degree=2)
+        else:
+            kw.update(smode=R.S_NONE)
+        return kw
+
+    def method(nd):
+        return method_for(args.dense_correction if nd > 0 else args.correction)
     prec = {"fp32": R.PREC_FP32, "fp64": R.PREC_FP64}[args.precision]
     sizes = gen.served_stream(args.requests, seed=args.seed, n_lo=args.n_lo, n_hi=args.n_hi)
     out = {
         "metric": "served mixed-size least-squares solves/s; p50/p99 latency (submit to x on the host)",
-        "requests": len(sizes), "n_range": [args.n_lo, args.n_hi], "method": "LSQR, Algorithm 2, M_b " +
-        ("Chebyshev degree 2 on S~ (explicit Y~)" if args.correction == "cheb2" else "none"),
+        "requests": len(sizes), "n_range": [args.n_lo, args.n_hi], "method": "LSQR, Algorithm 2; M_b " +
+        ("Chebyshev degree 2 on S~ (explicit Y~)" if args.correction == "cheb2" else "none") +
+        " (requests with dense rows: " +
+        ("Chebyshev degree 2" if args.dense_correction == "cheb2" else "none") + ")",
     }
     plain_idx = list(range(0, len(sizes), args.plain_every))
     plain_x = {}
@@ -82,7 +95,7 @@ def main():
             n, m, s, nd = sizes[i]
             p = gen.served_request(n, m, s, n_dense=nd)
             t1 = time.perf_counter()
-            S = R.Solver.from_problem(p, precision=R.PREC_FP64, maxit=2000, **method)
+            S = R.Solver.from_problem(p, precision=R.PREC_FP64, maxit=2000, **method(nd))
             t2 = time.perf_counter()
             S.upload()
             x, code, it, atr, rel = S.solve(torch.from_numpy(p.b).cuda(), tol=args.tol)
@@ -123,7 +136,7 @@ def main():
                     break
                 time.sleep(min(t_next - now, 0.002))
             ids[srv.submit(p.m, p.n, p.rowptr, p.col, p.val, p.b, tol=args.tol, precision=prec, maxit=2000,
-                           **method)] = i
+                           **method(sizes[i][3]))] = i
             if time.perf_counter() - last_report > 30:
                 last_report = time.perf_counter()
                 print("submitted %d, done %d" % (i + 1, len(results)), file=sys.stderr, flush=True)
@@ -136,6 +149,14 @@ def main():
         served_total = max(r[2] for r in results.values()) - t_start
         srv.close()
         res = [results[i][0] for i in range(len(probs))]
+        if args.records:
+            with open(args.records, "w") as f:
+                for i, r in enumerate(res):
+                    n, m, _, nd = sizes[i]
+                    rec = {k: r[k] for k in ("status", "iters", "atr_rel", "setup_ms", "wait_ms", "solve_ms",
+                                             "total_ms", "path", "launch_size")}
+                    rec.update(i=i, n=n, m=m, dense=nd, tile=list(r["tile"]))
+                    f.write(json.dumps(rec) + "\n")
         lat = np.array([r["total_ms"] for r in res])
         solve_ms = np.array([r["solve_ms"] for r in res])
         batched = [r for r in res if r["path"] == 0]
