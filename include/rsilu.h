@@ -213,8 +213,12 @@ typedef struct {
     int32_t levels_l1t;    /* ... of the L1^T backward solve */
     int32_t levels_u;      /* ... of the U backward solve */
     int32_t levels_ut;     /* ... of the U^T forward solve */
-    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY, _DENSE, _NONE or _CG) */
-    int32_t reserved;
+    int32_t smode;         /* S^ actually used (RSILU_S_IDENTITY, _DENSE, _NONE, _CG or _CHEB) */
+    int32_t sweep_schemes; /* hybrid schedule: byte f (f = 0 L1, 1 L1^T, 2 U, 3 U^T) has bit s
+                              set when a single-workgroup sweep of that factor uses level
+                              scheme s (0 two phases, 1 segmented, 2 one row per thread, 3
+                              segmented with rows of up to 64 chunks) and bit 7 when a level
+                              of it is a multi-CU launch */
     size_t device_bytes;   /* what rsilu_upload needs */
     int64_t nnz_y;         /* entries of the explicit Y~ (0 when applied implicitly) */
     double cheb_b;         /* RSILU_S_CHEB: upper end b of the Chebyshev interval [1, b] */

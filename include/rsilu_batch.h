@@ -156,10 +156,10 @@ rsilu_status_t rsilu_tune(rsilu_tuner_t t, rsilu_handle_t h, const double *b_dev
 
 /* Solve `count` problems with the autotuner's schedule, on stream s, and wait.
  * Every problem the batched kernel accepts is tuned (rsilu_tune, cached per
- * signature); the accepted problems start on one batched launch, which lasts as
- * long as its slowest problem, and the plain path (rsilu_solve, one problem after
- * another on a second stream of the batch object, beside the launch) takes the
- * rest. The slowest batched problem moves to the plain path while that shortens
+ * signature); those the tuner gives to the batched kernel (path 0) start on one
+ * batched launch, which lasts as long as its slowest problem, and the plain path
+ * (rsilu_solve, one problem after another on a second stream of the batch object,
+ * beside the launch) takes the rest. The slowest batched problem moves to the plain path while that shortens
  * the estimated makespan max(slowest batched time, sum of plain times), per
  * iteration (equal iteration counts assumed). The launch uses the tuned tile of
  * its slowest problem (*tile_used, may be NULL). Problems the batched kernel does

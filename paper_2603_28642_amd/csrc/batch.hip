@@ -1249,22 +1249,23 @@ rsilu_status_t rsilu_batch_solve_auto(rsilu_batch_t bt, rsilu_tuner_t t, int32_t
     try {
         // times per iteration of every accepted problem (cached per signature)
         std::vector<rsilu_tune_result_t> tr((size_t)count);
-        std::vector<int32_t> acc;
+        std::vector<int32_t> acc, tuned_plain;
         for (int32_t i = 0; i < count; ++i) {
             path[i] = 1;
             if (check_handle(*hs[i]) != RSILU_OK) continue;
             const rsilu_status_t rc = rsilu_tune(t, hs[i], b[i], x[i], &tr[(size_t)i], s);
             if (rc != RSILU_OK) return rc;
-            acc.push_back(i);
+            (tr[(size_t)i].path == 0 ? acc : tuned_plain).push_back(i);
         }
-        // All accepted problems start on the batched launch, which lasts as long as
-        // its slowest problem; the plain path runs its problems one after another
-        // beside it. Move the slowest batched problem to the plain path while that
-        // shortens max(slowest batched, sum of plain) (equal iteration counts assumed).
+        // The problems the tuner gives to the batched kernel start on the batched launch,
+        // which lasts as long as its slowest problem; the plain path runs the others one
+        // after another beside it. Move the slowest batched problem to the plain path while
+        // that shortens max(slowest batched, sum of plain) (equal iteration counts assumed).
         std::stable_sort(acc.begin(), acc.end(), [&](int32_t a, int32_t c) {
             return tr[(size_t)a].batched_ms_per_iter > tr[(size_t)c].batched_ms_per_iter;
         });
         double sum_p = 0.0;
+        for (int32_t i : tuned_plain) sum_p += tr[(size_t)i].plain_ms_per_iter;
         size_t top = 0;
         while (top < acc.size()) {
             const rsilu_tune_result_t &r = tr[(size_t)acc[top]];
@@ -1277,6 +1278,7 @@ rsilu_status_t rsilu_batch_solve_auto(rsilu_batch_t bt, rsilu_tuner_t t, int32_t
         std::vector<int32_t> plain;
         for (int32_t i = 0; i < count; ++i)
             if (check_handle(*hs[i]) != RSILU_OK) plain.push_back(i);
+        for (int32_t i : tuned_plain) plain.push_back(i);
         for (size_t q = 0; q < top; ++q) plain.push_back(acc[q]);
         std::vector<int32_t> batched(acc.begin() + (ptrdiff_t)top, acc.end());
         // one tile for the launch: the tuned tile of its slowest problem

@@ -718,6 +718,11 @@ rsilu_status_t rsilu_get_stats(rsilu_handle_t h, rsilu_stats_t *s)
     s->levels_u = h->lvU.nlev();
     s->levels_ut = h->lvUT.nlev();
     s->smode = h->smode;
+    s->sweep_schemes = 0;
+    const Sweep *sws[4] = {&h->swL1, &h->swL1T, &h->swU, &h->swUT};
+    for (int f = 0; f < 4; ++f)
+        for (const Sweep::Seg &g : sws[f]->segs)
+            s->sweep_schemes |= (g.wide_level >= 0 ? 0x80 : (1 << (g.scheme & 7))) << (8 * f);
     s->device_bytes = h->lay.total;
     s->nnz_y = yexplicit(*h) ? h->Y.nnz() : 0;
     s->cheb_b = h->cheb_b;

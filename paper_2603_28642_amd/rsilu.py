@@ -62,7 +62,7 @@ class rsilu_stats_t(ctypes.Structure):
                 ("nnz_l1", ctypes.c_int64), ("nnz_l2", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
                 ("psize", ctypes.c_int64), ("nmod", ctypes.c_int64), ("levels_l1", ctypes.c_int32),
                 ("levels_l1t", ctypes.c_int32), ("levels_u", ctypes.c_int32), ("levels_ut", ctypes.c_int32),
-                ("smode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
+                ("smode", ctypes.c_int32), ("sweep_schemes", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
                 ("nnz_y", ctypes.c_int64), ("cheb_b", ctypes.c_double), ("cheb_degree", ctypes.c_int32),
                 ("reserved2", ctypes.c_int32), ("cheb_scale", ctypes.c_double)]
 

@@ -96,16 +96,32 @@ def test_every_scheme_against_oracle(gpu_lib, name):
         assert np.array_equal(a.view(np.int64), b.view(np.int64)), (name, which)
 
 
+def _schemes(R, prob, params, sweep, precision):
+    """Level schemes the setup chose, per factor (bit s of byte f: scheme s in factor f)."""
+    kw = dict(mu=1.0, smode=R.S_NONE, trsv=R.TRSV_HYBRID, sweep=sweep, precision=precision, **params)
+    S = R.Solver.from_problem(prob, **kw)
+    mask = S.stats.sweep_schemes
+    S.close()
+    return [(mask >> (8 * f)) & 0xFF for f in range(4)]
+
+
+@pytest.mark.parametrize("name", ["c2-small", "long-factor"])
 @pytest.mark.parametrize("sweep", ["two_phase", "segmented", "rows"])
-def test_every_scheme_fp32(gpu_lib, sweep):
-    """FP32 sweeps: backward error in FP32 against the FP32-rounded operands."""
+def test_every_scheme_fp32(gpu_lib, sweep, name):
+    """FP32 sweeps: backward error in FP32 against the FP32-rounded operands. On the
+    long-factor problem the segmented scheme takes its wavefront-wide instantiation (rows of
+    17 to 64 chunks), which the setup reports."""
     R = gpu_lib
     sw = {"two_phase": R.SWEEP_TWO_PHASE, "segmented": R.SWEEP_SEGMENTED, "rows": R.SWEEP_ROWS}[sweep]
-    prob = gen.by_name("c2-small")
-    F = oracle.factor_problem(prob, mu=1.0, smode="none")
+    make, params = PROBLEMS[name]
+    prob = make()
+    F = oracle.factor_problem(prob, mu=1.0, smode="none", **params)
+    schemes = _schemes(R, prob, params, sw, R.PREC_FP32)
+    want_bit = {"two_phase": 1, "rows": 4}.get(sweep, 8 if name == "long-factor" else 2)
+    assert any(m & want_bit for m in schemes), (sweep, name, schemes)
     rhs = np.random.default_rng(22).standard_normal(prob.n)
     rhs32 = rhs.astype(np.float32).astype(np.float64)
-    got = _solves(R, prob, F, {}, sw, rhs, precision=R.PREC_FP32)
+    got = _solves(R, prob, F, params, sw, rhs, precision=R.PREC_FP32)
     for which, T, diag, _ in _operators(R, F):
         x = got[which]
         assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
@@ -114,7 +130,7 @@ def test_every_scheme_fp32(gpu_lib, sweep):
         resid = T32 @ x + d32 * x - rhs32
         scale = abs(T32) @ np.abs(x) + np.abs(d32 * x) + np.abs(rhs32)
         k = np.diff(T.rowptr) + 2
-        assert np.all(np.abs(resid) <= 4 * k * EPS32 * scale), (sweep, which)
+        assert np.all(np.abs(resid) <= 4 * k * EPS32 * scale), (sweep, name, which)
 
 
 @pytest.mark.parametrize("sweep", ["two_phase", "segmented", "rows"])

@@ -523,3 +523,30 @@ def test_chebyshev_plan_matches_oracle(name, ystore):
             setattr(prm, k_, v_)
         code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
         assert code == R.EINVAL and h is None, kw
+
+
+def test_sweep_schemes_reported():
+    """The level schemes the setup picks per factor (stats.sweep_schemes): forced schemes
+    everywhere; the segmented one takes its wavefront-wide instantiation (bit 3) for the
+    factors with rows of 17 to 64 chunks, in FP64 and FP32; multi-CU levels (bit 7) on the
+    grid case's wide levels."""
+    long_factor = (gen.random_sparse(900, 600, k=40, seed=5), dict(p=60, tau=0.0))
+    grid = (gen.by_name("c2-small"), {})
+
+    def masks(case, sweep, precision):
+        p, kw = case
+        prm = R.rsilu_params_default(mu=1.0, smode=R.S_NONE, sweep=sweep, precision=precision, **kw)
+        code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+        assert code == R.OK
+        m = R.rsilu_get_stats(h).sweep_schemes
+        R.rsilu_destroy(h)
+        return [(m >> (8 * f)) & 0xFF for f in range(4)]
+
+    for prec in (R.PREC_FP64, R.PREC_FP32):
+        assert masks(long_factor, R.SWEEP_TWO_PHASE, prec) == [1, 1, 1, 1]
+        assert masks(long_factor, R.SWEEP_ROWS, prec) == [4, 4, 4, 4]
+        seg = masks(long_factor, R.SWEEP_SEGMENTED, prec)
+        assert seg[0] == 8 and seg[2] == 8 and seg[1] == 2 and seg[3] == 2  # L1, U: rows up to 51 chunks
+        assert masks(long_factor, R.SWEEP_AUTO, prec) == seg
+        g = masks(grid, R.SWEEP_AUTO, prec)
+        assert all(m & 0x7F == 2 for m in g) and g[0] & 0x80 and g[3] & 0x80
