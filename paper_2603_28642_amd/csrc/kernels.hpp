@@ -28,8 +28,6 @@ struct alignas(256) DevState {
     // and a stop requested by the scalar step, committed after the x update
     double la, lb, rhobar, phibar, phi_rho, theta_rho, snorm;
     int32_t lstop, lstop_status;
-    uint32_t red_ticket;  // blocks of a one-launch reduction that have stored their partial
-    uint32_t pad1;
 };
 
 // CSR operator in device memory (values in FP64, or FP32 for the factors of
@@ -50,7 +48,7 @@ struct DPlan {
     const int32_t *seg_beg;
     const int32_t *seg_end;
     int32_t nlong, nseg, lanes, long_thresh;
-    int32_t unroll;  // entries per lane loaded at once by the paired-row kernel (2 or 4)
+    int32_t unroll;  // entries per lane loaded at once by the paired-row kernel (2, 3 or 4)
 };
 
 // Triangular operator: strictly triangular CSR, optional diagonal, level-ordered rows,
@@ -106,7 +104,7 @@ void launch_gather(hipStream_t s, int32_t m, int32_t n, const int32_t *perm, con
 template <class T>
 void launch_spmv(hipStream_t s, const DCsrT<T> &a, const DPlan &pl, const T *x, T *y, const T *aux, Epi epi,
                  Fin fin, double *partials, T *segpart, DevState *st, const int32_t *done);
-// a . b and the scalar step `fin`, in one launch (the last block to finish reduces)
+// a . b and the scalar step `fin` (per-block partials, then one block)
 void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin fin, double *partials,
                 DevState *st, const int32_t *done);
 // x_hat += alpha p; r -= alpha q; sentinel-fill the sync-free outputs; reset tickets
@@ -167,7 +165,7 @@ void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double
 void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
                       const DevState *st, const int32_t *done);
 void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done);
-// the update, then res . res with the step FIN_CG_BETA, in one launch
+// the update with the partials of res . res, then the step FIN_CG_BETA
 void launch_cg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
                           double *partials, DevState *st, const int32_t *done);
 // Chebyshev steps on S~: r = omega u, d = r / theta, w = 0; then per step, with

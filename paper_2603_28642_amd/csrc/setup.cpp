@@ -496,7 +496,9 @@ int32_t lanes_for(double avg)
 // Lanes per row of a CSR product and entries per lane loaded at once: two rows
 // per lane group with 4 lanes up to 8 entries per row on average, 8 lanes up to
 // 16 (2 entries per lane) and up to 32 (4), 16 lanes up to 64 and 32 lanes up to
-// 128 (4 entries per lane); one row per 64-lane group beyond.
+// 128 (3 entries per lane: fewer registers than 4, more wavefronts in flight; 3-5%
+// faster on the products with Y~ and Y~^T, measured alternating as in the S~ steps);
+// one row per 64-lane group beyond.
 int32_t spmv_lanes(double avg)
 {
     if (avg <= 8.0) return 4;
@@ -506,7 +508,7 @@ int32_t spmv_lanes(double avg)
     return 64;
 }
 
-int32_t spmv_unroll(double avg) { return avg <= 16.0 ? 2 : 4; }
+int32_t spmv_unroll(double avg) { return avg <= 16.0 ? 2 : (avg <= 32.0 ? 4 : 3); }
 
 SpmvPlan plan_spmv(const Csr &a)
 {
