@@ -311,6 +311,8 @@ class Factors:
     R: "CSR" = None  # removed rows of A_hat that were in A1 (Section 3.4), or None
     W_chol: np.ndarray = field(default=None)  # lower Cholesky factor of I - R M^{-1} R^T
     cg_steps: int = 2  # CG steps on S~ (cg mode)
+    cg_jacobi: bool = False  # the CG steps preconditioned by the diagonal of S~ (explicit Y~)
+    S_diag: object = None  # diag(S~) = 1 + the squared row norms of Y~ (cg_jacobi)
     lev: dict = field(default_factory=dict)
     Y: "CSR" = None  # explicit Y~ = L2 L1^{-1} (Section 3.2), or None: applied implicitly
     YT: "CSR" = None
@@ -361,10 +363,11 @@ def dense_S(L1, L2):
 
 
 def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale=True, smode="identity",
-           cg_steps=2, ystore=False, ytau=0.0, poly_degree=0, poly_delta=0.9):
+           cg_steps=2, ystore=False, ytau=0.0, poly_degree=0, poly_delta=0.9, cg_jacobi=False):
     """Setup: validate, prescale, ILUP, splitting, transposes, level sets, S~, with ystore
     the explicit Y~ (drop tolerance ytau), and in cheb mode the Chebyshev interval and
-    degree (poly_degree = 0: chosen by cheb_plan from poly_delta)."""
+    degree (poly_degree = 0: chosen by cheb_plan from poly_delta); cg_jacobi (cg mode with
+    the explicit Y~) preconditions the CG steps by diag(S~)."""
     rowptr, col, val = validate(m, n, rowptr, col, val)
     A = CSR(m, n, rowptr, col, val)
     colptr, rowind, cval = to_csc(m, n, rowptr, col, val)
@@ -399,7 +402,23 @@ def factor(m, n, rowptr, col, val, p=10, tau=1e-2, mu=0.1, small=1e-10, colscale
     F.poly_degree, F.poly_delta = int(poly_degree), float(poly_delta)
     if smode == "cheb" and m > n:
         _plan_chebyshev(F)
+    if cg_jacobi:
+        if smode != "cg" or not ystore:
+            raise ValueError("Jacobi-preconditioned CG needs cg mode and the explicit Y~")
+        F.cg_jacobi = True
+        F.S_diag = S_diagonal(F.Y)
     return F
+
+
+def S_diagonal(Y):
+    """diag(S~) = 1 + (Y~ Y~^T)_ii = 1 + the sum of the squared entries of row i of Y~, each
+    sum correctly rounded (math.fsum of the rounded squares)."""
+    d = np.ones(Y.nrows)
+    for i in range(Y.nrows):
+        v = Y.val[Y.rowptr[i]:Y.rowptr[i + 1]]
+        if v.size:
+            d[i] = 1.0 + math.fsum(v * v)
+    return d
 
 
 def _plan_chebyshev(F):
@@ -451,6 +470,8 @@ def add_rows(F, rowptr, col, val, tau=1e-2):
         G.YT = G.Y.transpose()
     if F.smode == "cheb":
         _plan_chebyshev(G)  # S~ changed with the rows
+    if F.cg_jacobi:
+        G.S_diag = S_diagonal(G.Y)
     if F.R is not None:
         G.W_chol = _woodbury_chol(G)
     return G
@@ -470,7 +491,10 @@ def S_product(F, d):
 
 def cg_S(F, u):
     """F.cg_steps steps of unpreconditioned conjugate gradients on S~ w = u from
-    w = 0 (Section 3.2; Table 3(a) takes two); stops early on a zero residual."""
+    w = 0 (Section 3.2; Table 3(a) takes two); stops early on a zero residual. With
+    F.cg_jacobi, preconditioned conjugate gradients with diag(S~) instead."""
+    if F.cg_jacobi:
+        return pcg_S(F, u)
     w = np.zeros_like(u)
     res = u.copy()
     p = u.copy()
@@ -489,6 +513,35 @@ def cg_S(F, u):
             rr_new = dot(res, res)
             p = res + (rr_new / rr) * p
             rr = rr_new
+    return w
+
+
+def pcg_S(F, u):
+    """F.cg_steps steps of conjugate gradients on S~ w = u preconditioned by D = diag(S~),
+    from w = 0: z = D^{-1} res, alpha = (res, z) / (p, S~ p), w += alpha p, res -= alpha S~ p,
+    z = D^{-1} res, beta = (res, z)_new / (res, z), p = z + beta p (the textbook method, as for
+    cg_S); stops early on a zero (res, z)."""
+    D = F.S_diag
+    w = np.zeros_like(u)
+    res = u.copy()
+    z = res / D
+    p = z.copy()
+    rz = dot(res, z)
+    for i in range(F.cg_steps):
+        if not rz > 0.0:
+            break
+        q = S_product(F, p)
+        pq = dot(p, q)
+        if not (pq > 0.0 and math.isfinite(pq)):
+            break
+        alpha = rz / pq
+        w = w + alpha * p
+        res = res - alpha * q
+        if i + 1 < F.cg_steps:
+            z = res / D
+            rz_new = dot(res, z)
+            p = z + (rz_new / rz) * p
+            rz = rz_new
     return w
 
 

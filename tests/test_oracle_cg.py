@@ -3,7 +3,11 @@
 * the implicit product S~ d equals (I + Y~ Y~^T) d with Y~ = L2 L1^{-1} formed densely;
 * one CG step from w = 0 is the closed form w = (u.u / u.S~u) u;
 * m - n steps reach the dense solve S~^{-1} u (CG terminates in at most m - n steps);
-* Algorithm 3 and Algorithm 2 with that many steps equal their dense-S~ forms.
+* Algorithm 3 and Algorithm 2 with that many steps equal their dense-S~ forms;
+* Jacobi-preconditioned CG (diag(S~) from the explicit Y~): the diagonal equals that of the
+  dense S~; one step is w = ((u, D^{-1}u) / (D^{-1}u, S~ D^{-1}u)) D^{-1}u; m - n steps reach
+  the dense solve; every iterate equals plain CG on D^{-1/2} S~ D^{-1/2} mapped back (the
+  textbook equivalence, with the symmetric scaling formed densely).
 """
 
 import numpy as np
@@ -67,3 +71,58 @@ def test_zero_rhs_stops():
     p = gen.random_sparse(40, 30, k=3, seed=62)
     F = oracle.factor_problem(p, p=4, tau=1e-2, mu=1.0, smode="cg")
     assert np.all(oracle.cg_S(F, np.zeros(10)) == 0.0)
+
+
+def _jacobi(prob, steps):
+    F = oracle.factor_problem(prob, p=4, tau=1e-2, mu=1.0, smode="cg", cg_steps=steps, ystore=True, ytau=0.0,
+                              cg_jacobi=True)
+    Yd = F.Y.dense()
+    return F, np.eye(F.m - F.n) + Yd @ Yd.T
+
+
+def test_jacobi_diagonal(prob):
+    F, S = _jacobi(prob, 1)
+    assert np.allclose(F.S_diag, np.diag(S), rtol=1e-15, atol=0)
+    assert F.cg_jacobi and np.all(F.S_diag >= 1.0)
+
+
+def test_jacobi_one_step_closed_form(prob):
+    F, S = _jacobi(prob, 1)
+    u = np.random.default_rng(3).standard_normal(F.m - F.n)
+    z = u / np.diag(S)
+    want = (u @ z) / (z @ S @ z) * z
+    assert np.allclose(oracle.cg_S(F, u), want, rtol=1e-12, atol=1e-14)
+
+
+def test_jacobi_full_steps_reach_dense_solve(prob):
+    F, S = _jacobi(prob, prob.m - prob.n)
+    u = np.random.default_rng(4).standard_normal(F.m - F.n)
+    want = np.linalg.solve(S, u)
+    assert np.allclose(oracle.cg_S(F, u), want, rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("steps", [2, 5])
+def test_jacobi_equals_cg_on_scaled_system(prob, steps):
+    """PCG with D on S~ w = u is CG on (D^{-1/2} S~ D^{-1/2}) v = D^{-1/2} u with w = D^{-1/2} v."""
+    import dataclasses
+
+    F, S = _jacobi(prob, steps)
+    u = np.random.default_rng(5).standard_normal(F.m - F.n)
+    d = np.sqrt(np.diag(S))
+    Ss = S / d[:, None] / d[None, :]
+    v = np.zeros_like(u)
+    r = u / d
+    pdir = r.copy()
+    rr = r @ r
+    for i in range(steps):
+        q = Ss @ pdir
+        a = rr / (pdir @ q)
+        v = v + a * pdir
+        r = r - a * q
+        rr_new = r @ r
+        pdir = r + (rr_new / rr) * pdir
+        rr = rr_new
+    assert np.allclose(oracle.cg_S(F, u), v / d, rtol=1e-10, atol=1e-13)
+    # and it differs from plain CG (the pin has teeth)
+    G = dataclasses.replace(F, cg_jacobi=False)
+    assert not np.allclose(oracle.cg_S(G, u), v / d, rtol=1e-6, atol=0)
