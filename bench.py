@@ -9,9 +9,9 @@ in HBM to x in HBM with the iteration count and ||A^T r|| on the host. Setup
 The default configuration is the paper's method with the A2 correction in every
 iteration: Algorithm 1 (left-preconditioned CGLS) with the preconditioner
 applied by Algorithm 2 with k = n, M_a = (L1 U)^T (L1 U) from the ILUP(10, 1e-2)
-factors (mu = 1), and M_b given by 32 CG steps on S~ = I + Y~ Y~^T, with Y~ =
-L2 L1^{-1} stored explicitly as a sparse matrix (Section 3.2; entries below
-1e-2 dropped). Beside it the JSON line carries the A1-only preconditioner
+factors (mu = 1), and M_b given by 20 CG steps on S~ = I + Y~ Y~^T preconditioned by
+diag(S~), with Y~ = L2 L1^{-1} stored explicitly as a sparse matrix (Section 3.2;
+entries below 1e-2 dropped). Beside it the JSON line carries the A1-only preconditioner
 (no M_b correction, LSQR; the Lauchli-type preconditioner of the related work)
 on the same workload, and the tiny workload with the dense S~ (Table 2 form).
 
@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--smode", default="cg", choices=["cg", "cheb", "none", "identity", "dense", "auto"],
                     help="S^ / M_b: CG steps on S~ (default), a Chebyshev polynomial in S~, none (A1 only), "
                          "identity, dense S~")
-    ap.add_argument("--cg-steps", type=int, default=32)
+    ap.add_argument("--cg-steps", type=int, default=20)
+    ap.add_argument("--cg-precond", default="jacobi", choices=["jacobi", "none"],
+                    help="preconditioner of the CG steps on S~: diag(S~) (needs the explicit Y~) or none")
     ap.add_argument("--poly-degree", type=int, default=0, help="Chebyshev degree (0: automatic)")
     ap.add_argument("--poly-delta", type=float, default=0.9, help="spectral spread the automatic degree meets")
     ap.add_argument("--ystore", default="explicit", choices=["explicit", "implicit"],
@@ -78,8 +80,8 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_CONFIG_KEYS = ("precision", "form", "krylov", "trsv", "smode", "mu", "tau", "p", "cg_steps", "ystore", "ytau",
-                       "poly_degree", "poly_delta")
+TRAFFIC_CONFIG_KEYS = ("precision", "form", "krylov", "trsv", "smode", "mu", "tau", "p", "cg_steps", "cg_precond",
+                       "ystore", "ytau", "poly_degree", "poly_delta")
 TRAFFIC_SOURCES = ("paper_2603_28642_amd/csrc/kernels.hip", "paper_2603_28642_amd/csrc/sweep_limits.hpp",
                    "paper_2603_28642_amd/csrc/setup.cpp")
 
@@ -182,6 +184,8 @@ def step_bytes(st, vb=8):
         # p = res + b p; and the steps' set-up (res = p = u, w = 0, (res, res)) and result copy
         "cg_vectors": 8 * (2 * k + 6 * k + k + 3 * k),
         "cg_setup": 8 * (4 * k + k + 2 * k),
+        # the Jacobi-preconditioned step also reads diag(S~) and writes z (its set-up too)
+        "cg_jacobi": 8 * 2 * k,
         # one Chebyshev step besides its two products: q, r, d, w read, r, d, w written
         "cheb_vectors": vb * 7 * k,
         "cheb_setup": vb * 4 * k,
@@ -192,7 +196,7 @@ def step_bytes(st, vb=8):
     }
 
 
-def iteration_bytes(st, form, smode, vb=8, ystore="implicit", cg_steps=0):
+def iteration_bytes(st, form, smode, vb=8, ystore="implicit", cg_steps=0, jacobi=False):
     """Algorithmic bytes of one iteration of Algorithm 1 with the given form (cg_steps: the CG
     steps, or the Chebyshev degree)."""
     b = step_bytes(st, vb)
@@ -204,6 +208,8 @@ def iteration_bytes(st, form, smode, vb=8, ystore="implicit", cg_steps=0):
     cg = 0
     if smode == "cg":
         cg = b["cg_setup"] + cg_steps * (b["spmv_Y"] + b["spmv_YT"] + vb * k + b["cg_vectors"])
+        if jacobi:
+            cg += (cg_steps + 1) * b["cg_jacobi"]
     elif smode == "cheb":
         cg = b["cheb_setup"] + cg_steps * (b["spmv_Y"] + b["spmv_YT"] + b["cheb_vectors"])
     if ystore == "explicit" and corr:
@@ -262,7 +268,7 @@ def cpu_baseline(prob, args, iters_per_solve):
             smode = "dense" if 0 < prob.m - prob.n <= 4096 and args.ystore != "explicit" else "identity"
         F = oracle.factor_problem(prob, p=args.p, tau=args.tau, mu=args.mu, smode=smode, cg_steps=args.cg_steps,
                                   ystore=args.ystore == "explicit", ytau=args.ytau, poly_degree=args.poly_degree,
-                                  poly_delta=args.poly_delta)
+                                  poly_delta=args.poly_delta, cg_jacobi=jacobi(args))
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         def run(maxit):
@@ -293,7 +299,8 @@ def cpu_baseline(prob, args, iters_per_solve):
         "cores": 1,
         "kind": "oracle",
         "sample": "oracle " + ("LSQR" if args.krylov == "lsqr" else "Algorithm 1") + " + Algorithm " + args.form[-1] +
-                  (" with %d CG steps on S~ (%s Y~)" % (args.cg_steps, args.ystore) if smode == "cg" else
+                  (" with %d%s CG steps on S~ (%s Y~)" % (args.cg_steps, " Jacobi-preconditioned" if jacobi(args) else "",
+                                                          args.ystore) if smode == "cg" else
                    " with a degree-%d Chebyshev M_b (%s Y~)" % (F.cheb_degree, args.ystore) if smode == "cheb" else
                    " (S^ %s)" % smode) +
                   " (plain C substitutions and products, numpy vectors, 1 thread) on the same "
@@ -301,6 +308,11 @@ def cpu_baseline(prob, args, iters_per_solve):
                   "GPU solve; oracle setup %.1f s not counted; host %s, nproc %d"
                   % (res.iters, t, per_iter * 1e3, iters_per_solve, t_setup, cpu, os.cpu_count() or 0),
     }
+
+
+def jacobi(args):
+    """Whether the CG steps on S~ are preconditioned by diag(S~)."""
+    return args.smode == "cg" and args.cg_precond == "jacobi" and args.ystore == "explicit"
 
 
 def make_solver(R, prob, args):
@@ -313,7 +325,8 @@ def make_solver(R, prob, args):
         precision={"fp64": R.PREC_FP64, "fp32": R.PREC_FP32}[args.precision],
         krylov={"pcgls": R.KRYLOV_PCGLS, "lsqr": R.KRYLOV_LSQR}[args.krylov],
         cg_steps=max(1, args.cg_steps), ystore={"explicit": R.Y_EXPLICIT, "implicit": R.Y_IMPLICIT}[args.ystore],
-        ytau=args.ytau, poly_degree=args.poly_degree, poly_delta=args.poly_delta)
+        ytau=args.ytau, poly_degree=args.poly_degree, poly_delta=args.poly_delta,
+        cg_precond=R.CG_JACOBI if jacobi(args) else R.CG_NONE)
 
 
 def timed_solves(prob, args, steps, warmup):
@@ -356,7 +369,7 @@ def timed_solves(prob, args, steps, warmup):
     status = {R.OK: "converged", R.NOT_CONVERGED: "not_converged", R.BREAKDOWN: "breakdown"}.get(code, str(code))
     b_iter = iteration_bytes(st, args.form, smode_used, 4 if args.precision == "fp32" else 8,
                              ystore=args.ystore, cg_steps=args.cg_steps if smode_used == "cg" else
-                             (st.cheb_degree if smode_used == "cheb" else 0))
+                             (st.cheb_degree if smode_used == "cheb" else 0), jacobi=jacobi(args))
     return dict(st=st, t_setup=t_setup, total=total, lat=lat, prof=prof, code=code, iters=iters, atr=atr, rel=rel,
                 smode=smode_used, status=status, t_solve=total / steps, b_solve=(iters + 1) * b_iter,
                 p50=1e3 * float(np.percentile(lat, 50)), p99=1e3 * float(np.percentile(lat, 99)))
@@ -385,6 +398,7 @@ def describe(args, r):
     }
     if r["smode"] == "cg":
         cfg["cg_steps"] = args.cg_steps
+        cfg["cg_precond"] = "jacobi" if jacobi(args) else "none"
     if r["smode"] == "cheb":
         cfg["chebyshev"] = {"degree": int(st.cheb_degree), "b": st.cheb_b, "delta": args.poly_delta}
     if r["smode"] != "none" and st.m > st.n:

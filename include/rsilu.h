@@ -89,7 +89,16 @@ enum {
                              w = 0 (Section 3.2; Table 3(a) uses two), S~ applied
                              implicitly as d + L2 L1^{-1} L1^{-T} L2^T d, or as
                              d + Y~ (Y~^T d) with the explicit Y~ (RSILU_Y_EXPLICIT);
+                             with cg_precond = RSILU_CG_JACOBI the steps are preconditioned
+                             by D = diag(S~) = 1 + the squared row norms of the explicit Y~
+                             (z = D^{-1} res, alpha = (res, z) / (p, S~ p), p = z + beta p);
                              FP64 with the hybrid or level schedule only */
+};
+
+/* Preconditioner of the CG steps on S~ (RSILU_S_CG). */
+enum {
+    RSILU_CG_NONE = 0,   /* plain CG (Table 3(a)) */
+    RSILU_CG_JACOBI = 1  /* diag(S~), from the explicit Y~ (needs RSILU_Y_EXPLICIT) */
 };
 
 /* How Y~ = L2 L1^{-1} is applied (Section 3.2; rsilu_params_t.ystore).
@@ -199,6 +208,9 @@ typedef struct {
     double poly_delta;   /* RSILU_S_CHEB: bound on the spread of the preconditioned spectrum
                             around 1 that the automatic degree meets, 0 < poly_delta < 1;
                             default 0.9 */
+    int32_t cg_precond;  /* RSILU_CG_*: preconditioner of the CG steps on S~; default
+                            RSILU_CG_NONE */
+    int32_t reserved3;   /* 0 */
 } rsilu_params_t;
 
 typedef struct {
@@ -234,7 +246,7 @@ typedef struct rsilu_ctx *rsilu_handle_t;
  * (Section 5.2 settings, with tau = 1e-2), colscale = 1, smode = AUTO,
  * maxit = 2000 (Section 5.1), trsv = HYBRID, poll = 8, form = ALG3,
  * precision = FP64, cg_steps = 2, krylov = PCGLS, graph = 1, sweep = AUTO,
- * ystore = IMPLICIT, ytau = 1e-2, poly_degree = 0, poly_delta = 0.9. */
+ * ystore = IMPLICIT, ytau = 1e-2, poly_degree = 0, poly_delta = 0.9, cg_precond = NONE. */
 void rsilu_params_default(rsilu_params_t *params);
 
 /* Setup on the host (Section 5.1 prescaling; Algorithms 4-6; the splitting

@@ -281,8 +281,16 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
     double *w = at<double>(c, c.lay.cg_w), *res = at<double>(c, c.lay.cg_r), *p = at<double>(c, c.lay.cg_p),
            *q = at<double>(c, c.lay.cg_q);
     ProfScope ps(c, s, RSILU_PROF_DENSE_S);
-    launch_cg_init(s, k, W.u, w, res, p, done);
-    launch_dot(s, k, res, res, FIN_CG_RR0, P.partials, P.st, done);
+    // Jacobi preconditioning (RSILU_CG_JACOBI): z = D^{-1} res takes res's place in the inner
+    // products and the directions; the scalar steps are the same
+    const bool jac = c.lay.cg_d != 0;
+    const double *dS = jac ? at<double>(c, c.lay.cg_d) : nullptr;
+    double *z = jac ? at<double>(c, c.lay.cg_z) : res;
+    if (jac)
+        launch_pcg_init(s, k, W.u, dS, w, res, z, p, done);
+    else
+        launch_cg_init(s, k, W.u, w, res, p, done);
+    launch_dot(s, k, res, z, FIN_CG_RR0, P.partials, P.st, done);
     for (int32_t i = 0; i < c.prm.cg_steps; ++i) {
         if (yexplicit(c)) {
             // q = p + Y~ (Y~^T p)
@@ -299,8 +307,12 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
         }
         launch_dot(s, k, p, q, FIN_CG_ALPHA, P.partials, P.st, done);
         if (i + 1 < c.prm.cg_steps) {
-            launch_cg_update_dot(s, k, p, q, w, res, P.partials, P.st, done);  // and beta from res . res
-            launch_cg_dir(s, k, res, p, P.st, done);
+            // the update with the partials of res . z, then beta; p = z + beta p
+            if (jac)
+                launch_pcg_update_dot(s, k, p, q, dS, w, res, z, P.partials, P.st, done);
+            else
+                launch_cg_update_dot(s, k, p, q, w, res, P.partials, P.st, done);
+            launch_cg_dir(s, k, z, p, P.st, done);
         } else {
             launch_cg_update(s, k, p, q, w, res, P.st, done);
         }
@@ -652,6 +664,8 @@ void rsilu_params_default(rsilu_params_t *p)
     p->ytau = 1e-2;
     p->poly_degree = 0;
     p->poly_delta = 0.9;
+    p->cg_precond = RSILU_CG_NONE;
+    p->reserved3 = 0;
 }
 
 const char *rsilu_status_string(rsilu_status_t s)
@@ -874,6 +888,7 @@ rsilu_status_t rsilu_upload(rsilu_handle_t h, void *dev_buf, size_t bytes, hipSt
     RSILU_HIP(put(L.perm, c.perm.data(), c.perm.size() * sizeof(int32_t)));
     RSILU_HIP(put(L.colnorm, c.colnorm.data(), c.colnorm.size() * sizeof(double)));
     RSILU_HIP(put(L.sfac, c.sfac.data(), c.sfac.size() * sizeof(double)));
+    if (L.cg_d) RSILU_HIP(put(L.cg_d, c.cg_diag.data(), c.cg_diag.size() * sizeof(double)));
     if (c.smode == RSILU_S_CHEB) {
         RSILU_HIP(put(L.cheb, c.cheb_c1.data(), c.cheb_c1.size() * sizeof(double)));
         RSILU_HIP(put(L.cheb + sizeof(double) * c.cheb_c1.size(), c.cheb_c2.data(), c.cheb_c2.size() * sizeof(double)));

@@ -123,6 +123,7 @@ struct Layout {
     size_t f32a = 0, f32b = 0;      // FP32 preconditioner: converted input and output (m floats each)
     size_t cg_w = 0, cg_r = 0, cg_p = 0, cg_q = 0;  // CG or Chebyshev steps on S~ (m - n each)
     size_t cheb = 0;  // Chebyshev step coefficients c1[K] then c2[K] (read by the batched kernel)
+    size_t cg_d = 0, cg_z = 0;  // Jacobi CG steps: diag(S~) and the preconditioned residual (m - n each)
     size_t l_v = 0, l_mv = 0, l_w = 0;              // LSQR: v, M v, w (n each)
     size_t partials = 0;  // reduction partials
     int32_t npartials = 0;
@@ -158,6 +159,8 @@ struct Ctx {
     double cheb_b = 1.0, cheb_theta = 1.0, cheb_omega = 1.0;
     int32_t cheb_K = 0;
     std::vector<double> cheb_c1, cheb_c2;
+    // Jacobi-preconditioned CG steps (RSILU_CG_JACOBI): diag(S~) in Y~'s device row order
+    std::vector<double> cg_diag;
     // Section 3.4, removed rows: R = the removed rows of A_hat that were in A1, and the packed
     // lower Cholesky factor of W = I - R M^{-1} R^T (Woodbury update of the preconditioner)
     Csr R, RT;

@@ -676,6 +676,46 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_dot(int32_t k, const doubl
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// Jacobi-preconditioned CG on S~ (d = diag(S~)): set-up, and the update with z = res / d and
+// the per-block partials of res . z (the grid of k_dot)
+__global__ __launch_bounds__(kBlock) void k_pcg_init(int32_t k, const double *__restrict__ u,
+                                                     const double *__restrict__ d, double *__restrict__ w,
+                                                     double *__restrict__ res, double *__restrict__ z,
+                                                     double *__restrict__ p, const int32_t *done)
+{
+    if (stop_now(done)) return;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        const double ui = u[i];
+        const double zi = ui / d[i];
+        w[i] = 0.0;
+        res[i] = ui;
+        z[i] = zi;
+        p[i] = zi;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_update_dot(int32_t k, const double *__restrict__ p,
+                                                           const double *__restrict__ q, const double *__restrict__ d,
+                                                           double *__restrict__ w, double *__restrict__ res,
+                                                           double *__restrict__ z, double *__restrict__ partials,
+                                                           const DevState *st, const int32_t *done)
+{
+    __shared__ double lds4[4];
+    if (stop_now(done)) return;
+    const double a = st->cg_alpha;
+    double s = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        w[i] = w[i] + a * p[i];
+        const double r = res[i] - a * q[i];
+        res[i] = r;
+        const double zi = r / d[i];
+        z[i] = zi;
+        s += r * zi;
+    }
+    const double t = block_sum256(s, lds4);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_dir(int32_t k, const double *__restrict__ res, double *__restrict__ p,
                                                    const DevState *st, const int32_t *done)
 {
@@ -1449,6 +1489,20 @@ void launch_dot(hipStream_t s, int32_t n, const double *a, const double *b, Fin 
     const int g = grid_for(n, 2048);
     hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, n, a, b, partials, done);
     hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, fin, st, done);
+}
+
+void launch_pcg_init(hipStream_t s, int32_t k, const double *u, const double *d, double *w, double *res, double *z,
+                     double *p, const int32_t *done)
+{
+    hipLaunchKernelGGL(k_pcg_init, dim3(grid_for(k)), dim3(kBlock), 0, s, k, u, d, w, res, z, p, done);
+}
+
+void launch_pcg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, const double *d, double *w,
+                           double *res, double *z, double *partials, DevState *st, const int32_t *done)
+{
+    const int g = grid_for(k, 2048);
+    hipLaunchKernelGGL(k_pcg_update_dot, dim3(g), dim3(kBlock), 0, s, k, p, q, d, w, res, z, partials, st, done);
+    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, FIN_CG_BETA, st, done);
 }
 
 void launch_cg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,

@@ -165,6 +165,12 @@ void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double
 void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
                       const DevState *st, const int32_t *done);
 void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done);
+// Jacobi-preconditioned CG on S~: res = u, z = u / d, p = z, w = 0; the update with
+// z = res / d and the partials of res . z, then the step FIN_CG_BETA
+void launch_pcg_init(hipStream_t s, int32_t k, const double *u, const double *d, double *w, double *res, double *z,
+                     double *p, const int32_t *done);
+void launch_pcg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, const double *d, double *w,
+                           double *res, double *z, double *partials, DevState *st, const int32_t *done);
 // the update with the partials of res . res, then the step FIN_CG_BETA
 void launch_cg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
                           double *partials, DevState *st, const int32_t *done);

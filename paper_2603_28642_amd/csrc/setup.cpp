@@ -683,6 +683,19 @@ void build_explicit_Y(Ctx &c)
     c.YdT = transpose(D);
     c.plY = plan_spmv(c.Yd);
     c.plYT = plan_spmv(c.YdT);
+    // diag(S~) = 1 + (Y~ Y~^T)_ii for the Jacobi-preconditioned CG steps, in device order
+    c.cg_diag.clear();
+    if (c.prm.cg_precond == RSILU_CG_JACOBI) {
+        c.cg_diag.assign((size_t)k, 1.0);
+        for (int32_t r = 0; r < k; ++r) {
+            double s = 0.0;
+            for (int32_t e = D.ptr[r]; e < D.ptr[(size_t)r + 1]; ++e) {
+                const double sq = D.val[e] * D.val[e];
+                s = s + sq;
+            }
+            c.cg_diag[(size_t)r] = 1.0 + s;
+        }
+    }
 }
 
 // Section 3.2 lets an approximation S^ of S~ stand in for it when that is cheaper to
@@ -839,6 +852,8 @@ rsilu_status_t build_factorization(Ctx &c, int64_t m, int64_t n, const int64_t *
           !(P.poly_delta < 1.0) || (P.precision == RSILU_PREC_FP32 && P.ystore != RSILU_Y_EXPLICIT))) ||
         (P.smode == RSILU_S_CG &&
          (P.precision != RSILU_PREC_FP64 || P.trsv == RSILU_TRSV_SYNCFREE || P.cg_steps < 1 || P.cg_steps > 256)) ||
+        (P.cg_precond != RSILU_CG_NONE && P.cg_precond != RSILU_CG_JACOBI) ||
+        (P.cg_precond == RSILU_CG_JACOBI && (P.smode != RSILU_S_CG || P.ystore != RSILU_Y_EXPLICIT)) ||
         (P.ystore != RSILU_Y_IMPLICIT && P.ystore != RSILU_Y_EXPLICIT) || !(P.ytau >= 0.0) || !std::isfinite(P.ytau) ||
         (P.ystore == RSILU_Y_EXPLICIT && (P.smode == RSILU_S_DENSE || P.trsv == RSILU_TRSV_SYNCFREE)) ||
         (P.form != RSILU_FORM_ALG3 && P.form != RSILU_FORM_ALG2) ||
@@ -1516,6 +1531,10 @@ void plan_layout(Ctx &c)
     if (c.smode == RSILU_S_CG || c.smode == RSILU_S_CHEB)
         for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
     if (c.smode == RSILU_S_CHEB) L.cheb = b.take(sizeof(double) * std::max<size_t>(2 * (size_t)c.cheb_K, 1));
+    if (c.smode == RSILU_S_CG && !c.cg_diag.empty()) {
+        L.cg_d = b.take(sizeof(double) * std::max<size_t>(k, 1));
+        L.cg_z = b.take(sizeof(double) * std::max<size_t>(k, 1));
+    }
     if (c.prm.krylov == RSILU_KRYLOV_LSQR)
         for (size_t *o : {&L.l_v, &L.l_mv, &L.l_w}) *o = b.take(sizeof(double) * n);
     // one partial per block of the largest reduction (a product's blocks hold

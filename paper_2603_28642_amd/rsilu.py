@@ -23,6 +23,7 @@ KRYLOV_PCGLS, KRYLOV_LSQR = 0, 1
 TRSV_SYNCFREE, TRSV_LEVELS, TRSV_HYBRID = 0, 1, 2
 SWEEP_AUTO, SWEEP_TWO_PHASE, SWEEP_SEGMENTED, SWEEP_ROWS = 0, 1, 2, 3
 Y_IMPLICIT, Y_EXPLICIT = 0, 1
+CG_NONE, CG_JACOBI = 0, 1
 # factor / level selectors
 L1, L2, U, AHAT, UDIAG, YEXP = 0, 1, 2, 3, 4, 5
 LEV_L1, LEV_L1T, LEV_U, LEV_UT = 0, 1, 2, 3
@@ -54,7 +55,7 @@ class rsilu_params_t(ctypes.Structure):
                 ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("graph", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("ystore", ctypes.c_int32), ("ytau", ctypes.c_double), ("poly_degree", ctypes.c_int32),
-                ("poly_delta", ctypes.c_double)]
+                ("poly_delta", ctypes.c_double), ("cg_precond", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
 
 
 class rsilu_stats_t(ctypes.Structure):

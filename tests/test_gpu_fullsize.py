@@ -1,12 +1,13 @@
 """Parity at the full sizes of the benchmarked configurations, in the launch configurations
-bench.py times: Algorithm 1 with Algorithm 2 and the M_b correction by CG(32) on S~ through
-the explicit Y~ (the headline), and beside it the A1-only preconditioner with LSQR.
+bench.py times: Algorithm 1 with Algorithm 2 and the M_b correction by 20 Jacobi-preconditioned
+CG steps on S~ through the explicit Y~ (the headline), and beside it the A1-only preconditioner
+with LSQR.
 
 * grid workload, 600000 x 400000, with the correction: the products with the explicit Y~
-  and Y~^T componentwise; one application of the correction with CG(8) element by element;
-  four Algorithm 1 steps with CG(8) against the oracle's (x to 1e-8); the whole solve in the
-  headline configuration: converged, the true ||A^T r|| at the tolerance, the iteration
-  count within 2% of the oracle's. CG(32) iterates are held at the whole-solve level only:
+  and Y~^T componentwise; one application of the correction with CG(8), plain and Jacobi,
+  element by element; four Algorithm 1 steps with each against the oracle's (x to 1e-8); the
+  whole solve in the headline configuration: converged, the true ||A^T r|| at the tolerance,
+  the iteration count within 2% of the oracle's. Longer CG runs are held at the whole-solve level only:
   past some 16 CG steps the iterates depend on the rounding of the inner products well
   beyond eps, on the oracle as on the GPU. The Chebyshev M_b (a fixed polynomial, degree
   80 here): one application element by element and four LSQR steps;
@@ -137,7 +138,14 @@ def test_c4_fp32_preconditioner(gpu_lib):
 
 # ------------------------------------------------------------------ with the A2 correction
 
-HEAD = dict(mu=1.0, form=1, smode=3, cg_steps=32, ystore=1, ytau=1e-2)  # the headline configuration
+HEAD = dict(mu=1.0, form=1, smode=3, cg_steps=20, ystore=1, ytau=1e-2, cg_precond=1)  # the headline configuration
+
+
+def with_jacobi(F, steps):
+    """The oracle's factors with `steps` Jacobi-preconditioned CG steps on S~."""
+    import dataclasses
+
+    return dataclasses.replace(F, cg_steps=steps, cg_jacobi=True, S_diag=oracle.S_diagonal(F.Y))
 
 
 @pytest.fixture(scope="module")
@@ -171,25 +179,28 @@ def test_c2_products_with_Y(gpu_lib, c2y):
     S.close()
 
 
-def test_c2_correction_apply_and_four_steps(gpu_lib, c2y):
+@pytest.mark.parametrize("precond", [0, 1])
+def test_c2_correction_apply_and_four_steps(gpu_lib, c2y, precond):
     R = gpu_lib
     import torch
 
     prob, F = c2y
-    S = R.Solver.from_problem(prob, **dict(HEAD, cg_steps=8)).upload()
+    if precond:
+        F = with_jacobi(F, 8)
+    S = R.Solver.from_problem(prob, **dict(HEAD, cg_steps=8, cg_precond=precond)).upload()
     z = np.random.default_rng(52).standard_normal(prob.n)
     h = torch.empty(prob.n, dtype=torch.float64, device="cuda")
     assert R.rsilu_apply_z(S.h, torch.from_numpy(z).cuda(), h) == R.OK
     ratio = elementwise(h.cpu().numpy(), oracle.apply_alg2(F, z), 1e-8, 1e-11)
     S.close()
-    S = R.Solver.from_problem(prob, maxit=4, **dict(HEAD, cg_steps=8)).upload()
+    S = R.Solver.from_problem(prob, maxit=4, **dict(HEAD, cg_steps=8, cg_precond=precond)).upload()
     x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=1e-14)
     got = x.cpu().numpy()
     S.close()
     res = oracle.pcgls(F, prob.b, tol=1e-14, maxit=4, form="alg2")
     err = np.linalg.norm(got - res.x) / np.linalg.norm(res.x)
-    print("grid 600000 x 400000, CG(8) correction: apply elementwise ratio %.2e; 4 steps x rel diff %.2e" % (
-        ratio, err))
+    print("grid 600000 x 400000, %sCG(8) correction: apply elementwise ratio %.2e; 4 steps x rel diff %.2e" % (
+        "Jacobi " if precond else "", ratio, err))
     assert ratio <= 1.0
     assert it == res.iters == 4 and err <= 1e-8
     assert abs(atr - res.atr_norm) <= 1e-6 * res.atr_norm
@@ -206,11 +217,11 @@ def test_c2_headline_whole_solve(gpu_lib, c2y):
     x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=tol)
     got = x.cpu().numpy()
     S.close()
-    res = oracle.pcgls(dataclasses.replace(F, cg_steps=32), prob.b, tol=tol, maxit=2000, form="alg2")
+    res = oracle.pcgls(with_jacobi(F, 20), prob.b, tol=tol, maxit=2000, form="alg2")
     A = prob.scipy()
     atb = np.linalg.norm(A.T @ prob.b)
     ball = np.linalg.norm(A.T @ (A @ (got - res.x))) / atb
-    print("grid 600000 x 400000, CG(32) correction: gpu its %d, oracle its %d, true rel %.2e, ball %.2e" % (
+    print("grid 600000 x 400000, Jacobi CG(20) correction: gpu its %d, oracle its %d, true rel %.2e, ball %.2e" % (
         it, res.iters, rel, ball))
     assert code == R.OK and res.status == "ok"
     assert abs(it - res.iters) <= max(1, int(0.02 * res.iters))

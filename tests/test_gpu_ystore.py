@@ -231,3 +231,72 @@ def test_graph_replays_equal_eager_explicit_Y(gpu_lib):
         assert np.array_equal(to_host(x2), outs[-1][0]) and it2 == it
         S.close()
     assert all(np.array_equal(o[0], outs[0][0]) and o[1] == outs[0][1] for o in outs)
+
+
+# ------------------------------------------------------------------ Jacobi-preconditioned CG
+
+
+def jacobi_solver(R, prob, steps, **kw):
+    return solver(R, prob, "cg", steps=steps, cg_precond=R.CG_JACOBI, **kw)
+
+
+def jacobi_factors(prob, steps):
+    return oracle.factor_problem(prob, mu=1.0, smode="cg", cg_steps=steps, ystore=True, ytau=1e-2, cg_jacobi=True)
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("mode", ["hybrid", "levels"])
+def test_apply_jacobi_cg(gpu_lib, name, mode):
+    """One Algorithm 2 application with 8 Jacobi-preconditioned CG steps on S~ against the
+    oracle's, element by element (the bounds of the plain CG(8) application)."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    trsv = {"hybrid": R.TRSV_HYBRID, "levels": R.TRSV_LEVELS}[mode]
+    S = jacobi_solver(R, prob, 8, trsv=trsv)
+    F = jacobi_factors(prob, 8)
+    z = np.random.default_rng(25).standard_normal(prob.n)
+    h = empty(prob.n)
+    assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
+    want = oracle.apply_alg2(F, z)
+    rtol, atol = (1e-8, 1e-11) if name != "c3-mini" else (1e-6, 1e-9)
+    ratio = elementwise(to_host(h), want, rtol, atol)
+    print(f"{name} Jacobi CG(8) {mode}: elementwise ratio {ratio:.2e}")
+    assert ratio <= 1.0
+    S.close()
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_pcgls_jacobi_cg_steps(gpu_lib, name):
+    """Algorithm 1 with Jacobi CG(8): four steps, step for step."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    S = jacobi_solver(R, prob, 8, maxit=4)
+    x, code, it, atr, rel = S.solve(to_dev(prob.b), tol=1e-14)
+    got = to_host(x)
+    S.close()
+    res = oracle.pcgls(jacobi_factors(prob, 8), prob.b, tol=1e-14, maxit=4, form="alg2")
+    err = np.linalg.norm(got - res.x) / np.linalg.norm(res.x)
+    print(f"{name} Jacobi CG(8), 4 steps: its {it} / {res.iters}, x rel diff {err:.2e}")
+    assert it == res.iters
+    assert err <= (1e-6 if name == "c3-mini" else 1e-8)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2-small"])
+def test_pcgls_jacobi_cg20_converges_like_oracle(gpu_lib, name):
+    """The benchmarked M_b (20 Jacobi-preconditioned CG steps): iterations within 2% of the
+    oracle's, the true ||A^T r|| at the tolerance, the solution in its stop-test ball."""
+    R = gpu_lib
+    prob = PROBLEMS[name]()
+    tol = 1e-8
+    S = jacobi_solver(R, prob, 20, maxit=2000)
+    x, code, it, atr, rel = S.solve(to_dev(prob.b), tol=tol)
+    got = to_host(x)
+    S.close()
+    res = oracle.pcgls(jacobi_factors(prob, 20), prob.b, tol=tol, maxit=2000, form="alg2")
+    A = prob.scipy()
+    atb = np.linalg.norm(A.T @ prob.b)
+    ball = np.linalg.norm(A.T @ (A @ (got - res.x))) / atb
+    print(f"{name} Jacobi CG(20): its {it} / {res.iters}, rel {rel:.2e}, ball {ball:.2e}")
+    assert code == R.OK and res.status == "ok"
+    assert abs(it - res.iters) <= max(1, int(0.02 * res.iters))
+    assert rel <= 2 * tol and ball <= 4 * tol

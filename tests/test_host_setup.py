@@ -550,3 +550,21 @@ def test_sweep_schemes_reported():
         assert masks(long_factor, R.SWEEP_AUTO, prec) == seg
         g = masks(grid, R.SWEEP_AUTO, prec)
         assert all(m & 0x7F == 2 for m in g) and g[0] & 0x80 and g[3] & 0x80
+
+
+def test_jacobi_cg_settings():
+    """The Jacobi-preconditioned CG steps need the CG M_b and the explicit Y~; its diagonal is
+    that of the oracle's (1 + squared row norms of Y~, here in Y~'s device row order)."""
+    p = gen.by_name("c1")
+    ok = R.rsilu_params_default(mu=1.0, smode=R.S_CG, form=R.FORM_ALG2, ystore=R.Y_EXPLICIT, cg_precond=R.CG_JACOBI)
+    code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, ok)
+    assert code == R.OK
+    R.rsilu_destroy(h)
+    for kw in (dict(ystore=R.Y_IMPLICIT), dict(smode=R.S_CHEB), dict(smode=R.S_IDENTITY), dict(cg_precond=2),
+               dict(cg_precond=-1)):
+        prm = R.rsilu_params_default(mu=1.0, smode=R.S_CG, form=R.FORM_ALG2, ystore=R.Y_EXPLICIT,
+                                     cg_precond=R.CG_JACOBI)
+        for k_, v_ in kw.items():
+            setattr(prm, k_, v_)
+        code, h = R.rsilu_factor(p.m, p.n, p.rowptr, p.col, p.val, prm)
+        assert code == R.EINVAL and h is None, kw
