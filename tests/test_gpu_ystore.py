@@ -283,7 +283,7 @@ def test_pcgls_jacobi_cg_steps(gpu_lib, name):
 
 @pytest.mark.parametrize("name", ["c1", "c2-small"])
 def test_pcgls_jacobi_cg20_converges_like_oracle(gpu_lib, name):
-    """The benchmarked M_b (20 Jacobi-preconditioned CG steps): iterations within 2% of the
+    """20 Jacobi-preconditioned CG steps (the benchmark takes 24 with ytau 5e-2): iterations within 2% of the
     oracle's, the true ||A^T r|| at the tolerance, the solution in its stop-test ball."""
     R = gpu_lib
     prob = PROBLEMS[name]()
