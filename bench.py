@@ -41,11 +41,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", help="c2 (grid 600000 x 400000), c2-small, c1, c3-mini")
+    ap.add_argument("--workload", default="c2", help="c2 (grid 600000 x 400000), c2-seed<k> (the same with seed k), c2-small, c1, c3-mini")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--mu", type=float, default=1.0)
     ap.add_argument("--tau", type=float, default=1e-2)
-    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--p", type=int, default=20, help="ILUP fill per row (the experiments of Section 5 use 10; more fill pays on the grid workload)")
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--smode", default="cg", choices=["cg", "cheb", "none", "identity", "dense", "auto"],
                     help="S^ / M_b: CG steps on S~ (default), a Chebyshev polynomial in S~, none (A1 only), "

@@ -355,6 +355,9 @@ def by_name(name):
         return tiny_c1()
     if name == "c2":
         return grid_c2()
+    if name.startswith("c2-seed"):
+        # the same recipe and size with another seed (a second draw of the workload)
+        return grid_c2(seed=int(name[len("c2-seed"):]))
     if name == "c3":
         return sparse_dense_c3()
     if name == "c4":

@@ -1,22 +1,22 @@
 """Parity at the full sizes of the benchmarked configurations, in the launch configurations
 bench.py times: Algorithm 1 with Algorithm 2 and the M_b correction by 24 Jacobi-preconditioned
-CG steps on S~ through the explicit Y~ (entries below 5e-2 dropped; the headline), and beside it the A1-only preconditioner
-with LSQR.
+CG steps on S~ through the explicit Y~ (entries below 5e-2 dropped) on ILUP(20, 1e-2) factors (the
+headline), and beside it the A1-only preconditioner with LSQR.
 
-* grid workload, 600000 x 400000, with the correction: the products with the explicit Y~
-  and Y~^T componentwise; one application of the correction with CG(8), plain and Jacobi,
-  element by element; four Algorithm 1 steps with each against the oracle's (x to 1e-8); the
-  whole solve in the headline configuration: converged, the true ||A^T r|| at the tolerance,
+* grid workload, 600000 x 400000, with the correction: on ILUP(10, 1e-2) factors, the products
+  with the explicit Y~ and Y~^T componentwise, one application of the correction with CG(8),
+  plain and Jacobi, element by element, and four Algorithm 1 steps with each against the
+  oracle's (x to 1e-8); the whole solve in the headline configuration: converged, the true ||A^T r|| at the tolerance,
   the iteration count within 2% of the oracle's. Longer CG runs are held at the whole-solve level only:
   past some 16 CG steps the iterates depend on the rounding of the inner products well
   beyond eps, on the oracle as on the GPU. The Chebyshev M_b (a fixed polynomial, degree
   80 here): one application element by element and four LSQR steps;
 
-* grid workload, 600000 x 400000, A1 only: every triangular solve against the oracle's
-  substitutions (componentwise backward error, forward difference); four LSQR steps
+* grid workload, 600000 x 400000, A1 only (the ILUP(20, 1e-2) factors): every triangular solve
+  against the oracle's substitutions (componentwise backward error, forward difference); four LSQR steps
   against the oracle's; the whole solve against the oracle's (iteration counts within 2%,
   both solutions in the same stop-test ball);
-* the same generator at 1500000 x 1000000 with the FP32 preconditioner: the whole solve
+* the same generator at 1500000 x 1000000 with the FP32 preconditioner (ILUP(10, 1e-2)): the whole solve
   reaches the tolerance on the true residual, and lies in the stop-test ball of the FP64
   path on the same GPU and of the FP64 oracle (whose iteration count the FP64 path matches
   within 2%).
@@ -32,12 +32,13 @@ pytestmark = pytest.mark.gpu
 
 EPS = np.finfo(np.float64).eps / 2
 PARAMS = dict(mu=1.0, smode=2, form=1, krylov=1)  # S^ none, Algorithm 2 form, LSQR
+A1ONLY = dict(PARAMS, p=20)  # the benchmark's A1-only line: the headline's ILUP(20, 1e-2) factors
 
 
 @pytest.fixture(scope="module")
 def c2():
     prob = gen.by_name("c2")
-    F = oracle.factor_problem(prob, mu=1.0, smode="none")
+    F = oracle.factor_problem(prob, p=20, mu=1.0, smode="none")
     return prob, F
 
 
@@ -46,7 +47,7 @@ def test_c2_triangular_solves(gpu_lib, c2):
     import torch
 
     prob, F = c2
-    S = R.Solver.from_problem(prob, **PARAMS).upload()
+    S = R.Solver.from_problem(prob, **A1ONLY).upload()
     rhs = np.random.default_rng(21).standard_normal(prob.n)
     for which, T, diag, lower in [(R.T_L1, F.L1, None, True), (R.T_L1T, F.L1T, None, False),
                                   (R.T_U, F.U, F.Udiag, False), (R.T_UT, F.UT, F.Udiag, True)]:
@@ -69,7 +70,7 @@ def test_c2_four_lsqr_steps(gpu_lib, c2):
     import torch
 
     prob, F = c2
-    S = R.Solver.from_problem(prob, maxit=4, **PARAMS).upload()
+    S = R.Solver.from_problem(prob, maxit=4, **A1ONLY).upload()
     x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=1e-14)
     got = x.cpu().numpy()
     S.close()
@@ -85,7 +86,7 @@ def test_c2_whole_solve(gpu_lib, c2):
 
     prob, F = c2
     tol = 1e-8
-    S = R.Solver.from_problem(prob, maxit=2000, **PARAMS).upload()
+    S = R.Solver.from_problem(prob, maxit=2000, **A1ONLY).upload()
     x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=tol)
     got = x.cpu().numpy()
     S.close()
@@ -97,7 +98,7 @@ def test_c2_whole_solve(gpu_lib, c2):
     assert np.linalg.norm(A.T @ (prob.b - A @ got)) <= 2 * tol * atb
     e = got - res.x
     assert np.linalg.norm(A.T @ (A @ e)) <= 4 * tol * atb
-    print("grid 600000 x 400000: gpu its %d, oracle its %d, ||A^T A e|| / ||A^T b|| = %.2e" % (
+    print("grid 600000 x 400000, A1 only: gpu its %d, oracle its %d, ||A^T A e|| / ||A^T b|| = %.2e" % (
         it, res.iters, np.linalg.norm(A.T @ (A @ e)) / atb))
 
 
@@ -138,8 +139,8 @@ def test_c4_fp32_preconditioner(gpu_lib):
 
 # ------------------------------------------------------------------ with the A2 correction
 
-HEAD = dict(mu=1.0, form=1, smode=3, cg_steps=24, ystore=1, ytau=5e-2, cg_precond=1)  # the headline configuration
-STEP = dict(HEAD, ytau=1e-2)  # the same with the Y~ of the step-for-step checks
+HEAD = dict(p=20, mu=1.0, form=1, smode=3, cg_steps=24, ystore=1, ytau=5e-2, cg_precond=1)  # the headline configuration
+STEP = dict(HEAD, p=10, ytau=1e-2)  # the factors and Y~ of the step-for-step checks (the oracle fixture's)
 
 
 def with_jacobi(F, steps):
@@ -213,7 +214,7 @@ def test_c2_headline_whole_solve(gpu_lib):
     import torch
 
     prob = gen.by_name("c2")
-    F = oracle.factor_problem(prob, mu=1.0, smode="cg", cg_steps=24, ystore=True, ytau=5e-2, cg_jacobi=True)
+    F = oracle.factor_problem(prob, p=20, mu=1.0, smode="cg", cg_steps=24, ystore=True, ytau=5e-2, cg_jacobi=True)
     tol = 1e-8
     S = R.Solver.from_problem(prob, maxit=2000, **HEAD).upload()
     x, code, it, atr, rel = S.solve(torch.from_numpy(prob.b).cuda(), tol=tol)
@@ -223,7 +224,7 @@ def test_c2_headline_whole_solve(gpu_lib):
     A = prob.scipy()
     atb = np.linalg.norm(A.T @ prob.b)
     ball = np.linalg.norm(A.T @ (A @ (got - res.x))) / atb
-    print("grid 600000 x 400000, Jacobi CG(24) correction (ytau 5e-2): gpu its %d, oracle its %d, true rel %.2e, ball %.2e" % (
+    print("grid 600000 x 400000, ILUP(20), Jacobi CG(24) correction (ytau 5e-2): gpu its %d, oracle its %d, true rel %.2e, ball %.2e" % (
         it, res.iters, rel, ball))
     assert code == R.OK and res.status == "ok"
     assert abs(it - res.iters) <= max(1, int(0.02 * res.iters))
