@@ -409,6 +409,12 @@ typedef struct {
 } rsilu_profile_t;
 
 rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable);
+/* The same with only the classes whose bit is set in `mask` timed (bit i: class i; 0 turns
+ * profiling off; rsilu_set_profiling(h, 1) sets every bit). Each timed launch group adds two
+ * event records to the stream, so timing only the classes a caller needs keeps the solve's
+ * own time close to that of an unprofiled solve. Resets the counters like
+ * rsilu_set_profiling; EINVAL for a NULL handle or a bit at or above RSILU_PROF_COUNT. */
+rsilu_status_t rsilu_set_profiling_mask(rsilu_handle_t h, uint32_t mask);
 rsilu_status_t rsilu_get_profile(rsilu_handle_t h, rsilu_profile_t *out);
 
 /* Release the handle's host memory and any HIP objects it created (not the

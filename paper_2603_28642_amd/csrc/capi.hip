@@ -54,7 +54,7 @@ class ProfScope {
 public:
     ProfScope(Ctx &c, hipStream_t s, int cls, double bytes = 0.0) : c_(c), s_(s), cls_(cls), bytes_(bytes)
     {
-        if (!c_.prof) return;
+        if (!c_.prof || !((c_.prof_mask >> cls_) & 1u)) return;
         while (c_.ev_next + 2 > c_.ev_pool.size()) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return;
@@ -1154,8 +1154,15 @@ rsilu_status_t rsilu_apply_z(rsilu_handle_t h, const double *z, double *hout, hi
 
 rsilu_status_t rsilu_set_profiling(rsilu_handle_t h, int32_t enable)
 {
+    return rsilu_set_profiling_mask(h, enable ? (1u << RSILU_PROF_COUNT) - 1u : 0u);
+}
+
+rsilu_status_t rsilu_set_profiling_mask(rsilu_handle_t h, uint32_t mask)
+{
     if (!h) return RSILU_EINVAL;
-    h->prof = enable != 0;
+    if (mask >> RSILU_PROF_COUNT) return RSILU_EINVAL;
+    h->prof_mask = mask;
+    h->prof = mask != 0;
     h->ev_open.clear();
     h->ev_next = 0;
     for (int i = 0; i < RSILU_PROF_COUNT; ++i) {

@@ -176,8 +176,10 @@ struct Ctx {
     void *graph_exec = nullptr;  // hipGraphExec_t of `poll` captured iterations (per upload)
     void *cap_stream = nullptr;  // hipStream_t the iterations are captured on
 
-    // kernel timing (rsilu_set_profiling)
+    // kernel timing (rsilu_set_profiling, rsilu_set_profiling_mask): prof is set when any
+    // class is timed, prof_mask holds the timed classes (bit i: class i)
     bool prof = false;
+    uint32_t prof_mask = 0;
     std::vector<void *> ev_pool;                // hipEvent_t
     struct EvRec {
         int cls, idx, iter;  // class, first of two events, iteration it belongs to (0 = init)

@@ -35,7 +35,7 @@ EXPORTS = [
     "rsilu_get_stats",
     "rsilu_get_perm", "rsilu_get_colnorm", "rsilu_factor_nnz", "rsilu_get_factor", "rsilu_get_levels",
     "rsilu_solve", "rsilu_spmv", "rsilu_trsv", "rsilu_apply", "rsilu_apply_z", "rsilu_set_profiling",
-    "rsilu_get_profile",
+    "rsilu_set_profiling_mask", "rsilu_get_profile",
     "rsilu_destroy", "rsilu_status_string",
     "rsilu_server_create", "rsilu_server_submit", "rsilu_server_poll", "rsilu_server_drain", "rsilu_server_destroy",
     "rsilu_batch_tiles", "rsilu_batch_accepts", "rsilu_batch_create", "rsilu_batch_solve", "rsilu_batch_solve_auto", "rsilu_batch_destroy",
@@ -168,6 +168,8 @@ def lib():
         L.rsilu_apply_z.restype = ctypes.c_int
         L.rsilu_set_profiling.argtypes = [P, I32]
         L.rsilu_set_profiling.restype = ctypes.c_int
+        L.rsilu_set_profiling_mask.argtypes = [P, ctypes.c_uint32]
+        L.rsilu_set_profiling_mask.restype = ctypes.c_int
         L.rsilu_get_profile.argtypes = [P, ctypes.POINTER(rsilu_profile_t)]
         L.rsilu_get_profile.restype = ctypes.c_int
         L.rsilu_destroy.argtypes = [P]
@@ -368,6 +370,14 @@ def rsilu_apply_z(h, z_dev, h_dev, stream=None):
 
 def rsilu_set_profiling(h, enable):
     return lib().rsilu_set_profiling(h, 1 if enable else 0)
+
+
+def rsilu_set_profiling_mask(h, names):
+    """Time only the named classes (names from PROF_NAMES; empty: profiling off)."""
+    mask = 0
+    for name in names:
+        mask |= 1 << PROF_NAMES.index(name)
+    return lib().rsilu_set_profiling_mask(h, mask)
 
 
 def rsilu_get_profile(h):

@@ -206,6 +206,11 @@ def test_device_calls_need_upload():
     assert R.lib().rsilu_spmv(h, 0, dummy, ctypes.c_void_p(0x2000), None) == R.ESTATE
     assert R.lib().rsilu_upload(h, ctypes.c_void_p(0x1001), 1 << 30, None) == R.EINVAL  # misaligned
     assert R.lib().rsilu_upload(h, ctypes.c_void_p(0x1000), 16, None) == R.ENOMEM  # too small
+    # profiling classes: bits below RSILU_PROF_COUNT only
+    assert R.lib().rsilu_set_profiling_mask(h, 1 << len(R.PROF_NAMES)) == R.EINVAL
+    assert R.lib().rsilu_set_profiling_mask(None, 1) == R.EINVAL
+    assert R.rsilu_set_profiling_mask(h, R.PROF_NAMES) == R.OK
+    assert R.rsilu_set_profiling_mask(h, []) == R.OK
     R.rsilu_destroy(h)
     R.rsilu_destroy(None)
 
