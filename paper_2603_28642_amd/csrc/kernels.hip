@@ -1100,10 +1100,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                     const int c = ca + tid;
                     const bool has = c < cb;
                     const int cc = min(c, cb - 1);
+                    // LDS returns in issue order: the slot words first, then the
+                    // gathers they address, and only then the row data that the
+                    // row's last lane needs after the scan.
                     const uint2 sl0 = eslot4[cc];
+                    const int cr = crow[cc];
                     T v0, v1, v2, v3;
                     load_chunk<T>(evals, cc, v0, v1, v2, v3);
-                    const int cr = crow[cc];
+                    const uint2 sl = has ? sl0 : make_uint2(zzs, zzs);
+                    const T g0 = xw[sl.x & 0xffffu], g1 = xw[sl.x >> 16];
+                    const T g2 = xw[sl.y & 0xffffu], g3 = xw[sl.y >> 16];
+                    __builtin_amdgcn_sched_barrier(0);
                     const int key = has ? (cr & 0x7fff) : 0xffff;
                     const bool last = has && (cr & 0x8000) != 0;
                     const int pp = min(cr & 0x7fff, npos - 1);
@@ -1111,11 +1118,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_trsv_sweep(const unsigned cha
                     const T dgv = hd ? dg[pp] : (T)1;
                     const T add = al[pp];
                     const int row = rowid[pp];
-                    const uint2 sl = has ? sl0 : make_uint2(zzs, zzs);
-                    T t = v0 * xw[sl.x & 0xffffu];
-                    t += v1 * xw[sl.x >> 16];
-                    t += v2 * xw[sl.y & 0xffffu];
-                    t += v3 * xw[sl.y >> 16];
+                    T t = v0 * g0;
+                    t += v1 * g1;
+                    t += v2 * g2;
+                    t += v3 * g3;
                     T v = has ? t : (T)0;
                     v = seg_scan<T, SCHEME == kSchemeSegmentedWide>(v, key, span);
                     if (last) {
