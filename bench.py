@@ -9,7 +9,7 @@ in HBM to x in HBM with the iteration count and ||A^T r|| on the host. Setup
 The default configuration is the paper's method with the A2 correction in every
 iteration: Algorithm 1 (left-preconditioned CGLS) with the preconditioner
 applied by Algorithm 2 with k = n, M_a = (L1 U)^T (L1 U) from the ILUP(20, 1e-2)
-factors (mu = 1), and M_b given by 24 CG steps on S~ = I + Y~ Y~^T preconditioned by
+factors (mu = 1), and M_b given by 28 CG steps on S~ = I + Y~ Y~^T preconditioned by
 diag(S~), with Y~ = L2 L1^{-1} stored explicitly as a sparse matrix (Section 3.2;
 entries below 5e-2 dropped). Beside it the JSON line carries the A1-only preconditioner
 (no M_b correction, LSQR; the Lauchli-type preconditioner of the related work)
@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--smode", default="cg", choices=["cg", "cheb", "none", "identity", "dense", "auto"],
                     help="S^ / M_b: CG steps on S~ (default), a Chebyshev polynomial in S~, none (A1 only), "
                          "identity, dense S~")
-    ap.add_argument("--cg-steps", type=int, default=24)
+    ap.add_argument("--cg-steps", type=int, default=28)
     ap.add_argument("--cg-precond", default="jacobi", choices=["jacobi", "none"],
                     help="preconditioner of the CG steps on S~: diag(S~) (needs the explicit Y~) or none")
     ap.add_argument("--poly-degree", type=int, default=0, help="Chebyshev degree (0: automatic)")
