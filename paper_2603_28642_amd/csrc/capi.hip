@@ -286,11 +286,15 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
     const bool jac = c.lay.cg_d != 0;
     const double *dS = jac ? at<double>(c, c.lay.cg_d) : nullptr;
     double *z = jac ? at<double>(c, c.lay.cg_z) : res;
+    // per-block partials: (p, q) of the current step, and (res, z) of two steps in turn
+    // (step i writes rr[i & 1] and reads the previous step's rr[(i + 1) & 1])
+    double *pq = at<double>(c, c.lay.cg_part);
+    double *rr[2] = {pq + kCgParts, pq + 2 * kCgParts};
     if (jac)
         launch_pcg_init(s, k, W.u, dS, w, res, z, p, done);
     else
         launch_cg_init(s, k, W.u, w, res, p, done);
-    launch_dot(s, k, res, z, FIN_CG_RR0, P.partials, P.st, done);
+    launch_cg_dot(s, k, res, z, rr[1], done);
     for (int32_t i = 0; i < c.prm.cg_steps; ++i) {
         if (yexplicit(c)) {
             // q = p + Y~ (Y~^T p)
@@ -305,16 +309,17 @@ void cg_solve_S(Ctx &c, hipStream_t s, const Ptrs &P, const Pre<double> &W, cons
                          RSILU_PROF_TRSV_L1);
             launch_spmv<double>(s, W.L2, P.pL2, W.s2, q, p, EPI_ADD, FIN_NONE, P.partials, W.segpart, P.st, done);
         }
-        launch_dot(s, k, p, q, FIN_CG_ALPHA, P.partials, P.st, done);
+        launch_cg_dot(s, k, p, q, pq, done);
+        double *rr_old = rr[(i + 1) & 1], *rr_new = rr[i & 1];
         if (i + 1 < c.prm.cg_steps) {
-            // the update with the partials of res . z, then beta; p = z + beta p
+            // alpha, the update with the partials of res . z; then beta and p = z + beta p
             if (jac)
-                launch_pcg_update_dot(s, k, p, q, dS, w, res, z, P.partials, P.st, done);
+                launch_pcg_update_dot(s, k, p, q, dS, w, res, z, pq, rr_old, rr_new, done);
             else
-                launch_cg_update_dot(s, k, p, q, w, res, P.partials, P.st, done);
-            launch_cg_dir(s, k, z, p, P.st, done);
+                launch_cg_update_dot(s, k, p, q, w, res, pq, rr_old, rr_new, done);
+            launch_cg_dir(s, k, z, p, rr_old, rr_new, done);
         } else {
-            launch_cg_update(s, k, p, q, w, res, P.st, done);
+            launch_cg_update(s, k, p, q, w, res, pq, rr_old, done);
         }
     }
     launch_copy(s, k, w, W.u, done);

@@ -124,6 +124,7 @@ struct Layout {
     size_t cg_w = 0, cg_r = 0, cg_p = 0, cg_q = 0;  // CG or Chebyshev steps on S~ (m - n each)
     size_t cheb = 0;  // Chebyshev step coefficients c1[K] then c2[K] (read by the batched kernel)
     size_t cg_d = 0, cg_z = 0;  // Jacobi CG steps: diag(S~) and the preconditioned residual (m - n each)
+    size_t cg_part = 0;  // CG steps: per-block partials of (p, q) and of two steps' (res, z), kCgParts each
     size_t l_v = 0, l_mv = 0, l_w = 0;              // LSQR: v, M v, w (n each)
     size_t partials = 0;  // reduction partials
     int32_t npartials = 0;

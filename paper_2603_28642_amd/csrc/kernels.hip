@@ -108,6 +108,30 @@ __device__ __forceinline__ double block_sum256(double v, double *lds4)
     return s;
 }
 
+// The sum of nparts per-block partials, formed exactly as k_reduce_fin forms it, returned
+// to every thread of the block (lds5: 5 doubles).
+__device__ __forceinline__ double block_total_of(const double *__restrict__ parts, int nparts, double *lds5)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kBlock) s += parts[k];
+    const double t = block_sum256(s, lds5);
+    if (threadIdx.x == 0) lds5[4] = t;
+    __syncthreads();
+    return lds5[4];
+}
+
+// The CG scalars on S~ from the inner products: alpha = rr / (p, q), 0 when either is not
+// positive or not finite; beta = rr_new / rr_old, 0 when rr_old is not positive or rr_new
+// not finite.
+__device__ __forceinline__ double cg_alpha_of(double rr, double pq)
+{
+    return (rr > 0.0 && pq > 0.0 && isfinite(pq) && isfinite(rr)) ? rr / pq : 0.0;
+}
+__device__ __forceinline__ double cg_beta_of(double rr_old, double rr_new)
+{
+    return (rr_old > 0.0 && isfinite(rr_new)) ? rr_new / rr_old : 0.0;
+}
+
 __device__ void apply_fin(Fin fin, double total, DevState *st)
 {
     switch (fin) {
@@ -167,9 +191,6 @@ __device__ void apply_fin(Fin fin, double total, DevState *st)
         break;
     case FIN_ATR:
         st->atr = sqrt(total);
-        break;
-    case FIN_CG_RR0:
-        st->cg_rr = total;
         break;
     case FIN_L_BETA1: {
         const double b1 = sqrt(total);
@@ -250,13 +271,6 @@ __device__ void apply_fin(Fin fin, double total, DevState *st)
         }
         break;
     }
-    case FIN_CG_ALPHA:
-        st->cg_alpha = (st->cg_rr > 0.0 && total > 0.0 && isfinite(total) && isfinite(st->cg_rr)) ? st->cg_rr / total : 0.0;
-        break;
-    case FIN_CG_BETA:
-        st->cg_beta = (st->cg_rr > 0.0 && isfinite(total)) ? total / st->cg_rr : 0.0;
-        st->cg_rr = total;
-        break;
     default:
         break;
     }
@@ -642,13 +656,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int32_t k, const double *__r
     }
 }
 
+// The CG steps' scalars are formed by every block from the per-block partials of the
+// previous launches (pq: (p, q); rr_old / rr_new: (res, z) of the previous / this step), in
+// the order of k_reduce_fin, so no single-block launch sits between the steps' kernels.
 __global__ __launch_bounds__(kBlock) void k_cg_update(int32_t k, const double *__restrict__ p,
                                                       const double *__restrict__ q, double *__restrict__ w,
-                                                      double *__restrict__ res, const DevState *st,
-                                                      const int32_t *done)
+                                                      double *__restrict__ res, int32_t nparts,
+                                                      const double *__restrict__ pq_parts,
+                                                      const double *__restrict__ rr_parts, const int32_t *done)
 {
+    __shared__ double lds_a[5], lds_b[5];
     if (stop_now(done)) return;
-    const double a = st->cg_alpha;
+    const double a = cg_alpha_of(block_total_of(rr_parts, nparts, lds_b), block_total_of(pq_parts, nparts, lds_a));
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
         w[i] = w[i] + a * p[i];
         res[i] = res[i] - a * q[i];
@@ -659,12 +678,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int32_t k, const double *_
 // k_dot, so the sums are those of a separate dot product)
 __global__ __launch_bounds__(kBlock) void k_cg_update_dot(int32_t k, const double *__restrict__ p,
                                                           const double *__restrict__ q, double *__restrict__ w,
-                                                          double *__restrict__ res, double *__restrict__ partials,
-                                                          const DevState *st, const int32_t *done)
+                                                          double *__restrict__ res, int32_t nparts,
+                                                          const double *__restrict__ pq_parts,
+                                                          const double *__restrict__ rr_old, double *__restrict__ partials,
+                                                          const int32_t *done)
 {
     __shared__ double lds4[4];
+    __shared__ double lds_a[5], lds_b[5];
     if (stop_now(done)) return;
-    const double a = st->cg_alpha;
+    const double a = cg_alpha_of(block_total_of(rr_old, nparts, lds_b), block_total_of(pq_parts, nparts, lds_a));
     double s = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
         w[i] = w[i] + a * p[i];
@@ -697,12 +719,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int32_t k, const double *__
 __global__ __launch_bounds__(kBlock) void k_pcg_update_dot(int32_t k, const double *__restrict__ p,
                                                            const double *__restrict__ q, const double *__restrict__ d,
                                                            double *__restrict__ w, double *__restrict__ res,
-                                                           double *__restrict__ z, double *__restrict__ partials,
-                                                           const DevState *st, const int32_t *done)
+                                                           double *__restrict__ z, int32_t nparts,
+                                                           const double *__restrict__ pq_parts,
+                                                           const double *__restrict__ rr_old, double *__restrict__ partials,
+                                                           const int32_t *done)
 {
     __shared__ double lds4[4];
+    __shared__ double lds_a[5], lds_b[5];
     if (stop_now(done)) return;
-    const double a = st->cg_alpha;
+    const double a = cg_alpha_of(block_total_of(rr_old, nparts, lds_b), block_total_of(pq_parts, nparts, lds_a));
     double s = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
         w[i] = w[i] + a * p[i];
@@ -717,10 +742,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update_dot(int32_t k, const doub
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_dir(int32_t k, const double *__restrict__ res, double *__restrict__ p,
-                                                   const DevState *st, const int32_t *done)
+                                                   int32_t nparts, const double *__restrict__ rr_old,
+                                                   const double *__restrict__ rr_new, const int32_t *done)
 {
+    __shared__ double lds_a[5], lds_b[5];
     if (stop_now(done)) return;
-    const double bt = st->cg_beta;
+    const double bt = cg_beta_of(block_total_of(rr_old, nparts, lds_a), block_total_of(rr_new, nparts, lds_b));
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) p[i] = res[i] + bt * p[i];
 }
 
@@ -1503,20 +1530,28 @@ void launch_pcg_init(hipStream_t s, int32_t k, const double *u, const double *d,
     hipLaunchKernelGGL(k_pcg_init, dim3(grid_for(k)), dim3(kBlock), 0, s, k, u, d, w, res, z, p, done);
 }
 
-void launch_pcg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, const double *d, double *w,
-                           double *res, double *z, double *partials, DevState *st, const int32_t *done)
+int cg_nparts(int32_t k) { return grid_for(k, kCgParts); }
+
+void launch_cg_dot(hipStream_t s, int32_t k, const double *a, const double *b, double *parts, const int32_t *done)
 {
-    const int g = grid_for(k, 2048);
-    hipLaunchKernelGGL(k_pcg_update_dot, dim3(g), dim3(kBlock), 0, s, k, p, q, d, w, res, z, partials, st, done);
-    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, FIN_CG_BETA, st, done);
+    hipLaunchKernelGGL(k_dot, dim3(cg_nparts(k)), dim3(kBlock), 0, s, k, a, b, parts, done);
+}
+
+void launch_pcg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, const double *d, double *w,
+                           double *res, double *z, const double *pq_parts, const double *rr_old, double *rr_new,
+                           const int32_t *done)
+{
+    const int g = cg_nparts(k);
+    hipLaunchKernelGGL(k_pcg_update_dot, dim3(g), dim3(kBlock), 0, s, k, p, q, d, w, res, z, g, pq_parts, rr_old,
+                       rr_new, done);
 }
 
 void launch_cg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
-                          double *partials, DevState *st, const int32_t *done)
+                          const double *pq_parts, const double *rr_old, double *rr_new, const int32_t *done)
 {
-    const int g = grid_for(k, 2048);
-    hipLaunchKernelGGL(k_cg_update_dot, dim3(g), dim3(kBlock), 0, s, k, p, q, w, res, partials, st, done);
-    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(kBlock), 0, s, g, partials, FIN_CG_BETA, st, done);
+    const int g = cg_nparts(k);
+    hipLaunchKernelGGL(k_cg_update_dot, dim3(g), dim3(kBlock), 0, s, k, p, q, w, res, g, pq_parts, rr_old, rr_new,
+                       done);
 }
 
 void launch_update(hipStream_t s, int32_t n, int32_t m, const double *p, double *xh, const double *q, double *r,
@@ -1697,14 +1732,16 @@ void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double
 }
 
 void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
-                      const DevState *st, const int32_t *done)
+                      const double *pq_parts, const double *rr_parts, const int32_t *done)
 {
-    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(k)), dim3(kBlock), 0, s, k, p, q, w, res, st, done);
+    hipLaunchKernelGGL(k_cg_update, dim3(grid_for(k)), dim3(kBlock), 0, s, k, p, q, w, res, cg_nparts(k), pq_parts,
+                       rr_parts, done);
 }
 
-void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done)
+void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const double *rr_old, const double *rr_new,
+                   const int32_t *done)
 {
-    hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(k)), dim3(kBlock), 0, s, k, res, p, st, done);
+    hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(k)), dim3(kBlock), 0, s, k, res, p, cg_nparts(k), rr_old, rr_new, done);
 }
 
 template <class T>

@@ -23,7 +23,6 @@ struct alignas(256) DevState {
     int32_t err;     // a sync-free wait exceeded its bound
     int32_t pad0;
     uint32_t ticket[4];  // chunk dispensers of the sync-free solves
-    double cg_rr, cg_alpha, cg_beta;  // scalars of the CG steps on S~
     // LSQR: alpha, beta, the Givens rotation's state and step coefficients, ||D^{-1} s||,
     // and a stop requested by the scalar step, committed after the x update
     double la, lb, rhobar, phibar, phi_rho, theta_rho, snorm;
@@ -82,9 +81,7 @@ enum Fin : int32_t {
     FIN_RHO0 = 4,   // rho = sum
     FIN_BETA = 5,   // beta = sum / rho; rho = sum
     FIN_ATR = 6,    // atr = sqrt(sum)
-    FIN_CG_RR0 = 7, // cg_rr = sum
-    FIN_CG_ALPHA = 8,  // cg_alpha = cg_rr / sum (0 when either is 0 or not finite)
-    FIN_CG_BETA = 9,   // cg_beta = sum / cg_rr (0 when cg_rr is 0); cg_rr = sum
+    // (7 to 9: unused; the CG steps on S~ form their scalars in their own kernels)
     FIN_L_BETA1 = 10,  // LSQR init: lb = phibar = sqrt(sum) (= ||P b||); 0 -> done, converged
     FIN_L_S1 = 11,     // LSQR init: snorm = sqrt(sum); nb = zn = lb snorm (= ||A^T b||)
     FIN_L_ALPHA0 = 12, // LSQR init: la = rhobar = sqrt(sum); <= 0 or not finite -> breakdown
@@ -160,20 +157,28 @@ void launch_dense_chol_solve(hipStream_t s, int32_t k, const double *lfac, doubl
 void launch_copy(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);
 // dst += src
 void launch_add(hipStream_t s, int32_t n, const double *src, double *dst, const int32_t *done);
-// CG on S~: res = p = u, w = 0; then w += alpha p, res -= alpha q; p = res + beta p
+// CG on S~: res = p = u, w = 0; then w += alpha p, res -= alpha q; p = res + beta p. The
+// scalars come from per-block partials (cg_nparts(k) of each, in arrays of kCgParts):
+// pq_parts of (p, q), rr_old / rr_new of (res, res) or (res, z) of the previous / this step,
+// each kernel forming alpha or beta itself.
+int cg_nparts(int32_t k);
+// per-block partials of a . b over k entries (cg_nparts(k) blocks)
+void launch_cg_dot(hipStream_t s, int32_t k, const double *a, const double *b, double *parts, const int32_t *done);
 void launch_cg_init(hipStream_t s, int32_t k, const double *u, double *w, double *res, double *p, const int32_t *done);
 void launch_cg_update(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
-                      const DevState *st, const int32_t *done);
-void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const DevState *st, const int32_t *done);
+                      const double *pq_parts, const double *rr_parts, const int32_t *done);
+void launch_cg_dir(hipStream_t s, int32_t k, const double *res, double *p, const double *rr_old, const double *rr_new,
+                   const int32_t *done);
 // Jacobi-preconditioned CG on S~: res = u, z = u / d, p = z, w = 0; the update with
-// z = res / d and the partials of res . z, then the step FIN_CG_BETA
+// z = res / d and the partials of res . z (into rr_new)
 void launch_pcg_init(hipStream_t s, int32_t k, const double *u, const double *d, double *w, double *res, double *z,
                      double *p, const int32_t *done);
 void launch_pcg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, const double *d, double *w,
-                           double *res, double *z, double *partials, DevState *st, const int32_t *done);
-// the update with the partials of res . res, then the step FIN_CG_BETA
+                           double *res, double *z, const double *pq_parts, const double *rr_old, double *rr_new,
+                           const int32_t *done);
+// the update with the partials of res . res (into rr_new)
 void launch_cg_update_dot(hipStream_t s, int32_t k, const double *p, const double *q, double *w, double *res,
-                          double *partials, DevState *st, const int32_t *done);
+                          const double *pq_parts, const double *rr_old, double *rr_new, const int32_t *done);
 // Chebyshev steps on S~: r = omega u, d = r / theta, w = 0; then per step, with
 // q = Y~ (Y~^T d): w += d, r -= d + q, d = c1 d + c2 r, and out = w when out is given (the
 // last step)

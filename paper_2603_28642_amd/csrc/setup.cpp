@@ -1531,6 +1531,7 @@ void plan_layout(Ctx &c)
     if (c.smode == RSILU_S_CG || c.smode == RSILU_S_CHEB)
         for (size_t *o : {&L.cg_w, &L.cg_r, &L.cg_p, &L.cg_q}) *o = b.take(sizeof(double) * std::max<size_t>(k, 1));
     if (c.smode == RSILU_S_CHEB) L.cheb = b.take(sizeof(double) * std::max<size_t>(2 * (size_t)c.cheb_K, 1));
+    if (c.smode == RSILU_S_CG) L.cg_part = b.take(sizeof(double) * 3 * (size_t)kCgParts);
     if (c.smode == RSILU_S_CG && !c.cg_diag.empty()) {
         L.cg_d = b.take(sizeof(double) * std::max<size_t>(k, 1));
         L.cg_z = b.take(sizeof(double) * std::max<size_t>(k, 1));

@@ -25,4 +25,8 @@ constexpr int kSchemeRows = 2;       // one row per thread, its chunks loaded kR
 constexpr int kSchemeSegmentedWide = 3;  // segmented, rows of up to 64 chunks (one wavefront)
 constexpr int kRowsRound = 2;
 
+// Blocks of the inner products of the CG steps on S~ (and so their per-block partials):
+// at most kCgParts; the setup reserves three such partial arrays.
+constexpr int kCgParts = 2048;
+
 }  // namespace rsilu
