@@ -148,10 +148,17 @@ def copy_probe(mib):
     src = torch.randn(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    for _ in range(3):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for i in range(3):
         dst.copy_(src)
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "copies": 3}), flush=True)
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    # read + written bytes per second of each copy: the device's copy ceiling for the roofline
+    gbs = [2.0 * n * 8 / (t * 1e-3) / 1e9 for t in ms]
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "copies": 3,
+                      "copy_ms": ms, "copy_gb_per_s": gbs}), flush=True)
 
 
 def step_bytes(st, vb=8):
