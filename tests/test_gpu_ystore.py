@@ -283,8 +283,9 @@ def test_pcgls_jacobi_cg_steps(gpu_lib, name):
 
 @pytest.mark.parametrize("name", ["c1", "c2-small"])
 def test_pcgls_jacobi_cg20_converges_like_oracle(gpu_lib, name):
-    """20 Jacobi-preconditioned CG steps (the benchmark takes 24 with ytau 5e-2): iterations within 2% of the
-    oracle's, the true ||A^T r|| at the tolerance, the solution in its stop-test ball."""
+    """20 Jacobi-preconditioned CG steps (the benchmark takes 28, with ytau 5e-2 and ILUP(20) factors):
+    iterations within 2% of the oracle's, the true ||A^T r|| at the tolerance, the solution in its
+    stop-test ball."""
     R = gpu_lib
     prob = PROBLEMS[name]()
     tol = 1e-8
@@ -300,3 +301,37 @@ def test_pcgls_jacobi_cg20_converges_like_oracle(gpu_lib, name):
     assert code == R.OK and res.status == "ok"
     assert abs(it - res.iters) <= max(1, int(0.02 * res.iters))
     assert rel <= 2 * tol and ball <= 4 * tol
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+@pytest.mark.parametrize("precond", ["plain", "jacobi"])
+def test_apply_few_cg_steps(gpu_lib, steps, precond):
+    """One Algorithm 2 application with 1, 2 (Table 3(a)) and 3 CG steps on S~, plain and
+    Jacobi-preconditioned, against the oracle's element by element: the first and last steps,
+    where the scalars come from the initial inner product and no new direction is formed."""
+    R = gpu_lib
+    prob = PROBLEMS["c2-small"]()
+    jac = precond == "jacobi"
+    S = solver(R, prob, "cg", steps=steps, cg_precond=R.CG_JACOBI if jac else R.CG_NONE)
+    F = oracle.factor_problem(prob, mu=1.0, smode="cg", cg_steps=steps, ystore=True, ytau=1e-2, cg_jacobi=jac)
+    z = np.random.default_rng(26).standard_normal(prob.n)
+    h = empty(prob.n)
+    assert R.rsilu_apply_z(S.h, to_dev(z), h) == R.OK
+    ratio = elementwise(to_host(h), oracle.apply_alg2(F, z), 1e-10, 1e-13)
+    print(f"c2-small {precond} CG({steps}): elementwise ratio {ratio:.2e}")
+    assert ratio <= 1.0
+    S.close()
+
+
+@pytest.mark.parametrize("precond", ["plain", "jacobi"])
+def test_apply_cg_zero_input(gpu_lib, precond):
+    """z = 0: every inner product of the CG steps is 0, so alpha and beta take their zero rules
+    and the application returns exactly 0 (no 0/0)."""
+    R = gpu_lib
+    prob = PROBLEMS["c2-small"]()
+    S = solver(R, prob, "cg", steps=4, cg_precond=R.CG_JACOBI if precond == "jacobi" else R.CG_NONE)
+    h = empty(prob.n)
+    assert R.rsilu_apply_z(S.h, to_dev(np.zeros(prob.n)), h) == R.OK
+    got = to_host(h)
+    S.close()
+    assert np.all(got == 0.0)
