@@ -6,8 +6,9 @@ headline), and beside it the A1-only preconditioner with LSQR.
 * grid workload, 600000 x 400000, with the correction: on ILUP(10, 1e-2) factors, the products
   with the explicit Y~ and Y~^T componentwise, one application of the correction with CG(8),
   plain and Jacobi, element by element, and four Algorithm 1 steps with each against the
-  oracle's (x to 1e-8); the whole solve in the headline configuration: converged, the true ||A^T r|| at the tolerance,
-  the iteration count within 2% of the oracle's. Longer CG runs are held at the whole-solve level only:
+  oracle's (x to 1e-8); the whole solve in the headline configuration: converged, the true
+  ||A^T r|| at the tolerance, the iteration count within 2% of the oracle's, x in its stop-test
+  ball and within 1e-7 of its x. Longer CG runs are held at the whole-solve level only:
   past some 16 CG steps the iterates depend on the rounding of the inner products well
   beyond eps, on the oracle as on the GPU. The Chebyshev M_b (a fixed polynomial, degree
   80 here): one application element by element and four LSQR steps;
